@@ -1,0 +1,196 @@
+"""Pins of the oracle's system matrix (Eq. (system): a_ij = length of ray i in
+pixel j) against facts that do not come from the oracle itself."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2412_07631_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def chord_length_edges(x0, y0, x1, y1, W):
+    """Length of the part of segment p0->p1 inside the square [-W/2, W/2]^2,
+    found by intersecting the segment with each of the four edges (not by the
+    slab method the oracle uses)."""
+    h = 0.5 * W
+    pts = []
+    for (ax, ay, bx, by) in ((-h, -h, h, -h), (h, -h, h, h), (h, h, -h, h), (-h, h, -h, -h)):
+        # solve p0 + t (p1 - p0) = a + s (b - a)
+        dx, dy = x1 - x0, y1 - y0
+        ex, ey = bx - ax, by - ay
+        den = dx * ey - dy * ex
+        if den == 0.0:
+            continue
+        t = ((ax - x0) * ey - (ay - y0) * ex) / den
+        s = ((ax - x0) * dy - (ay - y0) * dx) / den
+        if -1e-15 <= s <= 1 + 1e-15 and 0.0 <= t <= 1.0:
+            pts.append(t)
+    inside0 = abs(x0) <= h and abs(y0) <= h
+    inside1 = abs(x1) <= h and abs(y1) <= h
+    if inside0:
+        pts.append(0.0)
+    if inside1:
+        pts.append(1.0)
+    if len(pts) < 2:
+        return 0.0
+    return (max(pts) - min(pts)) * math.hypot(x1 - x0, y1 - y0)
+
+
+def brute_force_row(ray, N, W):
+    """Each pixel square clipped separately against the ray (Liang-Barsky)."""
+    x0, y0, x1, y1 = ray
+    dx, dy = x1 - x0, y1 - y0
+    L = math.hypot(dx, dy)
+    h = W / N
+    row = np.zeros(N * N)
+    for iy in range(N):
+        for ix in range(N):
+            xl, xr = -W / 2 + ix * h, -W / 2 + (ix + 1) * h
+            yl, yr = -W / 2 + iy * h, -W / 2 + (iy + 1) * h
+            t0, t1 = 0.0, 1.0
+            ok = True
+            for p, q in ((-dx, x0 - xl), (dx, xr - x0), (-dy, y0 - yl), (dy, yr - y0)):
+                if p == 0.0:
+                    if q < 0:
+                        ok = False
+                        break
+                    continue
+                r = q / p
+                if p < 0:
+                    t0 = max(t0, r)
+                else:
+                    t1 = min(t1, r)
+            if ok and t1 > t0:
+                row[iy * N + ix] = (t1 - t0) * L
+    return row
+
+
+def test_paper_dimensions():
+    """Rows = projections x detectors and columns = pixels, as the paper prints."""
+    with open(os.path.join(GOLDEN, "paper_dimensions.json")) as f:
+        g = json.load(f)
+    for s in g["systems"]:
+        sc = synth.scanner(s["n_pix"], s["n_angles"], s["n_det"])
+        assert sc.m == s["rows"], s["cite"]
+        assert sc.n == s["cols"], s["cite"]
+    for s in g["minimum_projections"]:
+        assert math.ceil(s["n_pix"] ** 2 / s["n_det"]) == s["min_angles"], s["cite"]
+    for s in g["columns"]:
+        assert s["n_pix"] ** 2 == s["cols"], s["cite"]
+    # ray count and order of the oracle's geometry: angle-major, m x 4
+    sc = synth.scanner(8, 6, 10)
+    r = O.rays(sc)
+    assert r.shape == (60, 4)
+    # all rays of one view share the source point
+    assert np.all(r[0:10, 0] == r[0, 0]) and np.all(r[10:20, 1] == r[10, 1])
+
+
+def test_row_sums_equal_chord_lengths():
+    sc = synth.workload_scanner("c1_32")
+    A = O.system_dense(sc)
+    R = O.rays(sc)
+    for i in range(sc.m):
+        L = chord_length_edges(*R[i], sc.grid_width)
+        assert abs(A[i].sum() - L) <= 1e-13, (i, A[i].sum(), L)
+    # the fan covers the circle circumscribing the grid: every pixel is crossed
+    # by some ray of every view, and the central bins always cross the grid
+    for k in range(sc.n_angles):
+        assert np.all(A[k * sc.n_det:(k + 1) * sc.n_det].sum(axis=0) > 0), k
+        assert A[k * sc.n_det + sc.n_det // 2].sum() > 0
+
+
+def test_random_rays_row_sums():
+    g = np.random.default_rng(7)
+    W, N = 1.3, 17
+    for _ in range(300):
+        p = g.uniform(-1.5, 1.5, size=4)
+        row = O.siddon_rows(p[None, :], N, W)[0]
+        assert abs(row.sum() - chord_length_edges(*p, W)) <= 1e-13
+
+
+def test_axis_aligned_rays():
+    """A ray along a pixel row crosses N pixels with length W/N each."""
+    N, W = 16, 1.0
+    h = W / N
+    rays = []
+    for iy in range(N):
+        y = -W / 2 + (iy + 0.5) * h
+        rays.append((-2.0, y, 2.0, y))          # horizontal, left to right
+    for ix in range(N):
+        x = -W / 2 + (ix + 0.3) * h
+        rays.append((x, 3.0, x, -3.0))           # vertical, downwards
+    rows = O.siddon_rows(np.array(rays), N, W)
+    for iy in range(N):
+        expect = np.zeros(N * N)
+        expect[iy * N: iy * N + N] = h
+        assert np.array_equal(rows[iy], expect) or np.max(np.abs(rows[iy] - expect)) <= 1e-16
+        assert abs(rows[iy].sum() - W) <= 1e-15
+    for ix in range(N):
+        r = rows[N + ix].reshape(N, N)
+        assert np.max(np.abs(r[:, ix] - h)) <= 1e-15
+        assert np.count_nonzero(r) == N
+
+
+def test_diagonal_ray_through_corners():
+    """The main diagonal passes through pixel corners: pixels (i, i) get
+    sqrt(2) W/N and the zero-length corner segments are dropped."""
+    N, W = 12, 1.0
+    row = O.siddon_rows(np.array([[-1.0, -1.0, 1.0, 1.0]]), N, W)[0]
+    nz = np.nonzero(row)[0]
+    assert list(nz) == [i * N + i for i in range(N)]
+    assert np.max(np.abs(row[nz] - math.sqrt(2) * W / N)) <= 1e-15
+
+
+@pytest.mark.parametrize("N,na,nd", [(8, 12, 16), (11, 7, 13), (16, 8, 24)])
+def test_brute_force_per_pixel(N, na, nd):
+    sc = synth.scanner(N, na, nd, grid_width=1.0)
+    A = O.system_dense(sc)
+    R = O.rays(sc)
+    for i in range(sc.m):
+        bf = brute_force_row(R[i], N, sc.grid_width)
+        assert np.max(np.abs(A[i] - bf)) <= 1e-14, i
+
+
+def test_quarter_turn_symmetry():
+    """With n_angles % 4 == 0, view k + n_angles/4 sees the image turned by
+    90 degrees: pixel (ix, iy) of view k maps to (N-1-iy, ix)."""
+    N, na, nd = 12, 8, 20
+    sc = synth.scanner(N, na, nd)
+    A = O.system_dense(sc)
+    perm = np.empty(N * N, dtype=np.int64)
+    for iy in range(N):
+        for ix in range(N):
+            perm[iy * N + ix] = ix * N + (N - 1 - iy)
+    q = na // 4
+    for k in range(na - q):
+        a = A[k * nd:(k + 1) * nd]
+        b = A[(k + q) * nd:(k + q + 1) * nd]
+        assert np.max(np.abs(b[:, perm] - a)) <= 1e-12
+
+
+def test_csr_matches_dense():
+    sc = synth.scanner(20, 9, 30)
+    A = O.system_dense(sc)
+    row_ptr, col, val = O.system_csr(sc)
+    D = np.zeros_like(A)
+    for i in range(sc.m):
+        s, e = row_ptr[i], row_ptr[i + 1]
+        assert np.all(np.diff(col[s:e]) > 0)
+        D[i, col[s:e]] = val[s:e]
+    assert np.array_equal(D, A)
+    x = np.random.default_rng(1).standard_normal(sc.n)
+    assert np.max(np.abs(O.csr_matvec((row_ptr, col, val), x) - A @ x)) <= 1e-13
+
+
+def test_generators_are_seeded():
+    a = synth.phantoms(1, 32, [0, 1])
+    b = synth.phantoms(1, 32, [0, 1])
+    assert np.array_equal(a, b)
+    assert a.shape == (1024, 2) and a.min() >= 0.0 and a.max() > 0
+    sizes = synth.uneven_batches()
+    assert sum(sizes) == 4096 and all(1 <= s <= 512 for s in sizes)
