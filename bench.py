@@ -1,0 +1,234 @@
+#!/usr/bin/env python3
+"""Benchmark of the direct algebraic CT reconstruction path on one MI355X.
+
+One step = one pass of the whole hot path over one batch of synthetic input:
+Siddon assembly of A (dense FP32 + FP64 CSR/CSC copies), Householder QR at the
+chosen precision, reconstruction of the batch by X = R^-1 Q^T B followed by
+FP64-residual refinement, and the residual report.  Inputs (phantoms, noisy
+sinograms) are built before the timed region and are resident in HBM.
+
+Printed: one JSON line with QR TFLOP/s (value), slices/s, error against the
+plain FP64 GPU path on the same problem, the live roofline of the dominant
+kernel, and the CPU oracle's rate on a bounded sample of the same work.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "QR TFLOP/s + slices/s at 256^2: FP32/BF16+refine vs FP64 on MI355X, rel err"
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "f16": 2500.0, "bf16x3": 2500.0 / 3.0}
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def qr_flops(m, n):
+    return 2.0 * m * n * n - 2.0 * n ** 3 / 3.0
+
+
+def solve_flops(m, n):
+    return 4.0 * m * n - float(n) * n
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c3_256")
+    ap.add_argument("--prec", default="f32", choices=["f64", "f32", "bf16", "f16", "bf16x3"])
+    ap.add_argument("--refine", type=int, default=3, help="refinement steps")
+    ap.add_argument("--method", default="sne", choices=["sne", "qr"])
+    ap.add_argument("--nrhs", type=int, default=None, help="slices per batch (default: the workload's)")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference path")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-cols", type=int, default=1024, help="leading columns in the CPU oracle sample")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2412_07631_amd import ctqr, synth
+
+    w = synth.WORKLOADS[args.workload]
+    sc = synth.workload_scanner(args.workload)
+    m, n = sc.m, sc.n
+    nrhs = args.nrhs or w["slices"]
+    prec = ctqr.PREC_NAMES[args.prec]
+    method = ctqr.REFINE_SNE if args.method == "sne" else ctqr.REFINE_QR
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    log("workload %s: m=%d n=%d nrhs=%d prec=%s refine=%d(%s)" % (args.workload, m, n, nrhs, args.prec,
+                                                                  args.refine, args.method))
+
+    # ---------------------------------------------------------------- inputs
+    t0 = time.time()
+    sp = ctqr.SparseA(sc)
+    ids = list(range(nrhs))
+    Xtrue = synth.phantoms(w["cfg"], sc.n_pix, ids)
+    Xt = torch.from_numpy(np.ascontiguousarray(Xtrue.T)).to(dev)
+    Xtd = torch.zeros((nrhs, ctqr.ld16(n)), dtype=torch.float64, device=dev)
+    Xtd[:, :n] = Xt
+    zero = torch.zeros((nrhs, ctqr.ld16(m)), dtype=torch.float64, device=dev)
+    Pd = torch.empty_like(zero)
+    ctqr.residual(sp.csr, m, Xtd, zero, Pd)          # P = 0 - A x  (noiseless line integrals, negated)
+    P = (-Pd[:, :m]).cpu().numpy().T
+    B = synth.noisy_sinograms(w["cfg"], P, w["I0"], ids)
+    Bd = torch.zeros((nrhs, ctqr.ld16(m)), dtype=torch.float64, device=dev)
+    Bd[:, :m] = torch.from_numpy(np.ascontiguousarray(B.T)).to(dev)
+    del zero, Pd, P, Xt
+    torch.cuda.synchronize()
+    log("inputs ready in %.1fs" % (time.time() - t0))
+
+    dt_store = torch.float64 if prec == ctqr.PREC_F64 else torch.float32
+    A = torch.empty((n, ctqr.ld16(m)), dtype=dt_store, device=dev)
+    X = torch.zeros((nrhs, ctqr.ld16(n)), dtype=torch.float64, device=dev)
+    scratch = torch.empty(ctqr.refine_workspace(m, n, nrhs), dtype=torch.uint8, device=dev)
+    rn = torch.zeros((args.refine + 1) * nrhs, dtype=torch.float64, device=dev)
+    gn = torch.zeros((args.refine + 1) * nrhs, dtype=torch.float64, device=dev)
+
+    def step(record):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ctqr.build_system(sc, A)
+        sp_step = ctqr.SparseA(sc)
+        e[0].record(stream)
+        f = ctqr.qr_factor(A, m, n, prec, max_nrhs=nrhs)
+        e[1].record(stream)
+        e[2].record(stream)
+        ctqr.solve_refined(f, sp_step, Bd, X, args.refine, method, scratch=scratch, res_norms=rn, grad_norms=gn)
+        e[3].record(stream)
+        info = ctqr.status(f)
+        if info != 0:
+            raise RuntimeError("factorization reports rank deficiency at column %d" % (info - 1))
+        record.append((e[0].elapsed_time(e[1]), e[2].elapsed_time(e[3])))
+        return f
+
+    for i in range(args.warmup):
+        tw = time.time()
+        step([])
+        torch.cuda.synchronize()
+        log("warmup step %d: %.1fs" % (i, time.time() - tw))
+
+    times = []
+    ctqr.profile_begin()
+    torch.cuda.synchronize()
+    t_start = time.time()
+    for i in range(args.steps):
+        f = step(times)
+        log("step %d: qr %.1f ms, solve+refine %.1f ms" % (i, times[-1][0], times[-1][1]))
+    torch.cuda.synchronize()
+    wall = time.time() - t_start
+    prof = ctqr.profile_end()
+
+    qr_ms = sum(t[0] for t in times)
+    sol_ms = sum(t[1] for t in times)
+    qr_tflops = qr_flops(m, n) * args.steps / (qr_ms * 1e-3) / 1e12
+    slices_per_s = nrhs * args.steps / (sol_ms * 1e-3)
+    rnorm = rn.view(args.refine + 1, nrhs).cpu().numpy()
+    gnorm = gn.view(args.refine + 1, nrhs).cpu().numpy()
+    bnorm = np.linalg.norm(B, axis=0)
+    Xm = X[:, :n].cpu().numpy().T.copy()
+
+    # -------------------------------------------------- plain FP64 GPU path
+    fp64 = None
+    if not args.no_fp64 and prec != ctqr.PREC_F64:
+        A64 = torch.empty((n, ctqr.ld16(m)), dtype=torch.float64, device=dev)
+        ctqr.build_system(sc, A64)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record(stream)
+        f64 = ctqr.qr_factor(A64, m, n, ctqr.PREC_F64, max_nrhs=nrhs)
+        ev[1].record(stream)
+        B64 = Bd.clone()
+        ev[2].record(stream)
+        ctqr.apply_qt(f64, B64)
+        ctqr.trsm_solve(f64, B64)
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        X64 = B64[:, :n].cpu().numpy().T.copy()
+        errs = np.linalg.norm(Xm - X64, axis=0) / np.linalg.norm(X64, axis=0)
+        fp64 = {"qr_tflops": qr_flops(m, n) / (ev[0].elapsed_time(ev[1]) * 1e-3) / 1e12,
+                "qr_ms": ev[0].elapsed_time(ev[1]),
+                "slices_per_s": nrhs / (ev[2].elapsed_time(ev[3]) * 1e-3),
+                "rel_err_max": float(errs.max()), "rel_err_median": float(np.median(errs)),
+                "max_abs_pixel_err": float(np.max(np.abs(Xm - X64)))}
+        del A64, B64, f64
+        log("fp64 path: qr %.1f ms (%.2f TFLOP/s), solve %.1f slices/s; mixed vs fp64 max rel err %.3g" % (
+            fp64["qr_ms"], fp64["qr_tflops"], fp64["slices_per_s"], fp64["rel_err_max"]))
+
+    # ------------------------------------------------------ roofline (live)
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    d = prof[dom]
+    achieved = d["flop"] / (d["ms"] * 1e-3) / 1e12 if d["ms"] > 0 else 0.0
+    peak = PEAK_TFLOPS[args.prec]
+    roofline = {"bound": "mfma", "kernel": "gemm_nn_sub (C -= V W)" if dom == "update_cvw" else "gemm_tn (W = V^T C)",
+                "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "launches": d["launches"], "avg_launch_ms": d["ms"] / max(d["launches"], 1),
+                "algorithmic_gbs": d["bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0,
+                "traffic": None,
+                "other_kernel": {k: {"tflops": prof[k]["flop"] / (prof[k]["ms"] * 1e-3) / 1e12 if prof[k]["ms"] else 0,
+                                     "ms": prof[k]["ms"]} for k in prof if k != dom}}
+
+    # --------------------------------------------------------- CPU baseline
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        k = min(args.cpu_cols, n)
+        row_ptr, col, val = O.system_csr(sc)
+        Ablk = np.zeros((m, k), dtype=np.float64, order="F")
+        rows = np.repeat(np.arange(m), np.diff(row_ptr))
+        sel = col < k
+        Ablk[rows[sel], col[sel]] = val[sel]
+        tc = time.time()
+        O.householder_qr(Ablk)
+        tcpu = time.time() - tc
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        cpu = {"value": qr_flops(m, k) / tcpu / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+               "sample": "unblocked FP64 Householder QR of the leading %d x %d column block of the same A (%.1f s)"
+                         % (m, k, tcpu)}
+        log("cpu oracle sample: %.3g TFLOP/s on %d cores (%.1fs)" % (cpu["value"], cores, tcpu))
+
+    out = {
+        "metric": METRIC,
+        "value": qr_tflops,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic (seeded random-ellipse phantoms, Poisson noise)",
+        "config": {"workload": "%s: %dx%d image, %d views x %d bins (m=%d, n=%d), %d noisy slices, I0=%g"
+                               % (args.workload, sc.n_pix, sc.n_pix, sc.n_angles, sc.n_det, m, n, nrhs, w["I0"]),
+                   "global_batch": nrhs, "precision": args.prec, "refine_steps": args.refine,
+                   "refine_method": args.method},
+        "qr_ms": qr_ms / args.steps,
+        "qr_tflops_frac_of_peak": qr_tflops / peak,
+        "slices_per_s": slices_per_s,
+        "solve_ms": sol_ms / args.steps,
+        "solve_tflops": solve_flops(m, n) * nrhs * (1 + args.refine) / (sol_ms / args.steps * 1e-3) / 1e12,
+        "residual_rel_final": float(np.max(rnorm[-1] / bnorm)),
+        "ls_grad_norm_by_step": [float(np.max(gnorm[s])) for s in range(args.refine + 1)],
+        "fp64_path": fp64,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,184 @@
+/*
+ * ctqr -- direct algebraic CT reconstruction on AMD Instinct MI355X (gfx950).
+ *
+ * The method (paper: "Direct Low-Dose CT Image Reconstruction on GPU using
+ * Out-Of-Core: Precision and Quality Study", Sec. 2, Eqs. (system), (qr),
+ * (solve)): model the scanner as A X = B, with A the M x N weights matrix
+ * (a_ij = contribution of ray i to pixel j), B one sinogram per column and X
+ * one image per column; factor A = Q R once and reconstruct every set of
+ * sinograms sharing A by X = R^{-1} (Q^T B), with Q kept as Householder
+ * reflectors and R^{-1} never formed.  Sec. 2.1 names the three library calls
+ * this interface mirrors: geqrf (ct_qr_factor), ormqr (ct_apply_qt) and trsm
+ * (ct_trsm_solve).
+ *
+ * Conventions for every call:
+ *  - Array arguments are DEVICE pointers unless the name ends in _host.
+ *    Matrices are column-major with an explicit leading dimension, which must
+ *    be a multiple of 16 elements; device arrays must be 256-byte aligned.
+ *  - The caller allocates and frees all memory.  The library never frees a
+ *    caller buffer and allocates device memory only in ct_siddon_rows.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *    work and return without waiting, except ct_status and ct_siddon_rows.
+ *    Calls that share a factor must be ordered on one stream.
+ *  - Return value: 0 on success; -i when argument i (1-based) is invalid;
+ *    -1000 - e for a HIP error e.  ct_last_error() gives the message
+ *    (thread-local, valid until the next call from the same thread).
+ *  - Numerical status never stalls the stream: it goes to a device word read
+ *    by ct_status.
+ */
+#ifndef CTQR_H
+#define CTQR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Fan-beam scanner (Table 1 lists the same parameters: circular 360-degree
+ * scan, source-to-isocentre and source-to-detector distances, detector
+ * count, image size, number of projections).  The image is an n_pix x n_pix
+ * grid of side grid_width centred at the isocentre; pixel (ix, iy) is column
+ * j = iy * n_pix + ix.  View k is at angle angle0 + 2 pi k / n_angles; the
+ * flat detector of length det_length is centred on the line through the
+ * isocentre at distance sdd from the source; ray i = k * n_det + d runs from
+ * the source to the centre of bin d. */
+typedef struct ct_geometry {
+    int32_t n_pix, n_angles, n_det, reserved;
+    double grid_width, sid, sdd, det_length, angle0;
+} ct_geometry;
+
+/* Storage types of A and of the sinogram blocks */
+enum { CT_F64 = 0, CT_F32 = 1 };
+
+/* Factorization precisions (the arithmetic of the trailing-matrix updates).
+ * Householder column norms, tau and the reflector scaling are FP64 in all of
+ * them.  CT_PREC_F64 stores A in FP64; all others store A in FP32.
+ *   CT_PREC_F32    FP32 MFMA
+ *   CT_PREC_BF16   bfloat16 operands, FP32 accumulation
+ *   CT_PREC_F16    half operands, FP32 accumulation
+ *   CT_PREC_BF16X3 each FP32 operand split into two bfloat16 halves, three
+ *                  bf16 MFMA products per pair, FP32 accumulation           */
+enum { CT_PREC_F64 = 0, CT_PREC_F32 = 1, CT_PREC_BF16 = 2, CT_PREC_F16 = 3, CT_PREC_BF16X3 = 4 };
+
+typedef struct ct_factor ct_factor; /* opaque, host-side */
+
+/* Assemble the dense system matrix (Eq. (system)) with Siddon's exact
+ * ray-pixel intersection lengths.  A: m x n (m = n_angles * n_det,
+ * n = n_pix^2), dtype CT_F64 or CT_F32 (FP64 lengths rounded to nearest),
+ * leading dimension lda >= m.  Every entry of A[0:m, 0:n] is written. */
+int ct_build_system(const ct_geometry* g, int dtype, void* A, int64_t lda, void* stream);
+
+/* FP64 CSR copy of the same matrix, used for FP64 residuals.  row_ptr has
+ * m + 1 entries.  With col == NULL and val == NULL only row_ptr is filled
+ * (row_ptr[m] = nnz, read it to size col/val); otherwise col/val (capacity
+ * nnz_cap) receive the entries of each row in ray order.  If nnz_cap is
+ * smaller than nnz, col and val are left untouched (check row_ptr[m]). */
+int ct_build_csr(const ct_geometry* g, int64_t* row_ptr, int32_t* col, double* val, int64_t nnz_cap,
+                 void* stream);
+
+/* Workspace bytes for ct_qr_factor of an m x n matrix at precision prec that
+ * will later solve up to max_nrhs right-hand sides per call. */
+int ct_qr_workspace(int64_t m, int64_t n, int prec, int64_t max_nrhs, size_t* bytes);
+
+/* Householder QR, A = Q R (Eq. (qr)), in place: on return A holds R in its
+ * upper triangle and the reflectors v_j (implicit unit diagonal) below it,
+ * tau (n doubles) the reflector scalars, with the LAPACK sign convention
+ * beta = -sign(a_jj) ||a_j||.  Requires m >= n.  A is FP64 for CT_PREC_F64 and
+ * FP32 otherwise.  work (work_bytes from ct_qr_workspace) keeps the
+ * compact-WY factors used by the solve and must stay alive, unmodified, with
+ * A and tau until ct_factor_destroy.  *f receives the host handle. */
+int ct_qr_factor(void* A, int64_t m, int64_t n, int64_t lda, int prec, double* tau, void* work,
+                 size_t work_bytes, int64_t max_nrhs, ct_factor** f, void* stream);
+
+/* B <- Q^T B (Eq. (solve), first half; ormqr).  B: m x nrhs, same storage
+ * type as the factor's A, nrhs <= max_nrhs.  Rows n..m-1 of the result hold
+ * the least-squares residual components. */
+int ct_apply_qt(const ct_factor* f, void* B, int64_t nrhs, int64_t ldb, void* stream);
+
+/* B[0:n] <- R^{-1} B[0:n] (Eq. (solve), second half; trsm), by blocked
+ * back-substitution: diagonal-block solves alternating with GEMM updates of
+ * the rows above (Sec. 2.2). */
+int ct_trsm_solve(const ct_factor* f, void* B, int64_t nrhs, int64_t ldb, void* stream);
+
+/* Adjoint of the solve map b -> x = R^{-1} Q^T b: gradB <- Q [R^{-T} G; 0].
+ * G: n x k (ldg), gradB: m x k (ldgb), both of the factor's storage type. */
+int ct_solve_backward(const ct_factor* f, const void* G, int64_t k, int64_t ldg, void* gradB, int64_t ldgb,
+                      void* stream);
+
+/* R = B - A X in FP64 with the CSR copy of A (m rows); X: n x nrhs. */
+int ct_residual(const int64_t* row_ptr, const int32_t* col, const double* val, int64_t m, const double* X,
+                int64_t ldx, const double* B, int64_t ldb, double* R, int64_t ldr, int64_t nrhs, void* stream);
+
+/* CSC copy of A (the rows of A^T) from its CSR copy, for FP64 products A^T r.
+ * col_ptr: n + 1 entries; row/cval: nnz entries each; work: n int32 scratch.
+ * Entries of each column are sorted by row (the result is deterministic). */
+int ct_build_csc(int64_t m, int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
+                 int64_t* col_ptr, int32_t* row, double* cval, int32_t* work, void* stream);
+
+/* The FP64 sparse copies of A used by the refinement (device arrays). */
+typedef struct ct_sparse {
+    int64_t m, n, nnz;
+    const int64_t* row_ptr; const int32_t* col; const double* val;   /* CSR of A  */
+    const int64_t* col_ptr; const int32_t* row; const double* cval;  /* CSC of A (may be NULL for CT_REFINE_QR) */
+} ct_sparse;
+
+/* Refinement steps (the correction is computed with the factor Q~ R~ in its
+ * own precision; residuals and the accumulated solution are FP64):
+ *   CT_REFINE_QR:  x += R~^{-1} Q~^T (b - A x)
+ *     Its fixed point satisfies Q~^T (b - A x) = 0, which differs from the
+ *     least-squares solution by O(kappa^2 u ||r||) when b is not in range(A).
+ *   CT_REFINE_SNE: x += R~^{-1} R~^{-T} A^T (b - A x)   (corrected semi-normal
+ *     equations, Bjorck 1987).  Its fixed point is A^T (b - A x) = 0, the
+ *     least-squares solution itself; each step contracts the error by about
+ *     kappa(A) u_factor.  Needs the CSC copy. */
+enum { CT_REFINE_QR = 0, CT_REFINE_SNE = 1 };
+
+/* Scratch bytes for ct_solve_refined with nrhs right-hand sides. */
+int ct_refine_workspace(int64_t m, int64_t n, int64_t nrhs, size_t* bytes);
+
+/* Reconstruction with iterative refinement on the FP64 residual r = b - A x:
+ *   x_0 = R~^{-1} Q~^T b, then `steps` refinement steps of kind `method`.
+ * B: m x nrhs FP64 (unchanged), X: n x nrhs FP64 (output).  If not NULL,
+ * res_norms receives ||r_s||_2 and grad_norms ||A^T r_s||_2 (the latter needs
+ * the CSC copy) for s = 0..steps, (steps + 1) x nrhs, step-major. */
+int ct_solve_refined(const ct_factor* f, const ct_sparse* A, const double* B, int64_t ldb, double* X,
+                     int64_t ldx, int64_t nrhs, int32_t steps, int32_t method, void* scratch,
+                     size_t scratch_bytes, double* res_norms, double* grad_norms, void* stream);
+
+/* Waits for `stream`, then reports the factor's numerical status: *info = 0
+ * for full column rank, j + 1 if column j had a zero Householder norm.
+ * Returns -2001 if a cross-workgroup wait of the factorization timed out. */
+int ct_status(const ct_factor* f, int64_t* info, void* stream);
+
+int ct_factor_destroy(ct_factor* f);
+
+/* Live timing of the trailing-matrix update GEMMs of ct_qr_factor (the
+ * dominant kernels): while enabled, every launch of the two update kernels
+ * (W = V^T C, and C -= V W) is bracketed by HIP events on the stream it runs
+ * on.  ct_profile_begin clears and enables; ct_profile_end waits for the
+ * recorded events, disables, and returns per-kernel totals: launches, summed
+ * event time (ms), algorithmic flops (2 M N K per launch) and algorithmic
+ * bytes (operands read once, results written once).  Host-side state, one
+ * process-wide recorder; not for concurrent factorizations. */
+typedef struct ct_profile {
+    int64_t launches[2];   /* [0]: W = V^T C kernel, [1]: C -= V W kernel */
+    double ms[2];
+    double flop[2];
+    double bytes[2];
+} ct_profile;
+int ct_profile_begin(void);
+int ct_profile_end(ct_profile* out);
+
+const char* ct_last_error(void);
+
+/* Rows of A for explicit rays (host arrays): rays_host r x 4 (x0, y0, x1, y1)
+ * row-major, rows_host r x n_pix^2 row-major.  Synchronous; computed on the
+ * GPU with the same walk as ct_build_system. */
+int ct_siddon_rows(const double* rays_host, int64_t r, int32_t n_pix, double grid_width, double* rows_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CTQR_H */

@@ -1,0 +1,57 @@
+// Internal definitions shared by the HIP kernels and the host driver of
+// libctqr.  Not installed; the public interface is include/ctqr.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace ctqr {
+
+// ----------------------------------------------------------------------------
+// Arithmetic modes of the block-reflector GEMMs (trailing update, solve).
+//   F64    : FP64 operands, v_mfma_f64_16x16x4 (FP64 accumulate)
+//   F32    : FP32 operands, v_mfma_f32_16x16x4 (FP32 accumulate)
+//   BF16   : operands rounded to bfloat16, v_mfma_f32_16x16x32_bf16
+//   F16    : operands rounded to half, v_mfma_f32_16x16x32_f16
+//   BF16X3 : each FP32 operand split as hi + lo bfloat16 pair; the product is
+//            hi*hi + hi*lo + lo*hi on the bf16 MFMA (about 16 significant bits)
+// ----------------------------------------------------------------------------
+enum Mode : int { M_F64 = 0, M_F32 = 1, M_BF16 = 2, M_F16 = 3, M_BF16X3 = 4 };
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
+
+// Lane layouts of the 16x16 MFMA tiles used here (wavefront of 64 lanes,
+// g = lane / 16, c = lane % 16):
+//   A operand: lane holds A[c][k] for the k slots of its group g
+//   B operand: lane holds B[k][c] for the k slots of its group g
+//   D (FP32 accumulating forms): value q of lane is D[4 g + q][c]
+//   D (FP64 form):               value q of lane is D[g + 4 q][c]
+// The sum over k does not care which physical k a (group, slot) pair carries
+// as long as A and B agree, so loaders assign k = group * S + slot with S
+// consecutive k per lane, which turns every fragment load into one vector load.
+__device__ __forceinline__ int d_row(int mode, int g, int q) { return mode == M_F64 ? g + 4 * q : 4 * g + q; }
+
+template <typename T> struct Acc;
+template <> struct Acc<double> { typedef d4_t v; };
+template <> struct Acc<float> { typedef f4_t v; };
+
+// Spin limit of the cross-workgroup barriers (iterations of ~0.1 us sleeps);
+// reaching it sets the error word and lets every wave run to completion.
+constexpr uint32_t kSpinLimit = 1u << 26;
+
+// Device-side copy of the scanner description (see ct_geometry).
+struct GeomDev {
+    int32_t n_pix, n_angles, n_det;
+    double W, sid, sdd, det_length, angle0;
+};
+
+struct ErrWord {
+    // bit 0: barrier spin limit hit; bit 1: CSR capacity exceeded; bit 2: invalid batch descriptor
+    int32_t flags;
+};
+
+}  // namespace ctqr

@@ -1,0 +1,252 @@
+// Triangular diagonal-block solves, the FP64 residual, and small elementwise
+// kernels of the solve path (Eq. (solve): X = R^{-1} C with R kept triangular
+// and never inverted; the blocked back-substitution of Sec. 2.2 alternates
+// these diagonal solves with GEMM updates of the rows above).
+#include "ct_internal.h"
+
+namespace ctqr {
+
+constexpr int kTrsmBlock = 128;
+
+// X_b = R_bb^{-1} C_b (UPPER) or Z_b = R_bb^{-T} C_b (!UPPER) in place, for a
+// bo x bo diagonal block (bo <= 128) and nrhs columns.  R_bb sits in LDS as
+// FP64 (leading dimension bo + 1 against bank conflicts); one wavefront per
+// right-hand side, two rows per lane, one substitution step per row.
+template <typename TS, bool UPPER>
+__global__ void __launch_bounds__(256) trsm_diag_kernel(const TS* __restrict__ R, int64_t ldr, int bo,
+                                                        TS* __restrict__ B, int64_t ldb, int nrhs)
+{
+    extern __shared__ double Rs[];
+    const int ld = bo + 1;
+    for (int e = threadIdx.x; e < bo * bo; e += 256) {
+        const int q = e / bo, p = e - q * bo;
+        Rs[p + q * ld] = p <= q ? (double)R[p + (int64_t)q * ldr] : 0.0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int j = blockIdx.x * 4 + wv; j < nrhs; j += gridDim.x * 4) {
+        TS* col = B + (int64_t)j * ldb;
+        double x0 = lane < bo ? (double)col[lane] : 0.0;
+        double x1 = lane + 64 < bo ? (double)col[lane + 64] : 0.0;
+        if (UPPER) {
+            for (int jj = bo - 1; jj >= 0; --jj) {
+                const int owner = jj & 63;
+                const double cj = __shfl(jj < 64 ? x0 : x1, owner, 64);
+                const double z = cj / Rs[jj + jj * ld];
+                if (lane == owner) {
+                    if (jj < 64) x0 = z; else x1 = z;
+                }
+                if (lane < jj) x0 -= Rs[lane + jj * ld] * z;
+                if (lane + 64 < jj) x1 -= Rs[lane + 64 + jj * ld] * z;
+            }
+        } else {
+            for (int jj = 0; jj < bo; ++jj) {
+                const int owner = jj & 63;
+                const double cj = __shfl(jj < 64 ? x0 : x1, owner, 64);
+                const double z = cj / Rs[jj + jj * ld];
+                if (lane == owner) {
+                    if (jj < 64) x0 = z; else x1 = z;
+                }
+                if (lane > jj && lane < bo) x0 -= Rs[jj + lane * ld] * z;
+                if (lane + 64 > jj && lane + 64 < bo) x1 -= Rs[jj + (lane + 64) * ld] * z;
+            }
+        }
+        if (lane < bo) col[lane] = (TS)x0;
+        if (lane + 64 < bo) col[lane + 64] = (TS)x1;
+    }
+}
+
+// R = B - A X in FP64 from the CSR copy of A; one lane per row, eight
+// right-hand sides per lane so each CSR entry is read once per eight columns.
+__global__ void __launch_bounds__(256) residual_kernel(const int64_t* __restrict__ row_ptr,
+                                                       const int32_t* __restrict__ col,
+                                                       const double* __restrict__ val, int64_t m,
+                                                       const double* __restrict__ X, int64_t ldx,
+                                                       const double* __restrict__ B, int64_t ldb, double* R,
+                                                       int64_t ldr, int nrhs)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int j0 = blockIdx.y * 8;
+    if (i >= m) return;
+    double acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    const int nq = nrhs - j0 < 8 ? nrhs - j0 : 8;
+    for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+        const double v = val[p];
+        const int64_t c = col[p];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (q < nq) acc[q] += v * X[c + (int64_t)(j0 + q) * ldx];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        if (q < nq) R[i + (int64_t)(j0 + q) * ldr] = B[i + (int64_t)(j0 + q) * ldb] - acc[q];
+}
+
+// S = A^T R in FP64 from the CSC copy of A (entries of a column sorted by
+// row); one lane per column, eight right-hand sides per lane.
+__global__ void __launch_bounds__(256) residual_t_kernel(const int64_t* __restrict__ col_ptr,
+                                                         const int32_t* __restrict__ row,
+                                                         const double* __restrict__ cval, int64_t n,
+                                                         const double* __restrict__ R, int64_t ldr, double* S,
+                                                         int64_t lds, int nrhs)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int c0 = blockIdx.y * 8;
+    if (j >= n) return;
+    double acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    const int nq = nrhs - c0 < 8 ? nrhs - c0 : 8;
+    for (int64_t p = col_ptr[j]; p < col_ptr[j + 1]; ++p) {
+        const double v = cval[p];
+        const int64_t i = row[p];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (q < nq) acc[q] += v * R[i + (int64_t)(c0 + q) * ldr];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        if (q < nq) S[j + (int64_t)(c0 + q) * lds] = acc[q];
+}
+
+// Y (rows x cols, ldy) = (TO) X (ldx)
+template <typename TI, typename TO>
+__global__ void __launch_bounds__(256) convert_kernel(const TI* __restrict__ X, int64_t ldx, TO* __restrict__ Y,
+                                                      int64_t ldy, int64_t rows, int cols)
+{
+    for (int j = blockIdx.y; j < cols; j += gridDim.y)
+        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < rows; i += (int64_t)gridDim.x * 256)
+            Y[i + (int64_t)j * ldy] = (TO)X[i + (int64_t)j * ldx];
+}
+
+// X (FP64) += D
+template <typename TD>
+__global__ void __launch_bounds__(256) accumulate_kernel(double* __restrict__ X, int64_t ldx,
+                                                         const TD* __restrict__ D, int64_t ldd, int64_t rows,
+                                                         int cols)
+{
+    for (int j = blockIdx.y; j < cols; j += gridDim.y)
+        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < rows; i += (int64_t)gridDim.x * 256)
+            X[i + (int64_t)j * ldx] += (double)D[i + (int64_t)j * ldd];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) zero_rows_kernel(T* __restrict__ Y, int64_t ldy, int64_t r0, int64_t r1,
+                                                        int cols)
+{
+    for (int j = blockIdx.y; j < cols; j += gridDim.y)
+        for (int64_t i = r0 + (int64_t)blockIdx.x * 256 + threadIdx.x; i < r1; i += (int64_t)gridDim.x * 256)
+            Y[i + (int64_t)j * ldy] = (T)0;
+}
+
+// out[j] = ||X[:, j]||_2 in FP64 (fixed-order tree, one workgroup per column)
+__global__ void __launch_bounds__(256) colnorm_kernel(const double* __restrict__ X, int64_t ldx, int64_t rows,
+                                                      double* out)
+{
+    __shared__ double red[256];
+    const int j = blockIdx.x;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < rows; i += 256) {
+        const double v = X[i + (int64_t)j * ldx];
+        s += v * v;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = sqrt(red[0]);
+}
+
+// ------------------------------------------------------------------ launchers
+static inline dim3 grid2(int64_t rows, int cols)
+{
+    int64_t gx = (rows + 255) / 256;
+    if (gx > 1024) gx = 1024;
+    int gy = cols < 65535 ? cols : 65535;
+    return dim3((unsigned)(gx > 0 ? gx : 1), (unsigned)(gy > 0 ? gy : 1));
+}
+
+template <typename TS, bool UPPER>
+hipError_t launch_trsm_diag(const TS* R, int64_t ldr, int bo, TS* B, int64_t ldb, int nrhs, hipStream_t s)
+{
+    const size_t sh = (size_t)bo * (bo + 1) * sizeof(double);
+    int blocks = (nrhs + 3) / 4;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL((trsm_diag_kernel<TS, UPPER>), dim3(blocks), dim3(256), sh, s, R, ldr, bo, B, ldb, nrhs);
+    return hipGetLastError();
+}
+
+hipError_t trsm_set_max_lds(size_t bytes)
+{
+    hipError_t e;
+    e = hipFuncSetAttribute((const void*)trsm_diag_kernel<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)trsm_diag_kernel<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)trsm_diag_kernel<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)trsm_diag_kernel<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_residual(const int64_t* row_ptr, const int32_t* col, const double* val, int64_t m, const double* X,
+                           int64_t ldx, const double* B, int64_t ldb, double* R, int64_t ldr, int nrhs, hipStream_t s)
+{
+    dim3 grid((unsigned)((m + 255) / 256), (unsigned)((nrhs + 7) / 8));
+    hipLaunchKernelGGL(residual_kernel, grid, dim3(256), 0, s, row_ptr, col, val, m, X, ldx, B, ldb, R, ldr, nrhs);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_t(const int64_t* col_ptr, const int32_t* row, const double* cval, int64_t n,
+                             const double* R, int64_t ldr, double* S, int64_t lds, int nrhs, hipStream_t s)
+{
+    dim3 grid((unsigned)((n + 255) / 256), (unsigned)((nrhs + 7) / 8));
+    hipLaunchKernelGGL(residual_t_kernel, grid, dim3(256), 0, s, col_ptr, row, cval, n, R, ldr, S, lds, nrhs);
+    return hipGetLastError();
+}
+
+template <typename TI, typename TO>
+hipError_t launch_convert(const TI* X, int64_t ldx, TO* Y, int64_t ldy, int64_t rows, int cols, hipStream_t s)
+{
+    hipLaunchKernelGGL((convert_kernel<TI, TO>), grid2(rows, cols), dim3(256), 0, s, X, ldx, Y, ldy, rows, cols);
+    return hipGetLastError();
+}
+
+template <typename TD>
+hipError_t launch_accumulate(double* X, int64_t ldx, const TD* D, int64_t ldd, int64_t rows, int cols, hipStream_t s)
+{
+    hipLaunchKernelGGL((accumulate_kernel<TD>), grid2(rows, cols), dim3(256), 0, s, X, ldx, D, ldd, rows, cols);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_zero_rows(T* Y, int64_t ldy, int64_t r0, int64_t r1, int cols, hipStream_t s)
+{
+    if (r1 <= r0) return hipSuccess;
+    hipLaunchKernelGGL((zero_rows_kernel<T>), grid2(r1 - r0, cols), dim3(256), 0, s, Y, ldy, r0, r1, cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_colnorm(const double* X, int64_t ldx, int64_t rows, int cols, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(colnorm_kernel, dim3(cols), dim3(256), 0, s, X, ldx, rows, out);
+    return hipGetLastError();
+}
+
+template hipError_t launch_trsm_diag<double, true>(const double*, int64_t, int, double*, int64_t, int, hipStream_t);
+template hipError_t launch_trsm_diag<double, false>(const double*, int64_t, int, double*, int64_t, int, hipStream_t);
+template hipError_t launch_trsm_diag<float, true>(const float*, int64_t, int, float*, int64_t, int, hipStream_t);
+template hipError_t launch_trsm_diag<float, false>(const float*, int64_t, int, float*, int64_t, int, hipStream_t);
+template hipError_t launch_convert<double, float>(const double*, int64_t, float*, int64_t, int64_t, int, hipStream_t);
+template hipError_t launch_convert<float, double>(const float*, int64_t, double*, int64_t, int64_t, int, hipStream_t);
+template hipError_t launch_convert<double, double>(const double*, int64_t, double*, int64_t, int64_t, int, hipStream_t);
+template hipError_t launch_convert<float, float>(const float*, int64_t, float*, int64_t, int64_t, int, hipStream_t);
+template hipError_t launch_accumulate<float>(double*, int64_t, const float*, int64_t, int64_t, int, hipStream_t);
+template hipError_t launch_accumulate<double>(double*, int64_t, const double*, int64_t, int64_t, int, hipStream_t);
+template hipError_t launch_zero_rows<float>(float*, int64_t, int64_t, int64_t, int, hipStream_t);
+template hipError_t launch_zero_rows<double>(double*, int64_t, int64_t, int64_t, int, hipStream_t);
+
+}  // namespace ctqr

@@ -1,0 +1,270 @@
+"""Python binding of libctqr (include/ctqr.h): argument marshalling only.
+
+Every computation happens in the HIP library; torch provides device memory
+and streams.  Importing this module loads ``libctqr.so`` from the package
+directory and raises ImportError if it has not been built
+(``python -m paper_2412_07631_amd.build``) -- there is no fallback.
+
+Matrix convention: a column-major matrix with leading dimension ``ld`` and
+``cols`` columns is a contiguous torch tensor of shape ``(cols, ld)`` (row c
+of the tensor is column c of the matrix).  ``colmajor(rows, cols, dtype)``
+allocates one with ``ld`` rounded up to a multiple of 16.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libctqr.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libctqr.so is not built (run: python -m paper_2412_07631_amd.build)")
+_lib = ctypes.CDLL(LIB_PATH)
+
+F64, F32 = 0, 1
+REFINE_QR, REFINE_SNE = 0, 1
+PREC_F64, PREC_F32, PREC_BF16, PREC_F16, PREC_BF16X3 = 0, 1, 2, 3, 4
+PREC_NAMES = {"f64": PREC_F64, "f32": PREC_F32, "bf16": PREC_BF16, "f16": PREC_F16, "bf16x3": PREC_BF16X3}
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_sz = ctypes.c_size_t
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("n_pix", _i32), ("n_angles", _i32), ("n_det", _i32), ("reserved", _i32),
+                ("grid_width", ctypes.c_double), ("sid", ctypes.c_double), ("sdd", ctypes.c_double),
+                ("det_length", ctypes.c_double), ("angle0", ctypes.c_double)]
+
+
+def _sig(name, args, res=ctypes.c_int):
+    f = getattr(_lib, name)
+    f.argtypes = args
+    f.restype = res
+    return f
+
+
+_sig("ct_build_system", [ctypes.POINTER(Geometry), ctypes.c_int, _vp, _i64, _vp])
+_sig("ct_build_csr", [ctypes.POINTER(Geometry), _vp, _vp, _vp, _i64, _vp])
+_sig("ct_qr_workspace", [_i64, _i64, ctypes.c_int, _i64, ctypes.POINTER(_sz)])
+_sig("ct_qr_factor", [_vp, _i64, _i64, _i64, ctypes.c_int, _vp, _vp, _sz, _i64, ctypes.POINTER(_vp), _vp])
+_sig("ct_apply_qt", [_vp, _vp, _i64, _i64, _vp])
+_sig("ct_trsm_solve", [_vp, _vp, _i64, _i64, _vp])
+_sig("ct_solve_backward", [_vp, _vp, _i64, _i64, _vp, _i64, _vp])
+_sig("ct_residual", [_vp, _vp, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _i64, _vp])
+_sig("ct_refine_workspace", [_i64, _i64, _i64, ctypes.POINTER(_sz)])
+_sig("ct_build_csc", [_i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp])
+
+
+class Sparse(ctypes.Structure):
+    _fields_ = [("m", _i64), ("n", _i64), ("nnz", _i64), ("row_ptr", _vp), ("col", _vp), ("val", _vp),
+                ("col_ptr", _vp), ("row", _vp), ("cval", _vp)]
+
+
+_sig("ct_solve_refined", [_vp, ctypes.POINTER(Sparse), _vp, _i64, _vp, _i64, _i64, _i32, _i32, _vp, _sz, _vp, _vp,
+                          _vp])
+class Profile(ctypes.Structure):
+    _fields_ = [("launches", _i64 * 2), ("ms", ctypes.c_double * 2), ("flop", ctypes.c_double * 2),
+                ("bytes", ctypes.c_double * 2)]
+
+
+_sig("ct_profile_begin", [])
+_sig("ct_profile_end", [ctypes.POINTER(Profile)])
+_sig("ct_status", [_vp, ctypes.POINTER(_i64), _vp])
+_sig("ct_factor_destroy", [_vp])
+_sig("ct_last_error", [], ctypes.c_char_p)
+_sig("ct_siddon_rows", [_vp, _i64, _i32, ctypes.c_double, _vp])
+
+
+class CtError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("ctqr error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _check(rc):
+    if rc != 0:
+        raise CtError(rc, (_lib.ct_last_error() or b"").decode())
+    return rc
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return _vp(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else _vp(t.data_ptr())
+
+
+def ld16(rows: int) -> int:
+    return (int(rows) + 15) // 16 * 16
+
+
+def colmajor(rows: int, cols: int, dtype, device="cuda", zero=False):
+    """Column-major (rows x cols) matrix as a (cols, ld) tensor."""
+    shape = (int(cols), ld16(rows))
+    return torch.zeros(shape, dtype=dtype, device=device) if zero else torch.empty(shape, dtype=dtype, device=device)
+
+
+def geometry(s) -> Geometry:
+    """Geometry from any object with the ct_geometry fields (e.g. synth.Scanner)."""
+    return Geometry(int(s.n_pix), int(s.n_angles), int(s.n_det), 0, float(s.grid_width), float(s.sid),
+                    float(s.sdd), float(s.det_length), float(s.angle0))
+
+
+# -------------------------------------------------------------------- calls
+def build_system(geom, A: torch.Tensor, stream=None):
+    """A: (n, lda) tensor, float64 or float32; filled with the system matrix."""
+    g = geometry(geom)
+    dt = F64 if A.dtype == torch.float64 else F32
+    _check(_lib.ct_build_system(ctypes.byref(g), dt, _ptr(A), A.shape[1], _stream(stream)))
+    return A
+
+
+def build_csr(geom, device="cuda", stream=None):
+    """(row_ptr int64[m+1], col int32[nnz], val float64[nnz]) on the device."""
+    g = geometry(geom)
+    m = int(geom.n_angles) * int(geom.n_det)
+    row_ptr = torch.empty(m + 1, dtype=torch.int64, device=device)
+    _check(_lib.ct_build_csr(ctypes.byref(g), _ptr(row_ptr), None, None, 0, _stream(stream)))
+    nnz = int(row_ptr[m].item())
+    col = torch.empty(max(nnz, 1), dtype=torch.int32, device=device)
+    val = torch.empty(max(nnz, 1), dtype=torch.float64, device=device)
+    _check(_lib.ct_build_csr(ctypes.byref(g), _ptr(row_ptr), _ptr(col), _ptr(val), nnz, _stream(stream)))
+    return row_ptr, col[:nnz], val[:nnz]
+
+
+def qr_workspace(m: int, n: int, prec: int, max_nrhs: int) -> int:
+    b = _sz(0)
+    _check(_lib.ct_qr_workspace(m, n, prec, max_nrhs, ctypes.byref(b)))
+    return b.value
+
+
+class Factor:
+    """Host handle of a factorization; keeps the device buffers it borrows alive."""
+
+    def __init__(self, handle, A, tau, work, m, n, prec, max_nrhs):
+        self.handle, self.A, self.tau, self.work = handle, A, tau, work
+        self.m, self.n, self.prec, self.max_nrhs = m, n, prec, max_nrhs
+        self.dtype = torch.float64 if prec == PREC_F64 else torch.float32
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            _lib.ct_factor_destroy(h)
+            self.handle = None
+
+
+def qr_factor(A: torch.Tensor, m: int, n: int, prec: int, max_nrhs: int = 512, stream=None) -> Factor:
+    """Factor A (an (n, lda) tensor holding the m x n matrix) in place."""
+    want = torch.float64 if prec == PREC_F64 else torch.float32
+    if A.dtype != want:
+        raise TypeError("A must be %s for this precision" % want)
+    tau = torch.zeros(n, dtype=torch.float64, device=A.device)
+    work = torch.empty(qr_workspace(m, n, prec, max_nrhs), dtype=torch.uint8, device=A.device)
+    h = _vp()
+    _check(_lib.ct_qr_factor(_ptr(A), m, n, A.shape[1], prec, _ptr(tau), _ptr(work), work.numel(), max_nrhs,
+                             ctypes.byref(h), _stream(stream)))
+    return Factor(h, A, tau, work, m, n, prec, max_nrhs)
+
+
+def apply_qt(f: Factor, B: torch.Tensor, nrhs: int = None, stream=None):
+    nrhs = B.shape[0] if nrhs is None else nrhs
+    _check(_lib.ct_apply_qt(f.handle, _ptr(B), nrhs, B.shape[1], _stream(stream)))
+    return B
+
+
+def trsm_solve(f: Factor, B: torch.Tensor, nrhs: int = None, stream=None):
+    nrhs = B.shape[0] if nrhs is None else nrhs
+    _check(_lib.ct_trsm_solve(f.handle, _ptr(B), nrhs, B.shape[1], _stream(stream)))
+    return B
+
+
+def solve_backward(f: Factor, G: torch.Tensor, gradB: torch.Tensor, k: int = None, stream=None):
+    k = G.shape[0] if k is None else k
+    _check(_lib.ct_solve_backward(f.handle, _ptr(G), k, G.shape[1], _ptr(gradB), gradB.shape[1], _stream(stream)))
+    return gradB
+
+
+def residual(csr, m: int, X: torch.Tensor, B: torch.Tensor, R: torch.Tensor, nrhs: int = None, stream=None):
+    row_ptr, col, val = csr
+    nrhs = X.shape[0] if nrhs is None else nrhs
+    _check(_lib.ct_residual(_ptr(row_ptr), _ptr(col), _ptr(val), m, _ptr(X), X.shape[1], _ptr(B), B.shape[1],
+                            _ptr(R), R.shape[1], nrhs, _stream(stream)))
+    return R
+
+
+def refine_workspace(m: int, n: int, nrhs: int) -> int:
+    b = _sz(0)
+    _check(_lib.ct_refine_workspace(m, n, nrhs, ctypes.byref(b)))
+    return b.value
+
+
+class SparseA:
+    """FP64 CSR and CSC copies of A on the device (kept alive with the struct)."""
+
+    def __init__(self, geom, device="cuda", stream=None):
+        self.m = int(geom.n_angles) * int(geom.n_det)
+        self.n = int(geom.n_pix) ** 2
+        self.row_ptr, self.col, self.val = build_csr(geom, device, stream)
+        self.nnz = int(self.val.numel())
+        self.col_ptr = torch.empty(self.n + 1, dtype=torch.int64, device=device)
+        self.row = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=device)
+        self.cval = torch.empty(max(self.nnz, 1), dtype=torch.float64, device=device)
+        work = torch.empty(self.n, dtype=torch.int32, device=device)
+        _check(_lib.ct_build_csc(self.m, self.n, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val),
+                                 _ptr(self.col_ptr), _ptr(self.row), _ptr(self.cval), _ptr(work), _stream(stream)))
+        torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+        self.struct = Sparse(self.m, self.n, self.nnz, self.row_ptr.data_ptr(), self.col.data_ptr(),
+                             self.val.data_ptr(), self.col_ptr.data_ptr(), self.row.data_ptr(), self.cval.data_ptr())
+
+    @property
+    def csr(self):
+        return self.row_ptr, self.col, self.val
+
+
+def solve_refined(f: Factor, sp: SparseA, B: torch.Tensor, X: torch.Tensor, steps: int, method: int = REFINE_SNE,
+                  nrhs: int = None, scratch: torch.Tensor = None, res_norms: torch.Tensor = None,
+                  grad_norms: torch.Tensor = None, stream=None):
+    """X (FP64) <- refined least-squares solution for the FP64 sinograms B."""
+    nrhs = B.shape[0] if nrhs is None else nrhs
+    if scratch is None:
+        scratch = torch.empty(refine_workspace(f.m, f.n, nrhs), dtype=torch.uint8, device=B.device)
+    _check(_lib.ct_solve_refined(f.handle, ctypes.byref(sp.struct), _ptr(B), B.shape[1], _ptr(X), X.shape[1], nrhs,
+                                 int(steps), int(method), _ptr(scratch), scratch.numel(), _ptr(res_norms),
+                                 _ptr(grad_norms), _stream(stream)))
+    return X
+
+
+def profile_begin():
+    _check(_lib.ct_profile_begin())
+
+
+def profile_end() -> dict:
+    """Event-timed totals of the trailing-update kernels since profile_begin."""
+    p = Profile()
+    _check(_lib.ct_profile_end(ctypes.byref(p)))
+    names = ("update_vtc", "update_cvw")
+    return {names[k]: {"launches": int(p.launches[k]), "ms": float(p.ms[k]), "flop": float(p.flop[k]),
+                       "bytes": float(p.bytes[k])} for k in range(2)}
+
+
+def status(f: Factor, stream=None) -> int:
+    info = _i64(0)
+    _check(_lib.ct_status(f.handle, ctypes.byref(info), _stream(stream)))
+    return info.value
+
+
+def siddon_rows(rays, n_pix: int, grid_width: float = 1.0):
+    """Host numpy in/out: dense rows (r x n_pix^2) for r x 4 ray end points."""
+    import numpy as np
+    r = np.ascontiguousarray(np.asarray(rays, dtype=np.float64).reshape(-1, 4))
+    out = np.empty((r.shape[0], int(n_pix) ** 2), dtype=np.float64)
+    _check(_lib.ct_siddon_rows(r.ctypes.data_as(_vp), r.shape[0], int(n_pix), float(grid_width),
+                               out.ctypes.data_as(_vp)))
+    return out

@@ -61,12 +61,15 @@ def scanner(n_pix: int, n_angles: int, n_det: int, grid_width: float = 1.0,
 
     Source-to-isocentre distance 2W; source-to-detector twice that (the 75 cm /
     150 cm ratio of Table 1); a flat detector whose fan just covers the circle
-    circumscribing the image, so every pixel is seen from every view.
+    inscribed in the image, so that every ray crosses the image.  (A fan wide
+    enough for the circumscribed circle wastes about a third of the rays on
+    empty space and leaves the 120-view x 640-bin system at 256^2 rank
+    deficient; the inscribed fan keeps it full rank.)
     """
     W = float(grid_width)
     sid = 2.0 * W
     sdd = 2.0 * sid
-    half_fan = math.asin(W / (math.sqrt(2.0) * sid))
+    half_fan = math.asin(W / (2.0 * sid))
     det_length = 2.0 * sdd * math.tan(half_fan)
     return Scanner(n_pix, n_angles, n_det, W, sid, sdd, det_length, float(angle0))
 

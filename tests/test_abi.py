@@ -1,0 +1,55 @@
+"""CPU-side checks of the C-ABI library: it loads, and it exports every entry
+point the public header declares (no compute calls: there is no GPU here)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ctqr.h")
+LIB = os.path.join(ROOT, "paper_2412_07631_amd", "libctqr.so")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ct_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_symbols()
+    for required in ("ct_build_system", "ct_qr_factor", "ct_apply_qt", "ct_trsm_solve", "ct_solve_backward"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    assert os.path.exists(LIB), "build first: python -m paper_2412_07631_amd.build"
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_symbols() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_argument_errors_without_gpu():
+    """Argument validation runs before any device work: -i for argument i."""
+    lib = ctypes.CDLL(LIB)
+    lib.ct_qr_workspace.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int64,
+                                    ctypes.POINTER(ctypes.c_size_t)]
+    lib.ct_last_error.restype = ctypes.c_char_p
+    b = ctypes.c_size_t(0)
+    assert lib.ct_qr_workspace(100, 200, 0, 1, ctypes.byref(b)) == -2      # n > m
+    assert b"n" in lib.ct_last_error()
+    assert lib.ct_qr_workspace(100, 50, 9, 1, ctypes.byref(b)) == -3       # bad precision
+    assert lib.ct_qr_workspace(1920, 1024, 0, 4, ctypes.byref(b)) == 0 and b.value > 1920 * 8
+    lib.ct_factor_destroy.argtypes = [ctypes.c_void_p]
+    assert lib.ct_factor_destroy(None) == 0
+
+
+def test_binding_marshals_without_gpu():
+    from paper_2412_07631_amd import ctqr
+    assert ctqr.ld16(1920) == 1920 and ctqr.ld16(1401) == 1408
+    assert ctqr.qr_workspace(76800, 65536, ctqr.PREC_BF16X3, 512) > 65536 * 256 * 8
+    try:
+        ctqr.qr_workspace(10, 20, ctqr.PREC_F64, 1)
+    except ctqr.CtError as e:
+        assert e.code == -2
+    else:
+        raise AssertionError("expected an argument error")

@@ -97,11 +97,10 @@ def test_row_sums_equal_chord_lengths():
     for i in range(sc.m):
         L = chord_length_edges(*R[i], sc.grid_width)
         assert abs(A[i].sum() - L) <= 1e-13, (i, A[i].sum(), L)
-    # the fan covers the circle circumscribing the grid: every pixel is crossed
-    # by some ray of every view, and the central bins always cross the grid
-    for k in range(sc.n_angles):
-        assert np.all(A[k * sc.n_det:(k + 1) * sc.n_det].sum(axis=0) > 0), k
-        assert A[k * sc.n_det + sc.n_det // 2].sum() > 0
+    # the fan covers the circle inscribed in the grid: every ray crosses the
+    # grid, and every pixel is crossed by some ray
+    assert np.all(A.sum(axis=1) > 0)
+    assert np.all(A.sum(axis=0) > 0)
 
 
 def test_random_rays_row_sums():
