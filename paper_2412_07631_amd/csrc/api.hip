@@ -33,6 +33,15 @@ hipError_t launch_tw(const TWp* Wp, int nz, int nbv, int N, const double* T, int
                      int64_t ldo, hipStream_t s);
 hipError_t launch_t_from_gram(const double* G, int64_t ldg, const double* tau, int nb, double* T, int64_t ldt,
                               hipStream_t s);
+hipError_t t_from_gram_set_max_lds(size_t bytes);
+template <typename TWp, typename TS>
+hipError_t launch_sum_slices(const TWp* Wp, int64_t wstride, int nz, int64_t count, TS* S, hipStream_t s);
+template <typename T>
+hipError_t launch_prep_v(const T* V, int64_t ldv, int64_t mk, int nb, T* Vm, int64_t ldm, T* Vt, int64_t ldvt,
+                         hipStream_t s);
+template <typename T>
+hipError_t launch_nt(const T* X, int64_t ldx, const T* Y, int64_t ldy, T* out, int64_t ldo, int64_t P, int Q,
+                     int64_t K, bool sub, int64_t ocap, int* nz_out, hipStream_t s);
 template <typename TS, bool UPPER>
 hipError_t launch_trsm_diag(const TS* R, int64_t ldr, int bo, TS* B, int64_t ldb, int nrhs, hipStream_t s);
 hipError_t trsm_set_max_lds(size_t bytes);
@@ -51,6 +60,13 @@ hipError_t launch_residual_t(const int64_t* col_ptr, const int32_t* row, const d
                              const double* R, int64_t ldr, double* S, int64_t lds, int nrhs, hipStream_t s);
 hipError_t launch_csc(const int64_t* row_ptr, const int32_t* col, const double* val, int64_t m, int64_t n,
                       int64_t* col_ptr, int32_t* row, double* cval, int32_t* work, hipStream_t s);
+hipError_t launch_spmv_rows_t(const int64_t* ptr, const int32_t* idx, const double* val, int64_t rows,
+                              const double* Xt, const double* Bt, double* Rt, int64_t ld, int nrhs, hipStream_t s);
+hipError_t launch_spmv_cols_t(const int64_t* ptr, const int32_t* idx, const double* val, int64_t cols,
+                              const double* Rt, double* St, int64_t ld, int nrhs, hipStream_t s);
+hipError_t launch_colnorm_t(const double* Zt, int64_t ld, int64_t rows, int nrhs, double* out, hipStream_t s);
+template <typename TI, typename TO, bool TO_T, bool ACC>
+hipError_t launch_transpose(const TI* in, TO* out, int64_t rows, int cols, int64_t ldc, int64_t ldt, hipStream_t s);
 }  // namespace ctqr
 
 using namespace ctqr;
@@ -100,7 +116,8 @@ static int device_setup()
     size_t want = 160 * 1024;
     if (p.maxSharedMemoryPerMultiProcessor > 0 && (size_t)p.maxSharedMemoryPerMultiProcessor < want)
         want = p.maxSharedMemoryPerMultiProcessor;
-    if (panel_set_max_lds(want) != hipSuccess || trsm_set_max_lds(want) != hipSuccess) {
+    if (panel_set_max_lds(want) != hipSuccess || trsm_set_max_lds(want) != hipSuccess ||
+        t_from_gram_set_max_lds(want) != hipSuccess) {
         (void)hipGetLastError();
         want = 64 * 1024;
     }
@@ -132,6 +149,10 @@ struct ct_factor {
     void* Wq;
     int64_t wq_elems;
     double* G;
+    void* Vm;          // masked copy of the current reflector block, column-major (ld ldvm)
+    void* Vt;          // the same block transposed (row-major, ld ldvt)
+    int64_t ldvm;
+    void* Ws;          // split-K sums
     uint64_t barrier_base;
     int rw;            // panel rows per workgroup
     int64_t max_nrhs;
@@ -140,7 +161,7 @@ struct ct_factor {
 static int nb_out_for(int prec) { return (prec == CT_PREC_F64 || prec == CT_PREC_F32) ? 128 : 256; }
 
 struct Layout {
-    size_t T_all, Tin, part, gpart, words, Wp, Wq, G, total;
+    size_t T_all, Tin, part, gpart, words, Wp, Wq, G, Vm, Vt, Ws, total;
     int64_t wp_elems, wq_elems;
 };
 
@@ -148,7 +169,6 @@ static size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static Layout layout(int64_t m, int64_t n, int prec, int64_t max_nrhs)
 {
-    (void)m;
     Layout L;
     const int nbo = nb_out_for(prec);
     const int64_t nblocks = (n + nbo - 1) / nbo;
@@ -164,6 +184,10 @@ static Layout layout(int64_t m, int64_t n, int prec, int64_t max_nrhs)
     L.Wp = off; off += up256((size_t)L.wp_elems * 8);
     L.Wq = off; off += up256((size_t)L.wq_elems * 8);
     L.G = off; off += up256((size_t)nbo * nbo * 8);
+    const int64_t ldm = (m + 15) / 16 * 16;
+    L.Vm = off; off += up256((size_t)ldm * nbo * 8);
+    L.Vt = off; off += up256((size_t)ldm * nbo * 8);
+    L.Ws = off; off += up256((size_t)L.wq_elems * 8);
     L.total = off;
     return L;
 }
@@ -216,6 +240,44 @@ struct ProfScope {
 
 // --------------------------------------------------------------- larfb core
 // C (mk x nc) <- (I - V op(T) V^T) C ; OPT 0: T^T (apply Q^T), 1: T (apply Q)
+static int64_t ldvt_of(int nbv) { return (nbv + 15) / 16 * 16; }
+
+// Masked copies of the reflector block into f->Vm / f->Vt
+template <typename TS>
+static int prep_block(ct_factor* f, const TS* V, int64_t ldv, int64_t mk, int nbv, hipStream_t s)
+{
+    CT_HIP(launch_prep_v<TS>(V, ldv, mk, nbv, (TS*)f->Vm, f->ldvm, (TS*)f->Vt, ldvt_of(nbv), s));
+    return 0;
+}
+
+// Block-reflector update with the LDS-tiled NT kernel (FP32 / FP64 arithmetic
+// equal to the storage type); the block must already be in f->Vm / f->Vt.
+template <typename TS, int OPT>
+static int larfb_nt(ct_factor* f, int64_t mk, int nbv, const double* T, int64_t ldt, TS* C, int64_t ldc, int nc,
+                    hipStream_t s, bool timed)
+{
+    const double fl = 2.0 * (double)mk * nbv * nc;
+    const int64_t ldw = ldvt_of(nbv);
+    int nz = 1;
+    {
+        ProfScope ps(timed ? 0 : -1, fl, ((double)mk * nbv + (double)mk * nc) * sizeof(TS) + (double)nbv * nc * sizeof(TS), s);
+        CT_HIP(launch_nt<TS>((const TS*)f->Vm, f->ldvm, C, ldc, (TS*)f->Wp, nbv, nbv, nc, mk, false,
+                             f->wp_elems * 8 / (int64_t)sizeof(TS), &nz, s));
+    }
+    const TS* Wsum = (const TS*)f->Wp;
+    if (nz > 1) {
+        CT_HIP((launch_sum_slices<TS, TS>((const TS*)f->Wp, (int64_t)nbv * nc, nz, (int64_t)nbv * nc, (TS*)f->Ws, s)));
+        Wsum = (const TS*)f->Ws;
+    }
+    CT_HIP((launch_tw<TS, TS, OPT, false>(Wsum, 1, nbv, nc, T, ldt, (TS*)f->Wq, nullptr, ldw, s)));
+    {
+        ProfScope ps(timed ? 1 : -1, fl, (double)mk * nbv * sizeof(TS) + (double)nbv * nc * sizeof(TS) + 2.0 * mk * nc * sizeof(TS), s);
+        int nz2;
+        CT_HIP(launch_nt<TS>((const TS*)f->Vt, ldw, (const TS*)f->Wq, ldw, C, ldc, mk, nc, nbv, true, 0, &nz2, s));
+    }
+    return 0;
+}
+
 template <int MODE, typename TS, int OPT>
 static int larfb(ct_factor* f, const TS* V, int64_t ldv, int64_t mk, int nbv, const double* T, int64_t ldt, TS* C,
                  int64_t ldc, int nc, hipStream_t s, bool timed = false)
@@ -236,10 +298,18 @@ static int larfb(ct_factor* f, const TS* V, int64_t ldv, int64_t mk, int nbv, co
     return 0;
 }
 
+// prepared: the block is already in f->Vm / f->Vt
 template <typename TS, int OPT>
 static int larfb_mode(ct_factor* f, int mode, const TS* V, int64_t ldv, int64_t mk, int nbv, const double* T,
-                      int64_t ldt, TS* C, int64_t ldc, int nc, hipStream_t s, bool timed = false)
+                      int64_t ldt, TS* C, int64_t ldc, int nc, hipStream_t s, bool timed = false, bool prepared = false)
 {
+    if (mode == M_F64 || mode == M_F32) {
+        if (!prepared) {
+            int r = prep_block<TS>(f, V, ldv, mk, nbv, s);
+            if (r) return r;
+        }
+        return larfb_nt<TS, OPT>(f, mk, nbv, T, ldt, C, ldc, nc, s, timed);
+    }
     if constexpr (sizeof(TS) == 8) {
         return larfb<M_F64, TS, OPT>(f, V, ldv, mk, nbv, T, ldt, C, ldc, nc, s, timed);
     } else {
@@ -265,14 +335,15 @@ static int trailing_mode(int prec)
 }
 
 // Gram of the masked reflector block and its compact-WY factor
+// Gram of the prepared (masked) block in f->Vm, in the storage precision, and
+// the compact-WY factor from it.
 template <typename TS>
-static int block_t(ct_factor* f, const TS* V, int64_t ldv, int64_t mk, int bo, const double* tau, double* T,
-                   int64_t ldt, hipStream_t s)
+static int block_t(ct_factor* f, int64_t mk, int bo, const double* tau, double* T, int64_t ldt, hipStream_t s)
 {
     int nz = 1;
-    CT_HIP((launch_tn<M_F64, TS, TS, double, true, true>(V, ldv, V, ldv, (double*)f->Wp, bo, bo, mk, f->wp_elems,
-                                                         &nz, s)));
-    CT_HIP((launch_tw<double, double, 2, false>((const double*)f->Wp, nz, bo, bo, nullptr, 0, f->G, nullptr, bo, s)));
+    CT_HIP(launch_nt<TS>((const TS*)f->Vm, f->ldvm, (const TS*)f->Vm, f->ldvm, (TS*)f->Wp, bo, bo, bo, mk, false,
+                         f->wp_elems * 8 / (int64_t)sizeof(TS), &nz, s));
+    CT_HIP((launch_sum_slices<TS, double>((const TS*)f->Wp, (int64_t)bo * bo, nz, (int64_t)bo * bo, f->G, s)));
     CT_HIP(launch_t_from_gram(f->G, bo, tau, bo, T, ldt, s));
     return 0;
 }
@@ -306,14 +377,18 @@ static int factor_impl(ct_factor* f, hipStream_t s)
                 if (r) return r;
             }
         }
-        if (bo > nbi) {
-            int r = block_t<TS>(f, A + k0 + k0 * lda, lda, mk, bo, f->tau + k0, Tb, nbo, s);
+        const int64_t nc = n - k0 - bo;
+        if (bo > nbi || nc > 0) {
+            int r = prep_block<TS>(f, A + k0 + k0 * lda, lda, mk, bo, s);
             if (r) return r;
         }
-        const int64_t nc = n - k0 - bo;
+        if (bo > nbi) {
+            int r = block_t<TS>(f, mk, bo, f->tau + k0, Tb, nbo, s);
+            if (r) return r;
+        }
         if (nc > 0) {
             int r = larfb_mode<TS, 0>(f, mode, A + k0 + k0 * lda, lda, mk, bo, Tb, nbo, A + k0 + (k0 + bo) * lda, lda,
-                                      (int)nc, s, true);
+                                      (int)nc, s, true, true);
             if (r) return r;
         }
     }
@@ -372,22 +447,22 @@ static int trsm_lt_impl(const ct_factor* fc, TS* Y, int64_t k, int64_t ldy, hipS
     ct_factor* f = const_cast<ct_factor*>(fc);
     const TS* A = (const TS*)f->A;
     const int64_t n = f->n, lda = f->lda;
-    typedef typename std::conditional<sizeof(TS) == 8, double, float>::type TE;
     const int tb = g_dev.trsm_block;
     const int64_t nb = (n + tb - 1) / tb;
     for (int64_t b = 0; b < nb; ++b) {
         const int64_t k0 = b * tb;
         const int bo = (int)std::min<int64_t>(tb, n - k0);
         if (k0 > 0) {
-            // Y[k0:k0+bo] -= R[0:k0, k0:k0+bo]^T Y[0:k0]
+            // Y[k0:k0+bo] -= R[0:k0, k0:k0+bo]^T Y[0:k0]  (columns of R are K-contiguous)
             int nz = 1;
-            if constexpr (sizeof(TS) == 8)
-                CT_HIP((launch_tn<M_F64, TS, TS, TE, false, false>(A + k0 * lda, lda, Y, ldy, (TE*)f->Wp, bo, (int)k, k0,
-                                                                   f->wp_elems * 8 / (int64_t)sizeof(TE), &nz, s)));
-            else
-                CT_HIP((launch_tn<M_F32, TS, TS, TE, false, false>(A + k0 * lda, lda, Y, ldy, (TE*)f->Wp, bo, (int)k, k0,
-                                                                   f->wp_elems * 8 / (int64_t)sizeof(TE), &nz, s)));
-            CT_HIP((launch_tw<TE, TS, 3, false>((const TE*)f->Wp, nz, bo, (int)k, nullptr, 0, Y + k0, nullptr, ldy, s)));
+            CT_HIP(launch_nt<TS>(A + k0 * lda, lda, Y, ldy, (TS*)f->Wp, bo, bo, (int)k, k0, false,
+                                 f->wp_elems * 8 / (int64_t)sizeof(TS), &nz, s));
+            const TS* Wsum = (const TS*)f->Wp;
+            if (nz > 1) {
+                CT_HIP((launch_sum_slices<TS, TS>((const TS*)f->Wp, (int64_t)bo * k, nz, (int64_t)bo * k, (TS*)f->Ws, s)));
+                Wsum = (const TS*)f->Ws;
+            }
+            CT_HIP((launch_tw<TS, TS, 3, false>(Wsum, 1, bo, (int)k, nullptr, 0, Y + k0, nullptr, ldy, s)));
         }
         CT_HIP((launch_trsm_diag<TS, false>(A + k0 + k0 * lda, lda, bo, Y + k0, ldy, (int)k, s)));
     }
@@ -411,42 +486,50 @@ static int refined_impl(const ct_factor* f, const ct_sparse* sp, const double* B
                         double* gnorms, hipStream_t s)
 {
     const int64_t m = f->m, n = f->n;
-    const int64_t ld = (m + 15) / 16 * 16, ldn = (n + 15) / 16 * 16;
-    double* R = (double*)scratch;
-    double* S = (double*)(scratch + up256((size_t)ld * nrhs * 8));
-    TS* C = (TS*)(scratch + up256((size_t)ld * nrhs * 8) + up256((size_t)ldn * nrhs * 8));
+    const int64_t ld = (m + 15) / 16 * 16;             // column-major correction block
+    const int64_t lt = (nrhs + 15) / 16 * 16;           // slice-contiguous blocks
+    char* p = scratch;
+    double* Bt = (double*)p; p += up256((size_t)m * lt * 8);
+    double* Rt = (double*)p; p += up256((size_t)m * lt * 8);
+    double* Xt = (double*)p; p += up256((size_t)n * lt * 8);
+    double* St = (double*)p; p += up256((size_t)n * lt * 8);
+    TS* C = (TS*)p;
     const bool have_csc = sp->col_ptr && sp->row && sp->cval;
+    const int nr = (int)nrhs;
+    CT_HIP((launch_transpose<double, double, true, false>(B, Bt, m, nr, ldb, lt, s)));
     // x_0 = R~^{-1} Q~^T b
-    CT_HIP((launch_convert<double, TS>(B, ldb, C, ld, m, (int)nrhs, s)));
+    CT_HIP((launch_convert<double, TS>(B, ldb, C, ld, m, nr, s)));
     int r = ct_apply_qt(f, C, nrhs, ld, s);
     if (r) return r;
     r = ct_trsm_solve(f, C, nrhs, ld, s);
     if (r) return r;
-    CT_HIP((launch_convert<TS, double>(C, ld, X, ldx, n, (int)nrhs, s)));
+    CT_HIP((launch_convert<TS, double>(C, ld, X, ldx, n, nr, s)));
+    CT_HIP((launch_transpose<TS, double, true, false>(C, Xt, n, nr, ld, lt, s)));
     for (int st = 0; st <= steps; ++st) {
         // r_st = b - A x_st (FP64)
-        CT_HIP(launch_residual(sp->row_ptr, sp->col, sp->val, m, X, ldx, B, ldb, R, ld, (int)nrhs, s));
-        if (rnorms) CT_HIP(launch_colnorm(R, ld, m, (int)nrhs, rnorms + (size_t)st * nrhs, s));
+        CT_HIP(launch_spmv_rows_t(sp->row_ptr, sp->col, sp->val, m, Xt, Bt, Rt, lt, nr, s));
+        if (rnorms) CT_HIP(launch_colnorm_t(Rt, lt, m, nr, rnorms + (size_t)st * nrhs, s));
         const bool need_grad = method == CT_REFINE_SNE ? st < steps : false;
         if (have_csc && (need_grad || gnorms)) {
-            CT_HIP(launch_residual_t(sp->col_ptr, sp->row, sp->cval, n, R, ld, S, ldn, (int)nrhs, s));
-            if (gnorms) CT_HIP(launch_colnorm(S, ldn, n, (int)nrhs, gnorms + (size_t)st * nrhs, s));
+            CT_HIP(launch_spmv_cols_t(sp->col_ptr, sp->row, sp->cval, n, Rt, St, lt, nr, s));
+            if (gnorms) CT_HIP(launch_colnorm_t(St, lt, n, nr, gnorms + (size_t)st * nrhs, s));
         }
         if (st == steps) break;
         if (method == CT_REFINE_SNE) {
             // x += R~^{-1} R~^{-T} (A^T r)
-            CT_HIP((launch_convert<double, TS>(S, ldn, C, ld, n, (int)nrhs, s)));
+            CT_HIP((launch_transpose<double, TS, false, false>(St, C, n, nr, ld, lt, s)));
             r = trsm_lt_impl<TS>(f, C, nrhs, ld, s);
             if (r) return r;
         } else {
             // x += R~^{-1} Q~^T r
-            CT_HIP((launch_convert<double, TS>(R, ld, C, ld, m, (int)nrhs, s)));
+            CT_HIP((launch_transpose<double, TS, false, false>(Rt, C, m, nr, ld, lt, s)));
             r = ct_apply_qt(f, C, nrhs, ld, s);
             if (r) return r;
         }
         r = ct_trsm_solve(f, C, nrhs, ld, s);
         if (r) return r;
-        CT_HIP((launch_accumulate<TS>(X, ldx, C, ld, n, (int)nrhs, s)));
+        CT_HIP((launch_accumulate<TS>(X, ldx, C, ld, n, nr, s)));
+        CT_HIP((launch_transpose<TS, double, true, true>(C, Xt, n, nr, ld, lt, s)));
     }
     return 0;
 }
@@ -528,6 +611,10 @@ int ct_qr_factor(void* A, int64_t m, int64_t n, int64_t lda, int prec, double* t
     f->Wp = w + L.Wp; f->wp_elems = L.wp_elems;
     f->Wq = w + L.Wq; f->wq_elems = L.wq_elems;
     f->G = (double*)(w + L.G);
+    f->Vm = w + L.Vm;
+    f->Vt = w + L.Vt;
+    f->ldvm = (m + 15) / 16 * 16;
+    f->Ws = w + L.Ws;
     f->barrier_base = 0;
     f->max_nrhs = max_nrhs;
 
@@ -626,8 +713,8 @@ int ct_refine_workspace(int64_t m, int64_t n, int64_t nrhs, size_t* bytes)
     CT_ARG(n > 0, 2, "n");
     CT_ARG(nrhs >= 0, 3, "nrhs");
     CT_ARG(bytes != nullptr, 4, "bytes");
-    const int64_t ld = (m + 15) / 16 * 16, ldn = (n + 15) / 16 * 16;
-    *bytes = 2 * up256((size_t)ld * nrhs * 8) + up256((size_t)ldn * nrhs * 8);
+    const int64_t ld = (m + 15) / 16 * 16, lt = (nrhs + 15) / 16 * 16;
+    *bytes = 2 * up256((size_t)m * lt * 8) + 2 * up256((size_t)n * lt * 8) + up256((size_t)ld * nrhs * 8);
     return 0;
 }
 

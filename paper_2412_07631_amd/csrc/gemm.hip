@@ -338,17 +338,23 @@ __global__ void __launch_bounds__(256) tw_kernel(const TWp* __restrict__ Wp, int
 // ---------------------------------------------------------------------------
 // Compact-WY factor of a reflector block from its Gram matrix G = V^T V:
 //   T_qq = tau_q,  T[p][q] = -tau_q sum_{l=p}^{q-1} T[p][l] G[l][q]  (p < q).
-// One workgroup; T lives in global memory (L2-resident), G column in LDS.
+// One workgroup.  For nb <= 128 T is built in LDS (FP64) and written once;
+// larger blocks build it in place in global memory (L2-resident).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(512) t_from_gram_kernel(const double* __restrict__ G, int64_t ldg,
                                                          const double* __restrict__ tau, int nb, double* T,
-                                                         int64_t ldt)
+                                                         int64_t ldt, int in_lds)
 {
-    extern __shared__ double gq[];
+    extern __shared__ double sh[];
     const int t = threadIdx.x;
+    double* gq = sh;                              // nb
+    double* Ts = sh + nb;                         // nb x (nb + 1) when in LDS
+    const int lds_ld = nb + 1;
+    double* Tw = in_lds ? Ts : T;
+    const int64_t ld = in_lds ? lds_ld : ldt;
     for (int e = t; e < nb * nb; e += 512) {
         const int q = e / nb, p = e - q * nb;
-        T[p + (int64_t)q * ldt] = 0.0;
+        Tw[p + (int64_t)q * ld] = 0.0;
     }
     __syncthreads();
     for (int q = 0; q < nb; ++q) {
@@ -356,13 +362,35 @@ __global__ void __launch_bounds__(512) t_from_gram_kernel(const double* __restri
         __syncthreads();
         const double tq = tau[q];
         for (int p = t; p < q; p += 512) {
-            double s = 0.0;
-            for (int l = p; l < q; ++l) s += T[p + (int64_t)l * ldt] * gq[l];
-            T[p + (int64_t)q * ldt] = -tq * s;
+            double s0 = 0.0, s1 = 0.0;
+            int l = p;
+            for (; l + 1 < q; l += 2) {
+                s0 += Tw[p + (int64_t)l * ld] * gq[l];
+                s1 += Tw[p + (int64_t)(l + 1) * ld] * gq[l + 1];
+            }
+            if (l < q) s0 += Tw[p + (int64_t)l * ld] * gq[l];
+            Tw[p + (int64_t)q * ld] = -tq * (s0 + s1);
         }
-        if (t == 0) T[q + (int64_t)q * ldt] = tq;
+        if (t == 0) Tw[q + (int64_t)q * ld] = tq;
         __threadfence_block();
         __syncthreads();
+    }
+    if (in_lds)
+        for (int e = t; e < nb * nb; e += 512) {
+            const int q = e / nb, p = e - q * nb;
+            T[p + (int64_t)q * ldt] = Ts[p + q * lds_ld];
+        }
+}
+
+// S[e] = sum_z W[z][e] over `count` contiguous elements (fixed order in z).
+template <typename TWp, typename TS>
+__global__ void __launch_bounds__(256) sum_slices_kernel(const TWp* __restrict__ Wp, int64_t wstride, int nz,
+                                                         int64_t count, TS* __restrict__ S)
+{
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256) {
+        double s = 0.0;
+        for (int z = 0; z < nz; ++z) s += (double)Wp[(int64_t)z * wstride + e];
+        S[e] = (TS)s;
     }
 }
 
@@ -445,10 +473,29 @@ hipError_t launch_tw(const TWp* Wp, int nz, int nbv, int N, const double* T, int
 hipError_t launch_t_from_gram(const double* G, int64_t ldg, const double* tau, int nb, double* T, int64_t ldt,
                               hipStream_t s)
 {
-    hipLaunchKernelGGL(t_from_gram_kernel, dim3(1), dim3(512), (size_t)nb * sizeof(double), s, G, ldg, tau, nb, T,
-                       ldt);
+    const int in_lds = nb <= 128 ? 1 : 0;
+    const size_t sh = ((size_t)nb + (in_lds ? (size_t)nb * (nb + 1) : 0)) * sizeof(double);
+    hipLaunchKernelGGL(t_from_gram_kernel, dim3(1), dim3(512), sh, s, G, ldg, tau, nb, T, ldt, in_lds);
     return hipGetLastError();
 }
+
+hipError_t t_from_gram_set_max_lds(size_t bytes)
+{
+    return hipFuncSetAttribute((const void*)t_from_gram_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename TWp, typename TS>
+hipError_t launch_sum_slices(const TWp* Wp, int64_t wstride, int nz, int64_t count, TS* S, hipStream_t s)
+{
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL((sum_slices_kernel<TWp, TS>), dim3((unsigned)blocks), dim3(256), 0, s, Wp, wstride, nz, count,
+                       S);
+    return hipGetLastError();
+}
+template hipError_t launch_sum_slices<float, float>(const float*, int64_t, int, int64_t, float*, hipStream_t);
+template hipError_t launch_sum_slices<double, double>(const double*, int64_t, int, int64_t, double*, hipStream_t);
+template hipError_t launch_sum_slices<float, double>(const float*, int64_t, int, int64_t, double*, hipStream_t);
 
 // ---------------------------------------------------------- instantiations
 #define CT_TN(MODE, TA, TB, TW, MA, MB)                                                                       \

@@ -1,0 +1,295 @@
+// LDS-tiled MFMA kernel for the block-reflector update of the trailing matrix
+// (the hot loop of the blocked Householder QR, Eq. (qr)) and of the Q^T B of
+// Eq. (solve).  Both products of C <- C - V (op(T) (V^T C)) are written as
+//     out[p][q] (+)= sum_k X[p][k] Y[q][k]            ("NT" form)
+// with BOTH operands K-contiguous:
+//   W  = V^T C :  X = Vm (masked reflector block, column-major: row i of X is
+//                 column i of Vm), Y = C (column-major: row j of Y is column j)
+//   C -= V W'  :  X = Vt (the same block transposed, row-major mk x nb),
+//                 Y = W' (column-major nb x nc)
+// so every global load is a 16-byte vector along K, tiles go to LDS without
+// transposition, and the MFMA fragments are single ds_read_b128 (FP32) or two
+// ds_read_b128 (FP64) per lane.
+//
+// Workgroup tile BP x BQ = 128 x 128, K step BK, 4 wavefronts in 2 x 2, each
+// 64 x 64 (4 x 4 blocks of 16x16 MFMA).  Global->register prefetch of the next
+// K step overlaps the MFMAs of the current one (two LDS buffers).  The tile
+// order is remapped so the 8 XCDs of MI355X each walk a contiguous range of
+// tiles and share their L2.
+#include "ct_internal.h"
+
+namespace ctqr {
+
+template <typename T> struct LdsTraits;
+template <> struct LdsTraits<double> { static constexpr int BK = 16, PAD = 2, KS = 4; typedef d4_t Acc; };
+template <> struct LdsTraits<float> { static constexpr int BK = 32, PAD = 4, KS = 4; typedef f4_t Acc; };
+
+constexpr int kBP = 128, kBQ = 128;
+
+struct NtArgs {
+    const void* X;   // BP rows of K-contiguous data, leading dimension ldx
+    int64_t ldx;
+    const void* Y;
+    int64_t ldy;
+    void* out;       // column-major P x Q (ld ldo) per split slice
+    int64_t ldo, ostride;
+    int64_t P;
+    int Q;
+    int64_t K, kslice;
+    int tiles_p, tiles_q;
+    int sub;         // 0: out = acc (split slice z at out + z*ostride), 1: out -= acc
+};
+
+template <typename T>
+__device__ __forceinline__ void mfma_nt(typename LdsTraits<T>::Acc& acc, const T (&a)[4], const T (&b)[4])
+{
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], acc, 0, 0, 0);
+    } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], acc, 0, 0, 0);
+    }
+}
+
+// one 16-byte vector of T
+template <typename T> struct V16;
+template <> struct V16<float> { typedef f4_t t; static constexpr int N = 4; };
+template <> struct V16<double> { typedef double t __attribute__((ext_vector_type(2))); static constexpr int N = 2; };
+
+template <typename T>
+__global__ void __launch_bounds__(256, 2) gemm_nt_kernel(NtArgs a)
+{
+    typedef LdsTraits<T> L;
+    constexpr int BK = L::BK, LDK = BK + L::PAD;
+    constexpr int VN = V16<T>::N;                  // elements per 16-byte vector
+    constexpr int VPR = BK / VN;                   // vectors per tile row
+    constexpr int ROWS_PER_PASS = 256 / VPR;       // tile rows loaded per pass of 256 threads
+    constexpr int PASSES = kBP / ROWS_PER_PASS;
+    typedef typename V16<T>::t vec_t;
+    typedef typename L::Acc Acc;
+
+    __shared__ T Xs[2][kBP * LDK];
+    __shared__ T Ys[2][kBQ * LDK];
+
+    // XCD-aware tile order: hardware places block b on XCD b % 8
+    const int nt = a.tiles_p * a.tiles_q;
+    const int b = blockIdx.x;
+    const int per = (nt + 7) / 8;
+    int tile = (b % 8) * per + b / 8;
+    if (nt % 8 != 0) tile = b;                      // uneven split: keep the plain order
+    if (tile >= nt) return;
+    const int tp = tile % a.tiles_p, tq = tile / a.tiles_p;
+    const int64_t p0 = (int64_t)tp * kBP;
+    const int q0 = tq * kBQ;
+    const int64_t kbeg = (int64_t)blockIdx.y * a.kslice;
+    int64_t kend = kbeg + a.kslice;
+    if (kend > a.K) kend = a.K;
+
+    const T* __restrict__ X = (const T*)a.X;
+    const T* __restrict__ Y = (const T*)a.Y;
+    const int t = threadIdx.x;
+    const int lr = t / VPR, lv = t % VPR;          // loader: row within pass, vector within row
+
+    vec_t xr[PASSES], yr[PASSES];
+    auto gload = [&](int64_t k0) {
+#pragma unroll
+        for (int ps = 0; ps < PASSES; ++ps) {
+            const int row = ps * ROWS_PER_PASS + lr;
+            const int64_t kk = k0 + lv * VN;
+            const int64_t pr = p0 + row;
+            const int qr = q0 + row;
+            vec_t vx = {}, vy = {};
+            if (kk + VN <= kend) {
+                if (pr < a.P) vx = *(const vec_t*)(X + pr * a.ldx + kk);
+                if (qr < a.Q) vy = *(const vec_t*)(Y + (int64_t)qr * a.ldy + kk);
+            } else {
+#pragma unroll
+                for (int e = 0; e < VN; ++e) {
+                    if (kk + e < kend) {
+                        if (pr < a.P) vx[e] = X[pr * a.ldx + kk + e];
+                        if (qr < a.Q) vy[e] = Y[(int64_t)qr * a.ldy + kk + e];
+                    }
+                }
+            }
+            xr[ps] = vx;
+            yr[ps] = vy;
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int ps = 0; ps < PASSES; ++ps) {
+            const int row = ps * ROWS_PER_PASS + lr;
+            *(vec_t*)&Xs[buf][row * LDK + lv * VN] = xr[ps];
+            *(vec_t*)&Ys[buf][row * LDK + lv * VN] = yr[ps];
+        }
+    };
+
+    const int lane = t & 63, wv = t >> 6;
+    const int c = lane & 15, g = lane >> 4;
+    const int wp = (wv >> 1) * 64, wq = (wv & 1) * 64;
+
+    Acc acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = Acc{0, 0, 0, 0};
+
+    // prefetch of the output tile for the subtracting epilogue (FP32 only: the
+    // FP64 accumulators leave no registers for it at two workgroups per CU)
+    constexpr bool F64 = sizeof(T) == 8;
+    constexpr bool PRE = !F64;
+    T cpre[4][4][PRE ? 4 : 1];
+    if (PRE && a.sub) {
+        T* O = (T*)a.out;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int q = q0 + wq + 16 * j + c;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t p = p0 + wp + 16 * i + (F64 ? g + 4 * r : 4 * g + r);
+                    if constexpr (PRE) cpre[i][j][r] = (p < a.P && q < a.Q) ? O[p + (int64_t)q * a.ldo] : (T)0;
+                }
+            }
+    }
+
+    if (kbeg < kend) {
+        gload(kbeg);
+        sstore(0);
+        __syncthreads();
+        int buf = 0;
+        for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+            const bool more = k0 + BK < kend;
+            if (more) gload(k0 + BK);
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 16) {
+                T af[4][4], bf[4][4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const T* src = &Xs[buf][(wp + 16 * i + c) * LDK + kk + 4 * g];
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) af[i][s] = src[s];
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const T* src = &Ys[buf][(wq + 16 * j + c) * LDK + kk + 4 * g];
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) bf[j][s] = src[s];
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) mfma_nt<T>(acc[i][j], af[i], bf[j]);
+            }
+            if (more) {
+                sstore(buf ^ 1);
+                __syncthreads();
+                buf ^= 1;
+            }
+        }
+    }
+
+    T* O = (T*)a.out;
+    if (!a.sub) O += (int64_t)blockIdx.y * a.ostride;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int q = q0 + wq + 16 * j + c;
+            if (q >= a.Q) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t p = p0 + wp + 16 * i + (F64 ? g + 4 * r : 4 * g + r);
+                if (p < a.P) {
+                    T* d = O + p + (int64_t)q * a.ldo;
+                    if constexpr (PRE) *d = a.sub ? cpre[i][j][r] - (T)acc[i][j][r] : (T)acc[i][j][r];
+                    else *d = a.sub ? *d - (T)acc[i][j][r] : (T)acc[i][j][r];
+                }
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Masked copies of a reflector block V (mk x nb, column-major, ld ldv):
+//   Vm (column-major, ld ldm): Vm[k][i] = V[k][i] for k > i, 1 for k == i, 0 above
+//   Vt (row-major mk x nb, ld ldvt >= nb): Vt[k][i] = Vm[k][i], zero for i >= nb
+// Tiles of 64 rows x 64 columns through LDS so both writes are coalesced.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) prep_v_kernel(const T* __restrict__ V, int64_t ldv, int64_t mk, int nb,
+                                                     T* __restrict__ Vm, int64_t ldm, T* __restrict__ Vt, int64_t ldvt)
+{
+    __shared__ T tile[64][65];
+    const int64_t k0 = (int64_t)blockIdx.x * 64;
+    const int i0 = blockIdx.y * 64;
+    const int t = threadIdx.x;
+    for (int e = t; e < 64 * 64; e += 256) {
+        const int ii = e / 64, kk = e % 64;            // kk fastest: coalesced along the column
+        const int64_t k = k0 + kk;
+        const int i = i0 + ii;
+        T v = (T)0;
+        if (k < mk && i < nb) {
+            v = k > i ? V[k + (int64_t)i * ldv] : (k == i ? (T)1 : (T)0);
+            Vm[k + (int64_t)i * ldm] = v;
+        }
+        tile[ii][kk] = v;
+    }
+    __syncthreads();
+    for (int e = t; e < 64 * 64; e += 256) {
+        const int kk = e / 64, ii = e % 64;            // ii fastest: coalesced along the row of Vt
+        const int64_t k = k0 + kk;
+        const int i = i0 + ii;
+        if (k < mk && i < ldvt) Vt[k * ldvt + i] = i < nb ? tile[ii][kk] : (T)0;
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+template <typename T>
+hipError_t launch_prep_v(const T* V, int64_t ldv, int64_t mk, int nb, T* Vm, int64_t ldm, T* Vt, int64_t ldvt,
+                         hipStream_t s)
+{
+    dim3 grid((unsigned)((mk + 63) / 64), (unsigned)((ldvt + 63) / 64));
+    hipLaunchKernelGGL(prep_v_kernel<T>, grid, dim3(256), 0, s, V, ldv, mk, nb, Vm, ldm, Vt, ldvt);
+    return hipGetLastError();
+}
+
+// out (P x Q) = X Y^T summed over K, split into slices; returns the slice count.
+template <typename T>
+hipError_t launch_nt(const T* X, int64_t ldx, const T* Y, int64_t ldy, T* out, int64_t ldo, int64_t P, int Q,
+                     int64_t K, bool sub, int64_t ocap, int* nz_out, hipStream_t s)
+{
+    constexpr int BK = LdsTraits<T>::BK;
+    NtArgs a;
+    a.X = X; a.ldx = ldx; a.Y = Y; a.ldy = ldy; a.out = out; a.ldo = ldo;
+    a.P = P; a.Q = Q; a.K = K; a.sub = sub ? 1 : 0;
+    a.tiles_p = (int)((P + kBP - 1) / kBP);
+    a.tiles_q = (Q + kBQ - 1) / kBQ;
+    a.ostride = ldo * (int64_t)Q;
+    const int tiles = a.tiles_p * a.tiles_q;
+    int nz = 1;
+    if (!sub) {
+        while (tiles * nz * 2 <= 1024 && K / (nz * 2) >= 8 * BK && nz < 256) nz *= 2;
+        while (nz > 1 && (int64_t)nz * a.ostride > ocap) nz /= 2;
+    }
+    int64_t ks = (K + nz - 1) / nz;
+    ks = (ks + BK - 1) / BK * BK;
+    nz = (int)((K + ks - 1) / ks);
+    if (nz < 1) nz = 1;
+    a.kslice = ks;
+    *nz_out = nz;
+    hipLaunchKernelGGL(gemm_nt_kernel<T>, dim3(tiles, nz), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template hipError_t launch_prep_v<float>(const float*, int64_t, int64_t, int, float*, int64_t, float*, int64_t,
+                                         hipStream_t);
+template hipError_t launch_prep_v<double>(const double*, int64_t, int64_t, int, double*, int64_t, double*, int64_t,
+                                          hipStream_t);
+template hipError_t launch_nt<float>(const float*, int64_t, const float*, int64_t, float*, int64_t, int64_t, int,
+                                     int64_t, bool, int64_t, int*, hipStream_t);
+template hipError_t launch_nt<double>(const double*, int64_t, const double*, int64_t, double*, int64_t, int64_t, int,
+                                      int64_t, bool, int64_t, int*, hipStream_t);
+
+}  // namespace ctqr

@@ -115,8 +115,22 @@ __global__ void __launch_bounds__(256) panel_qr_kernel(PanelArgs<TS> a)
             const int c = v & 31;
             double s = 0.0;
             if (c >= j && c < nbp) {
-                const double* base = a.part + (size_t)(j & 1) * a.P * 64;
-                for (int q = g; q < a.P; q += 4) s += base[(size_t)q * 64 + v];
+                // eight independent chains so the loads are all in flight together
+                const double* base = a.part + (size_t)(j & 1) * a.P * 64 + v;
+                double s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0, s6 = 0, s7 = 0;
+                int q = g;
+                for (; q + 28 < a.P; q += 32) {
+                    s0 += base[(size_t)q * 64];
+                    s1 += base[(size_t)(q + 4) * 64];
+                    s2 += base[(size_t)(q + 8) * 64];
+                    s3 += base[(size_t)(q + 12) * 64];
+                    s4 += base[(size_t)(q + 16) * 64];
+                    s5 += base[(size_t)(q + 20) * 64];
+                    s6 += base[(size_t)(q + 24) * 64];
+                    s7 += base[(size_t)(q + 28) * 64];
+                }
+                for (; q < a.P; q += 4) s0 += base[(size_t)q * 64];
+                s = ((s0 + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7));
             }
             red[g * 64 + v] = s;
         }
@@ -208,9 +222,18 @@ __global__ void __launch_bounds__(256) panel_qr_kernel(PanelArgs<TS> a)
     double* G = lds;                        // 32 x 32, G[q * 32 + p]
     double* T = lds + kPanelMax * kPanelMax;  // 32 x 32, T[q * 32 + p]
     for (int e = t; e < kPanelMax * kPanelMax; e += 256) {
-        double s = 0.0;
-        for (int q = 0; q < a.P; ++q) s += a.gpart[(size_t)q * (kPanelMax * kPanelMax) + e];
-        G[e] = s;
+        const double* gp = a.gpart + e;
+        const size_t st = kPanelMax * kPanelMax;
+        double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        int q = 0;
+        for (; q + 3 < a.P; q += 4) {
+            s0 += gp[(size_t)q * st];
+            s1 += gp[(size_t)(q + 1) * st];
+            s2 += gp[(size_t)(q + 2) * st];
+            s3 += gp[(size_t)(q + 3) * st];
+        }
+        for (; q < a.P; ++q) s0 += gp[(size_t)q * st];
+        G[e] = (s0 + s1) + (s2 + s3);
         T[e] = 0.0;
     }
     __syncthreads();

@@ -111,6 +111,144 @@ __global__ void __launch_bounds__(256) residual_t_kernel(const int64_t* __restri
         if (q < nq) S[j + (int64_t)(c0 + q) * lds] = acc[q];
 }
 
+// ---------------------------------------------------------------------------
+// Slice-contiguous ("transposed") layouts for the refinement: a vector block
+// Zt of r rows and nrhs slices stores element (i, j) at Zt[i * ld + j], so one
+// wavefront reads the 64 slices of a row with one coalesced load.
+// Rt = Bt - A Xt (CSR) and St = A^T Rt (CSC), one wavefront per matrix row
+// (column); CSR/CSC entries are wave-uniform scalar loads.  Rows are dealt
+// to the 8 XCDs in contiguous ranges so neighbouring rays, which cross
+// nearly the same pixels, share an L2.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t xcd_row(int64_t b, int64_t rows)
+{
+    if (rows % 8 != 0) return b;
+    return (b % 8) * (rows / 8) + b / 8;
+}
+
+__global__ void __launch_bounds__(64) spmv_rows_t_kernel(const int64_t* __restrict__ ptr,
+                                                         const int32_t* __restrict__ idx,
+                                                         const double* __restrict__ val, int64_t rows,
+                                                         const double* __restrict__ Xt, const double* __restrict__ Bt,
+                                                         double* __restrict__ Rt, int64_t ld, int nrhs)
+{
+    const int64_t i = xcd_row(blockIdx.x, rows);
+    const int lane = threadIdx.x;
+    const int64_t p0 = ptr[i], p1 = ptr[i + 1];
+    for (int j0 = 0; j0 < nrhs; j0 += 512) {
+        double acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+        for (int64_t p = p0; p < p1; ++p) {
+            const double v = val[p];
+            const double* xr = Xt + (int64_t)idx[p] * ld + j0 + lane;
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (j0 + lane + 64 * q < nrhs) acc[q] += v * xr[64 * q];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int j = j0 + lane + 64 * q;
+            if (j < nrhs) Rt[i * ld + j] = (Bt ? Bt[i * ld + j] : 0.0) - acc[q];
+        }
+    }
+}
+
+// St[j][q] = sum_{p in column j} cval[p] Rt[row[p]][q]  (sign +)
+__global__ void __launch_bounds__(64) spmv_cols_t_kernel(const int64_t* __restrict__ ptr,
+                                                         const int32_t* __restrict__ idx,
+                                                         const double* __restrict__ val, int64_t cols,
+                                                         const double* __restrict__ Rt, double* __restrict__ St,
+                                                         int64_t ld, int nrhs)
+{
+    const int64_t jc = xcd_row(blockIdx.x, cols);
+    const int lane = threadIdx.x;
+    const int64_t p0 = ptr[jc], p1 = ptr[jc + 1];
+    for (int j0 = 0; j0 < nrhs; j0 += 512) {
+        double acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+        for (int64_t p = p0; p < p1; ++p) {
+            const double v = val[p];
+            const double* rr = Rt + (int64_t)idx[p] * ld + j0 + lane;
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (j0 + lane + 64 * q < nrhs) acc[q] += v * rr[64 * q];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int j = j0 + lane + 64 * q;
+            if (j < nrhs) St[jc * ld + j] = acc[q];
+        }
+    }
+}
+
+// out[j] = ||Zt[:, j]||_2 over `rows` rows of a slice-contiguous block
+__global__ void __launch_bounds__(256) colnorm_t_kernel(const double* __restrict__ Zt, int64_t ld, int64_t rows,
+                                                        int nrhs, double* out)
+{
+    __shared__ double red[4][64];
+    const int j = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int part = threadIdx.x >> 6;
+    double s = 0.0;
+    if (j < nrhs)
+        for (int64_t i = part; i < rows; i += 4) {
+            const double v = Zt[i * ld + j];
+            s += v * v;
+        }
+    red[part][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (part == 0 && j < nrhs) out[j] = sqrt(((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x]);
+}
+
+// Transpose with conversion between a column-major block (rows x cols, ld ldc)
+// and a slice-contiguous block (element (i, j) at Zt[i * ldt + j]).
+//   TO_T: column-major -> slice-contiguous, else the reverse.  ACC adds.
+template <typename TI, typename TO, bool TO_T, bool ACC>
+__global__ void __launch_bounds__(256) transpose_kernel(const TI* __restrict__ in, TO* __restrict__ out, int64_t rows,
+                                                        int cols, int64_t ldc, int64_t ldt)
+{
+    __shared__ double tile[64][65];
+    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    const int j0 = blockIdx.y * 64;
+    const int t = threadIdx.x;
+    if (TO_T) {
+        for (int e = t; e < 64 * 64; e += 256) {
+            const int jj = e / 64, ii = e % 64;
+            const int64_t i = i0 + ii;
+            const int j = j0 + jj;
+            tile[jj][ii] = (i < rows && j < cols) ? (double)in[i + (int64_t)j * ldc] : 0.0;
+        }
+        __syncthreads();
+        for (int e = t; e < 64 * 64; e += 256) {
+            const int ii = e / 64, jj = e % 64;
+            const int64_t i = i0 + ii;
+            const int j = j0 + jj;
+            if (i < rows && j < cols) {
+                TO* d = out + i * ldt + j;
+                *d = ACC ? (TO)((double)*d + tile[jj][ii]) : (TO)tile[jj][ii];
+            }
+        }
+    } else {
+        for (int e = t; e < 64 * 64; e += 256) {
+            const int ii = e / 64, jj = e % 64;
+            const int64_t i = i0 + ii;
+            const int j = j0 + jj;
+            tile[jj][ii] = (i < rows && j < cols) ? (double)in[i * ldt + j] : 0.0;
+        }
+        __syncthreads();
+        for (int e = t; e < 64 * 64; e += 256) {
+            const int jj = e / 64, ii = e % 64;
+            const int64_t i = i0 + ii;
+            const int j = j0 + jj;
+            if (i < rows && j < cols) {
+                TO* d = out + i + (int64_t)j * ldc;
+                *d = ACC ? (TO)((double)*d + tile[jj][ii]) : (TO)tile[jj][ii];
+            }
+        }
+    }
+}
+
 // Y (rows x cols, ldy) = (TO) X (ldx)
 template <typename TI, typename TO>
 __global__ void __launch_bounds__(256) convert_kernel(const TI* __restrict__ X, int64_t ldx, TO* __restrict__ Y,
@@ -207,6 +345,41 @@ hipError_t launch_residual_t(const int64_t* col_ptr, const int32_t* row, const d
     hipLaunchKernelGGL(residual_t_kernel, grid, dim3(256), 0, s, col_ptr, row, cval, n, R, ldr, S, lds, nrhs);
     return hipGetLastError();
 }
+
+hipError_t launch_spmv_rows_t(const int64_t* ptr, const int32_t* idx, const double* val, int64_t rows,
+                              const double* Xt, const double* Bt, double* Rt, int64_t ld, int nrhs, hipStream_t s)
+{
+    hipLaunchKernelGGL(spmv_rows_t_kernel, dim3((unsigned)rows), dim3(64), 0, s, ptr, idx, val, rows, Xt, Bt, Rt, ld,
+                       nrhs);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_cols_t(const int64_t* ptr, const int32_t* idx, const double* val, int64_t cols,
+                              const double* Rt, double* St, int64_t ld, int nrhs, hipStream_t s)
+{
+    hipLaunchKernelGGL(spmv_cols_t_kernel, dim3((unsigned)cols), dim3(64), 0, s, ptr, idx, val, cols, Rt, St, ld, nrhs);
+    return hipGetLastError();
+}
+
+hipError_t launch_colnorm_t(const double* Zt, int64_t ld, int64_t rows, int nrhs, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(colnorm_t_kernel, dim3((unsigned)((nrhs + 63) / 64)), dim3(256), 0, s, Zt, ld, rows, nrhs, out);
+    return hipGetLastError();
+}
+
+template <typename TI, typename TO, bool TO_T, bool ACC>
+hipError_t launch_transpose(const TI* in, TO* out, int64_t rows, int cols, int64_t ldc, int64_t ldt, hipStream_t s)
+{
+    dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((cols + 63) / 64));
+    hipLaunchKernelGGL((transpose_kernel<TI, TO, TO_T, ACC>), grid, dim3(256), 0, s, in, out, rows, cols, ldc, ldt);
+    return hipGetLastError();
+}
+template hipError_t launch_transpose<double, double, true, false>(const double*, double*, int64_t, int, int64_t, int64_t, hipStream_t);
+template hipError_t launch_transpose<float, double, true, false>(const float*, double*, int64_t, int, int64_t, int64_t, hipStream_t);
+template hipError_t launch_transpose<float, double, true, true>(const float*, double*, int64_t, int, int64_t, int64_t, hipStream_t);
+template hipError_t launch_transpose<double, double, true, true>(const double*, double*, int64_t, int, int64_t, int64_t, hipStream_t);
+template hipError_t launch_transpose<double, float, false, false>(const double*, float*, int64_t, int, int64_t, int64_t, hipStream_t);
+template hipError_t launch_transpose<double, double, false, false>(const double*, double*, int64_t, int, int64_t, int64_t, hipStream_t);
 
 template <typename TI, typename TO>
 hipError_t launch_convert(const TI* X, int64_t ldx, TO* Y, int64_t ldy, int64_t rows, int cols, hipStream_t s)
