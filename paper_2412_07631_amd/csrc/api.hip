@@ -17,9 +17,10 @@ hipError_t launch_siddon_csr(const GeomDev& g, int64_t* row_ptr, int32_t* col, d
 hipError_t launch_siddon_rows(const double* rays, int64_t r, int32_t N, double W, double* rows, hipStream_t s);
 template <typename TS>
 hipError_t launch_panel(TS* A, int64_t lda, int64_t mk, int nbp, int rw, double* tau, double* T, int64_t ldt,
-                        double* part, double* gpart, uint64_t* counter, uint64_t* base, int64_t* info,
-                        int64_t col0, int32_t* err, hipStream_t s);
+                        double* part, double* gpart, uint64_t* counter, uint64_t* base, uint64_t* flag,
+                        uint64_t* flag_base, int64_t* info, int64_t col0, int32_t* err, hipStream_t s);
 size_t panel_lds_bytes(int nbp, int rw);
+int panel_aux_words();
 hipError_t panel_set_max_lds(size_t bytes);
 hipError_t panel_max_active(int* per_cu, size_t shmem);
 template <int MODE, typename TA, typename TB, typename TW, bool MA, bool MB_>
@@ -42,6 +43,9 @@ hipError_t launch_prep_v(const T* V, int64_t ldv, int64_t mk, int nb, T* Vm, int
 template <typename T>
 hipError_t launch_nt(const T* X, int64_t ldx, const T* Y, int64_t ldy, T* out, int64_t ldo, int64_t P, int Q,
                      int64_t K, bool sub, int64_t ocap, int* nz_out, hipStream_t s);
+template <int MODE>
+hipError_t launch_nt_lp(const float* X, int64_t ldx, const float* Y, int64_t ldy, float* out, int64_t ldo, int64_t P,
+                        int Q, int64_t K, bool sub, int64_t ocap, int* nz_out, hipStream_t s);
 template <typename TS, bool UPPER>
 hipError_t launch_trsm_diag(const TS* R, int64_t ldr, int bo, TS* B, int64_t ldb, int nrhs, hipStream_t s);
 hipError_t trsm_set_max_lds(size_t bytes);
@@ -154,11 +158,13 @@ struct ct_factor {
     int64_t ldvm;
     void* Ws;          // split-K sums
     uint64_t barrier_base;
+    uint64_t* flag;
+    uint64_t flag_base;
     int rw;            // panel rows per workgroup
     int64_t max_nrhs;
 };
 
-static int nb_out_for(int prec) { return (prec == CT_PREC_F64 || prec == CT_PREC_F32) ? 128 : 256; }
+static int nb_out_for(int prec) { (void)prec; return 128; }
 
 struct Layout {
     size_t T_all, Tin, part, gpart, words, Wp, Wq, G, Vm, Vt, Ws, total;
@@ -178,7 +184,7 @@ static Layout layout(int64_t m, int64_t n, int prec, int64_t max_nrhs)
     size_t off = 0;
     L.T_all = off; off += up256((size_t)nblocks * nbo * nbo * 8);
     L.Tin = off; off += up256(32 * 32 * 8);
-    L.part = off; off += up256(2 * 256 * 64 * 8);
+    L.part = off; off += up256(2 * 256 * 64 * 8 + 2 * 64 * 8);
     L.gpart = off; off += up256(256 * 1024 * 8);
     L.words = off; off += 256;
     L.Wp = off; off += up256((size_t)L.wp_elems * 8);
@@ -252,7 +258,17 @@ static int prep_block(ct_factor* f, const TS* V, int64_t ldv, int64_t mk, int nb
 
 // Block-reflector update with the LDS-tiled NT kernel (FP32 / FP64 arithmetic
 // equal to the storage type); the block must already be in f->Vm / f->Vt.
-template <typename TS, int OPT>
+template <typename TS, int MODE>
+static hipError_t nt_any(const TS* X, int64_t ldx, const TS* Y, int64_t ldy, TS* out, int64_t ldo, int64_t P, int Q,
+                         int64_t K, bool sub, int64_t ocap, int* nz, hipStream_t s)
+{
+    if constexpr (MODE == M_F64 || MODE == M_F32)
+        return launch_nt<TS>(X, ldx, Y, ldy, out, ldo, P, Q, K, sub, ocap, nz, s);
+    else
+        return launch_nt_lp<MODE>(X, ldx, Y, ldy, out, ldo, P, Q, K, sub, ocap, nz, s);
+}
+
+template <typename TS, int OPT, int MODE = (sizeof(TS) == 8 ? M_F64 : M_F32)>
 static int larfb_nt(ct_factor* f, int64_t mk, int nbv, const double* T, int64_t ldt, TS* C, int64_t ldc, int nc,
                     hipStream_t s, bool timed)
 {
@@ -261,8 +277,8 @@ static int larfb_nt(ct_factor* f, int64_t mk, int nbv, const double* T, int64_t 
     int nz = 1;
     {
         ProfScope ps(timed ? 0 : -1, fl, ((double)mk * nbv + (double)mk * nc) * sizeof(TS) + (double)nbv * nc * sizeof(TS), s);
-        CT_HIP(launch_nt<TS>((const TS*)f->Vm, f->ldvm, C, ldc, (TS*)f->Wp, nbv, nbv, nc, mk, false,
-                             f->wp_elems * 8 / (int64_t)sizeof(TS), &nz, s));
+        CT_HIP((nt_any<TS, MODE>((const TS*)f->Vm, f->ldvm, C, ldc, (TS*)f->Wp, nbv, nbv, nc, mk, false,
+                                 f->wp_elems * 8 / (int64_t)sizeof(TS), &nz, s)));
     }
     const TS* Wsum = (const TS*)f->Wp;
     if (nz > 1) {
@@ -273,55 +289,34 @@ static int larfb_nt(ct_factor* f, int64_t mk, int nbv, const double* T, int64_t 
     {
         ProfScope ps(timed ? 1 : -1, fl, (double)mk * nbv * sizeof(TS) + (double)nbv * nc * sizeof(TS) + 2.0 * mk * nc * sizeof(TS), s);
         int nz2;
-        CT_HIP(launch_nt<TS>((const TS*)f->Vt, ldw, (const TS*)f->Wq, ldw, C, ldc, mk, nc, nbv, true, 0, &nz2, s));
+        CT_HIP((nt_any<TS, MODE>((const TS*)f->Vt, ldw, (const TS*)f->Wq, ldw, C, ldc, mk, nc, nbv, true, 0, &nz2, s)));
     }
     return 0;
 }
 
-template <int MODE, typename TS, int OPT>
-static int larfb(ct_factor* f, const TS* V, int64_t ldv, int64_t mk, int nbv, const double* T, int64_t ldt, TS* C,
-                 int64_t ldc, int nc, hipStream_t s, bool timed = false)
-{
-    typedef typename std::conditional<MODE == M_F64, double, float>::type TE;
-    const double fl = 2.0 * (double)mk * nbv * nc;
-    int nz = 1;
-    {
-        ProfScope ps(timed ? 0 : -1, fl, ((double)mk * nbv + (double)mk * nc) * sizeof(TS) + (double)nbv * nc * sizeof(TE), s);
-        CT_HIP((launch_tn<MODE, TS, TS, TE, true, false>(V, ldv, C, ldc, (TE*)f->Wp, nbv, nc, mk,
-                                                         f->wp_elems * 8 / (int64_t)sizeof(TE), &nz, s)));
-    }
-    CT_HIP((launch_tw<TE, TE, OPT, false>((const TE*)f->Wp, nz, nbv, nc, T, ldt, (TE*)f->Wq, nullptr, nbv, s)));
-    {
-        ProfScope ps(timed ? 1 : -1, fl, (double)mk * nbv * sizeof(TS) + (double)nbv * nc * sizeof(TE) + 2.0 * mk * nc * sizeof(TS), s);
-        CT_HIP((launch_nn_sub<MODE, TS, TE, TS, true>(V, ldv, (const TE*)f->Wq, nullptr, nbv, C, ldc, mk, nc, nbv, s)));
-    }
-    return 0;
-}
 
 // prepared: the block is already in f->Vm / f->Vt
 template <typename TS, int OPT>
 static int larfb_mode(ct_factor* f, int mode, const TS* V, int64_t ldv, int64_t mk, int nbv, const double* T,
                       int64_t ldt, TS* C, int64_t ldc, int nc, hipStream_t s, bool timed = false, bool prepared = false)
 {
-    if (mode == M_F64 || mode == M_F32) {
-        if (!prepared) {
-            int r = prep_block<TS>(f, V, ldv, mk, nbv, s);
-            if (r) return r;
-        }
-        return larfb_nt<TS, OPT>(f, mk, nbv, T, ldt, C, ldc, nc, s, timed);
+    if (!prepared) {
+        int r = prep_block<TS>(f, V, ldv, mk, nbv, s);
+        if (r) return r;
     }
     if constexpr (sizeof(TS) == 8) {
-        return larfb<M_F64, TS, OPT>(f, V, ldv, mk, nbv, T, ldt, C, ldc, nc, s, timed);
+        return larfb_nt<TS, OPT, M_F64>(f, mk, nbv, T, ldt, C, ldc, nc, s, timed);
     } else {
         switch (mode) {
-            case M_F32: return larfb<M_F32, TS, OPT>(f, V, ldv, mk, nbv, T, ldt, C, ldc, nc, s, timed);
-            case M_BF16: return larfb<M_BF16, TS, OPT>(f, V, ldv, mk, nbv, T, ldt, C, ldc, nc, s, timed);
-            case M_F16: return larfb<M_F16, TS, OPT>(f, V, ldv, mk, nbv, T, ldt, C, ldc, nc, s, timed);
-            case M_BF16X3: return larfb<M_BF16X3, TS, OPT>(f, V, ldv, mk, nbv, T, ldt, C, ldc, nc, s, timed);
+            case M_F32: return larfb_nt<TS, OPT, M_F32>(f, mk, nbv, T, ldt, C, ldc, nc, s, timed);
+            case M_BF16: return larfb_nt<TS, OPT, M_BF16>(f, mk, nbv, T, ldt, C, ldc, nc, s, timed);
+            case M_F16: return larfb_nt<TS, OPT, M_F16>(f, mk, nbv, T, ldt, C, ldc, nc, s, timed);
+            case M_BF16X3: return larfb_nt<TS, OPT, M_BF16X3>(f, mk, nbv, T, ldt, C, ldc, nc, s, timed);
         }
     }
     return fail(-1, "%s", "unsupported precision");
 }
+
 
 static int trailing_mode(int prec)
 {
@@ -369,7 +364,7 @@ static int factor_impl(ct_factor* f, hipStream_t s)
             double* Tp = (bo == bi) ? Tb : f->Tin;
             const int64_t ldtp = (bo == bi) ? nbo : 32;
             CT_HIP(launch_panel<TS>(Vp, lda, mkp, bi, f->rw, f->tau + p0, Tp, ldtp, f->part, f->gpart, f->counter,
-                                    &f->barrier_base, f->info, p0, f->err, s));
+                                    &f->barrier_base, f->flag, &f->flag_base, f->info, p0, f->err, s));
             const int64_t rest = k0 + bo - (p0 + bi);
             if (rest > 0) {
                 int r = larfb_mode<TS, 0>(f, inner_mode, Vp, lda, mkp, bi, Tp, ldtp, A + p0 + (p0 + bi) * lda, lda,
@@ -608,6 +603,8 @@ int ct_qr_factor(void* A, int64_t m, int64_t n, int64_t lda, int prec, double* t
     f->counter = (uint64_t*)(w + L.words);
     f->info = (int64_t*)(w + L.words + 64);
     f->err = (int32_t*)(w + L.words + 128);
+    f->flag = (uint64_t*)(w + L.words + 192);
+    f->flag_base = 0;
     f->Wp = w + L.Wp; f->wp_elems = L.wp_elems;
     f->Wq = w + L.Wq; f->wq_elems = L.wq_elems;
     f->G = (double*)(w + L.G);
@@ -620,7 +617,7 @@ int ct_qr_factor(void* A, int64_t m, int64_t n, int64_t lda, int prec, double* t
 
     // panel geometry: rows per workgroup from the LDS budget; all workgroups
     // of a panel must be resident at once (one per CU at this LDS size)
-    const size_t lds_words = g_dev.lds_max / 8 - (256 + 64 + 32 + 4);
+    const size_t lds_words = g_dev.lds_max / 8 - panel_aux_words();
     int nbi = 32;
     int rw = (int)(lds_words / nbi);
     if ((rw & 1) == 0) --rw;

@@ -57,7 +57,9 @@ template <typename T> struct V16;
 template <> struct V16<float> { typedef f4_t t; static constexpr int N = 4; };
 template <> struct V16<double> { typedef double t __attribute__((ext_vector_type(2))); static constexpr int N = 2; };
 
-template <typename T>
+// SUB = false: partial products out[z] = X Y^T over K slice z (W = V^T C);
+// SUB = true: out -= X Y^T (the rank-nb update C -= V W').
+template <typename T, bool SUB>
 __global__ void __launch_bounds__(256, 2) gemm_nt_kernel(NtArgs a)
 {
     typedef LdsTraits<T> L;
@@ -140,7 +142,7 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_kernel(NtArgs a)
     constexpr bool F64 = sizeof(T) == 8;
     constexpr bool PRE = !F64;
     T cpre[4][4][PRE ? 4 : 1];
-    if (PRE && a.sub) {
+    if (PRE && SUB) {
         T* O = (T*)a.out;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
@@ -192,7 +194,7 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_kernel(NtArgs a)
     }
 
     T* O = (T*)a.out;
-    if (!a.sub) O += (int64_t)blockIdx.y * a.ostride;
+    if (!SUB) O += (int64_t)blockIdx.y * a.ostride;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -204,8 +206,8 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_kernel(NtArgs a)
                 const int64_t p = p0 + wp + 16 * i + (F64 ? g + 4 * r : 4 * g + r);
                 if (p < a.P) {
                     T* d = O + p + (int64_t)q * a.ldo;
-                    if constexpr (PRE) *d = a.sub ? cpre[i][j][r] - (T)acc[i][j][r] : (T)acc[i][j][r];
-                    else *d = a.sub ? *d - (T)acc[i][j][r] : (T)acc[i][j][r];
+                    if constexpr (PRE) *d = SUB ? cpre[i][j][r] - (T)acc[i][j][r] : (T)acc[i][j][r];
+                    else *d = SUB ? *d - (T)acc[i][j][r] : (T)acc[i][j][r];
                 }
             }
         }
@@ -279,7 +281,10 @@ hipError_t launch_nt(const T* X, int64_t ldx, const T* Y, int64_t ldy, T* out, i
     if (nz < 1) nz = 1;
     a.kslice = ks;
     *nz_out = nz;
-    hipLaunchKernelGGL(gemm_nt_kernel<T>, dim3(tiles, nz), dim3(256), 0, s, a);
+    if (sub)
+        hipLaunchKernelGGL((gemm_nt_kernel<T, true>), dim3(tiles, nz), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((gemm_nt_kernel<T, false>), dim3(tiles, nz), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -291,5 +296,218 @@ template hipError_t launch_nt<float>(const float*, int64_t, const float*, int64_
                                      int64_t, bool, int64_t, int*, hipStream_t);
 template hipError_t launch_nt<double>(const double*, int64_t, const double*, int64_t, double*, int64_t, int64_t, int,
                                       int64_t, bool, int64_t, int*, hipStream_t);
+
+
+// ---------------------------------------------------------------------------
+// Low-precision variant of the NT update (same operands, FP32 in memory, FP32
+// accumulation) on the 16x16x32 bf16 / f16 MFMA.  Each FP32 element is
+// rounded once, when its tile is staged into LDS:
+//   M_BF16 / M_F16: x -> bf16(x) / f16(x)                  (1 MFMA per block)
+//   M_BF16X3: x -> hi = bf16(x), lo = bf16(x - hi); the product is formed as
+//             lo*hi' + hi*lo' + hi*hi' (3 MFMA per block, about 16
+//             significant bits, FP32 range)
+// Tile 128 x 128, K step 64, one LDS buffer per operand half with register
+// prefetch of the next K step; fragments are one ds_read_b128 per half.
+// ---------------------------------------------------------------------------
+template <int MODE> struct LpT;
+template <> struct LpT<M_BF16> { typedef __bf16 e; typedef bf8_t v8; static constexpr bool X3 = false; };
+template <> struct LpT<M_F16> { typedef _Float16 e; typedef h8_t v8; static constexpr bool X3 = false; };
+template <> struct LpT<M_BF16X3> { typedef __bf16 e; typedef bf8_t v8; static constexpr bool X3 = true; };
+
+template <int MODE>
+__device__ __forceinline__ f4_t mfma_lp(const typename LpT<MODE>::v8& a, const typename LpT<MODE>::v8& b, f4_t acc)
+{
+    if constexpr (MODE == M_F16) return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc, 0, 0, 0);
+    else return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+}
+
+template <int MODE, bool SUB>
+__global__ void __launch_bounds__(256, 2) gemm_nt_lp_kernel(NtArgs a)
+{
+    typedef typename LpT<MODE>::e E;
+    typedef typename LpT<MODE>::v8 v8;
+    constexpr bool X3 = LpT<MODE>::X3;
+    constexpr int BK = 64, LDK = BK + 8;          // row stride 144 bytes
+    constexpr int NH = X3 ? 2 : 1;                // hi (and lo) halves
+    constexpr int VPR = BK / 4;                   // float4 per tile row
+    constexpr int RPP = 256 / VPR;                // rows per pass
+    constexpr int PASSES = kBP / RPP;             // 8
+
+    __shared__ E Xs[NH][kBP * LDK];
+    __shared__ E Ys[NH][kBQ * LDK];
+
+    const int nt = a.tiles_p * a.tiles_q;
+    const int b = blockIdx.x;
+    const int per = (nt + 7) / 8;
+    int tile = (b % 8) * per + b / 8;
+    if (nt % 8 != 0) tile = b;
+    if (tile >= nt) return;
+    const int tp = tile % a.tiles_p, tq = tile / a.tiles_p;
+    const int64_t p0 = (int64_t)tp * kBP;
+    const int q0 = tq * kBQ;
+    const int64_t kbeg = (int64_t)blockIdx.y * a.kslice;
+    int64_t kend = kbeg + a.kslice;
+    if (kend > a.K) kend = a.K;
+
+    const float* __restrict__ X = (const float*)a.X;
+    const float* __restrict__ Y = (const float*)a.Y;
+    const int t = threadIdx.x;
+    const int lr = t / VPR, lv = t % VPR;
+
+    f4_t xr[PASSES], yr[PASSES];
+    auto gload = [&](int64_t k0) {
+#pragma unroll
+        for (int ps = 0; ps < PASSES; ++ps) {
+            const int row = ps * RPP + lr;
+            const int64_t kk = k0 + lv * 4;
+            const int64_t pr = p0 + row;
+            const int qr = q0 + row;
+            f4_t vx = {0, 0, 0, 0}, vy = {0, 0, 0, 0};
+            if (kk + 4 <= kend) {
+                if (pr < a.P) vx = *(const f4_t*)(X + pr * a.ldx + kk);
+                if (qr < a.Q) vy = *(const f4_t*)(Y + (int64_t)qr * a.ldy + kk);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (kk + e < kend) {
+                        if (pr < a.P) vx[e] = X[pr * a.ldx + kk + e];
+                        if (qr < a.Q) vy[e] = Y[(int64_t)qr * a.ldy + kk + e];
+                    }
+            }
+            xr[ps] = vx;
+            yr[ps] = vy;
+        }
+    };
+    auto sstore = [&]() {
+#pragma unroll
+        for (int ps = 0; ps < PASSES; ++ps) {
+            const int row = ps * RPP + lr;
+            typedef E e4 __attribute__((ext_vector_type(4)));
+            e4 xh, yh, xl, yl;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                xh[e] = (E)xr[ps][e];
+                yh[e] = (E)yr[ps][e];
+                if constexpr (X3) {
+                    xl[e] = (E)(xr[ps][e] - (float)xh[e]);
+                    yl[e] = (E)(yr[ps][e] - (float)yh[e]);
+                }
+            }
+            *(e4*)&Xs[0][row * LDK + lv * 4] = xh;
+            *(e4*)&Ys[0][row * LDK + lv * 4] = yh;
+            if constexpr (X3) {
+                *(e4*)&Xs[NH - 1][row * LDK + lv * 4] = xl;
+                *(e4*)&Ys[NH - 1][row * LDK + lv * 4] = yl;
+            }
+        }
+    };
+
+    const int lane = t & 63, wv = t >> 6;
+    const int c = lane & 15, g = lane >> 4;
+    const int wp = (wv >> 1) * 64, wq = (wv & 1) * 64;
+
+    f4_t acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f4_t{0, 0, 0, 0};
+
+    if (kbeg < kend) {
+        gload(kbeg);
+        sstore();
+        __syncthreads();
+        for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+            const bool more = k0 + BK < kend;
+            if (more) gload(k0 + BK);
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 32) {
+                v8 ah[4], bh[4], al[4], bl[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    ah[i] = *(const v8*)&Xs[0][(wp + 16 * i + c) * LDK + kk + 8 * g];
+                    if constexpr (X3) al[i] = *(const v8*)&Xs[NH - 1][(wp + 16 * i + c) * LDK + kk + 8 * g];
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    bh[j] = *(const v8*)&Ys[0][(wq + 16 * j + c) * LDK + kk + 8 * g];
+                    if constexpr (X3) bl[j] = *(const v8*)&Ys[NH - 1][(wq + 16 * j + c) * LDK + kk + 8 * g];
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        if constexpr (X3) {
+                            acc[i][j] = mfma_lp<MODE>(al[i], bh[j], acc[i][j]);
+                            acc[i][j] = mfma_lp<MODE>(ah[i], bl[j], acc[i][j]);
+                        }
+                        acc[i][j] = mfma_lp<MODE>(ah[i], bh[j], acc[i][j]);
+                    }
+            }
+            if (more) {
+                __syncthreads();
+                sstore();
+                __syncthreads();
+            }
+        }
+    }
+
+    float* O = (float*)a.out;
+    if (!SUB) O += (int64_t)blockIdx.y * a.ostride;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int q = q0 + wq + 16 * j + c;
+            if (q >= a.Q) continue;
+            const int64_t pb = p0 + wp + 16 * i + 4 * g;
+            float* d = O + pb + (int64_t)q * a.ldo;
+            if (pb + 3 < a.P && (((uintptr_t)d & 15) == 0)) {
+                f4_t v = acc[i][j];
+                if (SUB) v = *(f4_t*)d - v;
+                *(f4_t*)d = v;
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (pb + r < a.P) d[r] = SUB ? d[r] - acc[i][j][r] : acc[i][j][r];
+            }
+        }
+}
+
+template <int MODE>
+hipError_t launch_nt_lp(const float* X, int64_t ldx, const float* Y, int64_t ldy, float* out, int64_t ldo, int64_t P,
+                        int Q, int64_t K, bool sub, int64_t ocap, int* nz_out, hipStream_t s)
+{
+    constexpr int BK = 64;
+    NtArgs a;
+    a.X = X; a.ldx = ldx; a.Y = Y; a.ldy = ldy; a.out = out; a.ldo = ldo;
+    a.P = P; a.Q = Q; a.K = K; a.sub = sub ? 1 : 0;
+    a.tiles_p = (int)((P + kBP - 1) / kBP);
+    a.tiles_q = (Q + kBQ - 1) / kBQ;
+    a.ostride = ldo * (int64_t)Q;
+    const int tiles = a.tiles_p * a.tiles_q;
+    int nz = 1;
+    if (!sub) {
+        while (tiles * nz * 2 <= 1024 && K / (nz * 2) >= 8 * BK && nz < 256) nz *= 2;
+        while (nz > 1 && (int64_t)nz * a.ostride > ocap) nz /= 2;
+    }
+    int64_t ks = (K + nz - 1) / nz;
+    ks = (ks + BK - 1) / BK * BK;
+    nz = (int)((K + ks - 1) / ks);
+    if (nz < 1) nz = 1;
+    a.kslice = ks;
+    *nz_out = nz;
+    if (sub)
+        hipLaunchKernelGGL((gemm_nt_lp_kernel<MODE, true>), dim3(tiles, nz), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((gemm_nt_lp_kernel<MODE, false>), dim3(tiles, nz), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template hipError_t launch_nt_lp<M_BF16>(const float*, int64_t, const float*, int64_t, float*, int64_t, int64_t, int,
+                                         int64_t, bool, int64_t, int*, hipStream_t);
+template hipError_t launch_nt_lp<M_F16>(const float*, int64_t, const float*, int64_t, float*, int64_t, int64_t, int,
+                                        int64_t, bool, int64_t, int*, hipStream_t);
+template hipError_t launch_nt_lp<M_BF16X3>(const float*, int64_t, const float*, int64_t, float*, int64_t, int64_t,
+                                           int, int64_t, bool, int64_t, int*, hipStream_t);
 
 }  // namespace ctqr

@@ -268,3 +268,40 @@ def siddon_rows(rays, n_pix: int, grid_width: float = 1.0):
     _check(_lib.ct_siddon_rows(r.ctypes.data_as(_vp), r.shape[0], int(n_pix), float(grid_width),
                                out.ctypes.data_as(_vp)))
     return out
+
+
+# ------------------------------------------------------------ differentiation
+class QRSolve(torch.autograd.Function):
+    """x = R^{-1} Q^T b for a batch of sinograms, differentiable in b.
+
+    forward(B, factor): B is (nrhs, m) -- one sinogram per row -- in the
+    factor's storage dtype; returns X (nrhs, n).  backward(G) returns
+    grad_B = (Q [R^{-T} g; 0])^T per row, computed by ct_solve_backward; the
+    factor receives no gradient.
+    """
+
+    @staticmethod
+    def forward(ctx, B, factor):
+        m, n = factor.m, factor.n
+        nrhs = B.shape[0]
+        C = torch.zeros((nrhs, ld16(m)), dtype=factor.dtype, device=B.device)
+        C[:, :m] = B
+        apply_qt(factor, C)
+        trsm_solve(factor, C)
+        ctx.factor = factor
+        return C[:, :n].clone()
+
+    @staticmethod
+    def backward(ctx, G):
+        f = ctx.factor
+        k = G.shape[0]
+        Gd = torch.zeros((k, ld16(f.n)), dtype=f.dtype, device=G.device)
+        Gd[:, :f.n] = G
+        Y = torch.empty((k, ld16(f.m)), dtype=f.dtype, device=G.device)
+        solve_backward(f, Gd, Y)
+        return Y[:, :f.m].clone(), None
+
+
+def qr_solve(B, factor):
+    """Differentiable reconstruction X = R^{-1} Q^T B (rows of B are sinograms)."""
+    return QRSolve.apply(B, factor)
