@@ -52,6 +52,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cols", type=int, default=1024, help="leading columns in the CPU oracle sample")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one plain 1 GiB device copy first (calibrates profiler byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -91,6 +93,14 @@ def main():
     del zero, Pd, P, Xt
     torch.cuda.synchronize()
     log("inputs ready in %.1fs" % (time.time() - t0))
+
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy probe: 1 GiB read + 1 GiB written")
 
     dt_store = torch.float64 if prec == ctqr.PREC_F64 else torch.float32
     A = torch.empty((n, ctqr.ld16(m)), dtype=dt_store, device=dev)

@@ -92,6 +92,39 @@ int ct_qr_workspace(int64_t m, int64_t n, int prec, int64_t max_nrhs, size_t* by
 int ct_qr_factor(void* A, int64_t m, int64_t n, int64_t lda, int prec, double* tau, void* work,
                  size_t work_bytes, int64_t max_nrhs, ct_factor** f, void* stream);
 
+/* Out-of-core factorization (Sec. 2.2: the matrix is split into blocks kept
+ * outside device memory, part of a faster tier caches them, and transfers
+ * overlap the GPU's computation, so the problem size is not bounded by
+ * device memory).  Here the outer tier is
+ * pinned host memory: A_host (m x n, column-major, leading dimension lda,
+ * FP64 for CT_PREC_F64 else FP32) must come from hipHostMalloc and is
+ * factored in place, with the same layout and results as ct_qr_factor.  The
+ * matrix is processed left-looking in column tiles of tile_cols columns (a
+ * multiple of 128): each tile is copied to the device, updated by every
+ * earlier reflector block, factored, and copied back while the next tile is
+ * processed.  Device memory is the caller's `work` buffer of work_bytes:
+ * beyond the minimum from ct_qr_stream_workspace, whole tiles stay resident
+ * (the leading ones first); the others are re-read from A_host when a later
+ * tile or a solve needs them, so a larger buffer means less host traffic.
+ * The host matrix is complete once `stream` reaches the end of the call's
+ * work.  The handle works with every solve call except the graph-captured
+ * ones; A_host, tau and work must stay alive until ct_factor_destroy.
+ * Returns -2002 after an injected copy failure (see ct_stream_inject_failure)
+ * with *f set: ct_qr_resume then continues from the failed tile. */
+int ct_qr_stream_workspace(int64_t m, int64_t n, int64_t lda, int prec, int64_t max_nrhs, int64_t tile_cols,
+                           size_t* min_bytes, size_t* all_resident_bytes);
+int ct_qr_factor_streamed(void* A_host, int64_t m, int64_t n, int64_t lda, int prec, double* tau, void* work,
+                          size_t work_bytes, int64_t max_nrhs, int64_t tile_cols, ct_factor** f, void* stream);
+/* Continue a streamed factorization from its first unfinished tile (no-op if
+ * it is complete). */
+int ct_qr_resume(ct_factor* f, void* stream);
+/* Tile count, resident tile count and first unfinished tile of a streamed
+ * factor (all 0 for an in-memory factor). */
+int ct_stream_info(const ct_factor* f, int64_t* tiles, int64_t* resident, int64_t* next_tile);
+/* Failure injection for tests: the next streamed factorization stops before
+ * tile `tile` as if its copy had failed (-1 disables). */
+int ct_stream_inject_failure(int64_t tile);
+
 /* B <- Q^T B (Eq. (solve), first half; ormqr).  B: m x nrhs, same storage
  * type as the factor's A, nrhs <= max_nrhs.  Rows n..m-1 of the result hold
  * the least-squares residual components. */
@@ -153,6 +186,34 @@ int ct_solve_refined(const ct_factor* f, const ct_sparse* A, const double* B, in
 int ct_status(const ct_factor* f, int64_t* info, void* stream);
 
 int ct_factor_destroy(ct_factor* f);
+
+/* Graph-captured solve over a device batch descriptor, for many batches of
+ * uneven size sharing one factor.  desc is a device int32 array: desc[0] = k,
+ * the index of the batch the next launch solves; desc[2+2k] and desc[3+2k]
+ * = first column and column count (<= max_cols) of batch k inside B
+ * (m x total columns, ldb, the factor's storage type).  The whole solve
+ * (Q^T then R^{-1}, Eq. (solve)) is captured once into a hipGraph with the
+ * launch plan of the max_cols size bucket; every kernel reads the descriptor,
+ * and the graph's last node advances desc[0], so consecutive launches walk the
+ * batch list with no host work.  `stream` must not be the legacy default
+ * stream during creation (capture).  The caller sets desc before the first
+ * launch and keeps B, desc and the factor alive until ct_solve_graph_destroy. */
+typedef struct ct_solve_graph ct_solve_graph;
+int ct_solve_graph_create(const ct_factor* f, void* B, int64_t ldb, int64_t max_cols, int32_t* desc,
+                          void* stream, ct_solve_graph** g);
+int ct_solve_graph_launch(ct_solve_graph* g, void* stream);
+int ct_solve_graph_destroy(ct_solve_graph* g);
+
+/* Autotuner of the solve kernels: for each batch-size bucket (<= 8, <= 32,
+ * <= 128, <= 512 columns, up to max_nrhs) it times every candidate launch
+ * plan -- tile width 16/32/64/128 along the slices and the split-K workgroup
+ * target -- on a full Q^T + R^{-1} solve, and keeps the fastest in the factor
+ * (used by ct_apply_qt, ct_trsm_solve, ct_solve_refined and graphs created
+ * afterwards).  Results are merged into the JSON file cache_path (may be
+ * NULL), keyed by architecture, storage type, m, n and bucket; cached buckets
+ * are not re-timed.  B: scratch of at least m x max_nrhs (ldb), overwritten.
+ * Synchronous. */
+int ct_autotune_solve(ct_factor* f, void* B, int64_t ldb, int64_t max_nrhs, const char* cache_path, void* stream);
 
 /* Live timing of the trailing-matrix update GEMMs of ct_qr_factor (the
  * dominant kernels): while enabled, every launch of the two update kernels

@@ -8,7 +8,10 @@
 #include <stdio.h>
 #include <string.h>
 #include <algorithm>
+#include <map>
 #include <new>
+#include <string>
+#include <vector>
 
 namespace ctqr {
 hipError_t launch_siddon_dense(const GeomDev& g, int dtype, void* A, int64_t lda, hipStream_t s);
@@ -28,26 +31,30 @@ hipError_t launch_tn(const TA* A, int64_t lda, const TB* B, int64_t ldb, TW* W, 
                      int64_t wcap, int* nz_out, hipStream_t s);
 template <int MODE, typename TA, typename TB, typename TC, bool MA>
 hipError_t launch_nn_sub(const TA* A, int64_t lda, const TB* Bhi, const TB* Blo, int64_t ldb, TC* C, int64_t ldc,
-                         int64_t M, int N, int K, hipStream_t s);
+                         int64_t M, int N, int K, hipStream_t s, const int32_t* desc = nullptr);
 template <typename TWp, typename TO, int OP, bool SPLIT>
 hipError_t launch_tw(const TWp* Wp, int nz, int nbv, int N, const double* T, int64_t ldt, TO* out, TO* out_lo,
-                     int64_t ldo, hipStream_t s);
+                     int64_t ldo, hipStream_t s, const int32_t* desc = nullptr);
 hipError_t launch_t_from_gram(const double* G, int64_t ldg, const double* tau, int nb, double* T, int64_t ldt,
                               hipStream_t s);
 hipError_t t_from_gram_set_max_lds(size_t bytes);
 template <typename TWp, typename TS>
-hipError_t launch_sum_slices(const TWp* Wp, int64_t wstride, int nz, int64_t count, TS* S, hipStream_t s);
+hipError_t launch_sum_slices(const TWp* Wp, int64_t wstride, int nz, int64_t count, TS* S, hipStream_t s,
+                             const int32_t* desc = nullptr, int per_col = 1);
 template <typename T>
 hipError_t launch_prep_v(const T* V, int64_t ldv, int64_t mk, int nb, T* Vm, int64_t ldm, T* Vt, int64_t ldvt,
                          hipStream_t s);
 template <typename T>
 hipError_t launch_nt(const T* X, int64_t ldx, const T* Y, int64_t ldy, T* out, int64_t ldo, int64_t P, int Q,
-                     int64_t K, bool sub, int64_t ocap, int* nz_out, hipStream_t s);
+                     int64_t K, bool sub, int64_t ocap, int* nz_out, hipStream_t s, const NtPlan* plan = nullptr,
+                     const int32_t* desc = nullptr, int desc_y = 0, int desc_out = 0);
 template <int MODE>
 hipError_t launch_nt_lp(const float* X, int64_t ldx, const float* Y, int64_t ldy, float* out, int64_t ldo, int64_t P,
                         int Q, int64_t K, bool sub, int64_t ocap, int* nz_out, hipStream_t s);
 template <typename TS, bool UPPER>
-hipError_t launch_trsm_diag(const TS* R, int64_t ldr, int bo, TS* B, int64_t ldb, int nrhs, hipStream_t s);
+hipError_t launch_trsm_diag(const TS* R, int64_t ldr, int bo, TS* B, int64_t ldb, int nrhs, hipStream_t s,
+                            const int32_t* desc = nullptr);
+hipError_t launch_advance_batch(int32_t* desc, hipStream_t s);
 hipError_t trsm_set_max_lds(size_t bytes);
 hipError_t launch_residual(const int64_t* row_ptr, const int32_t* col, const double* val, int64_t m, const double* X,
                            int64_t ldx, const double* B, int64_t ldb, double* R, int64_t ldr, int nrhs,
@@ -160,8 +167,10 @@ struct ct_factor {
     uint64_t barrier_base;
     uint64_t* flag;
     uint64_t flag_base;
+    NtPlan solve_plan[5];   // per batch-size bucket (<=8, <=32, <=128, <=512, more)
     int rw;            // panel rows per workgroup
     int64_t max_nrhs;
+    struct StreamState* st = nullptr;   // host-pinned streaming state (null: A is in device memory)
 };
 
 static int nb_out_for(int prec) { (void)prec; return 128; }
@@ -270,26 +279,36 @@ static hipError_t nt_any(const TS* X, int64_t ldx, const TS* Y, int64_t ldy, TS*
 
 template <typename TS, int OPT, int MODE = (sizeof(TS) == 8 ? M_F64 : M_F32)>
 static int larfb_nt(ct_factor* f, int64_t mk, int nbv, const double* T, int64_t ldt, TS* C, int64_t ldc, int nc,
-                    hipStream_t s, bool timed)
+                    hipStream_t s, bool timed, const NtPlan* plan = nullptr, const int32_t* desc = nullptr)
 {
     const double fl = 2.0 * (double)mk * nbv * nc;
     const int64_t ldw = ldvt_of(nbv);
     int nz = 1;
     {
         ProfScope ps(timed ? 0 : -1, fl, ((double)mk * nbv + (double)mk * nc) * sizeof(TS) + (double)nbv * nc * sizeof(TS), s);
-        CT_HIP((nt_any<TS, MODE>((const TS*)f->Vm, f->ldvm, C, ldc, (TS*)f->Wp, nbv, nbv, nc, mk, false,
-                                 f->wp_elems * 8 / (int64_t)sizeof(TS), &nz, s)));
+        if constexpr (MODE == M_F64 || MODE == M_F32)
+            CT_HIP(launch_nt<TS>((const TS*)f->Vm, f->ldvm, C, ldc, (TS*)f->Wp, nbv, nbv, nc, mk, false,
+                                 f->wp_elems * 8 / (int64_t)sizeof(TS), &nz, s, plan, desc, 1, 0));
+        else
+            CT_HIP((nt_any<TS, MODE>((const TS*)f->Vm, f->ldvm, C, ldc, (TS*)f->Wp, nbv, nbv, nc, mk, false,
+                                     f->wp_elems * 8 / (int64_t)sizeof(TS), &nz, s)));
     }
     const TS* Wsum = (const TS*)f->Wp;
     if (nz > 1) {
-        CT_HIP((launch_sum_slices<TS, TS>((const TS*)f->Wp, (int64_t)nbv * nc, nz, (int64_t)nbv * nc, (TS*)f->Ws, s)));
+        CT_HIP((launch_sum_slices<TS, TS>((const TS*)f->Wp, (int64_t)nbv * nc, nz, (int64_t)nbv * nc, (TS*)f->Ws, s,
+                                          desc, nbv)));
         Wsum = (const TS*)f->Ws;
     }
-    CT_HIP((launch_tw<TS, TS, OPT, false>(Wsum, 1, nbv, nc, T, ldt, (TS*)f->Wq, nullptr, ldw, s)));
+    CT_HIP((launch_tw<TS, TS, OPT, false>(Wsum, 1, nbv, nc, T, ldt, (TS*)f->Wq, nullptr, ldw, s, desc)));
     {
         ProfScope ps(timed ? 1 : -1, fl, (double)mk * nbv * sizeof(TS) + (double)nbv * nc * sizeof(TS) + 2.0 * mk * nc * sizeof(TS), s);
         int nz2;
-        CT_HIP((nt_any<TS, MODE>((const TS*)f->Vt, ldw, (const TS*)f->Wq, ldw, C, ldc, mk, nc, nbv, true, 0, &nz2, s)));
+        if constexpr (MODE == M_F64 || MODE == M_F32)
+            CT_HIP(launch_nt<TS>((const TS*)f->Vt, ldw, (const TS*)f->Wq, ldw, C, ldc, mk, nc, nbv, true, 0, &nz2, s,
+                                 plan, desc, 0, 1));
+        else
+            CT_HIP((nt_any<TS, MODE>((const TS*)f->Vt, ldw, (const TS*)f->Wq, ldw, C, ldc, mk, nc, nbv, true, 0, &nz2,
+                                     s)));
     }
     return 0;
 }
@@ -343,23 +362,28 @@ static int block_t(ct_factor* f, int64_t mk, int bo, const double* tau, double* 
     return 0;
 }
 
+// Factor the columns [c0, c1) of the matrix in place, assuming every earlier
+// reflector block has already been applied to them: inner panels of nb_in
+// columns with their updates inside the outer block, then the outer block's
+// compact-WY factor and its update of the remaining columns up to c1.
+// C points at column c0 (row 0); c0 is a multiple of nb_out.
 template <typename TS>
-static int factor_impl(ct_factor* f, hipStream_t s)
+static int factor_cols(ct_factor* f, TS* C, int64_t c0, int64_t c1, hipStream_t s)
 {
-    TS* A = (TS*)f->A;
-    const int64_t m = f->m, n = f->n, lda = f->lda;
+    const int64_t m = f->m, lda = f->lda;
     const int nbo = f->nb_out, nbi = f->nb_in;
     const int mode = trailing_mode(f->prec);
     const int inner_mode = sizeof(TS) == 8 ? M_F64 : M_F32;
-    for (int64_t b = 0; b < f->nblocks; ++b) {
-        const int64_t k0 = b * nbo;
-        const int bo = (int)std::min<int64_t>(nbo, n - k0);
+    for (int64_t k0 = c0; k0 < c1; k0 += nbo) {
+        const int64_t b = k0 / nbo;
+        const int bo = (int)std::min<int64_t>(nbo, c1 - k0);
         const int64_t mk = m - k0;
+        TS* Ab = C + (k0 - c0) * lda + k0;      // diagonal entry of the block
         double* Tb = f->T_all + (size_t)b * nbo * nbo;
         for (int64_t p0 = k0; p0 < k0 + bo; p0 += nbi) {
             const int bi = (int)std::min<int64_t>(nbi, k0 + bo - p0);
             const int64_t mkp = m - p0;
-            TS* Vp = A + p0 + p0 * lda;
+            TS* Vp = Ab + (p0 - k0) * lda + (p0 - k0);
             // the panel writes its T straight into the block's T when it is the only panel
             double* Tp = (bo == bi) ? Tb : f->Tin;
             const int64_t ldtp = (bo == bi) ? nbo : 32;
@@ -367,14 +391,13 @@ static int factor_impl(ct_factor* f, hipStream_t s)
                                     &f->barrier_base, f->flag, &f->flag_base, f->info, p0, f->err, s));
             const int64_t rest = k0 + bo - (p0 + bi);
             if (rest > 0) {
-                int r = larfb_mode<TS, 0>(f, inner_mode, Vp, lda, mkp, bi, Tp, ldtp, A + p0 + (p0 + bi) * lda, lda,
-                                          (int)rest, s);
+                int r = larfb_mode<TS, 0>(f, inner_mode, Vp, lda, mkp, bi, Tp, ldtp, Vp + bi * lda, lda, (int)rest, s);
                 if (r) return r;
             }
         }
-        const int64_t nc = n - k0 - bo;
+        const int64_t nc = c1 - k0 - bo;
         if (bo > nbi || nc > 0) {
-            int r = prep_block<TS>(f, A + k0 + k0 * lda, lda, mk, bo, s);
+            int r = prep_block<TS>(f, Ab, lda, mk, bo, s);
             if (r) return r;
         }
         if (bo > nbi) {
@@ -382,8 +405,7 @@ static int factor_impl(ct_factor* f, hipStream_t s)
             if (r) return r;
         }
         if (nc > 0) {
-            int r = larfb_mode<TS, 0>(f, mode, A + k0 + k0 * lda, lda, mk, bo, Tb, nbo, A + k0 + (k0 + bo) * lda, lda,
-                                      (int)nc, s, true, true);
+            int r = larfb_mode<TS, 0>(f, mode, Ab, lda, mk, bo, Tb, nbo, Ab + bo * lda, lda, (int)nc, s, true, true);
             if (r) return r;
         }
     }
@@ -391,47 +413,347 @@ static int factor_impl(ct_factor* f, hipStream_t s)
 }
 
 template <typename TS>
-static int apply_qt_impl(const ct_factor* fc, TS* B, int64_t nrhs, int64_t ldb, hipStream_t s, bool transpose)
+static int factor_impl(ct_factor* f, hipStream_t s)
+{
+    return factor_cols<TS>(f, (TS*)f->A, 0, f->n, s);
+}
+
+static int bucket_of(int64_t nrhs) { return nrhs <= 8 ? 0 : nrhs <= 32 ? 1 : nrhs <= 128 ? 2 : nrhs <= 512 ? 3 : 4; }
+
+// ------------------------------------------------------ host-pinned streaming
+// A streamed factor keeps V\R in the caller's pinned host matrix, as column
+// tiles of wt columns (wt a multiple of nb_out).  Tiles [0, nres) also stay in
+// device memory as the leading columns of a device matrix f->A with the same
+// leading dimension; the other tiles pass through kSlots staging slots, kept
+// as a small cache.  Copies run on two streams of their own (host to device
+// and device to host) and are ordered against the compute stream with events.
+constexpr int kSlots = 4;
+
+struct StreamState {
+    char* Ah = nullptr;
+    size_t es = 4;                 // bytes per element
+    int64_t wt = 0, ntiles = 0, nres = 0;
+    int64_t next_tile = 0;         // first tile not yet factored
+    hipStream_t cin = nullptr, cout = nullptr;
+    hipEvent_t done = nullptr;     // scratch event on the compute stream
+    char* slot[kSlots] = {};
+    int64_t held[kSlots] = {-1, -1, -1, -1};
+    int64_t r0[kSlots] = {}, r1[kSlots] = {};
+    uint64_t stamp[kSlots] = {};
+    int pins[kSlots] = {};
+    bool used_rec[kSlots] = {}, out_rec[kSlots] = {};
+    hipEvent_t ready[kSlots] = {}, used[kSlots] = {}, out[kSlots] = {};
+    std::vector<hipEvent_t> res_ready;   // resident tile t: its load from host
+    std::vector<char> res_loaded;
+    std::vector<hipEvent_t> d2h;          // tile t: its host copy is final
+    std::vector<char> d2h_rec;
+    uint64_t clock = 0;
+    ~StreamState()
+    {
+        if (cin) (void)hipStreamSynchronize(cin);
+        if (cout) (void)hipStreamSynchronize(cout);
+        for (int k = 0; k < kSlots; ++k) {
+            if (ready[k]) (void)hipEventDestroy(ready[k]);
+            if (used[k]) (void)hipEventDestroy(used[k]);
+            if (out[k]) (void)hipEventDestroy(out[k]);
+        }
+        for (hipEvent_t e : res_ready) if (e) (void)hipEventDestroy(e);
+        for (hipEvent_t e : d2h) if (e) (void)hipEventDestroy(e);
+        if (done) (void)hipEventDestroy(done);
+        if (cin) (void)hipStreamDestroy(cin);
+        if (cout) (void)hipStreamDestroy(cout);
+    }
+};
+
+static int64_t tile_width(const ct_factor* f, int64_t t) { return std::min(f->st->wt, f->n - t * f->st->wt); }
+
+static void stream_invalidate(StreamState* st)
+{
+    for (int k = 0; k < kSlots; ++k) st->held[k] = -1;
+}
+
+// Copy rows [r0, r1) of host tile t into slot k on the host-to-device stream.
+static int stream_load(ct_factor* f, int k, int64_t t, int64_t r0, int64_t r1)
+{
+    StreamState* st = f->st;
+    const size_t es = st->es, pitch = (size_t)f->lda * es;
+    if (st->used_rec[k]) CT_HIP(hipStreamWaitEvent(st->cin, st->used[k], 0));
+    if (st->out_rec[k]) CT_HIP(hipStreamWaitEvent(st->cin, st->out[k], 0));
+    if (st->d2h_rec[t]) CT_HIP(hipStreamWaitEvent(st->cin, st->d2h[t], 0));
+    const char* src = st->Ah + ((size_t)t * st->wt * f->lda + r0) * es;
+    CT_HIP(hipMemcpy2DAsync(st->slot[k] + r0 * es, pitch, src, pitch, (size_t)(r1 - r0) * es, (size_t)tile_width(f, t),
+                            hipMemcpyHostToDevice, st->cin));
+    CT_HIP(hipEventRecord(st->ready[k], st->cin));
+    st->held[k] = t;
+    st->r0[k] = r0;
+    st->r1[k] = r1;
+    st->stamp[k] = ++st->clock;
+    return 0;
+}
+
+static int find_slot(const StreamState* st, int64_t t, int64_t r0, int64_t r1)
+{
+    for (int k = 0; k < kSlots; ++k)
+        if (st->held[k] == t && st->r0[k] <= r0 && st->r1[k] >= r1) return k;
+    return -1;
+}
+
+static int victim_slot(const StreamState* st)
+{
+    int best = -1;
+    for (int k = 0; k < kSlots; ++k) {
+        if (st->pins[k]) continue;
+        if (st->held[k] < 0) return k;
+        if (best < 0 || st->stamp[k] < st->stamp[best]) best = k;
+    }
+    return best;
+}
+
+// First load of resident tile t (rows [0, m)), on the host-to-device stream.
+static int stream_load_resident(ct_factor* f, int64_t t)
+{
+    StreamState* st = f->st;
+    if (st->res_loaded[t]) return 0;
+    const size_t es = st->es, pitch = (size_t)f->lda * es;
+    const size_t off = (size_t)t * st->wt * f->lda * es;
+    CT_HIP(hipMemcpy2DAsync((char*)f->A + off, pitch, st->Ah + off, pitch, (size_t)f->m * es, (size_t)tile_width(f, t),
+                            hipMemcpyHostToDevice, st->cin));
+    CT_HIP(hipEventRecord(st->res_ready[t], st->cin));
+    st->res_loaded[t] = 1;
+    return 0;
+}
+
+// Make rows [r0, r1) of tile t usable by work enqueued next on stream s.
+// *ptr receives the device address of the tile's first column (row 0) and
+// *k the slot to release afterwards (-1 for a resident tile).
+static int stream_acquire(ct_factor* f, int64_t t, int64_t r0, int64_t r1, hipStream_t s, char** ptr, int* k)
+{
+    StreamState* st = f->st;
+    if (t < st->nres) {
+        int r = stream_load_resident(f, t);
+        if (r) return r;
+        CT_HIP(hipStreamWaitEvent(s, st->res_ready[t], 0));
+        *ptr = (char*)f->A + (size_t)t * st->wt * f->lda * st->es;
+        *k = -1;
+        return 0;
+    }
+    int j = find_slot(st, t, r0, r1);
+    if (j < 0) {
+        j = victim_slot(st);
+        if (j < 0) return fail(-1, "%s", "internal: no free staging slot");
+        int r = stream_load(f, j, t, r0, r1);
+        if (r) return r;
+    }
+    CT_HIP(hipStreamWaitEvent(s, st->ready[j], 0));
+    st->pins[j]++;
+    st->stamp[j] = ++st->clock;
+    *ptr = st->slot[j];
+    *k = j;
+    return 0;
+}
+
+static int stream_release(ct_factor* f, int k, hipStream_t s)
+{
+    if (k < 0) return 0;
+    StreamState* st = f->st;
+    st->pins[k]--;
+    CT_HIP(hipEventRecord(st->used[k], s));
+    st->used_rec[k] = true;
+    return 0;
+}
+
+// Start loading rows [r0, r1) of tile t if a slot is free for it.
+static int stream_prefetch(ct_factor* f, int64_t t, int64_t r0, int64_t r1)
+{
+    StreamState* st = f->st;
+    if (t < 0 || t >= st->ntiles) return 0;
+    if (t < st->nres) return stream_load_resident(f, t);
+    if (find_slot(st, t, r0, r1) >= 0) return 0;
+    const int j = victim_slot(st);
+    if (j < 0) return 0;
+    return stream_load(f, j, t, r0, r1);
+}
+
+// Column access for one pass over the factor in a fixed direction.  vpart:
+// the pass reads reflectors (rows [c0, m) of each tile), else it reads R
+// (rows [0, c0 + w)).  In-memory factors return plain addresses.
+template <typename TS>
+struct ColWalk {
+    ct_factor* f;
+    hipStream_t s;
+    int dir;
+    bool vpart;
+    int64_t cur = -1;
+    int k = -1;
+    char* base = nullptr;
+    int rc = 0;
+    ColWalk(ct_factor* f_, hipStream_t s_, int dir_, bool vpart_) : f(f_), s(s_), dir(dir_), vpart(vpart_) {}
+    void rows(int64_t t, int64_t* a, int64_t* b) const
+    {
+        const int64_t c0 = t * f->st->wt;
+        *a = vpart ? c0 : 0;
+        *b = vpart ? f->m : c0 + tile_width(f, t);
+    }
+    // device address of column c (row 0); nullptr on failure (rc holds the code)
+    TS* col(int64_t c)
+    {
+        if (!f->st) return (TS*)f->A + c * f->lda;
+        const int64_t t = c / f->st->wt;
+        if (t != cur) {
+            if (cur >= 0 && (rc = stream_release(f, k, s))) return nullptr;
+            cur = -1;
+            int64_t a, b;
+            rows(t, &a, &b);
+            if ((rc = stream_acquire(f, t, a, b, s, &base, &k))) return nullptr;
+            cur = t;
+            const int64_t nx = t + dir;
+            if (nx >= 0 && nx < f->st->ntiles) {
+                rows(nx, &a, &b);
+                if ((rc = stream_prefetch(f, nx, a, b))) return nullptr;
+            }
+        }
+        return (TS*)base + (c - cur * f->st->wt) * f->lda;
+    }
+    int finish()
+    {
+        if (cur >= 0) {
+            cur = -1;
+            return stream_release(f, k, s);
+        }
+        return 0;
+    }
+    ~ColWalk() { finish(); }
+};
+
+// Left-looking factorization of a streamed matrix, tile by tile from
+// st->next_tile: bring tile J in, apply every earlier reflector block to it
+// (in order), factor it, and copy it back to the host matrix while the next
+// tile is processed.
+static int64_t g_inject_fail_tile = -1;
+
+template <typename TS>
+static int stream_factor(ct_factor* f, hipStream_t s)
+{
+    StreamState* st = f->st;
+    const int64_t m = f->m, lda = f->lda, wt = st->wt;
+    const int nbo = f->nb_out;
+    const int mode = trailing_mode(f->prec);
+    for (int64_t J = st->next_tile; J < st->ntiles; ++J) {
+        if (g_inject_fail_tile == J) {
+            // test hook: behave as if the copy of tile J had failed
+            g_inject_fail_tile = -1;
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamSynchronize(st->cin);
+            (void)hipStreamSynchronize(st->cout);
+            stream_invalidate(st);
+            for (int k = 0; k < kSlots; ++k) st->pins[k] = 0;
+            st->next_tile = J;
+            return fail(-2002, "%s", "tile copy failed (injected); ct_qr_resume continues from the failed tile");
+        }
+        const int64_t c0 = J * wt, w = tile_width(f, J);
+        char* Cb;
+        int kc;
+        int r = stream_acquire(f, J, 0, m, s, &Cb, &kc);
+        if (r) return r;
+        TS* C = (TS*)Cb;
+        if (J == 0) {
+            r = stream_prefetch(f, 1, 0, m);
+            if (r) return r;
+        }
+        for (int64_t u = 0; u < J; ++u) {
+            const int64_t u0 = u * wt, uw = tile_width(f, u);
+            char* Vb;
+            int kv;
+            r = stream_acquire(f, u, u0, m, s, &Vb, &kv);
+            if (r) return r;
+            // overlap the next load with this tile's updates
+            r = (u + 1 < J) ? stream_prefetch(f, u + 1, (u + 1) * wt, m) : stream_prefetch(f, J + 1, 0, m);
+            if (r) return r;
+            const TS* V = (const TS*)Vb;
+            for (int64_t k0 = u0; k0 < u0 + uw; k0 += nbo) {
+                const int bo = (int)std::min<int64_t>(nbo, u0 + uw - k0);
+                const double* Tb = f->T_all + (size_t)(k0 / nbo) * nbo * nbo;
+                r = larfb_mode<TS, 0>(f, mode, V + (k0 - u0) * lda + k0, lda, m - k0, bo, Tb, nbo, C + k0, lda,
+                                      (int)w, s, true);
+                if (r) return r;
+            }
+            r = stream_release(f, kv, s);
+            if (r) return r;
+        }
+        r = factor_cols<TS>(f, C, c0, c0 + w, s);
+        if (r) return r;
+        // copy the finished tile back to the host matrix
+        CT_HIP(hipEventRecord(st->done, s));
+        CT_HIP(hipStreamWaitEvent(st->cout, st->done, 0));
+        const size_t pitch = (size_t)lda * st->es;
+        CT_HIP(hipMemcpy2DAsync(st->Ah + (size_t)c0 * lda * st->es, pitch, C, pitch, (size_t)m * st->es, (size_t)w,
+                                hipMemcpyDeviceToHost, st->cout));
+        CT_HIP(hipEventRecord(st->d2h[J], st->cout));
+        st->d2h_rec[J] = 1;
+        if (kc >= 0) {
+            CT_HIP(hipEventRecord(st->out[kc], st->cout));
+            st->out_rec[kc] = true;
+        }
+        r = stream_release(f, kc, s);
+        if (r) return r;
+        st->next_tile = J + 1;
+    }
+    // the host matrix is complete once the compute stream passes this point
+    CT_HIP(hipStreamWaitEvent(s, st->d2h[st->ntiles - 1], 0));
+    return 0;
+}
+
+// B <- Q^T B (transpose) or B <- Q B, block by block, in the factor's storage
+// precision.  desc: optional device batch descriptor (graph-captured solves).
+template <typename TS>
+static int apply_qt_impl(const ct_factor* fc, TS* B, int64_t nrhs, int64_t ldb, hipStream_t s, bool transpose,
+                         const int32_t* desc = nullptr)
 {
     ct_factor* f = const_cast<ct_factor*>(fc);
-    const TS* A = (const TS*)f->A;
     const int nbo = f->nb_out;
-    const int mode = f->f64 ? M_F64 : M_F32;
+    const NtPlan* plan = &f->solve_plan[bucket_of(nrhs)];
+    ColWalk<TS> walk(f, s, transpose ? 1 : -1, true);
     for (int64_t bb = 0; bb < f->nblocks; ++bb) {
         const int64_t b = transpose ? bb : f->nblocks - 1 - bb;
         const int64_t k0 = b * nbo;
         const int bo = (int)std::min<int64_t>(nbo, f->n - k0);
         const double* Tb = f->T_all + (size_t)b * nbo * nbo;
-        int r = transpose ? larfb_mode<TS, 0>(f, mode, A + k0 + k0 * f->lda, f->lda, f->m - k0, bo, Tb, nbo, B + k0,
-                                              ldb, (int)nrhs, s)
-                          : larfb_mode<TS, 1>(f, mode, A + k0 + k0 * f->lda, f->lda, f->m - k0, bo, Tb, nbo, B + k0,
-                                              ldb, (int)nrhs, s);
+        const TS* Vb = walk.col(k0);
+        if (!Vb) return walk.rc;
+        int r = prep_block<TS>(f, Vb + k0, f->lda, f->m - k0, bo, s);
+        if (r) return r;
+        r = transpose ? larfb_nt<TS, 0>(f, f->m - k0, bo, Tb, nbo, B + k0, ldb, (int)nrhs, s, false, plan, desc)
+                      : larfb_nt<TS, 1>(f, f->m - k0, bo, Tb, nbo, B + k0, ldb, (int)nrhs, s, false, plan, desc);
         if (r) return r;
     }
-    return 0;
+    return walk.finish();
 }
 
 template <typename TS>
-static int trsm_impl(const ct_factor* fc, TS* B, int64_t nrhs, int64_t ldb, hipStream_t s)
+static int trsm_impl(const ct_factor* fc, TS* B, int64_t nrhs, int64_t ldb, hipStream_t s,
+                     const int32_t* desc = nullptr)
 {
-    const TS* A = (const TS*)fc->A;
-    const int64_t n = fc->n, lda = fc->lda;
+    ct_factor* f = const_cast<ct_factor*>(fc);
+    const int64_t n = f->n, lda = f->lda;
     const int tb = g_dev.trsm_block;
     const int64_t nb = (n + tb - 1) / tb;
+    ColWalk<TS> walk(f, s, -1, false);
     for (int64_t b = nb - 1; b >= 0; --b) {
         const int64_t k0 = b * tb;
         const int bo = (int)std::min<int64_t>(tb, n - k0);
-        CT_HIP((launch_trsm_diag<TS, true>(A + k0 + k0 * lda, lda, bo, B + k0, ldb, (int)nrhs, s)));
+        const TS* Rb = walk.col(k0);       // column k0 of R, row 0
+        if (!Rb) return walk.rc;
+        CT_HIP((launch_trsm_diag<TS, true>(Rb + k0, lda, bo, B + k0, ldb, (int)nrhs, s, desc)));
         if (k0 > 0) {
             if constexpr (sizeof(TS) == 8)
-                CT_HIP((launch_nn_sub<M_F64, TS, TS, TS, false>(A + k0 * lda, lda, B + k0, nullptr, ldb, B, ldb, k0,
-                                                                (int)nrhs, bo, s)));
+                CT_HIP((launch_nn_sub<M_F64, TS, TS, TS, false>(Rb, lda, B + k0, nullptr, ldb, B, ldb, k0,
+                                                                (int)nrhs, bo, s, desc)));
             else
-                CT_HIP((launch_nn_sub<M_F32, TS, TS, TS, false>(A + k0 * lda, lda, B + k0, nullptr, ldb, B, ldb, k0,
-                                                                (int)nrhs, bo, s)));
+                CT_HIP((launch_nn_sub<M_F32, TS, TS, TS, false>(Rb, lda, B + k0, nullptr, ldb, B, ldb, k0,
+                                                                (int)nrhs, bo, s, desc)));
         }
     }
-    return 0;
+    return walk.finish();
 }
 
 // Y[0:n] <- R^{-T} Y[0:n]: forward substitution on the lower-triangular R^T,
@@ -440,17 +762,19 @@ template <typename TS>
 static int trsm_lt_impl(const ct_factor* fc, TS* Y, int64_t k, int64_t ldy, hipStream_t s)
 {
     ct_factor* f = const_cast<ct_factor*>(fc);
-    const TS* A = (const TS*)f->A;
     const int64_t n = f->n, lda = f->lda;
     const int tb = g_dev.trsm_block;
     const int64_t nb = (n + tb - 1) / tb;
+    ColWalk<TS> walk(f, s, 1, false);
     for (int64_t b = 0; b < nb; ++b) {
         const int64_t k0 = b * tb;
         const int bo = (int)std::min<int64_t>(tb, n - k0);
+        const TS* Rb = walk.col(k0);       // column k0 of R, row 0
+        if (!Rb) return walk.rc;
         if (k0 > 0) {
             // Y[k0:k0+bo] -= R[0:k0, k0:k0+bo]^T Y[0:k0]  (columns of R are K-contiguous)
             int nz = 1;
-            CT_HIP(launch_nt<TS>(A + k0 * lda, lda, Y, ldy, (TS*)f->Wp, bo, bo, (int)k, k0, false,
+            CT_HIP(launch_nt<TS>(Rb, lda, Y, ldy, (TS*)f->Wp, bo, bo, (int)k, k0, false,
                                  f->wp_elems * 8 / (int64_t)sizeof(TS), &nz, s));
             const TS* Wsum = (const TS*)f->Wp;
             if (nz > 1) {
@@ -459,9 +783,9 @@ static int trsm_lt_impl(const ct_factor* fc, TS* Y, int64_t k, int64_t ldy, hipS
             }
             CT_HIP((launch_tw<TS, TS, 3, false>(Wsum, 1, bo, (int)k, nullptr, 0, Y + k0, nullptr, ldy, s)));
         }
-        CT_HIP((launch_trsm_diag<TS, false>(A + k0 + k0 * lda, lda, bo, Y + k0, ldy, (int)k, s)));
+        CT_HIP((launch_trsm_diag<TS, false>(Rb + k0, lda, bo, Y + k0, ldy, (int)k, s)));
     }
-    return 0;
+    return walk.finish();
 }
 
 template <typename TS>
@@ -571,27 +895,14 @@ int ct_qr_workspace(int64_t m, int64_t n, int prec, int64_t max_nrhs, size_t* by
     return 0;
 }
 
-int ct_qr_factor(void* A, int64_t m, int64_t n, int64_t lda, int prec, double* tau, void* work, size_t work_bytes,
-                 int64_t max_nrhs, ct_factor** f_out, void* stream)
-{
-    CT_ARG(A != nullptr && aligned(A), 1, "A");
-    CT_ARG(m > 0, 2, "m");
-    CT_ARG(n > 0 && n <= m, 3, "n (need 0 < n <= m)");
-    CT_ARG(lda >= m && lda % 16 == 0, 4, "lda");
-    CT_ARG(prec >= CT_PREC_F64 && prec <= CT_PREC_BF16X3, 5, "prec");
-    CT_ARG(tau != nullptr, 6, "tau");
-    CT_ARG(work != nullptr && aligned(work), 7, "work");
-    CT_ARG(max_nrhs >= 0, 9, "max_nrhs");
-    CT_ARG(f_out != nullptr, 10, "f");
-    const Layout L = layout(m, n, prec, max_nrhs);
-    CT_ARG(work_bytes >= L.total, 8, "work_bytes (see ct_qr_workspace)");
-    int r = device_setup();
-    if (r) return r;
-    hipStream_t s = (hipStream_t)stream;
+}  // extern "C"
 
-    ct_factor* f = new (std::nothrow) ct_factor();
-    if (!f) return fail(-1001, "%s", "out of host memory");
-    char* w = (char*)work;
+// Handle set-up shared by the in-memory and the streamed factorization:
+// workspace partition and panel geometry (rows per workgroup from the LDS
+// budget; all workgroups of a panel must be resident at once).
+static int init_factor(ct_factor* f, void* A, int64_t m, int64_t n, int64_t lda, int prec, double* tau, char* w,
+                       const Layout& L, int64_t max_nrhs)
+{
     f->A = A; f->m = m; f->n = n; f->lda = lda; f->prec = prec; f->f64 = prec == CT_PREC_F64;
     f->tau = tau;
     f->nb_out = nb_out_for(prec);
@@ -614,9 +925,8 @@ int ct_qr_factor(void* A, int64_t m, int64_t n, int64_t lda, int prec, double* t
     f->Ws = w + L.Ws;
     f->barrier_base = 0;
     f->max_nrhs = max_nrhs;
+    for (int b = 0; b < 5; ++b) f->solve_plan[b] = NtPlan{b < 2 ? 32 : 128, 1024};
 
-    // panel geometry: rows per workgroup from the LDS budget; all workgroups
-    // of a panel must be resident at once (one per CU at this LDS size)
     const size_t lds_words = g_dev.lds_max / 8 - panel_aux_words();
     int nbi = 32;
     int rw = (int)(lds_words / nbi);
@@ -626,20 +936,47 @@ int ct_qr_factor(void* A, int64_t m, int64_t n, int64_t lda, int prec, double* t
         rw = (int)(lds_words / nbi);
         if ((rw & 1) == 0) --rw;
     }
-    if ((m + rw - 1) / rw > g_dev.cus) {
-        delete f;
-        return fail(-2, "%s", "m too large for a resident panel on this device");
-    }
+    if ((m + rw - 1) / rw > g_dev.cus) return fail(-2, "%s", "m too large for a resident panel on this device");
     int per_cu = 0;
     CT_HIP(panel_max_active(&per_cu, panel_lds_bytes(nbi, rw)));
-    if (per_cu < 1) {
-        delete f;
-        return fail(-1002, "%s", "panel kernel cannot be resident");
-    }
+    if (per_cu < 1) return fail(-1002, "%s", "panel kernel cannot be resident");
     f->nb_in = nbi;
     f->rw = rw;
+    return 0;
+}
 
-    CT_HIP(hipMemsetAsync(w + L.words, 0, 256, s));
+// Device bytes of the streamed factorization: the in-memory workspace, then
+// nres resident tiles, then the staging slots (none when every tile is resident).
+static size_t tile_bytes(int64_t lda, int64_t wt, size_t es) { return up256((size_t)lda * wt * es); }
+
+extern "C" {
+
+int ct_qr_factor(void* A, int64_t m, int64_t n, int64_t lda, int prec, double* tau, void* work, size_t work_bytes,
+                 int64_t max_nrhs, ct_factor** f_out, void* stream)
+{
+    CT_ARG(A != nullptr && aligned(A), 1, "A");
+    CT_ARG(m > 0, 2, "m");
+    CT_ARG(n > 0 && n <= m, 3, "n (need 0 < n <= m)");
+    CT_ARG(lda >= m && lda % 16 == 0, 4, "lda");
+    CT_ARG(prec >= CT_PREC_F64 && prec <= CT_PREC_BF16X3, 5, "prec");
+    CT_ARG(tau != nullptr, 6, "tau");
+    CT_ARG(work != nullptr && aligned(work), 7, "work");
+    CT_ARG(max_nrhs >= 0, 9, "max_nrhs");
+    CT_ARG(f_out != nullptr, 10, "f");
+    const Layout L = layout(m, n, prec, max_nrhs);
+    CT_ARG(work_bytes >= L.total, 8, "work_bytes (see ct_qr_workspace)");
+    int r = device_setup();
+    if (r) return r;
+    hipStream_t s = (hipStream_t)stream;
+
+    ct_factor* f = new (std::nothrow) ct_factor();
+    if (!f) return fail(-1001, "%s", "out of host memory");
+    r = init_factor(f, A, m, n, lda, prec, tau, (char*)work, L, max_nrhs);
+    if (r) {
+        delete f;
+        return r;
+    }
+    CT_HIP(hipMemsetAsync((char*)work + L.words, 0, 256, s));
     int rc = f->f64 ? factor_impl<double>(f, s) : factor_impl<float>(f, s);
     if (rc) {
         delete f;
@@ -649,6 +986,144 @@ int ct_qr_factor(void* A, int64_t m, int64_t n, int64_t lda, int prec, double* t
     return 0;
 }
 
+int ct_qr_stream_workspace(int64_t m, int64_t n, int64_t lda, int prec, int64_t max_nrhs, int64_t tile_cols,
+                           size_t* min_bytes, size_t* all_resident_bytes)
+{
+    CT_ARG(m > 0, 1, "m");
+    CT_ARG(n > 0 && n <= m, 2, "n (need 0 < n <= m)");
+    CT_ARG(lda >= m && lda % 16 == 0, 3, "lda");
+    CT_ARG(prec >= CT_PREC_F64 && prec <= CT_PREC_BF16X3, 4, "prec");
+    CT_ARG(max_nrhs >= 0, 5, "max_nrhs");
+    CT_ARG(tile_cols > 0 && tile_cols % nb_out_for(prec) == 0, 6, "tile_cols (a positive multiple of 128)");
+    CT_ARG(min_bytes != nullptr, 7, "min_bytes");
+    const size_t es = prec == CT_PREC_F64 ? 8 : 4;
+    const int64_t nt = (n + tile_cols - 1) / tile_cols;
+    const size_t base = layout(m, n, prec, max_nrhs).total, tb = tile_bytes(lda, tile_cols, es);
+    *min_bytes = base + std::min<int64_t>(nt, kSlots) * tb;
+    if (all_resident_bytes) *all_resident_bytes = base + nt * tb;
+    return 0;
+}
+
+int ct_qr_factor_streamed(void* A_host, int64_t m, int64_t n, int64_t lda, int prec, double* tau, void* work,
+                          size_t work_bytes, int64_t max_nrhs, int64_t tile_cols, ct_factor** f_out, void* stream)
+{
+    CT_ARG(A_host != nullptr, 1, "A_host");
+    CT_ARG(m > 0, 2, "m");
+    CT_ARG(n > 0 && n <= m, 3, "n (need 0 < n <= m)");
+    CT_ARG(lda >= m && lda % 16 == 0, 4, "lda");
+    CT_ARG(prec >= CT_PREC_F64 && prec <= CT_PREC_BF16X3, 5, "prec");
+    CT_ARG(tau != nullptr, 6, "tau");
+    CT_ARG(work != nullptr && aligned(work), 7, "work");
+    CT_ARG(max_nrhs >= 0, 9, "max_nrhs");
+    CT_ARG(tile_cols > 0 && tile_cols % nb_out_for(prec) == 0, 10, "tile_cols (a positive multiple of 128)");
+    CT_ARG(f_out != nullptr, 11, "f");
+    size_t need = 0, full = 0;
+    ct_qr_stream_workspace(m, n, lda, prec, max_nrhs, tile_cols, &need, &full);
+    CT_ARG(work_bytes >= need, 8, "work_bytes (see ct_qr_stream_workspace)");
+    int r = device_setup();
+    if (r) return r;
+    {
+        hipPointerAttribute_t at;
+        const hipError_t e = hipPointerGetAttributes(&at, A_host);
+        if (e != hipSuccess || at.type != hipMemoryTypeHost) {
+            (void)hipGetLastError();
+            return fail(-1, "%s", "invalid argument A_host (must be pinned host memory from hipHostMalloc)");
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const Layout L = layout(m, n, prec, max_nrhs);
+    const size_t es = prec == CT_PREC_F64 ? 8 : 4;
+    const size_t tb = tile_bytes(lda, tile_cols, es);
+    const int64_t nt = (n + tile_cols - 1) / tile_cols;
+    char* w = (char*)work;
+
+    ct_factor* f = new (std::nothrow) ct_factor();
+    StreamState* st = f ? new (std::nothrow) StreamState() : nullptr;
+    if (!st) {
+        delete f;
+        return fail(-1001, "%s", "out of host memory");
+    }
+    f->st = st;
+    st->Ah = (char*)A_host;
+    st->es = es;
+    st->wt = tile_cols;
+    st->ntiles = nt;
+    if (work_bytes >= full) {
+        st->nres = nt;
+    } else {
+        st->nres = (int64_t)((work_bytes - L.total - kSlots * tb) / tb);
+        for (int k = 0; k < kSlots; ++k) st->slot[k] = w + L.total + (size_t)st->nres * tb + (size_t)k * tb;
+    }
+    r = init_factor(f, w + L.total, m, n, lda, prec, tau, w, L, max_nrhs);
+    if (r) {
+        delete st;
+        delete f;
+        return r;
+    }
+    auto cleanup = [&](int code) {
+        delete st;
+        f->st = nullptr;
+        delete f;
+        return code;
+    };
+    hipError_t e = hipStreamCreateWithFlags(&st->cin, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&st->cout, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&st->done, hipEventDisableTiming);
+    for (int k = 0; k < kSlots && e == hipSuccess; ++k) {
+        e = hipEventCreateWithFlags(&st->ready[k], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&st->used[k], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&st->out[k], hipEventDisableTiming);
+    }
+    st->res_ready.assign(st->nres, nullptr);
+    st->res_loaded.assign(st->nres, 0);
+    st->d2h.assign(nt, nullptr);
+    st->d2h_rec.assign(nt, 0);
+    for (int64_t t = 0; t < st->nres && e == hipSuccess; ++t)
+        e = hipEventCreateWithFlags(&st->res_ready[t], hipEventDisableTiming);
+    for (int64_t t = 0; t < nt && e == hipSuccess; ++t)
+        e = hipEventCreateWithFlags(&st->d2h[t], hipEventDisableTiming);
+    if (e != hipSuccess) {
+        snprintf(g_err, sizeof g_err, "stream set-up: %s", hipGetErrorString(e));
+        return cleanup(-1000 - (int)e);
+    }
+    e = hipMemsetAsync(w + L.words, 0, 256, s);
+    if (e != hipSuccess) {
+        snprintf(g_err, sizeof g_err, "hipMemsetAsync: %s", hipGetErrorString(e));
+        return cleanup(-1000 - (int)e);
+    }
+    const int rc = f->f64 ? stream_factor<double>(f, s) : stream_factor<float>(f, s);
+    if (rc == -2002) {
+        *f_out = f;     // resumable
+        return rc;
+    }
+    if (rc) return cleanup(rc);
+    *f_out = f;
+    return 0;
+}
+
+int ct_qr_resume(ct_factor* f, void* stream)
+{
+    CT_ARG(f != nullptr && f->st != nullptr, 1, "f (a streamed factor)");
+    if (f->st->next_tile >= f->st->ntiles) return 0;
+    hipStream_t s = (hipStream_t)stream;
+    return f->f64 ? stream_factor<double>(f, s) : stream_factor<float>(f, s);
+}
+
+int ct_stream_info(const ct_factor* f, int64_t* tiles, int64_t* resident, int64_t* next_tile)
+{
+    CT_ARG(f != nullptr, 1, "f");
+    const StreamState* st = f->st;
+    if (tiles) *tiles = st ? st->ntiles : 0;
+    if (resident) *resident = st ? st->nres : 0;
+    if (next_tile) *next_tile = st ? st->next_tile : 0;
+    return 0;
+}
+
+int ct_stream_inject_failure(int64_t tile)
+{
+    g_inject_fail_tile = tile;
+    return 0;
+}
 
 int ct_apply_qt(const ct_factor* f, void* B, int64_t nrhs, int64_t ldb, void* stream)
 {
@@ -769,8 +1244,187 @@ int ct_status(const ct_factor* f, int64_t* info, void* stream)
 
 int ct_factor_destroy(ct_factor* f)
 {
+    if (f) delete f->st;
     delete f;
     return 0;
+}
+
+// ------------------------------------------------------------- graph solves
+struct ct_solve_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+int ct_solve_graph_create(const ct_factor* f, void* B, int64_t ldb, int64_t max_cols, int32_t* desc, void* stream,
+                          ct_solve_graph** out)
+{
+    CT_ARG(f != nullptr, 1, "f");
+    CT_ARG(B != nullptr && aligned(B), 2, "B");
+    CT_ARG(ldb >= f->m && ldb % 16 == 0, 3, "ldb");
+    CT_ARG(max_cols > 0 && max_cols <= f->max_nrhs, 4, "max_cols (1..max_nrhs)");
+    CT_ARG(desc != nullptr, 5, "desc");
+    CT_ARG(stream != nullptr, 6, "stream (capture needs a created stream)");
+    CT_ARG(out != nullptr, 7, "g");
+    CT_ARG(f->st == nullptr, 1, "f (graph-captured solves need a factor held in device memory)");
+    hipStream_t s = (hipStream_t)stream;
+    ct_solve_graph* g = new (std::nothrow) ct_solve_graph();
+    if (!g) return fail(-1001, "%s", "out of host memory");
+    CT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    int r = f->f64 ? apply_qt_impl<double>(f, (double*)B, max_cols, ldb, s, true, desc)
+                   : apply_qt_impl<float>(f, (float*)B, max_cols, ldb, s, true, desc);
+    if (!r)
+        r = f->f64 ? trsm_impl<double>(f, (double*)B, max_cols, ldb, s, desc)
+                   : trsm_impl<float>(f, (float*)B, max_cols, ldb, s, desc);
+    if (!r) {
+        hipError_t e = launch_advance_batch(desc, s);
+        if (e != hipSuccess) r = -1000 - (int)e;
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t ee = hipStreamEndCapture(s, &graph);
+    if (r || ee != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        delete g;
+        if (r) return r;
+        CT_HIP(ee);
+    }
+    g->graph = graph;
+    hipError_t ie = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        delete g;
+        CT_HIP(ie);
+    }
+    *out = g;
+    return 0;
+}
+
+int ct_solve_graph_launch(ct_solve_graph* g, void* stream)
+{
+    CT_ARG(g != nullptr, 1, "g");
+    CT_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return 0;
+}
+
+int ct_solve_graph_destroy(ct_solve_graph* g)
+{
+    if (!g) return 0;
+    (void)hipGraphExecDestroy(g->exec);
+    (void)hipGraphDestroy(g->graph);
+    delete g;
+    return 0;
+}
+
+// --------------------------------------------------------------- autotuner
+
+static std::string tune_key(const ct_factor* f, int bucket)
+{
+    char buf[160];
+    snprintf(buf, sizeof buf, "gfx950/%s/%lld/%lld/%d", f->f64 ? "f64" : "f32", (long long)f->m, (long long)f->n,
+             bucket);
+    return buf;
+}
+
+// the cache is a flat JSON object {"key": [bq, split_target], ...}
+static std::map<std::string, NtPlan> read_cache(const char* path)
+{
+    std::map<std::string, NtPlan> out;
+    FILE* fp = path ? fopen(path, "r") : nullptr;
+    if (!fp) return out;
+    std::string text;
+    char buf[4096];
+    size_t k;
+    while ((k = fread(buf, 1, sizeof buf, fp)) > 0) text.append(buf, k);
+    fclose(fp);
+    size_t pos = 0;
+    while ((pos = text.find('"', pos)) != std::string::npos) {
+        const size_t end = text.find('"', pos + 1);
+        if (end == std::string::npos) break;
+        const std::string key = text.substr(pos + 1, end - pos - 1);
+        int bq = 0, sp = 0;
+        if (sscanf(text.c_str() + end + 1, " : [ %d , %d ]", &bq, &sp) == 2 &&
+            (bq == 16 || bq == 32 || bq == 64 || bq == 128) && sp > 0)
+            out[key] = NtPlan{bq, sp};
+        pos = end + 1;
+    }
+    return out;
+}
+
+static void write_cache(const char* path, const std::map<std::string, NtPlan>& m)
+{
+    if (!path) return;
+    FILE* fp = fopen(path, "w");
+    if (!fp) return;
+    fprintf(fp, "{\n");
+    size_t i = 0;
+    for (auto& kv : m)
+        fprintf(fp, "  \"%s\": [%d, %d]%s\n", kv.first.c_str(), kv.second.bq, kv.second.split_target,
+                ++i < m.size() ? "," : "");
+    fprintf(fp, "}\n");
+    fclose(fp);
+}
+
+int ct_autotune_solve(ct_factor* f, void* B, int64_t ldb, int64_t max_nrhs, const char* cache_path, void* stream)
+{
+    CT_ARG(f != nullptr, 1, "f");
+    CT_ARG(B != nullptr && aligned(B), 2, "B");
+    CT_ARG(ldb >= f->m && ldb % 16 == 0, 3, "ldb");
+    CT_ARG(max_nrhs > 0 && max_nrhs <= f->max_nrhs, 4, "max_nrhs (1..factor max_nrhs)");
+    hipStream_t s = (hipStream_t)stream;
+    std::map<std::string, NtPlan> cache = read_cache(cache_path);
+    static const int sizes[4] = {8, 32, 128, 512};
+    static const int splits[3] = {512, 1024, 2048};
+    hipEvent_t e0, e1;
+    CT_HIP(hipEventCreate(&e0));
+    CT_HIP(hipEventCreate(&e1));
+    int rc = 0;
+    for (int b = 0; b < 4 && !rc; ++b) {
+        const int64_t cols = std::min<int64_t>(sizes[b], max_nrhs);
+        if (b > 0 && sizes[b - 1] >= max_nrhs) break;
+        const std::string key = tune_key(f, b);
+        auto hit = cache.find(key);
+        if (hit != cache.end()) {
+            f->solve_plan[b] = hit->second;
+            continue;
+        }
+        float best = 1e30f;
+        NtPlan best_plan = f->solve_plan[b];
+        for (int bq : {16, 32, 64, 128}) {
+            if (bq > 2 * cols && bq > 16) continue;
+            for (int sp : splits) {
+                f->solve_plan[b] = NtPlan{bq, sp};
+                float tmin = 1e30f;
+                for (int rep = 0; rep < 3 && !rc; ++rep) {
+                    hipError_t e = hipEventRecord(e0, s);
+                    if (e == hipSuccess) {
+                        rc = f->f64 ? apply_qt_impl<double>(f, (double*)B, cols, ldb, s, true)
+                                    : apply_qt_impl<float>(f, (float*)B, cols, ldb, s, true);
+                        if (!rc)
+                            rc = f->f64 ? trsm_impl<double>(f, (double*)B, cols, ldb, s)
+                                        : trsm_impl<float>(f, (float*)B, cols, ldb, s);
+                        e = hipEventRecord(e1, s);
+                    }
+                    if (e == hipSuccess) e = hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                    if (e != hipSuccess) rc = -1000 - (int)e;
+                    if (rep > 0 && ms < tmin) tmin = ms;   // first run warms up
+                }
+                if (!rc && tmin < best) {
+                    best = tmin;
+                    best_plan = f->solve_plan[b];
+                }
+            }
+        }
+        f->solve_plan[b] = best_plan;
+        cache[key] = best_plan;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!rc) {
+        for (int b = 4; b < 5; ++b) f->solve_plan[b] = f->solve_plan[3];
+        write_cache(cache_path, cache);
+    }
+    return rc;
 }
 
 int ct_profile_begin(void)

@@ -49,6 +49,24 @@ struct GeomDev {
     double W, sid, sdd, det_length, angle0;
 };
 
+// Launch plan of the LDS-tiled NT update kernel: tile width along the
+// right-hand-side / trailing-column dimension (16, 32, 64 or 128) and the
+// workgroup count the split-K heuristic aims for.
+struct NtPlan {
+    int bq;
+    int split_target;
+};
+
+// Batch descriptor of a graph-captured solve: desc[0] = index of the current
+// batch, desc[2 + 2k], desc[3 + 2k] = column offset and count of batch k.
+__device__ __forceinline__ int desc_count(const int32_t* desc, int n)
+{
+    if (!desc) return n;
+    const int c = desc[3 + 2 * desc[0]];
+    return c < n ? c : n;
+}
+__device__ __forceinline__ int desc_offset(const int32_t* desc) { return desc ? desc[2 + 2 * desc[0]] : 0; }
+
 struct ErrWord {
     // bit 0: barrier spin limit hit; bit 1: CSR capacity exceeded; bit 2: invalid batch descriptor
     int32_t flags;

@@ -208,6 +208,7 @@ struct NnArgs {
     int64_t ldc;
     int64_t M;
     int N, K;
+    const int32_t* desc;   // batch descriptor: columns of Bhi and C start at its offset
 };
 
 template <int MODE, typename TA, typename TB, typename TC, bool MASKA, int MB, int NB, int WM, int WN>
@@ -218,14 +219,16 @@ __global__ void __launch_bounds__(256) gemm_nn_sub_kernel(NnArgs args)
     typedef typename Tr::Acc Acc;
     constexpr int KS = Tr::KS, KC = 4 * KS;
     const TA* __restrict__ A = (const TA*)args.A;
-    const TB* __restrict__ Bh = (const TB*)args.Bhi;
-    TC* __restrict__ C = (TC*)args.C;
+    const int doff = desc_offset(args.desc);
+    const int Ne = desc_count(args.desc, args.N);
+    const TB* __restrict__ Bh = (const TB*)args.Bhi + (int64_t)doff * args.ldb;
+    TC* __restrict__ C = (TC*)args.C + (int64_t)doff * args.ldc;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int c = lane & 15, g = lane >> 4;
     const int wm = wv / WN, wn = wv % WN;
     const int64_t r0 = ((int64_t)blockIdx.x * WM + wm) * 16 * MB;
     const int j0 = (blockIdx.y * WN + wn) * 16 * NB;
-    if (r0 >= args.M || j0 >= args.N) return;
+    if (r0 >= args.M || j0 >= Ne) return;
 
     Acc acc[MB][NB];
 #pragma unroll
@@ -254,7 +257,7 @@ __global__ void __launch_bounds__(256) gemm_nn_sub_kernel(NnArgs args)
 #pragma unroll
         for (int bj = 0; bj < NB; ++bj) {
             const int j = j0 + 16 * bj + c;
-            if (j < args.N) {
+            if (j < Ne) {
                 load_run<E, TB, KS>(Bh + kl + (int64_t)j * args.ldb, valid, b[bj]);
             } else {
 #pragma unroll
@@ -271,7 +274,7 @@ __global__ void __launch_bounds__(256) gemm_nn_sub_kernel(NnArgs args)
 #pragma unroll
         for (int bj = 0; bj < NB; ++bj) {
             const int j = j0 + 16 * bj + c;
-            if (j >= args.N) continue;
+            if (j >= Ne) continue;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int64_t r = r0 + 16 * bi + d_row(MODE, g, q);
@@ -294,10 +297,12 @@ __global__ void __launch_bounds__(256) gemm_nn_sub_kernel(NnArgs args)
 template <typename TWp, typename TO, int OP, bool SPLIT>
 __global__ void __launch_bounds__(256) tw_kernel(const TWp* __restrict__ Wp, int64_t wstride, int nz, int nbv, int N,
                                                  const double* __restrict__ T, int64_t ldt, TO* out, TO* out_lo,
-                                                 int64_t ldo)
+                                                 int64_t ldo, const int32_t* desc)
 {
     extern __shared__ double sw[];   // nbv x 16
+    N = desc_count(desc, N);
     const int j0 = blockIdx.x * 16;
+    if (j0 >= N) return;
     const int t = threadIdx.x;
     const int ncol = N - j0 < 16 ? N - j0 : 16;
     for (int e = t; e < nbv * 16; e += 256) {
@@ -382,11 +387,14 @@ __global__ void __launch_bounds__(512) t_from_gram_kernel(const double* __restri
         }
 }
 
-// S[e] = sum_z W[z][e] over `count` contiguous elements (fixed order in z).
+// S[e] = sum_z W[z][e] over `count` contiguous elements (fixed order in z);
+// with a descriptor, count = per_col * (batch column count).
 template <typename TWp, typename TS>
 __global__ void __launch_bounds__(256) sum_slices_kernel(const TWp* __restrict__ Wp, int64_t wstride, int nz,
-                                                         int64_t count, TS* __restrict__ S)
+                                                         int64_t count, TS* __restrict__ S, const int32_t* desc,
+                                                         int per_col)
 {
+    if (desc) count = (int64_t)per_col * desc_count(desc, (int)(count / per_col));
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256) {
         double s = 0.0;
         for (int z = 0; z < nz; ++z) s += (double)Wp[(int64_t)z * wstride + e];
@@ -446,10 +454,11 @@ hipError_t launch_tn(const TA* A, int64_t lda, const TB* B, int64_t ldb, TW* W, 
 
 template <int MODE, typename TA, typename TB, typename TC, bool MA>
 hipError_t launch_nn_sub(const TA* A, int64_t lda, const TB* Bhi, const TB* Blo, int64_t ldb, TC* C, int64_t ldc,
-                         int64_t M, int N, int K, hipStream_t s)
+                         int64_t M, int N, int K, hipStream_t s, const int32_t* desc)
 {
     NnArgs a;
     a.A = A; a.lda = lda; a.Bhi = Bhi; a.Blo = Blo; a.ldb = ldb; a.C = C; a.ldc = ldc; a.M = M; a.N = N; a.K = K;
+    a.desc = desc;
     if (N <= 64) {
         dim3 grid(cdiv(M, 16 * 4 * 4), cdiv(N, 64), 1);
         hipLaunchKernelGGL((gemm_nn_sub_kernel<MODE, TA, TB, TC, MA, 4, 4, 4, 1>), grid, dim3(256), 0, s, a);
@@ -462,11 +471,11 @@ hipError_t launch_nn_sub(const TA* A, int64_t lda, const TB* Bhi, const TB* Blo,
 
 template <typename TWp, typename TO, int OP, bool SPLIT>
 hipError_t launch_tw(const TWp* Wp, int nz, int nbv, int N, const double* T, int64_t ldt, TO* out, TO* out_lo,
-                     int64_t ldo, hipStream_t s)
+                     int64_t ldo, hipStream_t s, const int32_t* desc)
 {
     const size_t sh = (size_t)nbv * 16 * sizeof(double);
     hipLaunchKernelGGL((tw_kernel<TWp, TO, OP, SPLIT>), dim3(cdiv(N, 16)), dim3(256), sh, s, Wp, (int64_t)nbv * N,
-                       nz, nbv, N, T, ldt, out, out_lo, ldo);
+                       nz, nbv, N, T, ldt, out, out_lo, ldo, desc);
     return hipGetLastError();
 }
 
@@ -485,17 +494,21 @@ hipError_t t_from_gram_set_max_lds(size_t bytes)
 }
 
 template <typename TWp, typename TS>
-hipError_t launch_sum_slices(const TWp* Wp, int64_t wstride, int nz, int64_t count, TS* S, hipStream_t s)
+hipError_t launch_sum_slices(const TWp* Wp, int64_t wstride, int nz, int64_t count, TS* S, hipStream_t s,
+                             const int32_t* desc, int per_col)
 {
     int64_t blocks = (count + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL((sum_slices_kernel<TWp, TS>), dim3((unsigned)blocks), dim3(256), 0, s, Wp, wstride, nz, count,
-                       S);
+                       S, desc, per_col > 0 ? per_col : 1);
     return hipGetLastError();
 }
-template hipError_t launch_sum_slices<float, float>(const float*, int64_t, int, int64_t, float*, hipStream_t);
-template hipError_t launch_sum_slices<double, double>(const double*, int64_t, int, int64_t, double*, hipStream_t);
-template hipError_t launch_sum_slices<float, double>(const float*, int64_t, int, int64_t, double*, hipStream_t);
+template hipError_t launch_sum_slices<float, float>(const float*, int64_t, int, int64_t, float*, hipStream_t,
+                                                    const int32_t*, int);
+template hipError_t launch_sum_slices<double, double>(const double*, int64_t, int, int64_t, double*, hipStream_t,
+                                                      const int32_t*, int);
+template hipError_t launch_sum_slices<float, double>(const float*, int64_t, int, int64_t, double*, hipStream_t,
+                                                     const int32_t*, int);
 
 // ---------------------------------------------------------- instantiations
 #define CT_TN(MODE, TA, TB, TW, MA, MB)                                                                       \
@@ -513,7 +526,8 @@ CT_TN(M_BF16X3, float, float, float, true, false)
 
 #define CT_NN(MODE, TA, TB, TC, MA)                                                                            \
     template hipError_t launch_nn_sub<MODE, TA, TB, TC, MA>(const TA*, int64_t, const TB*, const TB*, int64_t, \
-                                                           TC*, int64_t, int64_t, int, int, hipStream_t);
+                                                           TC*, int64_t, int64_t, int, int, hipStream_t,       \
+                                                           const int32_t*);
 CT_NN(M_F64, double, double, double, true)
 CT_NN(M_F64, double, double, double, false)
 CT_NN(M_F32, float, float, float, true)
@@ -524,7 +538,7 @@ CT_NN(M_BF16X3, float, float, float, true)
 
 #define CT_TW(TWp, TO, OP, SPLIT)                                                                          \
     template hipError_t launch_tw<TWp, TO, OP, SPLIT>(const TWp*, int, int, int, const double*, int64_t, TO*, \
-                                                      TO*, int64_t, hipStream_t);
+                                                      TO*, int64_t, hipStream_t, const int32_t*);
 CT_TW(double, double, 0, false)
 CT_TW(double, double, 1, false)
 CT_TW(double, double, 2, false)

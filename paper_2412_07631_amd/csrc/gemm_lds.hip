@@ -38,7 +38,23 @@ struct NtArgs {
     int64_t K, kslice;
     int tiles_p, tiles_q;
     int sub;         // 0: out = acc (split slice z at out + z*ostride), 1: out -= acc
+    // optional device batch descriptor (desc[0] = current batch k; batch k
+    // has column offset desc[2+2k] and count desc[3+2k]): Q is clipped to the
+    // count, and Y (desc_y) or out (desc_out) start at the offset
+    const int32_t* desc;
+    int desc_y, desc_out;
 };
+
+__device__ __forceinline__ void apply_desc(const NtArgs& a, int& Q, const char*& Y, size_t ysz, char*& out, size_t osz)
+{
+    if (a.desc) {
+        const int cur = a.desc[0];
+        const int off = a.desc[2 + 2 * cur], cnt = a.desc[3 + 2 * cur];
+        if (cnt < Q) Q = cnt;
+        if (a.desc_y) Y += (size_t)off * a.ldy * ysz;
+        if (a.desc_out) out += (size_t)off * a.ldo * osz;
+    }
+}
 
 template <typename T>
 __device__ __forceinline__ void mfma_nt(typename LdsTraits<T>::Acc& acc, const T (&a)[4], const T (&b)[4])
@@ -59,7 +75,7 @@ template <> struct V16<double> { typedef double t __attribute__((ext_vector_type
 
 // SUB = false: partial products out[z] = X Y^T over K slice z (W = V^T C);
 // SUB = true: out -= X Y^T (the rank-nb update C -= V W').
-template <typename T, bool SUB>
+template <typename T, bool SUB, int BQ = kBQ>
 __global__ void __launch_bounds__(256, 2) gemm_nt_kernel(NtArgs a)
 {
     typedef LdsTraits<T> L;
@@ -68,11 +84,15 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_kernel(NtArgs a)
     constexpr int VPR = BK / VN;                   // vectors per tile row
     constexpr int ROWS_PER_PASS = 256 / VPR;       // tile rows loaded per pass of 256 threads
     constexpr int PASSES = kBP / ROWS_PER_PASS;
+    constexpr int YPASSES = (BQ + ROWS_PER_PASS - 1) / ROWS_PER_PASS;
+    // waves: 2 x 2 of 64 x 64 for the 128-wide tile, else 4 x 1 of 32 x BQ
+    constexpr int WM = BQ == 128 ? 2 : 4, WN = 4 / WM;
+    constexpr int MI = kBP / (16 * WM), NJ = BQ / (16 * WN);
     typedef typename V16<T>::t vec_t;
     typedef typename L::Acc Acc;
 
     __shared__ T Xs[2][kBP * LDK];
-    __shared__ T Ys[2][kBQ * LDK];
+    __shared__ T Ys[2][BQ * LDK];
 
     // XCD-aware tile order: hardware places block b on XCD b % 8
     const int nt = a.tiles_p * a.tiles_q;
@@ -83,38 +103,52 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_kernel(NtArgs a)
     if (tile >= nt) return;
     const int tp = tile % a.tiles_p, tq = tile / a.tiles_p;
     const int64_t p0 = (int64_t)tp * kBP;
-    const int q0 = tq * kBQ;
+    const int q0 = tq * BQ;
     const int64_t kbeg = (int64_t)blockIdx.y * a.kslice;
     int64_t kend = kbeg + a.kslice;
     if (kend > a.K) kend = a.K;
 
+    int Qe = a.Q;
+    const char* Yc = (const char*)a.Y;
+    char* Oc = (char*)a.out;
+    apply_desc(a, Qe, Yc, sizeof(T), Oc, sizeof(T));
+    if (q0 >= Qe) return;
     const T* __restrict__ X = (const T*)a.X;
-    const T* __restrict__ Y = (const T*)a.Y;
+    const T* __restrict__ Y = (const T*)Yc;
     const int t = threadIdx.x;
     const int lr = t / VPR, lv = t % VPR;          // loader: row within pass, vector within row
 
-    vec_t xr[PASSES], yr[PASSES];
+    vec_t xr[PASSES], yr[YPASSES];
     auto gload = [&](int64_t k0) {
+        const int64_t kk = k0 + lv * VN;
 #pragma unroll
         for (int ps = 0; ps < PASSES; ++ps) {
             const int row = ps * ROWS_PER_PASS + lr;
-            const int64_t kk = k0 + lv * VN;
             const int64_t pr = p0 + row;
-            const int qr = q0 + row;
-            vec_t vx = {}, vy = {};
+            vec_t vx = {};
             if (kk + VN <= kend) {
                 if (pr < a.P) vx = *(const vec_t*)(X + pr * a.ldx + kk);
-                if (qr < a.Q) vy = *(const vec_t*)(Y + (int64_t)qr * a.ldy + kk);
             } else {
 #pragma unroll
-                for (int e = 0; e < VN; ++e) {
-                    if (kk + e < kend) {
-                        if (pr < a.P) vx[e] = X[pr * a.ldx + kk + e];
-                        if (qr < a.Q) vy[e] = Y[(int64_t)qr * a.ldy + kk + e];
-                    }
-                }
+                for (int e = 0; e < VN; ++e)
+                    if (kk + e < kend && pr < a.P) vx[e] = X[pr * a.ldx + kk + e];
             }
             xr[ps] = vx;
+        }
+#pragma unroll
+        for (int ps = 0; ps < YPASSES; ++ps) {
+            const int row = ps * ROWS_PER_PASS + lr;
+            const int qr = q0 + row;
+            vec_t vy = {};
+            if (row < BQ) {
+                if (kk + VN <= kend) {
+                    if (qr < Qe) vy = *(const vec_t*)(Y + (int64_t)qr * a.ldy + kk);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VN; ++e)
+                        if (kk + e < kend && qr < Qe) vy[e] = Y[(int64_t)qr * a.ldy + kk + e];
+                }
+            }
             yr[ps] = vy;
         }
     };
@@ -123,90 +157,100 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_kernel(NtArgs a)
         for (int ps = 0; ps < PASSES; ++ps) {
             const int row = ps * ROWS_PER_PASS + lr;
             *(vec_t*)&Xs[buf][row * LDK + lv * VN] = xr[ps];
-            *(vec_t*)&Ys[buf][row * LDK + lv * VN] = yr[ps];
+        }
+#pragma unroll
+        for (int ps = 0; ps < YPASSES; ++ps) {
+            const int row = ps * ROWS_PER_PASS + lr;
+            if (row < BQ) *(vec_t*)&Ys[buf][row * LDK + lv * VN] = yr[ps];
         }
     };
 
     const int lane = t & 63, wv = t >> 6;
     const int c = lane & 15, g = lane >> 4;
-    const int wp = (wv >> 1) * 64, wq = (wv & 1) * 64;
+    const int wp = (wv / WN) * (16 * MI), wq = (wv % WN) * (16 * NJ);
 
-    Acc acc[4][4];
+    Acc acc[MI][NJ];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = Acc{0, 0, 0, 0};
+        for (int j = 0; j < NJ; ++j) acc[i][j] = Acc{0, 0, 0, 0};
 
-    // prefetch of the output tile for the subtracting epilogue (FP32 only: the
-    // FP64 accumulators leave no registers for it at two workgroups per CU)
     constexpr bool F64 = sizeof(T) == 8;
-    constexpr bool PRE = !F64;
-    T cpre[4][4][PRE ? 4 : 1];
-    if (PRE && SUB) {
-        T* O = (T*)a.out;
+    auto compute = [&](int buf) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int kk = 0; kk < BK; kk += 16) {
+            T bf[NJ][4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < NJ; ++j) {
+                const T* src = &Ys[buf][(wq + 16 * j + c) * LDK + kk + 4 * g];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) bf[j][s] = src[s];
+            }
+#pragma unroll
+            for (int i = 0; i < MI; ++i) {
+                T af[4];
+                const T* src = &Xs[buf][(wp + 16 * i + c) * LDK + kk + 4 * g];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) af[s] = src[s];
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) mfma_nt<T>(acc[i][j], af, bf[j]);
+            }
+        }
+    };
+    // the subtracting epilogue's C tile is fetched during the last K step,
+    // when the prefetch registers are free, so its latency hides behind it
+    // (FP32 only: the FP64 accumulators already fill the register file)
+    constexpr bool PRE = SUB && !F64;
+    T cpre[MI][NJ][PRE ? 4 : 1];
+    auto load_c = [&]() {
+        if constexpr (!PRE) return;
+        const T* O = (const T*)Oc;
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
                 const int q = q0 + wq + 16 * j + c;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int64_t p = p0 + wp + 16 * i + (F64 ? g + 4 * r : 4 * g + r);
-                    if constexpr (PRE) cpre[i][j][r] = (p < a.P && q < a.Q) ? O[p + (int64_t)q * a.ldo] : (T)0;
+                    if constexpr (PRE) cpre[i][j][r] = (p < a.P && q < Qe) ? O[p + (int64_t)q * a.ldo] : (T)0;
                 }
             }
-    }
+    };
 
     if (kbeg < kend) {
         gload(kbeg);
         sstore(0);
         __syncthreads();
         int buf = 0;
-        for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
-            const bool more = k0 + BK < kend;
-            if (more) gload(k0 + BK);
-#pragma unroll
-            for (int kk = 0; kk < BK; kk += 16) {
-                T af[4][4], bf[4][4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const T* src = &Xs[buf][(wp + 16 * i + c) * LDK + kk + 4 * g];
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) af[i][s] = src[s];
-                }
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const T* src = &Ys[buf][(wq + 16 * j + c) * LDK + kk + 4 * g];
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) bf[j][s] = src[s];
-                }
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) mfma_nt<T>(acc[i][j], af[i], bf[j]);
-            }
-            if (more) {
-                sstore(buf ^ 1);
-                __syncthreads();
-                buf ^= 1;
-            }
+        int64_t k0 = kbeg;
+        for (; k0 + BK < kend; k0 += BK) {
+            gload(k0 + BK);
+            compute(buf);
+            sstore(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
         }
+        if constexpr (SUB) load_c();
+        compute(buf);
+    } else if constexpr (SUB) {
+        load_c();
     }
 
-    T* O = (T*)a.out;
+    T* O = (T*)Oc;
     if (!SUB) O += (int64_t)blockIdx.y * a.ostride;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < NJ; ++j) {
             const int q = q0 + wq + 16 * j + c;
-            if (q >= a.Q) continue;
+            if (q >= Qe) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t p = p0 + wp + 16 * i + (F64 ? g + 4 * r : 4 * g + r);
                 if (p < a.P) {
                     T* d = O + p + (int64_t)q * a.ldo;
-                    if constexpr (PRE) *d = SUB ? cpre[i][j][r] - (T)acc[i][j][r] : (T)acc[i][j][r];
+                    if constexpr (PRE) *d = cpre[i][j][r] - (T)acc[i][j][r];
                     else *d = SUB ? *d - (T)acc[i][j][r] : (T)acc[i][j][r];
                 }
             }
@@ -258,21 +302,29 @@ hipError_t launch_prep_v(const T* V, int64_t ldv, int64_t mk, int nb, T* Vm, int
 }
 
 // out (P x Q) = X Y^T summed over K, split into slices; returns the slice count.
+// Tile-width and split-K choices of the NT launches (set by the autotuner;
+// the defaults suit the wide trailing updates).
+NtPlan g_nt_default = {128, 1024};
+
 template <typename T>
 hipError_t launch_nt(const T* X, int64_t ldx, const T* Y, int64_t ldy, T* out, int64_t ldo, int64_t P, int Q,
-                     int64_t K, bool sub, int64_t ocap, int* nz_out, hipStream_t s)
+                     int64_t K, bool sub, int64_t ocap, int* nz_out, hipStream_t s, const NtPlan* plan,
+                     const int32_t* desc, int desc_y, int desc_out)
 {
     constexpr int BK = LdsTraits<T>::BK;
+    const NtPlan pl = plan ? *plan : g_nt_default;
+    const int bq = pl.bq;
     NtArgs a;
     a.X = X; a.ldx = ldx; a.Y = Y; a.ldy = ldy; a.out = out; a.ldo = ldo;
     a.P = P; a.Q = Q; a.K = K; a.sub = sub ? 1 : 0;
+    a.desc = desc; a.desc_y = desc_y; a.desc_out = desc_out;
     a.tiles_p = (int)((P + kBP - 1) / kBP);
-    a.tiles_q = (Q + kBQ - 1) / kBQ;
+    a.tiles_q = (Q + bq - 1) / bq;
     a.ostride = ldo * (int64_t)Q;
     const int tiles = a.tiles_p * a.tiles_q;
     int nz = 1;
     if (!sub) {
-        while (tiles * nz * 2 <= 1024 && K / (nz * 2) >= 8 * BK && nz < 256) nz *= 2;
+        while (tiles * nz * 2 <= pl.split_target && K / (nz * 2) >= 8 * BK && nz < 256) nz *= 2;
         while (nz > 1 && (int64_t)nz * a.ostride > ocap) nz /= 2;
     }
     int64_t ks = (K + nz - 1) / nz;
@@ -281,10 +333,18 @@ hipError_t launch_nt(const T* X, int64_t ldx, const T* Y, int64_t ldy, T* out, i
     if (nz < 1) nz = 1;
     a.kslice = ks;
     *nz_out = nz;
-    if (sub)
-        hipLaunchKernelGGL((gemm_nt_kernel<T, true>), dim3(tiles, nz), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL((gemm_nt_kernel<T, false>), dim3(tiles, nz), dim3(256), 0, s, a);
+#define CT_NT_LAUNCH(BQV)                                                                   \
+    if (sub)                                                                                \
+        hipLaunchKernelGGL((gemm_nt_kernel<T, true, BQV>), dim3(tiles, nz), dim3(256), 0, s, a); \
+    else                                                                                    \
+        hipLaunchKernelGGL((gemm_nt_kernel<T, false, BQV>), dim3(tiles, nz), dim3(256), 0, s, a);
+    switch (bq) {
+        case 16: CT_NT_LAUNCH(16) break;
+        case 32: CT_NT_LAUNCH(32) break;
+        case 64: CT_NT_LAUNCH(64) break;
+        default: CT_NT_LAUNCH(128) break;
+    }
+#undef CT_NT_LAUNCH
     return hipGetLastError();
 }
 
@@ -293,9 +353,11 @@ template hipError_t launch_prep_v<float>(const float*, int64_t, int64_t, int, fl
 template hipError_t launch_prep_v<double>(const double*, int64_t, int64_t, int, double*, int64_t, double*, int64_t,
                                           hipStream_t);
 template hipError_t launch_nt<float>(const float*, int64_t, const float*, int64_t, float*, int64_t, int64_t, int,
-                                     int64_t, bool, int64_t, int*, hipStream_t);
+                                     int64_t, bool, int64_t, int*, hipStream_t, const NtPlan*, const int32_t*, int,
+                                     int);
 template hipError_t launch_nt<double>(const double*, int64_t, const double*, int64_t, double*, int64_t, int64_t, int,
-                                      int64_t, bool, int64_t, int*, hipStream_t);
+                                      int64_t, bool, int64_t, int*, hipStream_t, const NtPlan*, const int32_t*, int,
+                                      int);
 
 
 // ---------------------------------------------------------------------------
@@ -412,43 +474,72 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_lp_kernel(NtArgs a)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f4_t{0, 0, 0, 0};
 
+    auto compute = [&]() {
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 32) {
+            v8 bh[4], bl[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                bh[j] = *(const v8*)&Ys[0][(wq + 16 * j + c) * LDK + kk + 8 * g];
+                if constexpr (X3) bl[j] = *(const v8*)&Ys[NH - 1][(wq + 16 * j + c) * LDK + kk + 8 * g];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const v8 ah = *(const v8*)&Xs[0][(wp + 16 * i + c) * LDK + kk + 8 * g];
+                v8 al;
+                if constexpr (X3) al = *(const v8*)&Xs[NH - 1][(wp + 16 * i + c) * LDK + kk + 8 * g];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if constexpr (X3) {
+                        acc[i][j] = mfma_lp<MODE>(al, bh[j], acc[i][j]);
+                        acc[i][j] = mfma_lp<MODE>(ah, bl[j], acc[i][j]);
+                    }
+                    acc[i][j] = mfma_lp<MODE>(ah, bh[j], acc[i][j]);
+                }
+            }
+        }
+    };
+
+    // the subtracting epilogue's C tile is fetched during the last K step,
+    // when the prefetch registers are free, so its latency hides behind it
+    f4_t cpre[4][4];
+    auto load_c = [&]() {
+        const float* O = (const float*)a.out;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int q = q0 + wq + 16 * j + c;
+                const int64_t pb = p0 + wp + 16 * i + 4 * g;
+                f4_t v = {0, 0, 0, 0};
+                if (q < a.Q) {
+                    const float* d = O + pb + (int64_t)q * a.ldo;
+                    if (pb + 3 < a.P && (((uintptr_t)d & 15) == 0)) v = *(const f4_t*)d;
+                    else
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            if (pb + r < a.P) v[r] = d[r];
+                }
+                cpre[i][j] = v;
+            }
+    };
+
     if (kbeg < kend) {
         gload(kbeg);
         sstore();
         __syncthreads();
-        for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
-            const bool more = k0 + BK < kend;
-            if (more) gload(k0 + BK);
-#pragma unroll
-            for (int kk = 0; kk < BK; kk += 32) {
-                v8 ah[4], bh[4], al[4], bl[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    ah[i] = *(const v8*)&Xs[0][(wp + 16 * i + c) * LDK + kk + 8 * g];
-                    if constexpr (X3) al[i] = *(const v8*)&Xs[NH - 1][(wp + 16 * i + c) * LDK + kk + 8 * g];
-                }
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    bh[j] = *(const v8*)&Ys[0][(wq + 16 * j + c) * LDK + kk + 8 * g];
-                    if constexpr (X3) bl[j] = *(const v8*)&Ys[NH - 1][(wq + 16 * j + c) * LDK + kk + 8 * g];
-                }
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        if constexpr (X3) {
-                            acc[i][j] = mfma_lp<MODE>(al[i], bh[j], acc[i][j]);
-                            acc[i][j] = mfma_lp<MODE>(ah[i], bl[j], acc[i][j]);
-                        }
-                        acc[i][j] = mfma_lp<MODE>(ah[i], bh[j], acc[i][j]);
-                    }
-            }
-            if (more) {
-                __syncthreads();
-                sstore();
-                __syncthreads();
-            }
+        int64_t k0 = kbeg;
+        for (; k0 + BK < kend; k0 += BK) {
+            gload(k0 + BK);
+            compute();
+            __syncthreads();
+            sstore();
+            __syncthreads();
         }
+        if constexpr (SUB) load_c();
+        compute();
+    } else if constexpr (SUB) {
+        load_c();
     }
 
     float* O = (float*)a.out;
@@ -461,14 +552,14 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_lp_kernel(NtArgs a)
             if (q >= a.Q) continue;
             const int64_t pb = p0 + wp + 16 * i + 4 * g;
             float* d = O + pb + (int64_t)q * a.ldo;
+            f4_t v = acc[i][j];
+            if constexpr (SUB) v = cpre[i][j] - v;
             if (pb + 3 < a.P && (((uintptr_t)d & 15) == 0)) {
-                f4_t v = acc[i][j];
-                if (SUB) v = *(f4_t*)d - v;
                 *(f4_t*)d = v;
             } else {
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    if (pb + r < a.P) d[r] = SUB ? d[r] - acc[i][j][r] : acc[i][j][r];
+                    if (pb + r < a.P) d[r] = v[r];
             }
         }
 }
@@ -481,6 +572,7 @@ hipError_t launch_nt_lp(const float* X, int64_t ldx, const float* Y, int64_t ldy
     NtArgs a;
     a.X = X; a.ldx = ldx; a.Y = Y; a.ldy = ldy; a.out = out; a.ldo = ldo;
     a.P = P; a.Q = Q; a.K = K; a.sub = sub ? 1 : 0;
+    a.desc = nullptr; a.desc_y = 0; a.desc_out = 0;
     a.tiles_p = (int)((P + kBP - 1) / kBP);
     a.tiles_q = (Q + kBQ - 1) / kBQ;
     a.ostride = ldo * (int64_t)Q;

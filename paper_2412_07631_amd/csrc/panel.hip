@@ -125,20 +125,21 @@ __global__ void __launch_bounds__(256) panel_qr_kernel(PanelArgs<TS> a)
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             const int v = t & 63, g = t >> 6;
             const double* base = a.part + (size_t)(j & 1) * a.P * 64 + v;
-            // all loads of this lane in flight at once (P <= 256: at most 64)
-            double acc[16];
-#pragma unroll
-            for (int u = 0; u < 16; ++u) acc[u] = 0.0;
-            for (int q0 = g; q0 < a.P; q0 += 64) {
-#pragma unroll
-                for (int u = 0; u < 16; ++u) {
-                    const int q = q0 + 4 * u;
-                    if (q < a.P) acc[u] += base[(size_t)q * 64];
-                }
-            }
+            // one round trip: every load of this lane is issued before any is
+            // consumed (P <= 256, so at most 64 per lane, in two halves)
             double s = 0.0;
 #pragma unroll
-            for (int u = 0; u < 16; ++u) s += acc[u];
+            for (int half = 0; half < 2; ++half) {
+                if (half == 1 && a.P <= 128) break;
+                double x[32];
+#pragma unroll
+                for (int u = 0; u < 32; ++u) {
+                    const int q = g + 4 * (u + 32 * half);
+                    x[u] = q < a.P ? base[(size_t)q * 64] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 32; ++u) s += x[u];
+            }
             red[g * 64 + v] = s;
             __syncthreads();
             if (t < 64) {
@@ -209,30 +210,40 @@ __global__ void __launch_bounds__(256) panel_qr_kernel(PanelArgs<TS> a)
                 Tl[j * 33 + j] = sc[2];
             }
         }
-        // (4) apply H_j to this workgroup's rows, one row per lane at a time
+        // (4) apply H_j to this workgroup's rows: first v (column j scaled,
+        // pivot set to beta), then the rank-1 update with one column per
+        // thread and eight row phases, so the inner loop has no branches
         if (sc[3] == 0.0) {
             const double scl = sc[0], beta = sc[1];
-            double wr[kPanelMax];
-#pragma unroll
-            for (int c = 0; c < kPanelMax; ++c) wr[c] = wv[c];
             for (int r = t; r < rows; r += 256) {
                 const int64_t gr = r0 + r;
-                if (gr < j) continue;
-                double v;
-                if (gr == j) {
-                    pan[j * rw + r] = beta;
-                    v = 1.0;
-                } else {
-                    v = pan[j * rw + r] * scl;
-                    pan[j * rw + r] = v;
+                if (gr > j) pan[j * rw + r] *= scl;
+                else if (gr == j) pan[j * rw + r] = beta;
+            }
+            __syncthreads();
+            const int c = t & 31, g = t >> 5;
+            if (c > j && c < nbp) {
+                const double wc = wv[c];
+                const double* vj = pan + j * rw;
+                double* pc = pan + c * rw;
+                int rs = (int)((int64_t)j - r0);
+                if (rs < 0) rs = 0;
+                // the pivot row (gr == j) takes v = 1
+                if (rs < rows && r0 + rs == j && (rs & 7) == g) {
+                    pc[rs] -= wc;
+                    rs += 8;
                 }
-                double x[kPanelMax];
-#pragma unroll
-                for (int c = 0; c < kPanelMax; ++c)
-                    if (c > j && c < nbp) x[c] = pan[c * rw + r];
-#pragma unroll
-                for (int c = 0; c < kPanelMax; ++c)
-                    if (c > j && c < nbp) pan[c * rw + r] = x[c] - wr[c] * v;
+                int r = rs + ((g - rs) & 7);
+                if (r < rows && r0 + r == j) r += 8;
+                for (; r + 24 < rows; r += 32) {
+                    const double v0 = vj[r], v1 = vj[r + 8], v2 = vj[r + 16], v3 = vj[r + 24];
+                    const double x0 = pc[r], x1 = pc[r + 8], x2 = pc[r + 16], x3 = pc[r + 24];
+                    pc[r] = x0 - wc * v0;
+                    pc[r + 8] = x1 - wc * v1;
+                    pc[r + 16] = x2 - wc * v2;
+                    pc[r + 24] = x3 - wc * v3;
+                }
+                for (; r < rows; r += 8) pc[r] -= wc * vj[r];
             }
         }
         __syncthreads();

@@ -14,9 +14,16 @@ constexpr int kTrsmBlock = 128;
 // right-hand side, two rows per lane, one substitution step per row.
 template <typename TS, bool UPPER>
 __global__ void __launch_bounds__(256) trsm_diag_kernel(const TS* __restrict__ R, int64_t ldr, int bo,
-                                                        TS* __restrict__ B, int64_t ldb, int nrhs)
+                                                        TS* __restrict__ B, int64_t ldb, int nrhs,
+                                                        const int32_t* desc)
 {
     extern __shared__ double Rs[];
+    if (desc) {
+        const int cur = desc[0];
+        B += (int64_t)desc[2 + 2 * cur] * ldb;
+        if (desc[3 + 2 * cur] < nrhs) nrhs = desc[3 + 2 * cur];
+    }
+    if (blockIdx.x * 4 >= nrhs) return;
     const int ld = bo + 1;
     for (int e = threadIdx.x; e < bo * bo; e += 256) {
         const int q = e / bo, p = e - q * bo;
@@ -309,12 +316,22 @@ static inline dim3 grid2(int64_t rows, int cols)
 }
 
 template <typename TS, bool UPPER>
-hipError_t launch_trsm_diag(const TS* R, int64_t ldr, int bo, TS* B, int64_t ldb, int nrhs, hipStream_t s)
+hipError_t launch_trsm_diag(const TS* R, int64_t ldr, int bo, TS* B, int64_t ldb, int nrhs, hipStream_t s,
+                            const int32_t* desc)
 {
     const size_t sh = (size_t)bo * (bo + 1) * sizeof(double);
     int blocks = (nrhs + 3) / 4;
     if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL((trsm_diag_kernel<TS, UPPER>), dim3(blocks), dim3(256), sh, s, R, ldr, bo, B, ldb, nrhs);
+    hipLaunchKernelGGL((trsm_diag_kernel<TS, UPPER>), dim3(blocks), dim3(256), sh, s, R, ldr, bo, B, ldb, nrhs, desc);
+    return hipGetLastError();
+}
+
+// Advance the batch cursor of a graph-captured solve (last node of the graph).
+__global__ void advance_batch_kernel(int32_t* desc) { desc[0] += 1; }
+
+hipError_t launch_advance_batch(int32_t* desc, hipStream_t s)
+{
+    hipLaunchKernelGGL(advance_batch_kernel, dim3(1), dim3(1), 0, s, desc);
     return hipGetLastError();
 }
 
@@ -409,10 +426,14 @@ hipError_t launch_colnorm(const double* X, int64_t ldx, int64_t rows, int cols, 
     return hipGetLastError();
 }
 
-template hipError_t launch_trsm_diag<double, true>(const double*, int64_t, int, double*, int64_t, int, hipStream_t);
-template hipError_t launch_trsm_diag<double, false>(const double*, int64_t, int, double*, int64_t, int, hipStream_t);
-template hipError_t launch_trsm_diag<float, true>(const float*, int64_t, int, float*, int64_t, int, hipStream_t);
-template hipError_t launch_trsm_diag<float, false>(const float*, int64_t, int, float*, int64_t, int, hipStream_t);
+template hipError_t launch_trsm_diag<double, true>(const double*, int64_t, int, double*, int64_t, int, hipStream_t,
+                                                   const int32_t*);
+template hipError_t launch_trsm_diag<double, false>(const double*, int64_t, int, double*, int64_t, int, hipStream_t,
+                                                    const int32_t*);
+template hipError_t launch_trsm_diag<float, true>(const float*, int64_t, int, float*, int64_t, int, hipStream_t,
+                                                  const int32_t*);
+template hipError_t launch_trsm_diag<float, false>(const float*, int64_t, int, float*, int64_t, int, hipStream_t,
+                                                   const int32_t*);
 template hipError_t launch_convert<double, float>(const double*, int64_t, float*, int64_t, int64_t, int, hipStream_t);
 template hipError_t launch_convert<float, double>(const float*, int64_t, double*, int64_t, int64_t, int, hipStream_t);
 template hipError_t launch_convert<double, double>(const double*, int64_t, double*, int64_t, int64_t, int, hipStream_t);

@@ -51,6 +51,12 @@ _sig("ct_build_system", [ctypes.POINTER(Geometry), ctypes.c_int, _vp, _i64, _vp]
 _sig("ct_build_csr", [ctypes.POINTER(Geometry), _vp, _vp, _vp, _i64, _vp])
 _sig("ct_qr_workspace", [_i64, _i64, ctypes.c_int, _i64, ctypes.POINTER(_sz)])
 _sig("ct_qr_factor", [_vp, _i64, _i64, _i64, ctypes.c_int, _vp, _vp, _sz, _i64, ctypes.POINTER(_vp), _vp])
+_sig("ct_qr_stream_workspace", [_i64, _i64, _i64, ctypes.c_int, _i64, _i64, ctypes.POINTER(_sz), ctypes.POINTER(_sz)])
+_sig("ct_qr_factor_streamed", [_vp, _i64, _i64, _i64, ctypes.c_int, _vp, _vp, _sz, _i64, _i64, ctypes.POINTER(_vp),
+                               _vp])
+_sig("ct_qr_resume", [_vp, _vp])
+_sig("ct_stream_info", [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)])
+_sig("ct_stream_inject_failure", [_i64])
 _sig("ct_apply_qt", [_vp, _vp, _i64, _i64, _vp])
 _sig("ct_trsm_solve", [_vp, _vp, _i64, _i64, _vp])
 _sig("ct_solve_backward", [_vp, _vp, _i64, _i64, _vp, _i64, _vp])
@@ -74,6 +80,10 @@ class Profile(ctypes.Structure):
 _sig("ct_profile_begin", [])
 _sig("ct_profile_end", [ctypes.POINTER(Profile)])
 _sig("ct_status", [_vp, ctypes.POINTER(_i64), _vp])
+_sig("ct_solve_graph_create", [_vp, _vp, _i64, _i64, _vp, _vp, ctypes.POINTER(_vp)])
+_sig("ct_solve_graph_launch", [_vp, _vp])
+_sig("ct_solve_graph_destroy", [_vp])
+_sig("ct_autotune_solve", [_vp, _vp, _i64, _i64, ctypes.c_char_p, _vp])
 _sig("ct_factor_destroy", [_vp])
 _sig("ct_last_error", [], ctypes.c_char_p)
 _sig("ct_siddon_rows", [_vp, _i64, _i32, ctypes.c_double, _vp])
@@ -173,6 +183,55 @@ def qr_factor(A: torch.Tensor, m: int, n: int, prec: int, max_nrhs: int = 512, s
     return Factor(h, A, tau, work, m, n, prec, max_nrhs)
 
 
+def qr_stream_workspace(m: int, n: int, lda: int, prec: int, max_nrhs: int, tile_cols: int):
+    """(minimum, all-tiles-resident) device bytes of a streamed factorization."""
+    a, b = _sz(0), _sz(0)
+    _check(_lib.ct_qr_stream_workspace(m, n, lda, prec, max_nrhs, tile_cols, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def qr_factor_streamed(A_host: torch.Tensor, m: int, n: int, prec: int, tile_cols: int = 1024,
+                       device_bytes: int = None, max_nrhs: int = 512, device="cuda", stream=None) -> Factor:
+    """Out-of-core factorization of a pinned host matrix (an (n, lda) tensor
+    holding the m x n matrix), in place.  device_bytes caps the device buffer
+    (default: enough to keep every tile resident).  A copy failure injected
+    with inject_failure() raises CtError(-2002) carrying the resumable factor
+    as its .factor attribute."""
+    want = torch.float64 if prec == PREC_F64 else torch.float32
+    if A_host.dtype != want or A_host.device.type != "cpu" or not A_host.is_pinned():
+        raise TypeError("A_host must be a pinned CPU tensor of %s" % want)
+    lda = A_host.shape[1]
+    lo, full = qr_stream_workspace(m, n, lda, prec, max_nrhs, tile_cols)
+    nbytes = full if device_bytes is None else max(lo, min(full, int(device_bytes)))
+    tau = torch.zeros(n, dtype=torch.float64, device=device)
+    work = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    h = _vp()
+    rc = _lib.ct_qr_factor_streamed(_ptr(A_host), m, n, lda, prec, _ptr(tau), _ptr(work), work.numel(), max_nrhs,
+                                    tile_cols, ctypes.byref(h), _stream(stream))
+    f = Factor(h, A_host, tau, work, m, n, prec, max_nrhs) if h.value else None
+    if rc != 0:
+        err = CtError(rc, (_lib.ct_last_error() or b"").decode())
+        err.factor = f
+        raise err
+    return f
+
+
+def qr_resume(f: Factor, stream=None):
+    _check(_lib.ct_qr_resume(f.handle, _stream(stream)))
+    return f
+
+
+def stream_info(f: Factor):
+    """(tiles, resident tiles, first unfinished tile) of a streamed factor."""
+    a, b, c = _i64(0), _i64(0), _i64(0)
+    _check(_lib.ct_stream_info(f.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def inject_failure(tile: int):
+    _check(_lib.ct_stream_inject_failure(tile))
+
+
 def apply_qt(f: Factor, B: torch.Tensor, nrhs: int = None, stream=None):
     nrhs = B.shape[0] if nrhs is None else nrhs
     _check(_lib.ct_apply_qt(f.handle, _ptr(B), nrhs, B.shape[1], _stream(stream)))
@@ -239,6 +298,48 @@ def solve_refined(f: Factor, sp: SparseA, B: torch.Tensor, X: torch.Tensor, step
                                  int(steps), int(method), _ptr(scratch), scratch.numel(), _ptr(res_norms),
                                  _ptr(grad_norms), _stream(stream)))
     return X
+
+
+def batch_descriptor(sizes, device="cuda"):
+    """Device descriptor for a list of batch sizes laid out back to back:
+    [current batch, 0, offset_0, count_0, offset_1, count_1, ...] (int32)."""
+    d = [0, 0]
+    off = 0
+    for c in sizes:
+        d += [off, int(c)]
+        off += int(c)
+    return torch.tensor(d, dtype=torch.int32, device=device)
+
+
+class SolveGraph:
+    """A captured solve (Q^T then R^{-1}) over the batch descriptor `desc` of
+    columns inside B; each launch solves the current batch and advances it."""
+
+    def __init__(self, f: Factor, B: torch.Tensor, max_cols: int, desc: torch.Tensor, stream=None):
+        self.f, self.B, self.desc = f, B, desc
+        st = stream if stream is not None else torch.cuda.Stream()
+        self.stream = st
+        h = _vp()
+        with torch.cuda.stream(st):
+            _check(_lib.ct_solve_graph_create(f.handle, _ptr(B), B.shape[1], int(max_cols), _ptr(desc),
+                                              _vp(st.cuda_stream), ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self, stream=None):
+        _check(_lib.ct_solve_graph_launch(self.handle, _stream(stream)))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            _lib.ct_solve_graph_destroy(h)
+            self.handle = None
+
+
+def autotune_solve(f: Factor, B: torch.Tensor, max_nrhs: int, cache_path: str = None, stream=None):
+    """Time the candidate launch plans of the solve kernels per batch bucket and
+    keep the fastest in the factor (B is scratch, overwritten)."""
+    _check(_lib.ct_autotune_solve(f.handle, _ptr(B), B.shape[1], int(max_nrhs),
+                                  cache_path.encode() if cache_path else None, _stream(stream)))
 
 
 def profile_begin():

@@ -53,3 +53,43 @@ def test_binding_marshals_without_gpu():
         assert e.code == -2
     else:
         raise AssertionError("expected an argument error")
+
+
+def test_stream_workspace_arithmetic():
+    """Streamed factorization: the minimum device buffer is the in-memory
+    workspace plus four staging tiles; keeping every tile resident needs the
+    workspace plus all tiles (tile = lda x tile_cols elements, 256-B rounded)."""
+    from paper_2412_07631_amd import ctqr
+    m, n, lda = 3360, 2304, 3360
+    base = ctqr.qr_workspace(m, n, ctqr.PREC_F64, 8)
+    lo, full = ctqr.qr_stream_workspace(m, n, lda, ctqr.PREC_F64, 8, 256)
+    tile = (lda * 256 * 8 + 255) // 256 * 256
+    assert lo == base + 4 * tile and full == base + 9 * tile
+    lo32, full32 = ctqr.qr_stream_workspace(m, n, lda, ctqr.PREC_BF16X3, 8, 1024)
+    assert full32 == ctqr.qr_workspace(m, n, ctqr.PREC_BF16X3, 8) + 3 * ((lda * 1024 * 4 + 255) // 256 * 256)
+    assert lo32 == full32          # three tiles: fewer than the staging slots
+    for bad_tile in (0, 100, -128):
+        try:
+            ctqr.qr_stream_workspace(m, n, lda, ctqr.PREC_F64, 8, bad_tile)
+        except ctqr.CtError as e:
+            assert e.code == -6
+        else:
+            raise AssertionError("expected an argument error")
+
+
+def test_streamed_factor_argument_errors_without_gpu():
+    from paper_2412_07631_amd import ctqr
+    lib = ctqr._lib
+    h = ctypes.c_void_p()
+    # tile_cols not a multiple of 128 (argument 10), n > m (argument 3)
+    assert lib.ct_qr_factor_streamed(ctypes.c_void_p(256), 100, 50, 112, ctqr.PREC_F64, ctypes.c_void_p(256),
+                                     ctypes.c_void_p(256), 1 << 30, 1, 100, ctypes.byref(h), None) == -10
+    assert lib.ct_qr_factor_streamed(ctypes.c_void_p(256), 100, 150, 112, ctqr.PREC_F64, ctypes.c_void_p(256),
+                                     ctypes.c_void_p(256), 1 << 30, 1, 128, ctypes.byref(h), None) == -3
+    # a buffer below the minimum (argument 8)
+    assert lib.ct_qr_factor_streamed(ctypes.c_void_p(256), 100, 50, 112, ctqr.PREC_F64, ctypes.c_void_p(256),
+                                     ctypes.c_void_p(256), 1024, 1, 128, ctypes.byref(h), None) == -8
+    assert lib.ct_qr_resume(None, None) == -1
+    with __import__("pytest").raises(TypeError):
+        import torch
+        ctqr.qr_factor_streamed(torch.zeros((4, 16)), 16, 4, ctqr.PREC_F32, tile_cols=128)
