@@ -38,6 +38,8 @@ hipError_t launch_tw(const TWp* Wp, int nz, int nbv, int N, const double* T, int
 hipError_t launch_t_from_gram(const double* G, int64_t ldg, const double* tau, int nb, double* T, int64_t ldt,
                               hipStream_t s);
 hipError_t t_from_gram_set_max_lds(size_t bytes);
+hipError_t launch_t12(const double* G12, int64_t ldg, const double* T1, const double* T2, int64_t ldt, double* M,
+                      int n1, int n2, double* T12, hipStream_t s);
 template <typename TWp, typename TS>
 hipError_t launch_sum_slices(const TWp* Wp, int64_t wstride, int nz, int64_t count, TS* S, hipStream_t s,
                              const int32_t* desc = nullptr, int per_col = 1);
@@ -173,7 +175,10 @@ struct ct_factor {
     struct StreamState* st = nullptr;   // host-pinned streaming state (null: A is in device memory)
 };
 
-static int nb_out_for(int prec) { (void)prec; return 128; }
+// Outer block width: the workspace is sized for kNbMax; an in-memory factor
+// uses kNbMax, a streamed one kNbMax when its tiles allow, else 128.
+constexpr int kNbMax = 256;
+static int nb_out_for(int prec) { (void)prec; return kNbMax; }
 
 struct Layout {
     size_t T_all, Tin, part, gpart, words, Wp, Wq, G, Vm, Vt, Ws, total;
@@ -358,7 +363,16 @@ static int block_t(ct_factor* f, int64_t mk, int bo, const double* tau, double* 
     CT_HIP(launch_nt<TS>((const TS*)f->Vm, f->ldvm, (const TS*)f->Vm, f->ldvm, (TS*)f->Wp, bo, bo, bo, mk, false,
                          f->wp_elems * 8 / (int64_t)sizeof(TS), &nz, s));
     CT_HIP((launch_sum_slices<TS, double>((const TS*)f->Wp, (int64_t)bo * bo, nz, (int64_t)bo * bo, f->G, s)));
-    CT_HIP(launch_t_from_gram(f->G, bo, tau, bo, T, ldt, s));
+    if (bo <= 128) {
+        CT_HIP(launch_t_from_gram(f->G, bo, tau, bo, T, ldt, s));
+    } else {
+        // two halves, each built in LDS, then their coupling block
+        const int n1 = 128, n2 = bo - 128;
+        CT_HIP(launch_t_from_gram(f->G, bo, tau, n1, T, ldt, s));
+        CT_HIP(launch_t_from_gram(f->G + n1 + (int64_t)n1 * bo, bo, tau + n1, n2, T + n1 + (int64_t)n1 * ldt, ldt, s));
+        CT_HIP(launch_t12(f->G + (int64_t)n1 * bo, bo, T, T + n1 + (int64_t)n1 * ldt, ldt, (double*)f->Wq, n1, n2,
+                          T + (int64_t)n1 * ldt, s));
+    }
     return 0;
 }
 
@@ -901,11 +915,11 @@ int ct_qr_workspace(int64_t m, int64_t n, int prec, int64_t max_nrhs, size_t* by
 // workspace partition and panel geometry (rows per workgroup from the LDS
 // budget; all workgroups of a panel must be resident at once).
 static int init_factor(ct_factor* f, void* A, int64_t m, int64_t n, int64_t lda, int prec, double* tau, char* w,
-                       const Layout& L, int64_t max_nrhs)
+                       const Layout& L, int64_t max_nrhs, int nbo)
 {
     f->A = A; f->m = m; f->n = n; f->lda = lda; f->prec = prec; f->f64 = prec == CT_PREC_F64;
     f->tau = tau;
-    f->nb_out = nb_out_for(prec);
+    f->nb_out = nbo;
     f->nblocks = (n + f->nb_out - 1) / f->nb_out;
     f->T_all = (double*)(w + L.T_all);
     f->Tin = (double*)(w + L.Tin);
@@ -971,7 +985,7 @@ int ct_qr_factor(void* A, int64_t m, int64_t n, int64_t lda, int prec, double* t
 
     ct_factor* f = new (std::nothrow) ct_factor();
     if (!f) return fail(-1001, "%s", "out of host memory");
-    r = init_factor(f, A, m, n, lda, prec, tau, (char*)work, L, max_nrhs);
+    r = init_factor(f, A, m, n, lda, prec, tau, (char*)work, L, max_nrhs, kNbMax);
     if (r) {
         delete f;
         return r;
@@ -994,7 +1008,7 @@ int ct_qr_stream_workspace(int64_t m, int64_t n, int64_t lda, int prec, int64_t 
     CT_ARG(lda >= m && lda % 16 == 0, 3, "lda");
     CT_ARG(prec >= CT_PREC_F64 && prec <= CT_PREC_BF16X3, 4, "prec");
     CT_ARG(max_nrhs >= 0, 5, "max_nrhs");
-    CT_ARG(tile_cols > 0 && tile_cols % nb_out_for(prec) == 0, 6, "tile_cols (a positive multiple of 128)");
+    CT_ARG(tile_cols > 0 && tile_cols % 128 == 0, 6, "tile_cols (a positive multiple of 128)");
     CT_ARG(min_bytes != nullptr, 7, "min_bytes");
     const size_t es = prec == CT_PREC_F64 ? 8 : 4;
     const int64_t nt = (n + tile_cols - 1) / tile_cols;
@@ -1015,7 +1029,7 @@ int ct_qr_factor_streamed(void* A_host, int64_t m, int64_t n, int64_t lda, int p
     CT_ARG(tau != nullptr, 6, "tau");
     CT_ARG(work != nullptr && aligned(work), 7, "work");
     CT_ARG(max_nrhs >= 0, 9, "max_nrhs");
-    CT_ARG(tile_cols > 0 && tile_cols % nb_out_for(prec) == 0, 10, "tile_cols (a positive multiple of 128)");
+    CT_ARG(tile_cols > 0 && tile_cols % 128 == 0, 10, "tile_cols (a positive multiple of 128)");
     CT_ARG(f_out != nullptr, 11, "f");
     size_t need = 0, full = 0;
     ct_qr_stream_workspace(m, n, lda, prec, max_nrhs, tile_cols, &need, &full);
@@ -1054,7 +1068,7 @@ int ct_qr_factor_streamed(void* A_host, int64_t m, int64_t n, int64_t lda, int p
         st->nres = (int64_t)((work_bytes - L.total - kSlots * tb) / tb);
         for (int k = 0; k < kSlots; ++k) st->slot[k] = w + L.total + (size_t)st->nres * tb + (size_t)k * tb;
     }
-    r = init_factor(f, w + L.total, m, n, lda, prec, tau, w, L, max_nrhs);
+    r = init_factor(f, w + L.total, m, n, lda, prec, tau, w, L, max_nrhs, tile_cols % kNbMax == 0 ? kNbMax : 128);
     if (r) {
         delete st;
         delete f;

@@ -67,6 +67,29 @@ __device__ __forceinline__ int desc_count(const int32_t* desc, int n)
 }
 __device__ __forceinline__ int desc_offset(const int32_t* desc) { return desc ? desc[2 + 2 * desc[0]] : 0; }
 
+// Output tile of workgroup b in the NT update kernels.  The hardware places
+// workgroup b on XCD b % 8; with the grid padded to a multiple of 8, each XCD
+// takes a contiguous range of the tile sequence.  The sequence walks bands of
+// kBand tile columns row by row (columns fastest), so the tiles that run at
+// the same time on one XCD share their row and column operand blocks in L2.
+// Returns false for the padding workgroups.
+constexpr int kBand = 8;
+__device__ __forceinline__ bool tile_of(int b, int tiles_p, int tiles_q, int& tp, int& tq)
+{
+    const int nt = tiles_p * tiles_q;
+    const int per = (nt + 7) / 8;
+    const int L = (b % 8) * per + b / 8;
+    if (L >= nt) return false;
+    const int band = L / (kBand * tiles_p);
+    const int rest = tiles_q - band * kBand;
+    const int gq = rest < kBand ? rest : kBand;
+    const int local = L - band * kBand * tiles_p;
+    tq = band * kBand + local % gq;
+    tp = local / gq;
+    return true;
+}
+__host__ __forceinline__ int padded_tiles(int nt) { return (nt + 7) / 8 * 8; }
+
 struct ErrWord {
     // bit 0: barrier spin limit hit; bit 1: CSR capacity exceeded; bit 2: invalid batch descriptor
     int32_t flags;

@@ -387,6 +387,52 @@ __global__ void __launch_bounds__(512) t_from_gram_kernel(const double* __restri
         }
 }
 
+// Compact-WY factor of two consecutive reflector blocks V = [V1 V2] from the
+// factors of each (H1 H2 = I - V T V^T):
+//   T = [ T1   -T1 (V1^T V2) T2 ]
+//       [ 0     T2              ]
+// STEP 0: M = G12 T2 (n1 x n2, ld n1), with G12 = V1^T V2 and T2 upper
+// triangular; STEP 1: T12 = -T1 M, T1 upper triangular.  One output per thread.
+template <int STEP>
+__global__ void __launch_bounds__(256) t12_kernel(const double* __restrict__ A, int64_t lda,
+                                                  const double* __restrict__ Tt, int64_t ldt, double* __restrict__ out,
+                                                  int64_t ldo, int n1, int n2)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= n1 * n2) return;
+    const int i = e % n1, j = e / n1;
+    double s0 = 0.0, s1 = 0.0;
+    if (STEP == 0) {
+        // A = G12 (n1 x n2), Tt = T2: sum over l <= j of G12[i][l] T2[l][j]
+        int l = 0;
+        for (; l + 1 <= j; l += 2) {
+            s0 += A[i + (int64_t)l * lda] * Tt[l + (int64_t)j * ldt];
+            s1 += A[i + (int64_t)(l + 1) * lda] * Tt[(l + 1) + (int64_t)j * ldt];
+        }
+        if (l <= j) s0 += A[i + (int64_t)l * lda] * Tt[l + (int64_t)j * ldt];
+        out[i + (int64_t)j * ldo] = s0 + s1;
+    } else {
+        // A = M (n1 x n2), Tt = T1: -(sum over l >= i of T1[i][l] M[l][j])
+        int l = i;
+        for (; l + 1 < n1; l += 2) {
+            s0 += Tt[i + (int64_t)l * ldt] * A[l + (int64_t)j * lda];
+            s1 += Tt[i + (int64_t)(l + 1) * ldt] * A[(l + 1) + (int64_t)j * lda];
+        }
+        if (l < n1) s0 += Tt[i + (int64_t)l * ldt] * A[l + (int64_t)j * lda];
+        out[i + (int64_t)j * ldo] = -(s0 + s1);
+    }
+}
+
+hipError_t launch_t12(const double* G12, int64_t ldg, const double* T1, const double* T2, int64_t ldt, double* M,
+                      int n1, int n2, double* T12, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)((n1 * n2 + 255) / 256);
+    hipLaunchKernelGGL((t12_kernel<0>), dim3(blocks), dim3(256), 0, s, G12, ldg, T2, ldt, M, (int64_t)n1, n1, n2);
+    hipLaunchKernelGGL((t12_kernel<1>), dim3(blocks), dim3(256), 0, s, (const double*)M, (int64_t)n1, T1, ldt, T12,
+                       ldt, n1, n2);
+    return hipGetLastError();
+}
+
 // S[e] = sum_z W[z][e] over `count` contiguous elements (fixed order in z);
 // with a descriptor, count = per_col * (batch column count).
 template <typename TWp, typename TS>

@@ -94,14 +94,8 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_kernel(NtArgs a)
     __shared__ T Xs[2][kBP * LDK];
     __shared__ T Ys[2][BQ * LDK];
 
-    // XCD-aware tile order: hardware places block b on XCD b % 8
-    const int nt = a.tiles_p * a.tiles_q;
-    const int b = blockIdx.x;
-    const int per = (nt + 7) / 8;
-    int tile = (b % 8) * per + b / 8;
-    if (nt % 8 != 0) tile = b;                      // uneven split: keep the plain order
-    if (tile >= nt) return;
-    const int tp = tile % a.tiles_p, tq = tile / a.tiles_p;
+    int tp, tq;
+    if (!tile_of(blockIdx.x, a.tiles_p, a.tiles_q, tp, tq)) return;
     const int64_t p0 = (int64_t)tp * kBP;
     const int q0 = tq * BQ;
     const int64_t kbeg = (int64_t)blockIdx.y * a.kslice;
@@ -201,21 +195,30 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_kernel(NtArgs a)
     // when the prefetch registers are free, so its latency hides behind it
     // (FP32 only: the FP64 accumulators already fill the register file)
     constexpr bool PRE = SUB && !F64;
-    T cpre[MI][NJ][PRE ? 4 : 1];
+    // FP32 accumulators hold rows 4g..4g+3 of one column: one 16-byte access
+    typedef Acc accv_t;
+    accv_t cpre[MI][NJ];
     auto load_c = [&]() {
-        if constexpr (!PRE) return;
-        const T* O = (const T*)Oc;
+        if constexpr (PRE) {
+            const T* O = (const T*)Oc;
 #pragma unroll
-        for (int i = 0; i < MI; ++i)
+            for (int i = 0; i < MI; ++i)
 #pragma unroll
-            for (int j = 0; j < NJ; ++j) {
-                const int q = q0 + wq + 16 * j + c;
+                for (int j = 0; j < NJ; ++j) {
+                    const int q = q0 + wq + 16 * j + c;
+                    const int64_t pb = p0 + wp + 16 * i + 4 * g;
+                    accv_t v = {0, 0, 0, 0};
+                    if (q < Qe) {
+                        const T* d = O + pb + (int64_t)q * a.ldo;
+                        if (pb + 3 < a.P && (((uintptr_t)d & 15) == 0)) v = *(const accv_t*)d;
+                        else
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int64_t p = p0 + wp + 16 * i + (F64 ? g + 4 * r : 4 * g + r);
-                    if constexpr (PRE) cpre[i][j][r] = (p < a.P && q < Qe) ? O[p + (int64_t)q * a.ldo] : (T)0;
+                            for (int r = 0; r < 4; ++r)
+                                if (pb + r < a.P) v[r] = d[r];
+                    }
+                    cpre[i][j] = v;
                 }
-            }
+        }
     };
 
     if (kbeg < kend) {
@@ -245,13 +248,26 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_kernel(NtArgs a)
         for (int j = 0; j < NJ; ++j) {
             const int q = q0 + wq + 16 * j + c;
             if (q >= Qe) continue;
+            if constexpr (!F64) {
+                const int64_t pb = p0 + wp + 16 * i + 4 * g;
+                T* d = O + pb + (int64_t)q * a.ldo;
+                accv_t v = acc[i][j];
+                if constexpr (PRE) v = cpre[i][j] - v;
+                if (pb + 3 < a.P && (((uintptr_t)d & 15) == 0)) {
+                    *(accv_t*)d = v;
+                } else {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t p = p0 + wp + 16 * i + (F64 ? g + 4 * r : 4 * g + r);
-                if (p < a.P) {
-                    T* d = O + p + (int64_t)q * a.ldo;
-                    if constexpr (PRE) *d = cpre[i][j][r] - (T)acc[i][j][r];
-                    else *d = SUB ? *d - (T)acc[i][j][r] : (T)acc[i][j][r];
+                    for (int r = 0; r < 4; ++r)
+                        if (pb + r < a.P) d[r] = v[r];
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t p = p0 + wp + 16 * i + g + 4 * r;
+                    if (p < a.P) {
+                        T* d = O + p + (int64_t)q * a.ldo;
+                        *d = SUB ? *d - (T)acc[i][j][r] : (T)acc[i][j][r];
+                    }
                 }
             }
         }
@@ -335,9 +351,9 @@ hipError_t launch_nt(const T* X, int64_t ldx, const T* Y, int64_t ldy, T* out, i
     *nz_out = nz;
 #define CT_NT_LAUNCH(BQV)                                                                   \
     if (sub)                                                                                \
-        hipLaunchKernelGGL((gemm_nt_kernel<T, true, BQV>), dim3(tiles, nz), dim3(256), 0, s, a); \
+        hipLaunchKernelGGL((gemm_nt_kernel<T, true, BQV>), dim3(padded_tiles(tiles), nz), dim3(256), 0, s, a); \
     else                                                                                    \
-        hipLaunchKernelGGL((gemm_nt_kernel<T, false, BQV>), dim3(tiles, nz), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((gemm_nt_kernel<T, false, BQV>), dim3(padded_tiles(tiles), nz), dim3(256), 0, s, a);
     switch (bq) {
         case 16: CT_NT_LAUNCH(16) break;
         case 32: CT_NT_LAUNCH(32) break;
@@ -398,13 +414,8 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_lp_kernel(NtArgs a)
     __shared__ E Xs[NH][kBP * LDK];
     __shared__ E Ys[NH][kBQ * LDK];
 
-    const int nt = a.tiles_p * a.tiles_q;
-    const int b = blockIdx.x;
-    const int per = (nt + 7) / 8;
-    int tile = (b % 8) * per + b / 8;
-    if (nt % 8 != 0) tile = b;
-    if (tile >= nt) return;
-    const int tp = tile % a.tiles_p, tq = tile / a.tiles_p;
+    int tp, tq;
+    if (!tile_of(blockIdx.x, a.tiles_p, a.tiles_q, tp, tq)) return;
     const int64_t p0 = (int64_t)tp * kBP;
     const int q0 = tq * kBQ;
     const int64_t kbeg = (int64_t)blockIdx.y * a.kslice;
@@ -589,9 +600,9 @@ hipError_t launch_nt_lp(const float* X, int64_t ldx, const float* Y, int64_t ldy
     a.kslice = ks;
     *nz_out = nz;
     if (sub)
-        hipLaunchKernelGGL((gemm_nt_lp_kernel<MODE, true>), dim3(tiles, nz), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((gemm_nt_lp_kernel<MODE, true>), dim3(padded_tiles(tiles), nz), dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL((gemm_nt_lp_kernel<MODE, false>), dim3(tiles, nz), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((gemm_nt_lp_kernel<MODE, false>), dim3(padded_tiles(tiles), nz), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
