@@ -39,14 +39,88 @@ def solve_flops(m, n):
     return 4.0 * m * n - float(n) * n
 
 
+def batched_leg(ctqr, synth, torch, f, sc, Bd, dev, total):
+    """Uneven batches (seeded sizes 1..512) of sinograms through the
+    graph-captured solve, then the adjoint on 64 upstream gradients with a
+    central finite-difference check (step 1e-3) on the same factor."""
+    m, n = sc.m, sc.n
+    sizes = synth.uneven_batches(total, 1, 512, cfg=4)
+    nr = Bd.shape[0]
+    idx = torch.arange(total, device=dev) % nr
+    src = Bd[idx, :].to(f.dtype)                           # (total, ld) storage-typed sinograms
+    Bb = torch.zeros_like(src)
+    desc = ctqr.batch_descriptor(sizes, device=dev)
+    caps = (8, 32, 128, 512)
+    cap_of = lambda c: next(x for x in caps if c <= x)
+    graphs = {c: ctqr.SolveGraph(f, Bb, c, desc) for c in sorted({cap_of(c) for c in sizes})}
+    gs = torch.cuda.Stream()
+    torch.cuda.synchronize()
+
+    def run_graphs():
+        Bb.copy_(src)
+        desc[0] = 0
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(gs)
+        for c in sizes:
+            graphs[cap_of(c)].launch(gs)
+        e1.record(gs)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    run_graphs()                                           # first replay (untimed)
+    g_ms = run_graphs()
+    Xg = Bb[:, :n].clone()
+    # the same batches solved eagerly, for time and agreement
+    Bb.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    off = 0
+    for c in sizes:
+        blk = Bb[off:off + c]
+        ctqr.apply_qt(f, blk)
+        ctqr.trsm_solve(f, blk)
+        off += c
+    e1.record()
+    torch.cuda.synchronize()
+    eager_ms = e0.elapsed_time(e1)
+    agree = float(((Xg - Bb[:, :n]).abs().max() / Bb[:, :n].abs().max()).item())
+
+    # adjoint: 64 FP32 upstream gradients; FD check along seeded directions
+    k = 64
+    G = torch.from_numpy(np.ascontiguousarray(synth.gradients(n, k).T)).to(dev, f.dtype)
+    B0 = src[:k, :m].clone().requires_grad_(True)
+    X0 = ctqr.qr_solve(B0, f)
+    e0.record()
+    (gB,) = torch.autograd.grad(X0, B0, G)
+    e1.record()
+    torch.cuda.synchronize()
+    bwd_ms = e0.elapsed_time(e1)
+    D = torch.from_numpy(np.ascontiguousarray(synth.directions(m, 4).T)).to(dev, torch.float64)
+    h = 1e-3
+    fd_err = 0.0
+    with torch.no_grad():
+        for j in range(4):
+            bp = (B0[j:j + 1].double() + h * D[j:j + 1]).to(f.dtype)
+            bm = (B0[j:j + 1].double() - h * D[j:j + 1]).to(f.dtype)
+            dx = (ctqr.qr_solve(bp, f).double() - ctqr.qr_solve(bm, f).double()) / (2 * h)
+            fd = float((dx * G[j:j + 1].double()).sum())
+            an = float((gB[j:j + 1].double() * D[j:j + 1]).sum())
+            fd_err = max(fd_err, abs(fd - an) / max(abs(an), 1e-30))
+    return {"sinograms": total, "batches": len(sizes), "graph_slices_per_s": total / (g_ms * 1e-3),
+            "eager_slices_per_s": total / (eager_ms * 1e-3), "graph_vs_eager_max_rel_diff": agree,
+            "adjoint_gradients": k, "adjoint_ms": bwd_ms, "fd_step": h, "fd_max_rel_err": fd_err}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c3_256")
-    ap.add_argument("--prec", default="f32", choices=["f64", "f32", "bf16", "f16", "bf16x3"])
-    ap.add_argument("--refine", type=int, default=3, help="refinement steps")
+    ap.add_argument("--prec", default="bf16x3", choices=["f64", "f32", "bf16", "f16", "bf16x3"])
+    ap.add_argument("--refine", type=int, default=4, help="refinement steps")
     ap.add_argument("--method", default="sne", choices=["sne", "qr"])
     ap.add_argument("--nrhs", type=int, default=None, help="slices per batch (default: the workload's)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference path")
@@ -54,6 +128,9 @@ def main():
     ap.add_argument("--cpu-cols", type=int, default=1024, help="leading columns in the CPU oracle sample")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 1 GiB device copy first (calibrates profiler byte counters)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the uneven-batch graph solve and the adjoint leg on the same factor")
+    ap.add_argument("--batched-total", type=int, default=4096, help="sinograms in the uneven-batch leg")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -177,12 +254,27 @@ def main():
         log("fp64 path: qr %.1f ms (%.2f TFLOP/s), solve %.1f slices/s; mixed vs fp64 max rel err %.3g" % (
             fp64["qr_ms"], fp64["qr_tflops"], fp64["slices_per_s"], fp64["rel_err_max"]))
 
+    # ------------------------------------- uneven batches and the adjoint
+    batched = None
+    if not args.no_batched:
+        batched = batched_leg(ctqr, synth, torch, f, sc, Bd, dev, args.batched_total)
+
     # ------------------------------------------------------ roofline (live)
     dom = max(prof, key=lambda k: prof[k]["ms"])
     d = prof[dom]
     achieved = d["flop"] / (d["ms"] * 1e-3) / 1e12 if d["ms"] > 0 else 0.0
     peak = PEAK_TFLOPS[args.prec]
-    roofline = {"bound": "mfma", "kernel": "gemm_nn_sub (C -= V W)" if dom == "update_cvw" else "gemm_tn (W = V^T C)",
+    tname = {"f64": "gemm_nt_kernel<double, %s, 128>", "f32": "gemm_nt_kernel<float, %s, 128>",
+             "bf16": "gemm_nt_lp_kernel<2, %s, false, false>", "f16": "gemm_nt_lp_kernel<3, %s, false, false>",
+             "bf16x3": "gemm_nt_lp_kernel<4, %s>"}[args.prec]
+    if args.prec == "bf16x3":
+        split = os.environ.get("CTQR_X3_PRESPLIT", "1") != "0"
+        args_cvw, args_vtc = ("true, true, true", "false, true, false") if split else ("true, false, false",
+                                                                                       "false, false, false")
+        kname = (tname % args_cvw) + " (C -= V W')" if dom == "update_cvw" else (tname % args_vtc) + " (W = V^T C)"
+    else:
+        kname = (tname % "true") + " (C -= V W')" if dom == "update_cvw" else (tname % "false") + " (W = V^T C)"
+    roofline = {"bound": "mfma", "kernel": kname,
                 "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "launches": d["launches"], "avg_launch_ms": d["ms"] / max(d["launches"], 1),
                 "algorithmic_gbs": d["bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0,
@@ -234,6 +326,7 @@ def main():
         "residual_rel_final": float(np.max(rnorm[-1] / bnorm)),
         "ls_grad_norm_by_step": [float(np.max(gnorm[s])) for s in range(args.refine + 1)],
         "fp64_path": fp64,
+        "batched": batched,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -125,6 +125,16 @@ int ct_stream_info(const ct_factor* f, int64_t* tiles, int64_t* resident, int64_
  * tile `tile` as if its copy had failed (-1 disables). */
 int ct_stream_inject_failure(int64_t tile);
 
+/* The Householder panels wait for each other's column reductions (their
+ * workgroups must all be resident; the handle checks the occupancy).  A wait
+ * longer than its limit (default 0.5 s; normal waits take microseconds) sets
+ * the error word that ct_status reports as -2001, and every later wait of the
+ * same factorization ends at once, so a factorization whose workgroups could
+ * not all be resident fails in bounded time instead of waiting forever.  For
+ * tests: set the limit in 100 MHz ticks for later factorizations (ticks < 0
+ * restores the default; 0 makes every wait give up). */
+int ct_debug_wait_limit(int64_t ticks);
+
 /* B <- Q^T B (Eq. (solve), first half; ormqr).  B: m x nrhs, same storage
  * type as the factor's A, nrhs <= max_nrhs.  Rows n..m-1 of the result hold
  * the least-squares residual components. */

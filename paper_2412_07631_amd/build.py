@@ -3,7 +3,8 @@
     python -m paper_2412_07631_amd.build      # or: from ... import build; build.build()
 
 Objects go to ``_build/`` next to this file; the shared library lands in the
-package directory, where the binding loads it.
+package directory, where the binding loads it, next to ``ctqr_bench``, a
+native driver of the C-ABI used for profiler runs.
 """
 from __future__ import annotations
 
@@ -51,8 +52,16 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
     os.replace(tmp, OUT)
+    # native driver of the C-ABI (profiling runs without Python)
+    exe = os.path.join(HERE, "ctqr_bench")
+    cmd = [HIPCC, "-O2", "-std=c++17", os.path.join(CSRC, "ctqr_bench.cpp"), "-o", exe + ".tmp",
+           "-L" + HERE, "-lctqr", "-Wl,-rpath,$ORIGIN"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("driver build failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
+    os.replace(exe + ".tmp", exe)
     if verbose:
-        print("built", OUT)
+        print("built", OUT, "and", exe)
     return OUT
 
 

@@ -6,6 +6,7 @@
 #include "../../include/ctqr.h"
 
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 #include <algorithm>
 #include <map>
@@ -24,8 +25,10 @@ hipError_t launch_panel(TS* A, int64_t lda, int64_t mk, int nbp, int rw, double*
                         uint64_t* flag_base, int64_t* info, int64_t col0, int32_t* err, hipStream_t s);
 size_t panel_lds_bytes(int nbp, int rw);
 int panel_aux_words();
+int panel_max_rows();
 hipError_t panel_set_max_lds(size_t bytes);
 hipError_t panel_max_active(int* per_cu, size_t shmem);
+void panel_set_wait_limit(int64_t ticks);
 template <int MODE, typename TA, typename TB, typename TW, bool MA, bool MB_>
 hipError_t launch_tn(const TA* A, int64_t lda, const TB* B, int64_t ldb, TW* W, int M, int N, int64_t K,
                      int64_t wcap, int* nz_out, hipStream_t s);
@@ -49,15 +52,26 @@ hipError_t launch_prep_v(const T* V, int64_t ldv, int64_t mk, int nb, T* Vm, int
 template <typename T>
 hipError_t launch_nt(const T* X, int64_t ldx, const T* Y, int64_t ldy, T* out, int64_t ldo, int64_t P, int Q,
                      int64_t K, bool sub, int64_t ocap, int* nz_out, hipStream_t s, const NtPlan* plan = nullptr,
-                     const int32_t* desc = nullptr, int desc_y = 0, int desc_out = 0);
+                     const int32_t* desc = nullptr, int desc_y = 0, int desc_out = 0, int maskx = 0);
 template <int MODE>
-hipError_t launch_nt_lp(const float* X, int64_t ldx, const float* Y, int64_t ldy, float* out, int64_t ldo, int64_t P,
-                        int Q, int64_t K, bool sub, int64_t ocap, int* nz_out, hipStream_t s);
+hipError_t launch_nt_lp(const void* X, int64_t ldx, const void* Y, int64_t ldy, float* out, int64_t ldo, int64_t P,
+                        int Q, int64_t K, bool sub, int64_t ocap, int* nz_out, hipStream_t s,
+                        const void* Xlo = nullptr, const void* Ylo = nullptr);
+hipError_t launch_split_x3(const float* src, int64_t lds, void* hi, void* lo, int64_t ldd, int64_t rows, int64_t cols,
+                           hipStream_t s);
 template <typename TS, bool UPPER>
 hipError_t launch_trsm_diag(const TS* R, int64_t ldr, int bo, TS* B, int64_t ldb, int nrhs, hipStream_t s,
                             const int32_t* desc = nullptr);
 hipError_t launch_advance_batch(int32_t* desc, hipStream_t s);
 hipError_t trsm_set_max_lds(size_t bytes);
+template <typename TS>
+hipError_t launch_rinv(const TS* A, int64_t lda, int64_t n, TS* RiR, TS* RiC, hipStream_t s);
+template <typename TS>
+hipError_t launch_rt(const TS* A, int64_t lda, int64_t n, TS* Rt, hipStream_t s);
+template <typename TS>
+hipError_t launch_copy_block(const TS* src, int64_t lds, TS* dst, int64_t ldd, int rows, int cols, hipStream_t s,
+                             const int32_t* desc);
+hipError_t rinv_set_max_lds(size_t bytes);
 hipError_t launch_residual(const int64_t* row_ptr, const int32_t* col, const double* val, int64_t m, const double* X,
                            int64_t ldx, const double* B, int64_t ldb, double* R, int64_t ldr, int nrhs,
                            hipStream_t s);
@@ -77,7 +91,8 @@ hipError_t launch_spmv_rows_t(const int64_t* ptr, const int32_t* idx, const doub
                               const double* Xt, const double* Bt, double* Rt, int64_t ld, int nrhs, hipStream_t s);
 hipError_t launch_spmv_cols_t(const int64_t* ptr, const int32_t* idx, const double* val, int64_t cols,
                               const double* Rt, double* St, int64_t ld, int nrhs, hipStream_t s);
-hipError_t launch_colnorm_t(const double* Zt, int64_t ld, int64_t rows, int nrhs, double* out, hipStream_t s);
+hipError_t launch_colnorm_t(const double* Zt, int64_t ld, int64_t rows, int nrhs, double* out, double* part,
+                            hipStream_t s);
 template <typename TI, typename TO, bool TO_T, bool ACC>
 hipError_t launch_transpose(const TI* in, TO* out, int64_t rows, int cols, int64_t ldc, int64_t ldt, hipStream_t s);
 }  // namespace ctqr
@@ -130,6 +145,7 @@ static int device_setup()
     if (p.maxSharedMemoryPerMultiProcessor > 0 && (size_t)p.maxSharedMemoryPerMultiProcessor < want)
         want = p.maxSharedMemoryPerMultiProcessor;
     if (panel_set_max_lds(want) != hipSuccess || trsm_set_max_lds(want) != hipSuccess ||
+        rinv_set_max_lds(want) != hipSuccess ||
         t_from_gram_set_max_lds(want) != hipSuccess) {
         (void)hipGetLastError();
         want = 64 * 1024;
@@ -173,21 +189,46 @@ struct ct_factor {
     int rw;            // panel rows per workgroup
     int64_t max_nrhs;
     struct StreamState* st = nullptr;   // host-pinned streaming state (null: A is in device memory)
+    // solve-side copies of R (in-memory factors): inverses of the 128 x 128
+    // diagonal blocks, row- and column-major, and the row-major block columns
+    void* RiR = nullptr;
+    void* RiC = nullptr;
+    void* Rt = nullptr;
+    // row-major copies of the outer reflector blocks (in-memory factors),
+    // written by the factorization and reused by every solve
+    void* VtAll = nullptr;
+    // T of every outer block in the storage type (FP32 factors; FP64 ones use T_all)
+    void* Tf = nullptr;
+    // bfloat16 high / low parts of the current reflector block (BF16x3 updates)
+    void* S3 = nullptr;
 };
 
 // Outer block width: the workspace is sized for kNbMax; an in-memory factor
 // uses kNbMax, a streamed one kNbMax when its tiles allow, else 128.
 constexpr int kNbMax = 256;
+
+// BF16x3 updates take the reflector block and W' already split into
+// bfloat16 halves (one split per block instead of one per tile);
+// CTQR_X3_PRESPLIT=0 splits inside the update kernel instead.
+static bool x3_presplit()
+{
+    static int v = -1;
+    if (v < 0) {
+        const char* e = getenv("CTQR_X3_PRESPLIT");
+        v = (e && e[0] == '0') ? 0 : 1;
+    }
+    return v == 1;
+}
 static int nb_out_for(int prec) { (void)prec; return kNbMax; }
 
 struct Layout {
-    size_t T_all, Tin, part, gpart, words, Wp, Wq, G, Vm, Vt, Ws, total;
+    size_t T_all, Tin, part, gpart, words, Wp, Wq, G, Vm, Vt, Ws, Ri, Rt, VtAll, Tf, S3, total;
     int64_t wp_elems, wq_elems;
 };
 
 static size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static Layout layout(int64_t m, int64_t n, int prec, int64_t max_nrhs)
+static Layout layout(int64_t m, int64_t n, int prec, int64_t max_nrhs, bool r_copies = true)
 {
     Layout L;
     const int nbo = nb_out_for(prec);
@@ -208,6 +249,16 @@ static Layout layout(int64_t m, int64_t n, int prec, int64_t max_nrhs)
     L.Vm = off; off += up256((size_t)ldm * nbo * 8);
     L.Vt = off; off += up256((size_t)ldm * nbo * 8);
     L.Ws = off; off += up256((size_t)L.wq_elems * 8);
+    // R copies for the solves: 2 inverses per 128-row block, and the block
+    // columns above the diagonal (128^2 nbt (nbt - 1) / 2 elements)
+    const size_t es = prec == CT_PREC_F64 ? 8 : 4;
+    const int64_t nbt = (n + 127) / 128;
+    L.Ri = off; off += r_copies ? up256((size_t)2 * nbt * 128 * 128 * es) : 0;
+    L.Rt = off; off += r_copies ? up256((size_t)128 * 128 * (size_t)(nbt * (nbt - 1) / 2) * es) : 0;
+    // reflector blocks, row-major: block b holds (m - b nbo) rows of nbo
+    L.VtAll = off; off += r_copies ? up256((size_t)(nblocks * m - nbo * (nblocks * (nblocks - 1) / 2)) * nbo * es) : 0;
+    L.Tf = off; off += prec == CT_PREC_F64 ? 0 : up256((size_t)nblocks * nbo * nbo * 4);
+    L.S3 = off; off += prec == CT_PREC_BF16X3 ? up256((size_t)ldm * nbo * 4) : 0;
     L.total = off;
     return L;
 }
@@ -264,10 +315,31 @@ static int64_t ldvt_of(int nbv) { return (nbv + 15) / 16 * 16; }
 
 // Masked copies of the reflector block into f->Vm / f->Vt
 template <typename TS>
-static int prep_block(ct_factor* f, const TS* V, int64_t ldv, int64_t mk, int nbv, hipStream_t s)
+static int prep_block(ct_factor* f, const TS* V, int64_t ldv, int64_t mk, int nbv, hipStream_t s,
+                      TS* vt_dst = nullptr)
 {
-    CT_HIP(launch_prep_v<TS>(V, ldv, mk, nbv, (TS*)f->Vm, f->ldvm, (TS*)f->Vt, ldvt_of(nbv), s));
+    CT_HIP(launch_prep_v<TS>(V, ldv, mk, nbv, (TS*)f->Vm, f->ldvm, vt_dst ? vt_dst : (TS*)f->Vt, ldvt_of(nbv), s));
     return 0;
+}
+
+// Operands of a block-reflector update: the block K-contiguous by reflector
+// (vm, ld ldvm; mask: read in place from the factored matrix, triangle
+// masked by the kernel) and K-contiguous by row (vt, ld ldvt).
+struct VOps {
+    const void* vm;
+    int64_t ldvm;
+    int mask;
+    const void* vt;
+    int64_t ldvt;
+    const void* tts;   // T in the storage type (column-major, ld as T, zero below
+                       // the diagonal) for an MFMA T^T W; null: FP64 T through tw
+};
+
+// Offset (elements) of outer block b in the row-major reflector store.
+static size_t vt_offset(const ct_factor* f, int64_t b)
+{
+    const int64_t nbo = f->nb_out;
+    return (size_t)(b * f->m - nbo * (b * (b - 1) / 2)) * (size_t)ldvt_of(nbo);
 }
 
 // Block-reflector update with the LDS-tiled NT kernel (FP32 / FP64 arithmetic
@@ -284,19 +356,32 @@ static hipError_t nt_any(const TS* X, int64_t ldx, const TS* Y, int64_t ldy, TS*
 
 template <typename TS, int OPT, int MODE = (sizeof(TS) == 8 ? M_F64 : M_F32)>
 static int larfb_nt(ct_factor* f, int64_t mk, int nbv, const double* T, int64_t ldt, TS* C, int64_t ldc, int nc,
-                    hipStream_t s, bool timed, const NtPlan* plan = nullptr, const int32_t* desc = nullptr)
+                    hipStream_t s, bool timed, const NtPlan* plan = nullptr, const int32_t* desc = nullptr,
+                    const VOps* ops = nullptr)
 {
     const double fl = 2.0 * (double)mk * nbv * nc;
     const int64_t ldw = ldvt_of(nbv);
+    const VOps o = ops ? *ops : VOps{f->Vm, f->ldvm, 0, f->Vt, ldw, nullptr};
     int nz = 1;
     {
         ProfScope ps(timed ? 0 : -1, fl, ((double)mk * nbv + (double)mk * nc) * sizeof(TS) + (double)nbv * nc * sizeof(TS), s);
-        if constexpr (MODE == M_F64 || MODE == M_F32)
-            CT_HIP(launch_nt<TS>((const TS*)f->Vm, f->ldvm, C, ldc, (TS*)f->Wp, nbv, nbv, nc, mk, false,
-                                 f->wp_elems * 8 / (int64_t)sizeof(TS), &nz, s, plan, desc, 1, 0));
-        else
-            CT_HIP((nt_any<TS, MODE>((const TS*)f->Vm, f->ldvm, C, ldc, (TS*)f->Wp, nbv, nbv, nc, mk, false,
-                                     f->wp_elems * 8 / (int64_t)sizeof(TS), &nz, s)));
+        if constexpr (MODE == M_F64 || MODE == M_F32) {
+            CT_HIP(launch_nt<TS>((const TS*)o.vm, o.ldvm, C, ldc, (TS*)f->Wp, nbv, nbv, nc, mk, false,
+                                 f->wp_elems * 8 / (int64_t)sizeof(TS), &nz, s, plan, desc, 1, 0, o.mask));
+        } else {
+            if (o.mask) return fail(-1, "%s", "internal: masked operand on the low-precision kernel");
+            if (MODE == M_BF16X3 && f->S3) {
+                // the block's bfloat16 halves, column-major like Vm
+                char* hi = (char*)f->S3;
+                char* lo = hi + (size_t)o.ldvm * nbv * 2;
+                CT_HIP(launch_split_x3((const float*)o.vm, o.ldvm, hi, lo, o.ldvm, mk, nbv, s));
+                CT_HIP(launch_nt_lp<M_BF16X3>(hi, o.ldvm, C, ldc, (float*)f->Wp, nbv, nbv, nc, mk, false,
+                                              f->wp_elems * 2, &nz, s, lo, nullptr));
+            } else {
+                CT_HIP((nt_any<TS, MODE>((const TS*)o.vm, o.ldvm, C, ldc, (TS*)f->Wp, nbv, nbv, nc, mk, false,
+                                         f->wp_elems * 8 / (int64_t)sizeof(TS), &nz, s)));
+            }
+        }
     }
     const TS* Wsum = (const TS*)f->Wp;
     if (nz > 1) {
@@ -304,16 +389,33 @@ static int larfb_nt(ct_factor* f, int64_t mk, int nbv, const double* T, int64_t 
                                           desc, nbv)));
         Wsum = (const TS*)f->Ws;
     }
-    CT_HIP((launch_tw<TS, TS, OPT, false>(Wsum, 1, nbv, nc, T, ldt, (TS*)f->Wq, nullptr, ldw, s, desc)));
+    if (OPT == 0 && o.tts) {
+        // W' = T^T W on the NT kernel: row p of T^T is column p of T
+        int nz1;
+        CT_HIP(launch_nt<TS>((const TS*)o.tts, ldt, Wsum, nbv, (TS*)f->Wq, ldw, nbv, nc, nbv, false, 0, &nz1, s, plan,
+                             desc, 0, 0));
+    } else {
+        CT_HIP((launch_tw<TS, TS, OPT, false>(Wsum, 1, nbv, nc, T, ldt, (TS*)f->Wq, nullptr, ldw, s, desc)));
+    }
     {
         ProfScope ps(timed ? 1 : -1, fl, (double)mk * nbv * sizeof(TS) + (double)nbv * nc * sizeof(TS) + 2.0 * mk * nc * sizeof(TS), s);
         int nz2;
         if constexpr (MODE == M_F64 || MODE == M_F32)
-            CT_HIP(launch_nt<TS>((const TS*)f->Vt, ldw, (const TS*)f->Wq, ldw, C, ldc, mk, nc, nbv, true, 0, &nz2, s,
+            CT_HIP(launch_nt<TS>((const TS*)o.vt, o.ldvt, (const TS*)f->Wq, ldw, C, ldc, mk, nc, nbv, true, 0, &nz2, s,
                                  plan, desc, 0, 1));
-        else
-            CT_HIP((nt_any<TS, MODE>((const TS*)f->Vt, ldw, (const TS*)f->Wq, ldw, C, ldc, mk, nc, nbv, true, 0, &nz2,
-                                     s)));
+        else if (MODE == M_BF16X3 && f->S3) {
+            // V (row-major) and W' in bfloat16 halves: V to the split scratch,
+            // W' to the split-K sum buffer, which is free by now
+            char* vh = (char*)f->S3;
+            char* vl = vh + (size_t)mk * o.ldvt * 2;
+            char* wh = (char*)f->Ws;
+            char* wl = wh + (size_t)ldw * nc * 2;
+            CT_HIP(launch_split_x3((const float*)o.vt, o.ldvt, vh, vl, o.ldvt, o.ldvt, mk, s));
+            CT_HIP(launch_split_x3((const float*)f->Wq, ldw, wh, wl, ldw, ldw, nc, s));
+            CT_HIP(launch_nt_lp<M_BF16X3>(vh, o.ldvt, wh, ldw, C, ldc, mk, nc, nbv, true, 0, &nz2, s, vl, wl));
+        } else
+            CT_HIP((nt_any<TS, MODE>((const TS*)o.vt, o.ldvt, (const TS*)f->Wq, ldw, C, ldc, mk, nc, nbv, true, 0,
+                                     &nz2, s)));
     }
     return 0;
 }
@@ -322,20 +424,22 @@ static int larfb_nt(ct_factor* f, int64_t mk, int nbv, const double* T, int64_t 
 // prepared: the block is already in f->Vm / f->Vt
 template <typename TS, int OPT>
 static int larfb_mode(ct_factor* f, int mode, const TS* V, int64_t ldv, int64_t mk, int nbv, const double* T,
-                      int64_t ldt, TS* C, int64_t ldc, int nc, hipStream_t s, bool timed = false, bool prepared = false)
+                      int64_t ldt, TS* C, int64_t ldc, int nc, hipStream_t s, bool timed = false, bool prepared = false,
+                      const VOps* ops = nullptr)
 {
     if (!prepared) {
         int r = prep_block<TS>(f, V, ldv, mk, nbv, s);
         if (r) return r;
     }
     if constexpr (sizeof(TS) == 8) {
-        return larfb_nt<TS, OPT, M_F64>(f, mk, nbv, T, ldt, C, ldc, nc, s, timed);
+        return larfb_nt<TS, OPT, M_F64>(f, mk, nbv, T, ldt, C, ldc, nc, s, timed, nullptr, nullptr, ops);
     } else {
         switch (mode) {
-            case M_F32: return larfb_nt<TS, OPT, M_F32>(f, mk, nbv, T, ldt, C, ldc, nc, s, timed);
-            case M_BF16: return larfb_nt<TS, OPT, M_BF16>(f, mk, nbv, T, ldt, C, ldc, nc, s, timed);
-            case M_F16: return larfb_nt<TS, OPT, M_F16>(f, mk, nbv, T, ldt, C, ldc, nc, s, timed);
-            case M_BF16X3: return larfb_nt<TS, OPT, M_BF16X3>(f, mk, nbv, T, ldt, C, ldc, nc, s, timed);
+            case M_F32: return larfb_nt<TS, OPT, M_F32>(f, mk, nbv, T, ldt, C, ldc, nc, s, timed, nullptr, nullptr, ops);
+            case M_BF16: return larfb_nt<TS, OPT, M_BF16>(f, mk, nbv, T, ldt, C, ldc, nc, s, timed, nullptr, nullptr, ops);
+            case M_F16: return larfb_nt<TS, OPT, M_F16>(f, mk, nbv, T, ldt, C, ldc, nc, s, timed, nullptr, nullptr, ops);
+            case M_BF16X3:
+                return larfb_nt<TS, OPT, M_BF16X3>(f, mk, nbv, T, ldt, C, ldc, nc, s, timed, nullptr, nullptr, ops);
         }
     }
     return fail(-1, "%s", "unsupported precision");
@@ -372,8 +476,18 @@ static int block_t(ct_factor* f, int64_t mk, int bo, const double* tau, double* 
         CT_HIP(launch_t_from_gram(f->G + n1 + (int64_t)n1 * bo, bo, tau + n1, n2, T + n1 + (int64_t)n1 * ldt, ldt, s));
         CT_HIP(launch_t12(f->G + (int64_t)n1 * bo, bo, T, T + n1 + (int64_t)n1 * ldt, ldt, (double*)f->Wq, n1, n2,
                           T + (int64_t)n1 * ldt, s));
+        CT_HIP(launch_zero_rows<double>(T, ldt, n1, bo, n1, s));     // below the diagonal blocks
     }
     return 0;
+}
+
+// T of outer block b in the storage type, for the MFMA form of T^T W.
+template <typename TS>
+static const TS* t_storage(const ct_factor* f, int64_t b)
+{
+    const size_t off = (size_t)b * f->nb_out * f->nb_out;
+    if constexpr (sizeof(TS) == 8) return (const TS*)(f->T_all + off);
+    else return f->Tf ? (const TS*)f->Tf + off : nullptr;
 }
 
 // Factor the columns [c0, c1) of the matrix in place, assuming every earlier
@@ -410,16 +524,23 @@ static int factor_cols(ct_factor* f, TS* C, int64_t c0, int64_t c1, hipStream_t 
             }
         }
         const int64_t nc = c1 - k0 - bo;
-        if (bo > nbi || nc > 0) {
-            int r = prep_block<TS>(f, Ab, lda, mk, bo, s);
+        // the row-major copy of the block goes to its persistent place when
+        // the solves keep one
+        TS* vt_dst = f->VtAll ? (TS*)f->VtAll + vt_offset(f, b) : nullptr;
+        if (bo > nbi || nc > 0 || vt_dst) {
+            int r = prep_block<TS>(f, Ab, lda, mk, bo, s, vt_dst);
             if (r) return r;
         }
         if (bo > nbi) {
             int r = block_t<TS>(f, mk, bo, f->tau + k0, Tb, nbo, s);
             if (r) return r;
         }
+        if constexpr (sizeof(TS) == 4)
+            if (f->Tf) CT_HIP((launch_convert<double, float>(Tb, nbo, (float*)f->Tf + (size_t)b * nbo * nbo, nbo, bo, bo, s)));
         if (nc > 0) {
-            int r = larfb_mode<TS, 0>(f, mode, Ab, lda, mk, bo, Tb, nbo, Ab + bo * lda, lda, (int)nc, s, true, true);
+            const VOps ops{f->Vm, f->ldvm, 0, vt_dst ? (const void*)vt_dst : f->Vt, ldvt_of(bo), t_storage<TS>(f, b)};
+            int r = larfb_mode<TS, 0>(f, mode, Ab, lda, mk, bo, Tb, nbo, Ab + bo * lda, lda, (int)nc, s, true, true,
+                                      &ops);
             if (r) return r;
         }
     }
@@ -734,10 +855,20 @@ static int apply_qt_impl(const ct_factor* fc, TS* B, int64_t nrhs, int64_t ldb, 
         const double* Tb = f->T_all + (size_t)b * nbo * nbo;
         const TS* Vb = walk.col(k0);
         if (!Vb) return walk.rc;
-        int r = prep_block<TS>(f, Vb + k0, f->lda, f->m - k0, bo, s);
-        if (r) return r;
-        r = transpose ? larfb_nt<TS, 0>(f, f->m - k0, bo, Tb, nbo, B + k0, ldb, (int)nrhs, s, false, plan, desc)
-                      : larfb_nt<TS, 1>(f, f->m - k0, bo, Tb, nbo, B + k0, ldb, (int)nrhs, s, false, plan, desc);
+        int r;
+        VOps ops;
+        const VOps* op = nullptr;
+        if (f->VtAll) {
+            // the block read in place (masked) and its stored row-major copy
+            ops = VOps{Vb + k0, f->lda, 1, (const TS*)f->VtAll + vt_offset(f, b), ldvt_of(bo), t_storage<TS>(f, b)};
+        } else {
+            r = prep_block<TS>(f, Vb + k0, f->lda, f->m - k0, bo, s);
+            if (r) return r;
+            ops = VOps{f->Vm, f->ldvm, 0, f->Vt, ldvt_of(bo), t_storage<TS>(f, b)};
+        }
+        op = &ops;
+        r = transpose ? larfb_nt<TS, 0>(f, f->m - k0, bo, Tb, nbo, B + k0, ldb, (int)nrhs, s, false, plan, desc, op)
+                      : larfb_nt<TS, 1>(f, f->m - k0, bo, Tb, nbo, B + k0, ldb, (int)nrhs, s, false, plan, desc, op);
         if (r) return r;
     }
     return walk.finish();
@@ -751,6 +882,25 @@ static int trsm_impl(const ct_factor* fc, TS* B, int64_t nrhs, int64_t ldb, hipS
     const int64_t n = f->n, lda = f->lda;
     const int tb = g_dev.trsm_block;
     const int64_t nb = (n + tb - 1) / tb;
+    if (f->Rt) {
+        // per block, last first: X_b = R_bb^{-1} B_b (copy to scratch, then a
+        // product with the stored inverse), then B[0:k0] -= R[0:k0, b] X_b with
+        // the row-major copy of the block column; both on the NT kernel
+        const NtPlan* plan = &f->solve_plan[bucket_of(nrhs)];
+        TS* S = (TS*)f->Wq;
+        for (int64_t b = nb - 1; b >= 0; --b) {
+            const int64_t k0 = b * 128;
+            const int bo = (int)std::min<int64_t>(128, n - k0);
+            int nz;
+            CT_HIP((launch_copy_block<TS>(B + k0, ldb, S, 128, bo, (int)nrhs, s, desc)));
+            CT_HIP(launch_nt<TS>((const TS*)f->RiR + (size_t)b * 128 * 128, 128, S, 128, B + k0, ldb, bo, (int)nrhs,
+                                 bo, false, 0, &nz, s, plan, desc, 0, 1));
+            if (k0 > 0)
+                CT_HIP(launch_nt<TS>((const TS*)f->Rt + (size_t)128 * 128 * (size_t)(b * (b - 1) / 2), 128, B + k0,
+                                     ldb, B, ldb, k0, (int)nrhs, bo, true, 0, &nz, s, plan, desc, 1, 1));
+        }
+        return 0;
+    }
     ColWalk<TS> walk(f, s, -1, false);
     for (int64_t b = nb - 1; b >= 0; --b) {
         const int64_t k0 = b * tb;
@@ -797,7 +947,16 @@ static int trsm_lt_impl(const ct_factor* fc, TS* Y, int64_t k, int64_t ldy, hipS
             }
             CT_HIP((launch_tw<TS, TS, 3, false>(Wsum, 1, bo, (int)k, nullptr, 0, Y + k0, nullptr, ldy, s)));
         }
-        CT_HIP((launch_trsm_diag<TS, false>(Rb + k0, lda, bo, Y + k0, ldy, (int)k, s)));
+        if (f->RiC) {
+            // Z_b = R_bb^{-T} Y_b with the stored inverse (column-major rows of R_bb^{-T})
+            TS* S = (TS*)f->Wq;
+            int nz;
+            CT_HIP((launch_copy_block<TS>(Y + k0, ldy, S, 128, bo, (int)k, s, nullptr)));
+            CT_HIP(launch_nt<TS>((const TS*)f->RiC + (size_t)b * 128 * 128, 128, S, 128, Y + k0, ldy, bo, (int)k, bo,
+                                 false, 0, &nz, s));
+        } else {
+            CT_HIP((launch_trsm_diag<TS, false>(Rb + k0, lda, bo, Y + k0, ldy, (int)k, s)));
+        }
     }
     return walk.finish();
 }
@@ -826,7 +985,8 @@ static int refined_impl(const ct_factor* f, const ct_sparse* sp, const double* B
     double* Rt = (double*)p; p += up256((size_t)m * lt * 8);
     double* Xt = (double*)p; p += up256((size_t)n * lt * 8);
     double* St = (double*)p; p += up256((size_t)n * lt * 8);
-    TS* C = (TS*)p;
+    TS* C = (TS*)p; p += up256((size_t)ld * nrhs * 8);
+    double* Np = (double*)p;                            // column-norm partials (256 x nrhs)
     const bool have_csc = sp->col_ptr && sp->row && sp->cval;
     const int nr = (int)nrhs;
     CT_HIP((launch_transpose<double, double, true, false>(B, Bt, m, nr, ldb, lt, s)));
@@ -841,11 +1001,11 @@ static int refined_impl(const ct_factor* f, const ct_sparse* sp, const double* B
     for (int st = 0; st <= steps; ++st) {
         // r_st = b - A x_st (FP64)
         CT_HIP(launch_spmv_rows_t(sp->row_ptr, sp->col, sp->val, m, Xt, Bt, Rt, lt, nr, s));
-        if (rnorms) CT_HIP(launch_colnorm_t(Rt, lt, m, nr, rnorms + (size_t)st * nrhs, s));
+        if (rnorms) CT_HIP(launch_colnorm_t(Rt, lt, m, nr, rnorms + (size_t)st * nrhs, Np, s));
         const bool need_grad = method == CT_REFINE_SNE ? st < steps : false;
         if (have_csc && (need_grad || gnorms)) {
             CT_HIP(launch_spmv_cols_t(sp->col_ptr, sp->row, sp->cval, n, Rt, St, lt, nr, s));
-            if (gnorms) CT_HIP(launch_colnorm_t(St, lt, n, nr, gnorms + (size_t)st * nrhs, s));
+            if (gnorms) CT_HIP(launch_colnorm_t(St, lt, n, nr, gnorms + (size_t)st * nrhs, Np, s));
         }
         if (st == steps) break;
         if (method == CT_REFINE_SNE) {
@@ -937,17 +1097,19 @@ static int init_factor(ct_factor* f, void* A, int64_t m, int64_t n, int64_t lda,
     f->Vt = w + L.Vt;
     f->ldvm = (m + 15) / 16 * 16;
     f->Ws = w + L.Ws;
+    f->Tf = f->f64 ? nullptr : (void*)(w + L.Tf);
+    f->S3 = prec == CT_PREC_BF16X3 && x3_presplit() ? (void*)(w + L.S3) : nullptr;
     f->barrier_base = 0;
     f->max_nrhs = max_nrhs;
     for (int b = 0; b < 5; ++b) f->solve_plan[b] = NtPlan{b < 2 ? 32 : 128, 1024};
 
     const size_t lds_words = g_dev.lds_max / 8 - panel_aux_words();
     int nbi = 32;
-    int rw = (int)(lds_words / nbi);
+    int rw = (int)std::min<size_t>(lds_words / nbi, (size_t)panel_max_rows());
     if ((rw & 1) == 0) --rw;
     if ((m + rw - 1) / rw > g_dev.cus) {
         nbi = 16;
-        rw = (int)(lds_words / nbi);
+        rw = (int)std::min<size_t>(lds_words / nbi, (size_t)panel_max_rows());
         if ((rw & 1) == 0) --rw;
     }
     if ((m + rw - 1) / rw > g_dev.cus) return fail(-2, "%s", "m too large for a resident panel on this device");
@@ -991,7 +1153,27 @@ int ct_qr_factor(void* A, int64_t m, int64_t n, int64_t lda, int prec, double* t
         return r;
     }
     CT_HIP(hipMemsetAsync((char*)work + L.words, 0, 256, s));
+    f->VtAll = (char*)work + L.VtAll;
     int rc = f->f64 ? factor_impl<double>(f, s) : factor_impl<float>(f, s);
+    if (!rc && g_dev.trsm_block == 128) {
+        // solve-side copies of R: diagonal-block inverses and row-major block columns
+        const size_t es = f->f64 ? 8 : 4;
+        f->RiR = (char*)work + L.Ri;
+        f->RiC = (char*)work + L.Ri + (size_t)((n + 127) / 128) * 128 * 128 * es;
+        f->Rt = (char*)work + L.Rt;
+        hipError_t e;
+        if (f->f64) {
+            e = launch_rinv<double>((const double*)A, lda, n, (double*)f->RiR, (double*)f->RiC, s);
+            if (e == hipSuccess) e = launch_rt<double>((const double*)A, lda, n, (double*)f->Rt, s);
+        } else {
+            e = launch_rinv<float>((const float*)A, lda, n, (float*)f->RiR, (float*)f->RiC, s);
+            if (e == hipSuccess) e = launch_rt<float>((const float*)A, lda, n, (float*)f->Rt, s);
+        }
+        if (e != hipSuccess) {
+            snprintf(g_err, sizeof g_err, "R copies: %s", hipGetErrorString(e));
+            rc = -1000 - (int)e;
+        }
+    }
     if (rc) {
         delete f;
         return rc;
@@ -1012,7 +1194,7 @@ int ct_qr_stream_workspace(int64_t m, int64_t n, int64_t lda, int prec, int64_t 
     CT_ARG(min_bytes != nullptr, 7, "min_bytes");
     const size_t es = prec == CT_PREC_F64 ? 8 : 4;
     const int64_t nt = (n + tile_cols - 1) / tile_cols;
-    const size_t base = layout(m, n, prec, max_nrhs).total, tb = tile_bytes(lda, tile_cols, es);
+    const size_t base = layout(m, n, prec, max_nrhs, false).total, tb = tile_bytes(lda, tile_cols, es);
     *min_bytes = base + std::min<int64_t>(nt, kSlots) * tb;
     if (all_resident_bytes) *all_resident_bytes = base + nt * tb;
     return 0;
@@ -1045,7 +1227,7 @@ int ct_qr_factor_streamed(void* A_host, int64_t m, int64_t n, int64_t lda, int p
         }
     }
     hipStream_t s = (hipStream_t)stream;
-    const Layout L = layout(m, n, prec, max_nrhs);
+    const Layout L = layout(m, n, prec, max_nrhs, false);
     const size_t es = prec == CT_PREC_F64 ? 8 : 4;
     const size_t tb = tile_bytes(lda, tile_cols, es);
     const int64_t nt = (n + tile_cols - 1) / tile_cols;
@@ -1133,6 +1315,12 @@ int ct_stream_info(const ct_factor* f, int64_t* tiles, int64_t* resident, int64_
     return 0;
 }
 
+int ct_debug_wait_limit(int64_t ticks)
+{
+    panel_set_wait_limit(ticks);
+    return 0;
+}
+
 int ct_stream_inject_failure(int64_t tile)
 {
     g_inject_fail_tile = tile;
@@ -1200,7 +1388,8 @@ int ct_refine_workspace(int64_t m, int64_t n, int64_t nrhs, size_t* bytes)
     CT_ARG(nrhs >= 0, 3, "nrhs");
     CT_ARG(bytes != nullptr, 4, "bytes");
     const int64_t ld = (m + 15) / 16 * 16, lt = (nrhs + 15) / 16 * 16;
-    *bytes = 2 * up256((size_t)m * lt * 8) + 2 * up256((size_t)n * lt * 8) + up256((size_t)ld * nrhs * 8);
+    *bytes = 2 * up256((size_t)m * lt * 8) + 2 * up256((size_t)n * lt * 8) + up256((size_t)ld * nrhs * 8) +
+             up256((size_t)256 * lt * 8);
     return 0;
 }
 

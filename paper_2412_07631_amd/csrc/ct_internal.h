@@ -39,9 +39,12 @@ template <typename T> struct Acc;
 template <> struct Acc<double> { typedef d4_t v; };
 template <> struct Acc<float> { typedef f4_t v; };
 
-// Spin limit of the cross-workgroup barriers (iterations of ~0.1 us sleeps);
-// reaching it sets the error word and lets every wave run to completion.
-constexpr uint32_t kSpinLimit = 1u << 26;
+// Time limit of one cross-workgroup wait, in ticks of the 100 MHz real-time
+// counter (0.5 s; a normal wait takes microseconds).  A wait that reaches it
+// sets bit 0 of the error word; every other wait, in this launch and in later
+// ones, sees the bit and ends at once, so a launch whose workgroups are not
+// all resident ends with an error instead of waiting without bound.
+constexpr uint64_t kWaitTicks = 50000000ull;
 
 // Device-side copy of the scanner description (see ct_geometry).
 struct GeomDev {

@@ -1,0 +1,151 @@
+// Native driver of libctqr (C-ABI only, no Python): assembles the Siddon
+// system matrix of a fan-beam scanner, factors it once at the chosen
+// precision and solves one block of right-hand sides, timing each phase with
+// HIP events.  Used for profiler runs (hardware counters) where a Python
+// process would add its own dispatches, and as a minimal example of the
+// interface.  An optional plain device-to-device copy of known size runs
+// first, so that the byte counters of a profiler can be calibrated on it.
+//
+//   ctqr_bench [--n-pix 256] [--views 120] [--bins 640]
+//              [--prec f64|f32|bf16|f16|bf16x3] [--nrhs 16] [--copy-mib 0]
+//
+// Scanner: grid width 1, source-isocentre distance 2, source-detector 4, flat
+// detector whose fan covers the circle inscribed in the image (the reading of
+// the paper's Table 1 geometry used throughout the library's tests).
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <vector>
+
+#include "../../include/ctqr.h"
+
+#define HIP_OK(x)                                                                       \
+    do {                                                                                \
+        hipError_t e_ = (x);                                                            \
+        if (e_ != hipSuccess) {                                                         \
+            fprintf(stderr, "%s failed: %s\n", #x, hipGetErrorString(e_));              \
+            exit(1);                                                                    \
+        }                                                                               \
+    } while (0)
+#define CT_OK(x)                                                                        \
+    do {                                                                                \
+        int r_ = (x);                                                                   \
+        if (r_ != 0) {                                                                  \
+            fprintf(stderr, "%s returned %d: %s\n", #x, r_, ct_last_error());           \
+            exit(1);                                                                    \
+        }                                                                               \
+    } while (0)
+
+static int prec_of(const char* s)
+{
+    if (!strcmp(s, "f64")) return CT_PREC_F64;
+    if (!strcmp(s, "f32")) return CT_PREC_F32;
+    if (!strcmp(s, "bf16")) return CT_PREC_BF16;
+    if (!strcmp(s, "f16")) return CT_PREC_F16;
+    if (!strcmp(s, "bf16x3")) return CT_PREC_BF16X3;
+    fprintf(stderr, "unknown precision %s\n", s);
+    exit(2);
+}
+
+int main(int argc, char** argv)
+{
+    int n_pix = 256, views = 120, bins = 640, nrhs = 16;
+    long copy_mib = 0;
+    const char* pname = "bf16x3";
+    for (int i = 1; i + 1 < argc; i += 2) {
+        if (!strcmp(argv[i], "--n-pix")) n_pix = atoi(argv[i + 1]);
+        else if (!strcmp(argv[i], "--views")) views = atoi(argv[i + 1]);
+        else if (!strcmp(argv[i], "--bins")) bins = atoi(argv[i + 1]);
+        else if (!strcmp(argv[i], "--prec")) pname = argv[i + 1];
+        else if (!strcmp(argv[i], "--nrhs")) nrhs = atoi(argv[i + 1]);
+        else if (!strcmp(argv[i], "--copy-mib")) copy_mib = atol(argv[i + 1]);
+        else {
+            fprintf(stderr, "unknown option %s\n", argv[i]);
+            return 2;
+        }
+    }
+    const int prec = prec_of(pname);
+    ct_geometry g;
+    memset(&g, 0, sizeof g);
+    g.n_pix = n_pix;
+    g.n_angles = views;
+    g.n_det = bins;
+    g.grid_width = 1.0;
+    g.sid = 2.0;
+    g.sdd = 4.0;
+    g.det_length = 2.0 * g.sdd * tan(asin(g.grid_width / (2.0 * g.sid)));
+    g.angle0 = 0.0;
+    const int64_t m = (int64_t)views * bins, n = (int64_t)n_pix * n_pix;
+    const int64_t lda = (m + 15) / 16 * 16;
+    const size_t es = prec == CT_PREC_F64 ? 8 : 4;
+    printf("m %lld n %lld prec %s nrhs %d\n", (long long)m, (long long)n, pname, nrhs);
+    fflush(stdout);
+
+    hipStream_t s;
+    HIP_OK(hipStreamCreate(&s));
+    if (copy_mib > 0) {
+        const size_t bytes = (size_t)copy_mib << 20;
+        void *a, *b;
+        HIP_OK(hipMalloc(&a, bytes));
+        HIP_OK(hipMalloc(&b, bytes));
+        HIP_OK(hipMemsetAsync(a, 1, bytes, s));
+        HIP_OK(hipMemcpyAsync(b, a, bytes, hipMemcpyDeviceToDevice, s));
+        HIP_OK(hipStreamSynchronize(s));
+        HIP_OK(hipFree(a));
+        HIP_OK(hipFree(b));
+        printf("copy probe: %ld MiB read, %ld MiB written\n", copy_mib, copy_mib);
+        fflush(stdout);
+    }
+
+    void *A, *work, *B;
+    double* tau;
+    size_t wbytes = 0;
+    CT_OK(ct_qr_workspace(m, n, prec, nrhs, &wbytes));
+    HIP_OK(hipMalloc(&A, (size_t)n * lda * es));
+    HIP_OK(hipMalloc(&tau, (size_t)n * sizeof(double)));
+    HIP_OK(hipMalloc(&work, wbytes));
+    HIP_OK(hipMalloc(&B, (size_t)nrhs * lda * es));
+    {
+        // right-hand sides: a fixed pseudo-random pattern (the factorization
+        // and the solve do not depend on the values)
+        std::vector<char> h((size_t)nrhs * lda * es);
+        uint64_t x = 0x9E3779B97F4A7C15ull;
+        for (size_t i = 0; i < (size_t)nrhs * lda; ++i) {
+            x ^= x << 13; x ^= x >> 7; x ^= x << 17;
+            const double v = (double)(x >> 11) / 9007199254740992.0;
+            if (es == 8) ((double*)h.data())[i] = v;
+            else ((float*)h.data())[i] = (float)v;
+        }
+        HIP_OK(hipMemcpy(B, h.data(), h.size(), hipMemcpyHostToDevice));
+    }
+    hipEvent_t ev[4];
+    for (auto& e : ev) HIP_OK(hipEventCreate(&e));
+    CT_OK(ct_build_system(&g, prec == CT_PREC_F64 ? CT_F64 : CT_F32, A, lda, s));
+    ct_factor* f = nullptr;
+    HIP_OK(hipEventRecord(ev[0], s));
+    CT_OK(ct_qr_factor(A, m, n, lda, prec, tau, work, wbytes, nrhs, &f, s));
+    HIP_OK(hipEventRecord(ev[1], s));
+    HIP_OK(hipEventRecord(ev[2], s));
+    CT_OK(ct_apply_qt(f, B, nrhs, lda, s));
+    CT_OK(ct_trsm_solve(f, B, nrhs, lda, s));
+    HIP_OK(hipEventRecord(ev[3], s));
+    int64_t info = 0;
+    CT_OK(ct_status(f, &info, s));
+    float qr_ms = 0, sol_ms = 0;
+    HIP_OK(hipEventElapsedTime(&qr_ms, ev[0], ev[1]));
+    HIP_OK(hipEventElapsedTime(&sol_ms, ev[2], ev[3]));
+    const double fl = 2.0 * m * (double)n * n - 2.0 * (double)n * n * n / 3.0;
+    printf("info %lld qr_ms %.1f qr_tflops %.2f solve_ms %.2f\n", (long long)info, qr_ms, fl / (qr_ms * 1e-3) / 1e12,
+           sol_ms);
+    CT_OK(ct_factor_destroy(f));
+    HIP_OK(hipFree(A));
+    HIP_OK(hipFree(tau));
+    HIP_OK(hipFree(work));
+    HIP_OK(hipFree(B));
+    HIP_OK(hipStreamDestroy(s));
+    return info == 0 ? 0 : 3;
+}

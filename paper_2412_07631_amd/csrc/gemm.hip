@@ -387,6 +387,50 @@ __global__ void __launch_bounds__(512) t_from_gram_kernel(const double* __restri
         }
 }
 
+// The same factor for nb <= 128 through its inverse: T^{-1} is upper
+// triangular with diagonal 1 / tau and the strictly upper part of the Gram
+// matrix (for H_1 ... H_nb = I - V T V^T; the two-reflector case reads
+// T = [t1, -t1 g t2; 0, t2] and its inverse [1/t1, g; 0, 1/t2]).  Column q of
+// T solves T^{-1} x = e_q by back-substitution, so every column is
+// independent: one thread per column, no barrier between columns.  G's upper
+// triangle and T are kept packed in LDS (entry (i, j), i <= j, at
+// j (j + 1) / 2 + i), FP64.
+__global__ void __launch_bounds__(128) t_from_gram_inv_kernel(const double* __restrict__ G, int64_t ldg,
+                                                              const double* __restrict__ tau, int nb, double* T,
+                                                              int64_t ldt)
+{
+    extern __shared__ double sh[];
+    const int np = nb * (nb + 1) / 2;
+    double* Gp = sh;
+    double* Xp = sh + np;
+    double* tl = Xp + np;                         // tau
+    const int t = threadIdx.x;
+    for (int j = 0; j < nb; ++j)
+        for (int i = t; i <= j; i += 128) Gp[j * (j + 1) / 2 + i] = G[i + (int64_t)j * ldg];
+    for (int i = t; i < nb; i += 128) tl[i] = tau[i];
+    __syncthreads();
+    if (t < nb) {
+        const int q = t;
+        const int cq = q * (q + 1) / 2;
+        Xp[cq + q] = tl[q];
+        for (int i = q - 1; i >= 0; --i) {
+            double s0 = 0.0, s1 = 0.0;
+            int l = i + 1;
+            for (; l + 1 <= q; l += 2) {
+                s0 += Gp[l * (l + 1) / 2 + i] * Xp[cq + l];
+                s1 += Gp[(l + 1) * (l + 2) / 2 + i] * Xp[cq + l + 1];
+            }
+            if (l <= q) s0 += Gp[l * (l + 1) / 2 + i] * Xp[cq + l];
+            Xp[cq + i] = -tl[i] * (s0 + s1);
+        }
+    }
+    __syncthreads();
+    for (int e = t; e < nb * nb; e += 128) {
+        const int q = e / nb, p = e - q * nb;
+        T[p + (int64_t)q * ldt] = p <= q ? Xp[q * (q + 1) / 2 + p] : 0.0;
+    }
+}
+
 // Compact-WY factor of two consecutive reflector blocks V = [V1 V2] from the
 // factors of each (H1 H2 = I - V T V^T):
 //   T = [ T1   -T1 (V1^T V2) T2 ]
@@ -528,6 +572,11 @@ hipError_t launch_tw(const TWp* Wp, int nz, int nbv, int N, const double* T, int
 hipError_t launch_t_from_gram(const double* G, int64_t ldg, const double* tau, int nb, double* T, int64_t ldt,
                               hipStream_t s)
 {
+    if (nb <= 128) {
+        const size_t shi = ((size_t)nb * (nb + 1) + nb) * sizeof(double);
+        hipLaunchKernelGGL(t_from_gram_inv_kernel, dim3(1), dim3(128), shi, s, G, ldg, tau, nb, T, ldt);
+        return hipGetLastError();
+    }
     const int in_lds = nb <= 128 ? 1 : 0;
     const size_t sh = ((size_t)nb + (in_lds ? (size_t)nb * (nb + 1) : 0)) * sizeof(double);
     hipLaunchKernelGGL(t_from_gram_kernel, dim3(1), dim3(512), sh, s, G, ldg, tau, nb, T, ldt, in_lds);
@@ -536,7 +585,11 @@ hipError_t launch_t_from_gram(const double* G, int64_t ldg, const double* tau, i
 
 hipError_t t_from_gram_set_max_lds(size_t bytes)
 {
-    return hipFuncSetAttribute((const void*)t_from_gram_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    hipError_t e = hipFuncSetAttribute((const void*)t_from_gram_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)t_from_gram_inv_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
 }
 
 template <typename TWp, typename TS>

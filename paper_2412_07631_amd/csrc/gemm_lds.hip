@@ -43,6 +43,13 @@ struct NtArgs {
     // count, and Y (desc_y) or out (desc_out) start at the offset
     const int32_t* desc;
     int desc_y, desc_out;
+    // X is a reflector block read in place (column p of the block from its
+    // diagonal down): entries above the diagonal read as 0, the diagonal as 1
+    int maskx;
+    // split operands of the BF16x3 kernel: X / Y hold the bfloat16 high parts
+    // and Xlo / Ylo the low parts, same leading dimension
+    const void* Xlo;
+    const void* Ylo;
 };
 
 __device__ __forceinline__ void apply_desc(const NtArgs& a, int& Q, const char*& Y, size_t ysz, char*& out, size_t osz)
@@ -126,6 +133,13 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_kernel(NtArgs a)
 #pragma unroll
                 for (int e = 0; e < VN; ++e)
                     if (kk + e < kend && pr < a.P) vx[e] = X[pr * a.ldx + kk + e];
+            }
+            if (a.maskx && kk < a.P) {
+#pragma unroll
+                for (int e = 0; e < VN; ++e) {
+                    const int64_t k = kk + e;
+                    vx[e] = k > pr ? vx[e] : (k == pr ? (T)1 : (T)0);
+                }
             }
             xr[ps] = vx;
         }
@@ -325,7 +339,7 @@ NtPlan g_nt_default = {128, 1024};
 template <typename T>
 hipError_t launch_nt(const T* X, int64_t ldx, const T* Y, int64_t ldy, T* out, int64_t ldo, int64_t P, int Q,
                      int64_t K, bool sub, int64_t ocap, int* nz_out, hipStream_t s, const NtPlan* plan,
-                     const int32_t* desc, int desc_y, int desc_out)
+                     const int32_t* desc, int desc_y, int desc_out, int maskx)
 {
     constexpr int BK = LdsTraits<T>::BK;
     const NtPlan pl = plan ? *plan : g_nt_default;
@@ -334,6 +348,7 @@ hipError_t launch_nt(const T* X, int64_t ldx, const T* Y, int64_t ldy, T* out, i
     a.X = X; a.ldx = ldx; a.Y = Y; a.ldy = ldy; a.out = out; a.ldo = ldo;
     a.P = P; a.Q = Q; a.K = K; a.sub = sub ? 1 : 0;
     a.desc = desc; a.desc_y = desc_y; a.desc_out = desc_out;
+    a.maskx = maskx;
     a.tiles_p = (int)((P + kBP - 1) / kBP);
     a.tiles_q = (Q + bq - 1) / bq;
     a.ostride = ldo * (int64_t)Q;
@@ -370,10 +385,10 @@ template hipError_t launch_prep_v<double>(const double*, int64_t, int64_t, int, 
                                           hipStream_t);
 template hipError_t launch_nt<float>(const float*, int64_t, const float*, int64_t, float*, int64_t, int64_t, int,
                                      int64_t, bool, int64_t, int*, hipStream_t, const NtPlan*, const int32_t*, int,
-                                     int);
+                                     int, int);
 template hipError_t launch_nt<double>(const double*, int64_t, const double*, int64_t, double*, int64_t, int64_t, int,
                                       int64_t, bool, int64_t, int*, hipStream_t, const NtPlan*, const int32_t*, int,
-                                      int);
+                                      int, int);
 
 
 // ---------------------------------------------------------------------------
@@ -399,7 +414,32 @@ __device__ __forceinline__ f4_t mfma_lp(const typename LpT<MODE>::v8& a, const t
     else return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
 }
 
-template <int MODE, bool SUB>
+// 16 bytes of bfloat16 (8 values)
+typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+
+// 8 consecutive bfloat16 of row `row` from K index kk (zero past kend or the
+// last row).
+__device__ __forceinline__ u4v load_bf8(const __bf16* M, int64_t ld, int64_t row, int64_t rows, int64_t kk,
+                                        int64_t kend)
+{
+    u4v v = {0, 0, 0, 0};
+    if (row >= rows) return v;
+    const __bf16* p = M + row * ld + kk;
+    if (kk + 8 <= kend) return *(const u4v*)p;
+    uint16_t e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const uint16_t* q = (const uint16_t*)p;
+    for (int i = 0; i < 8; ++i)
+        if (kk + i < kend) e[i] = q[i];
+    v[0] = e[0] | ((uint32_t)e[1] << 16);
+    v[1] = e[2] | ((uint32_t)e[3] << 16);
+    v[2] = e[4] | ((uint32_t)e[5] << 16);
+    v[3] = e[6] | ((uint32_t)e[7] << 16);
+    return v;
+}
+
+// PX / PY (BF16X3 only): the operand comes already split into bfloat16 high
+// and low parts (Xlo / Ylo), so staging is a plain copy into LDS.
+template <int MODE, bool SUB, bool PX = false, bool PY = false>
 __global__ void __launch_bounds__(256, 2) gemm_nt_lp_kernel(NtArgs a)
 {
     typedef typename LpT<MODE>::e E;
@@ -411,8 +451,8 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_lp_kernel(NtArgs a)
     constexpr int RPP = 256 / VPR;                // rows per pass
     constexpr int PASSES = kBP / RPP;             // 8
 
-    __shared__ E Xs[NH][kBP * LDK];
-    __shared__ E Ys[NH][kBQ * LDK];
+    __shared__ __attribute__((aligned(16))) E Xs[NH][kBP * LDK];
+    __shared__ __attribute__((aligned(16))) E Ys[NH][kBQ * LDK];
 
     int tp, tq;
     if (!tile_of(blockIdx.x, a.tiles_p, a.tiles_q, tp, tq)) return;
@@ -427,50 +467,95 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_lp_kernel(NtArgs a)
     const int t = threadIdx.x;
     const int lr = t / VPR, lv = t % VPR;
 
-    f4_t xr[PASSES], yr[PASSES];
+    // FP32 operands: 16 float per thread-row vector, split when staged
+    f4_t xr[PX ? 1 : PASSES], yr[PY ? 1 : PASSES];
+    // split operands: 8 bfloat16 per 16-byte vector, 4 passes of 32 rows
+    constexpr int VB = BK / 8, RB = 256 / VB, PB = kBP / RB;
+    u4v xs[PX ? 2 * PB : 1], ys[PY ? 2 * PB : 1];
+    const int lrb = t / VB, lvb = t % VB;
     auto gload = [&](int64_t k0) {
+        if constexpr (PX) {
+            const __bf16* Xh = (const __bf16*)a.X;
+            const __bf16* Xl = (const __bf16*)a.Xlo;
 #pragma unroll
-        for (int ps = 0; ps < PASSES; ++ps) {
-            const int row = ps * RPP + lr;
-            const int64_t kk = k0 + lv * 4;
-            const int64_t pr = p0 + row;
-            const int qr = q0 + row;
-            f4_t vx = {0, 0, 0, 0}, vy = {0, 0, 0, 0};
-            if (kk + 4 <= kend) {
-                if (pr < a.P) vx = *(const f4_t*)(X + pr * a.ldx + kk);
-                if (qr < a.Q) vy = *(const f4_t*)(Y + (int64_t)qr * a.ldy + kk);
-            } else {
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (kk + e < kend) {
-                        if (pr < a.P) vx[e] = X[pr * a.ldx + kk + e];
-                        if (qr < a.Q) vy[e] = Y[(int64_t)qr * a.ldy + kk + e];
-                    }
+            for (int ps = 0; ps < PB; ++ps) {
+                const int64_t pr = p0 + ps * RB + lrb, kk = k0 + lvb * 8;
+                xs[ps] = load_bf8(Xh, a.ldx, pr, a.P, kk, kend);
+                xs[PB + ps] = load_bf8(Xl, a.ldx, pr, a.P, kk, kend);
             }
-            xr[ps] = vx;
-            yr[ps] = vy;
+        }
+        if constexpr (PY) {
+            const __bf16* Yh = (const __bf16*)a.Y;
+            const __bf16* Yl = (const __bf16*)a.Ylo;
+#pragma unroll
+            for (int ps = 0; ps < PB; ++ps) {
+                const int64_t qr = q0 + ps * RB + lrb, kk = k0 + lvb * 8;
+                ys[ps] = load_bf8(Yh, a.ldy, qr, a.Q, kk, kend);
+                ys[PB + ps] = load_bf8(Yl, a.ldy, qr, a.Q, kk, kend);
+            }
+        }
+        if constexpr (!PX || !PY) {
+#pragma unroll
+            for (int ps = 0; ps < PASSES; ++ps) {
+                const int row = ps * RPP + lr;
+                const int64_t kk = k0 + lv * 4;
+                const int64_t pr = p0 + row;
+                const int qr = q0 + row;
+                f4_t vx = {0, 0, 0, 0}, vy = {0, 0, 0, 0};
+                if (kk + 4 <= kend) {
+                    if (!PX && pr < a.P) vx = *(const f4_t*)(X + pr * a.ldx + kk);
+                    if (!PY && qr < a.Q) vy = *(const f4_t*)(Y + (int64_t)qr * a.ldy + kk);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (kk + e < kend) {
+                            if (!PX && pr < a.P) vx[e] = X[pr * a.ldx + kk + e];
+                            if (!PY && qr < a.Q) vy[e] = Y[(int64_t)qr * a.ldy + kk + e];
+                        }
+                }
+                if constexpr (!PX) xr[ps] = vx;
+                if constexpr (!PY) yr[ps] = vy;
+            }
         }
     };
     auto sstore = [&]() {
+        if constexpr (PX) {
 #pragma unroll
-        for (int ps = 0; ps < PASSES; ++ps) {
-            const int row = ps * RPP + lr;
-            typedef E e4 __attribute__((ext_vector_type(4)));
-            e4 xh, yh, xl, yl;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                xh[e] = (E)xr[ps][e];
-                yh[e] = (E)yr[ps][e];
-                if constexpr (X3) {
-                    xl[e] = (E)(xr[ps][e] - (float)xh[e]);
-                    yl[e] = (E)(yr[ps][e] - (float)yh[e]);
-                }
+            for (int ps = 0; ps < PB; ++ps) {
+                const int row = ps * RB + lrb;
+                *(u4v*)&Xs[0][row * LDK + lvb * 8] = xs[ps];
+                *(u4v*)&Xs[NH - 1][row * LDK + lvb * 8] = xs[PB + ps];
             }
-            *(e4*)&Xs[0][row * LDK + lv * 4] = xh;
-            *(e4*)&Ys[0][row * LDK + lv * 4] = yh;
-            if constexpr (X3) {
-                *(e4*)&Xs[NH - 1][row * LDK + lv * 4] = xl;
-                *(e4*)&Ys[NH - 1][row * LDK + lv * 4] = yl;
+        }
+        if constexpr (PY) {
+#pragma unroll
+            for (int ps = 0; ps < PB; ++ps) {
+                const int row = ps * RB + lrb;
+                *(u4v*)&Ys[0][row * LDK + lvb * 8] = ys[ps];
+                *(u4v*)&Ys[NH - 1][row * LDK + lvb * 8] = ys[PB + ps];
+            }
+        }
+        if constexpr (!PX || !PY) {
+#pragma unroll
+            for (int ps = 0; ps < PASSES; ++ps) {
+                const int row = ps * RPP + lr;
+                typedef E e4 __attribute__((ext_vector_type(4)));
+                e4 xh, yh, xl, yl;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if constexpr (!PX) xh[e] = (E)xr[ps][e];
+                    if constexpr (!PY) yh[e] = (E)yr[ps][e];
+                    if constexpr (X3) {
+                        if constexpr (!PX) xl[e] = (E)(xr[ps][e] - (float)xh[e]);
+                        if constexpr (!PY) yl[e] = (E)(yr[ps][e] - (float)yh[e]);
+                    }
+                }
+                if constexpr (!PX) *(e4*)&Xs[0][row * LDK + lv * 4] = xh;
+                if constexpr (!PY) *(e4*)&Ys[0][row * LDK + lv * 4] = yh;
+                if constexpr (X3) {
+                    if constexpr (!PX) *(e4*)&Xs[NH - 1][row * LDK + lv * 4] = xl;
+                    if constexpr (!PY) *(e4*)&Ys[NH - 1][row * LDK + lv * 4] = yl;
+                }
             }
         }
     };
@@ -576,14 +661,16 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_lp_kernel(NtArgs a)
 }
 
 template <int MODE>
-hipError_t launch_nt_lp(const float* X, int64_t ldx, const float* Y, int64_t ldy, float* out, int64_t ldo, int64_t P,
-                        int Q, int64_t K, bool sub, int64_t ocap, int* nz_out, hipStream_t s)
+hipError_t launch_nt_lp(const void* X, int64_t ldx, const void* Y, int64_t ldy, float* out, int64_t ldo, int64_t P,
+                        int Q, int64_t K, bool sub, int64_t ocap, int* nz_out, hipStream_t s, const void* Xlo,
+                        const void* Ylo)
 {
     constexpr int BK = 64;
     NtArgs a;
     a.X = X; a.ldx = ldx; a.Y = Y; a.ldy = ldy; a.out = out; a.ldo = ldo;
     a.P = P; a.Q = Q; a.K = K; a.sub = sub ? 1 : 0;
-    a.desc = nullptr; a.desc_y = 0; a.desc_out = 0;
+    a.desc = nullptr; a.desc_y = 0; a.desc_out = 0; a.maskx = 0;
+    a.Xlo = Xlo; a.Ylo = Ylo;
     a.tiles_p = (int)((P + kBP - 1) / kBP);
     a.tiles_q = (Q + kBQ - 1) / kBQ;
     a.ostride = ldo * (int64_t)Q;
@@ -599,18 +686,58 @@ hipError_t launch_nt_lp(const float* X, int64_t ldx, const float* Y, int64_t ldy
     if (nz < 1) nz = 1;
     a.kslice = ks;
     *nz_out = nz;
+    const dim3 grid(padded_tiles(tiles), nz);
+    if constexpr (MODE == M_BF16X3) {
+        if (Xlo && Ylo) {
+            if (sub) hipLaunchKernelGGL((gemm_nt_lp_kernel<MODE, true, true, true>), grid, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((gemm_nt_lp_kernel<MODE, false, true, true>), grid, dim3(256), 0, s, a);
+            return hipGetLastError();
+        }
+        if (Xlo) {
+            if (sub) hipLaunchKernelGGL((gemm_nt_lp_kernel<MODE, true, true, false>), grid, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((gemm_nt_lp_kernel<MODE, false, true, false>), grid, dim3(256), 0, s, a);
+            return hipGetLastError();
+        }
+    }
     if (sub)
-        hipLaunchKernelGGL((gemm_nt_lp_kernel<MODE, true>), dim3(padded_tiles(tiles), nz), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((gemm_nt_lp_kernel<MODE, true>), grid, dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL((gemm_nt_lp_kernel<MODE, false>), dim3(padded_tiles(tiles), nz), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((gemm_nt_lp_kernel<MODE, false>), grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-template hipError_t launch_nt_lp<M_BF16>(const float*, int64_t, const float*, int64_t, float*, int64_t, int64_t, int,
-                                         int64_t, bool, int64_t, int*, hipStream_t);
-template hipError_t launch_nt_lp<M_F16>(const float*, int64_t, const float*, int64_t, float*, int64_t, int64_t, int,
-                                        int64_t, bool, int64_t, int*, hipStream_t);
-template hipError_t launch_nt_lp<M_BF16X3>(const float*, int64_t, const float*, int64_t, float*, int64_t, int64_t,
-                                           int, int64_t, bool, int64_t, int*, hipStream_t);
+// hi = bf16(x), lo = bf16(x - hi) for a column-major rows x cols FP32 block
+// (the same rounding as the BF16x3 kernel's staging).
+__global__ void __launch_bounds__(256) split_x3_kernel(const float* __restrict__ src, int64_t lds,
+                                                       __bf16* __restrict__ hi, __bf16* __restrict__ lo, int64_t ldd,
+                                                       int64_t rows, int64_t cols)
+{
+    const int64_t total = rows * cols;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int64_t c = e / rows, r = e - c * rows;
+        const float x = src[r + c * lds];
+        const __bf16 h = (__bf16)x;
+        hi[r + c * ldd] = h;
+        lo[r + c * ldd] = (__bf16)(x - (float)h);
+    }
+}
+
+hipError_t launch_split_x3(const float* src, int64_t lds, void* hi, void* lo, int64_t ldd, int64_t rows, int64_t cols,
+                           hipStream_t s)
+{
+    int64_t blocks = (rows * cols + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(split_x3_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, lds, (__bf16*)hi, (__bf16*)lo,
+                       ldd, rows, cols);
+    return hipGetLastError();
+}
+
+template hipError_t launch_nt_lp<M_BF16>(const void*, int64_t, const void*, int64_t, float*, int64_t, int64_t, int,
+                                         int64_t, bool, int64_t, int*, hipStream_t, const void*, const void*);
+template hipError_t launch_nt_lp<M_F16>(const void*, int64_t, const void*, int64_t, float*, int64_t, int64_t, int,
+                                        int64_t, bool, int64_t, int*, hipStream_t, const void*, const void*);
+template hipError_t launch_nt_lp<M_BF16X3>(const void*, int64_t, const void*, int64_t, float*, int64_t, int64_t, int,
+                                           int64_t, bool, int64_t, int*, hipStream_t, const void*, const void*);
 
 }  // namespace ctqr

@@ -63,6 +63,100 @@ __global__ void __launch_bounds__(256) trsm_diag_kernel(const TS* __restrict__ R
     }
 }
 
+// Inverses of the diagonal blocks of R, one workgroup per 128-row block.
+// The block (upper triangle) and its inverse are kept packed in LDS as FP64
+// (column-major triangle: entry (i, j), i <= j, at j (j + 1) / 2 + i); thread j
+// computes column j of the inverse by back-substitution against the unit
+// vector e_j, independently of the other columns.  Written in the storage type
+// twice: row-major (RiR, for X_b = R_bb^{-1} C_b) and column-major (RiC, for
+// Z_b = R_bb^{-T} C_b), both 128 x 128 with zeros outside the triangle.
+template <typename TS>
+__global__ void __launch_bounds__(128) rinv_kernel(const TS* __restrict__ A, int64_t lda, int64_t n,
+                                                   TS* __restrict__ RiR, TS* __restrict__ RiC)
+{
+    extern __shared__ double tri[];
+    constexpr int B = kTrsmBlock;
+    constexpr int NP = B * (B + 1) / 2;
+    double* Rp = tri;
+    double* Xp = tri + NP;
+    const int64_t k0 = (int64_t)blockIdx.x * B;
+    const int bo = (int)((n - k0) < B ? (n - k0) : B);
+    const TS* R = A + k0 + k0 * lda;
+    const int t = threadIdx.x;
+    for (int j = 0; j < bo; ++j)
+        for (int i = t; i <= j; i += B) Rp[j * (j + 1) / 2 + i] = (double)R[i + (int64_t)j * lda];
+    __syncthreads();
+    if (t < bo) {
+        const int j = t;
+        const int cj = j * (j + 1) / 2;
+        Xp[cj + j] = 1.0 / Rp[cj + j];
+        for (int i = j - 1; i >= 0; --i) {
+            double s0 = 0.0, s1 = 0.0;
+            int l = i + 1;
+            for (; l + 1 <= j; l += 2) {
+                s0 += Rp[l * (l + 1) / 2 + i] * Xp[cj + l];
+                s1 += Rp[(l + 1) * (l + 2) / 2 + i] * Xp[cj + l + 1];
+            }
+            if (l <= j) s0 += Rp[l * (l + 1) / 2 + i] * Xp[cj + l];
+            Xp[cj + i] = -(s0 + s1) / Rp[i * (i + 1) / 2 + i];
+        }
+    }
+    __syncthreads();
+    TS* outR = RiR + (size_t)blockIdx.x * B * B;
+    TS* outC = RiC + (size_t)blockIdx.x * B * B;
+    for (int e = t; e < B * B; e += B) {
+        const int i = e / B, j = e % B;          // row-major walk: (i, j) at i * B + j
+        outR[e] = (i <= j && j < bo) ? (TS)Xp[j * (j + 1) / 2 + i] : (TS)0;
+        const int jc = e / B, ic = e % B;        // column-major walk: (ic, jc) at jc * B + ic
+        outC[e] = (ic <= jc && jc < bo) ? (TS)Xp[jc * (jc + 1) / 2 + ic] : (TS)0;
+    }
+}
+
+// Row-major copies of the strictly-above-diagonal part of each block column
+// of R: for block b (columns k0 = 128 b .. k0 + bo), Rt_b[p * 128 + c] =
+// R[p][k0 + c] for rows p < k0 (zero for c >= bo).  Block b starts at element
+// 128 * 128 * b (b - 1) / 2.  Tiles of 32 rows x 128 columns pass through LDS
+// so that both the column-major reads and the row-major writes are coalesced.
+template <typename TS>
+__global__ void __launch_bounds__(256) rt_kernel(const TS* __restrict__ A, int64_t lda, int64_t n,
+                                                 TS* __restrict__ Rt)
+{
+    constexpr int B = kTrsmBlock;
+    __shared__ TS tile[B][33];
+    const int64_t b = blockIdx.y;
+    const int64_t k0 = b * B;
+    const int64_t p0 = (int64_t)blockIdx.x * 32;
+    if (p0 >= k0) return;
+    const int bo = (int)((n - k0) < B ? (n - k0) : B);
+    const int t = threadIdx.x;
+    for (int e = t; e < B * 32; e += 256) {
+        const int c = e / 32, r = e % 32;        // r fastest: along a column of R
+        const int64_t p = p0 + r;
+        tile[c][r] = (c < bo && p < k0) ? A[p + (k0 + c) * lda] : (TS)0;
+    }
+    __syncthreads();
+    TS* out = Rt + (size_t)B * B * (size_t)(b * (b - 1) / 2);
+    for (int e = t; e < B * 32; e += 256) {
+        const int r = e / B, c = e % B;          // c fastest: along a row of Rt
+        const int64_t p = p0 + r;
+        if (p < k0) out[p * B + c] = tile[c][r];
+    }
+}
+
+// dst[:, q] = src[:, q] for rows [0, rows) and the batch's columns; the
+// batch descriptor (if any) offsets the source columns.
+template <typename TS>
+__global__ void __launch_bounds__(256) copy_block_kernel(const TS* __restrict__ src, int64_t lds,
+                                                         TS* __restrict__ dst, int64_t ldd, int rows, int cols,
+                                                         const int32_t* desc)
+{
+    cols = desc_count(desc, cols);
+    src += (int64_t)desc_offset(desc) * lds;
+    for (int q = blockIdx.y; q < cols; q += gridDim.y)
+        for (int r = blockIdx.x * 256 + threadIdx.x; r < rows; r += gridDim.x * 256)
+            dst[r + (int64_t)q * ldd] = src[r + (int64_t)q * lds];
+}
+
 // R = B - A X in FP64 from the CSR copy of A; one lane per row, eight
 // right-hand sides per lane so each CSR entry is read once per eight columns.
 __global__ void __launch_bounds__(256) residual_kernel(const int64_t* __restrict__ row_ptr,
@@ -191,21 +285,38 @@ __global__ void __launch_bounds__(64) spmv_cols_t_kernel(const int64_t* __restri
 }
 
 // out[j] = ||Zt[:, j]||_2 over `rows` rows of a slice-contiguous block
+constexpr int kNormChunks = 256;
+
+// Column norms of a slice-contiguous block, in two deterministic passes:
+// workgroup (x, ch) sums the squares of rows ch, ch + kNormChunks, ... for 64
+// slices into part[ch][j]; the second pass adds the chunks in order.
 __global__ void __launch_bounds__(256) colnorm_t_kernel(const double* __restrict__ Zt, int64_t ld, int64_t rows,
-                                                        int nrhs, double* out)
+                                                        int nrhs, double* __restrict__ part)
 {
     __shared__ double red[4][64];
     const int j = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int part = threadIdx.x >> 6;
+    const int sub = threadIdx.x >> 6;
     double s = 0.0;
     if (j < nrhs)
-        for (int64_t i = part; i < rows; i += 4) {
+        for (int64_t i = blockIdx.y + (int64_t)kNormChunks * sub; i < rows; i += 4 * kNormChunks) {
             const double v = Zt[i * ld + j];
             s += v * v;
         }
-    red[part][threadIdx.x & 63] = s;
+    red[sub][threadIdx.x & 63] = s;
     __syncthreads();
-    if (part == 0 && j < nrhs) out[j] = sqrt(((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x]);
+    if (sub == 0 && j < nrhs)
+        part[(size_t)blockIdx.y * nrhs + j] =
+            ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+}
+
+__global__ void __launch_bounds__(256) colnorm_sum_kernel(const double* __restrict__ part, int nrhs,
+                                                          double* __restrict__ out)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= nrhs) return;
+    double s = 0.0;
+    for (int ch = 0; ch < kNormChunks; ++ch) s += part[(size_t)ch * nrhs + j];
+    out[j] = sqrt(s);
 }
 
 // Transpose with conversion between a column-major block (rows x cols, ld ldc)
@@ -326,6 +437,54 @@ hipError_t launch_trsm_diag(const TS* R, int64_t ldr, int bo, TS* B, int64_t ldb
     return hipGetLastError();
 }
 
+template <typename TS>
+hipError_t launch_rinv(const TS* A, int64_t lda, int64_t n, TS* RiR, TS* RiC, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)((n + kTrsmBlock - 1) / kTrsmBlock);
+    const size_t sh = (size_t)kTrsmBlock * (kTrsmBlock + 1) * sizeof(double);   // two packed triangles
+    hipLaunchKernelGGL(rinv_kernel<TS>, dim3(blocks), dim3(kTrsmBlock), sh, s, A, lda, n, RiR, RiC);
+    return hipGetLastError();
+}
+
+template <typename TS>
+hipError_t launch_rt(const TS* A, int64_t lda, int64_t n, TS* Rt, hipStream_t s)
+{
+    const int64_t nb = (n + kTrsmBlock - 1) / kTrsmBlock;
+    if (nb < 2) return hipSuccess;
+    const int64_t rows = (nb - 1) * kTrsmBlock;         // rows above the last block
+    hipLaunchKernelGGL(rt_kernel<TS>, dim3((unsigned)((rows + 31) / 32), (unsigned)nb), dim3(256), 0, s, A, lda, n,
+                       Rt);
+    return hipGetLastError();
+}
+
+template <typename TS>
+hipError_t launch_copy_block(const TS* src, int64_t lds, TS* dst, int64_t ldd, int rows, int cols, hipStream_t s,
+                             const int32_t* desc)
+{
+    unsigned gx = (unsigned)((rows + 255) / 256);
+    const unsigned gy = (unsigned)(cols < 65535 ? (cols > 0 ? cols : 1) : 65535);
+    hipLaunchKernelGGL(copy_block_kernel<TS>, dim3(gx, gy), dim3(256), 0, s, src, lds, dst, ldd, rows, cols, desc);
+    return hipGetLastError();
+}
+
+hipError_t rinv_set_max_lds(size_t bytes)
+{
+    hipError_t e = hipFuncSetAttribute((const void*)rinv_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)rinv_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
+
+template hipError_t launch_rinv<double>(const double*, int64_t, int64_t, double*, double*, hipStream_t);
+template hipError_t launch_rinv<float>(const float*, int64_t, int64_t, float*, float*, hipStream_t);
+template hipError_t launch_rt<double>(const double*, int64_t, int64_t, double*, hipStream_t);
+template hipError_t launch_rt<float>(const float*, int64_t, int64_t, float*, hipStream_t);
+template hipError_t launch_copy_block<double>(const double*, int64_t, double*, int64_t, int, int, hipStream_t,
+                                              const int32_t*);
+template hipError_t launch_copy_block<float>(const float*, int64_t, float*, int64_t, int, int, hipStream_t,
+                                             const int32_t*);
+
 // Advance the batch cursor of a graph-captured solve (last node of the graph).
 __global__ void advance_batch_kernel(int32_t* desc) { desc[0] += 1; }
 
@@ -378,9 +537,12 @@ hipError_t launch_spmv_cols_t(const int64_t* ptr, const int32_t* idx, const doub
     return hipGetLastError();
 }
 
-hipError_t launch_colnorm_t(const double* Zt, int64_t ld, int64_t rows, int nrhs, double* out, hipStream_t s)
+hipError_t launch_colnorm_t(const double* Zt, int64_t ld, int64_t rows, int nrhs, double* out, double* part,
+                            hipStream_t s)
 {
-    hipLaunchKernelGGL(colnorm_t_kernel, dim3((unsigned)((nrhs + 63) / 64)), dim3(256), 0, s, Zt, ld, rows, nrhs, out);
+    hipLaunchKernelGGL(colnorm_t_kernel, dim3((unsigned)((nrhs + 63) / 64), kNormChunks), dim3(256), 0, s, Zt, ld, rows,
+                       nrhs, part);
+    hipLaunchKernelGGL(colnorm_sum_kernel, dim3((unsigned)((nrhs + 255) / 256)), dim3(256), 0, s, part, nrhs, out);
     return hipGetLastError();
 }
 

@@ -57,6 +57,7 @@ _sig("ct_qr_factor_streamed", [_vp, _i64, _i64, _i64, ctypes.c_int, _vp, _vp, _s
 _sig("ct_qr_resume", [_vp, _vp])
 _sig("ct_stream_info", [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)])
 _sig("ct_stream_inject_failure", [_i64])
+_sig("ct_debug_wait_limit", [_i64])
 _sig("ct_apply_qt", [_vp, _vp, _i64, _i64, _vp])
 _sig("ct_trsm_solve", [_vp, _vp, _i64, _i64, _vp])
 _sig("ct_solve_backward", [_vp, _vp, _i64, _i64, _vp, _i64, _vp])
@@ -230,6 +231,12 @@ def stream_info(f: Factor):
 
 def inject_failure(tile: int):
     _check(_lib.ct_stream_inject_failure(tile))
+
+
+def debug_wait_limit(ticks: int):
+    """Time limit (100 MHz ticks) of one cross-workgroup wait of the panels;
+    negative restores the default."""
+    _check(_lib.ct_debug_wait_limit(ticks))
 
 
 def apply_qt(f: Factor, B: torch.Tensor, nrhs: int = None, stream=None):

@@ -57,16 +57,28 @@ def test_binding_marshals_without_gpu():
 
 def test_stream_workspace_arithmetic():
     """Streamed factorization: the minimum device buffer is the in-memory
-    workspace plus four staging tiles; keeping every tile resident needs the
-    workspace plus all tiles (tile = lda x tile_cols elements, 256-B rounded)."""
+    workspace without its solve-side copies (the diagonal-block inverses of R,
+    2 x 128 x 128 per 128-row block; the row-major block columns of R above the
+    diagonal, 128^2 b (b - 1) / 2 elements for b blocks; the row-major
+    reflector blocks, (m - 256 k) x 256 elements for outer block k) plus four
+    staging tiles; keeping every tile resident needs that workspace plus all
+    tiles (tile = lda x tile_cols elements, 256-B rounded)."""
     from paper_2412_07631_amd import ctqr
     m, n, lda = 3360, 2304, 3360
-    base = ctqr.qr_workspace(m, n, ctqr.PREC_F64, 8)
+    nbt = n // 128
+    nbo = (n + 255) // 256
+    up = lambda x: (x + 255) // 256 * 256
+    rcopies = (up(2 * nbt * 128 * 128 * 8) + up(128 * 128 * (nbt * (nbt - 1) // 2) * 8)
+               + up((nbo * m - 256 * (nbo * (nbo - 1) // 2)) * 256 * 8))
+    base = ctqr.qr_workspace(m, n, ctqr.PREC_F64, 8) - rcopies
     lo, full = ctqr.qr_stream_workspace(m, n, lda, ctqr.PREC_F64, 8, 256)
     tile = (lda * 256 * 8 + 255) // 256 * 256
     assert lo == base + 4 * tile and full == base + 9 * tile
     lo32, full32 = ctqr.qr_stream_workspace(m, n, lda, ctqr.PREC_BF16X3, 8, 1024)
-    assert full32 == ctqr.qr_workspace(m, n, ctqr.PREC_BF16X3, 8) + 3 * ((lda * 1024 * 4 + 255) // 256 * 256)
+    rc32 = (up(2 * nbt * 128 * 128 * 4) + up(128 * 128 * (nbt * (nbt - 1) // 2) * 4)
+            + up((nbo * m - 256 * (nbo * (nbo - 1) // 2)) * 256 * 4))
+    base32 = ctqr.qr_workspace(m, n, ctqr.PREC_BF16X3, 8) - rc32
+    assert full32 == base32 + 3 * ((lda * 1024 * 4 + 255) // 256 * 256)
     assert lo32 == full32          # three tiles: fewer than the staging slots
     for bad_tile in (0, 100, -128):
         try:

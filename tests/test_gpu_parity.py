@@ -257,3 +257,25 @@ def test_empty_batch_is_a_noop(ct):
     ct.apply_qt(f, Bd, nrhs=0)
     ct.trsm_solve(f, Bd, nrhs=0)
     assert torch.all(Bd == 1)
+
+
+# --------------------------------------------------------- failure handling
+def test_panel_wait_limit_fails_fast_and_recovers(ct):
+    """With the wait limit forced to zero from the host, every panel wait gives
+    up at once: the factorization ends (no hang) and ct_status reports -2001.
+    With the default limit restored the next factorization is correct."""
+    sc, A, VR, tau = problem("multi")
+    ct.debug_wait_limit(0)
+    try:
+        Ad = gpu_system(ct, sc, torch.float64)
+        f = ct.qr_factor(Ad, sc.m, sc.n, ct.PREC_F64, max_nrhs=1)
+        with pytest.raises(ct.CtError) as ei:
+            ct.status(f)
+        assert ei.value.code == -2001
+    finally:
+        ct.debug_wait_limit(-1)
+    Ad = gpu_system(ct, sc, torch.float64)
+    f = ct.qr_factor(Ad, sc.m, sc.n, ct.PREC_F64, max_nrhs=1)
+    assert ct.status(f) == 0
+    R, Rg = np.triu(VR[: sc.n]), np.triu(from_dev(Ad, sc.m)[: sc.n])
+    assert np.max(np.abs(Rg - R)) / np.max(np.abs(R)) <= 1e-12
