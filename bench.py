@@ -39,10 +39,13 @@ def solve_flops(m, n):
     return 4.0 * m * n - float(n) * n
 
 
-def batched_leg(ctqr, synth, torch, f, sc, Bd, dev, total):
+def batched_leg(ctqr, synth, torch, f, sc, Bd, dev, total, sp):
     """Uneven batches (seeded sizes 1..512) of sinograms through the
     graph-captured solve, then the adjoint on 64 upstream gradients with a
-    central finite-difference check (step 1e-3) on the same factor."""
+    central finite-difference check (step 1e-3) on the same factor.  The
+    finite differences use refined (FP64-residual) solves, so that their own
+    rounding (about kappa(A) u32 / h for plain FP32 solves) does not swamp
+    the comparison."""
     m, n = sc.m, sc.n
     sizes = synth.uneven_batches(total, 1, 512, cfg=4)
     nr = Bd.shape[0]
@@ -50,7 +53,7 @@ def batched_leg(ctqr, synth, torch, f, sc, Bd, dev, total):
     src = Bd[idx, :].to(f.dtype)                           # (total, ld) storage-typed sinograms
     Bb = torch.zeros_like(src)
     desc = ctqr.batch_descriptor(sizes, device=dev)
-    caps = (8, 32, 128, 512)
+    caps = (8, 16, 32, 64, 96, 128, 192, 256, 320, 384, 448, 512)
     cap_of = lambda c: next(x for x in caps if c <= x)
     graphs = {c: ctqr.SolveGraph(f, Bb, c, desc) for c in sorted({cap_of(c) for c in sizes})}
     gs = torch.cuda.Stream()
@@ -97,17 +100,20 @@ def batched_leg(ctqr, synth, torch, f, sc, Bd, dev, total):
     e1.record()
     torch.cuda.synchronize()
     bwd_ms = e0.elapsed_time(e1)
-    D = torch.from_numpy(np.ascontiguousarray(synth.directions(m, 4).T)).to(dev, torch.float64)
+    nd = 4
+    D = torch.from_numpy(np.ascontiguousarray(synth.directions(m, nd).T)).to(dev, torch.float64)
     h = 1e-3
-    fd_err = 0.0
+    Bpm = torch.zeros((2 * nd, ctqr.ld16(m)), dtype=torch.float64, device=dev)
     with torch.no_grad():
-        for j in range(4):
-            bp = (B0[j:j + 1].double() + h * D[j:j + 1]).to(f.dtype)
-            bm = (B0[j:j + 1].double() - h * D[j:j + 1]).to(f.dtype)
-            dx = (ctqr.qr_solve(bp, f).double() - ctqr.qr_solve(bm, f).double()) / (2 * h)
-            fd = float((dx * G[j:j + 1].double()).sum())
-            an = float((gB[j:j + 1].double() * D[j:j + 1]).sum())
-            fd_err = max(fd_err, abs(fd - an) / max(abs(an), 1e-30))
+        Bpm[:nd, :m] = B0[:nd].double() + h * D
+        Bpm[nd:, :m] = B0[:nd].double() - h * D
+    Xpm = torch.zeros((2 * nd, ctqr.ld16(n)), dtype=torch.float64, device=dev)
+    ctqr.solve_refined(f, sp, Bpm, Xpm, 4, ctqr.REFINE_SNE)
+    torch.cuda.synchronize()
+    dx = (Xpm[:nd, :n] - Xpm[nd:, :n]) / (2 * h)
+    fd = (dx * G[:nd].double()).sum(dim=1)
+    an = (gB[:nd].double() * D).sum(dim=1)
+    fd_err = float(((fd - an).abs() / an.abs()).max().item())
     return {"sinograms": total, "batches": len(sizes), "graph_slices_per_s": total / (g_ms * 1e-3),
             "eager_slices_per_s": total / (eager_ms * 1e-3), "graph_vs_eager_max_rel_diff": agree,
             "adjoint_gradients": k, "adjoint_ms": bwd_ms, "fd_step": h, "fd_max_rel_err": fd_err}
@@ -257,7 +263,7 @@ def main():
     # ------------------------------------- uneven batches and the adjoint
     batched = None
     if not args.no_batched:
-        batched = batched_leg(ctqr, synth, torch, f, sc, Bd, dev, args.batched_total)
+        batched = batched_leg(ctqr, synth, torch, f, sc, Bd, dev, args.batched_total, sp)
 
     # ------------------------------------------------------ roofline (live)
     dom = max(prof, key=lambda k: prof[k]["ms"])
@@ -268,10 +274,9 @@ def main():
              "bf16": "gemm_nt_lp_kernel<2, %s, false, false>", "f16": "gemm_nt_lp_kernel<3, %s, false, false>",
              "bf16x3": "gemm_nt_lp_kernel<4, %s>"}[args.prec]
     if args.prec == "bf16x3":
-        split = os.environ.get("CTQR_X3_PRESPLIT", "1") != "0"
-        args_cvw, args_vtc = ("true, true, true", "false, true, false") if split else ("true, false, false",
-                                                                                       "false, false, false")
-        kname = (tname % args_cvw) + " (C -= V W')" if dom == "update_cvw" else (tname % args_vtc) + " (W = V^T C)"
+        # both operands of C -= V W' and V of W = V^T C arrive split into bfloat16 halves
+        kname = (tname % "true, true, true") + " (C -= V W')" if dom == "update_cvw" else \
+            (tname % "false, true, false") + " (W = V^T C)"
     else:
         kname = (tname % "true") + " (C -= V W')" if dom == "update_cvw" else (tname % "false") + " (W = V^T C)"
     roofline = {"bound": "mfma", "kernel": kname,

@@ -25,7 +25,6 @@ hipError_t launch_panel(TS* A, int64_t lda, int64_t mk, int nbp, int rw, double*
                         uint64_t* flag_base, int64_t* info, int64_t col0, int32_t* err, hipStream_t s);
 size_t panel_lds_bytes(int nbp, int rw);
 int panel_aux_words();
-int panel_max_rows();
 hipError_t panel_set_max_lds(size_t bytes);
 hipError_t panel_max_active(int* per_cu, size_t shmem);
 void panel_set_wait_limit(int64_t ticks);
@@ -38,11 +37,8 @@ hipError_t launch_nn_sub(const TA* A, int64_t lda, const TB* Bhi, const TB* Blo,
 template <typename TWp, typename TO, int OP, bool SPLIT>
 hipError_t launch_tw(const TWp* Wp, int nz, int nbv, int N, const double* T, int64_t ldt, TO* out, TO* out_lo,
                      int64_t ldo, hipStream_t s, const int32_t* desc = nullptr);
-hipError_t launch_t_from_gram(const double* G, int64_t ldg, const double* tau, int nb, double* T, int64_t ldt,
-                              hipStream_t s);
-hipError_t t_from_gram_set_max_lds(size_t bytes);
-hipError_t launch_t12(const double* G12, int64_t ldg, const double* T1, const double* T2, int64_t ldt, double* M,
-                      int n1, int n2, double* T12, hipStream_t s);
+hipError_t launch_t_join(const double* G, int64_t ldg, double* T, int64_t ldt, double* M, int nb_panel, int bo,
+                         hipStream_t s);
 template <typename TWp, typename TS>
 hipError_t launch_sum_slices(const TWp* Wp, int64_t wstride, int nz, int64_t count, TS* S, hipStream_t s,
                              const int32_t* desc = nullptr, int per_col = 1);
@@ -145,8 +141,7 @@ static int device_setup()
     if (p.maxSharedMemoryPerMultiProcessor > 0 && (size_t)p.maxSharedMemoryPerMultiProcessor < want)
         want = p.maxSharedMemoryPerMultiProcessor;
     if (panel_set_max_lds(want) != hipSuccess || trsm_set_max_lds(want) != hipSuccess ||
-        rinv_set_max_lds(want) != hipSuccess ||
-        t_from_gram_set_max_lds(want) != hipSuccess) {
+        rinv_set_max_lds(want) != hipSuccess) {
         (void)hipGetLastError();
         want = 64 * 1024;
     }
@@ -167,7 +162,6 @@ struct ct_factor {
     int64_t nblocks;
     // workspace partition
     double* T_all;     // nblocks x nb_out x nb_out
-    double* Tin;       // 32 x 32
     double* part;      // 2 x 256 x 64
     double* gpart;     // 256 x 1024
     uint64_t* counter;
@@ -207,22 +201,10 @@ struct ct_factor {
 // uses kNbMax, a streamed one kNbMax when its tiles allow, else 128.
 constexpr int kNbMax = 256;
 
-// BF16x3 updates take the reflector block and W' already split into
-// bfloat16 halves (one split per block instead of one per tile);
-// CTQR_X3_PRESPLIT=0 splits inside the update kernel instead.
-static bool x3_presplit()
-{
-    static int v = -1;
-    if (v < 0) {
-        const char* e = getenv("CTQR_X3_PRESPLIT");
-        v = (e && e[0] == '0') ? 0 : 1;
-    }
-    return v == 1;
-}
 static int nb_out_for(int prec) { (void)prec; return kNbMax; }
 
 struct Layout {
-    size_t T_all, Tin, part, gpart, words, Wp, Wq, G, Vm, Vt, Ws, Ri, Rt, VtAll, Tf, S3, total;
+    size_t T_all, part, gpart, words, Wp, Wq, G, Vm, Vt, Ws, Ri, Rt, VtAll, Tf, S3, total;
     int64_t wp_elems, wq_elems;
 };
 
@@ -238,7 +220,6 @@ static Layout layout(int64_t m, int64_t n, int prec, int64_t max_nrhs, bool r_co
     L.wq_elems = (int64_t)nbo * std::max<int64_t>(n, std::max<int64_t>(max_nrhs, 1));
     size_t off = 0;
     L.T_all = off; off += up256((size_t)nblocks * nbo * nbo * 8);
-    L.Tin = off; off += up256(32 * 32 * 8);
     L.part = off; off += up256(2 * 256 * 64 * 8 + 2 * 64 * 8);
     L.gpart = off; off += up256(256 * 1024 * 8);
     L.words = off; off += 256;
@@ -457,27 +438,17 @@ static int trailing_mode(int prec)
     }
 }
 
-// Gram of the masked reflector block and its compact-WY factor
-// Gram of the prepared (masked) block in f->Vm, in the storage precision, and
-// the compact-WY factor from it.
+// Compact-WY factor of an outer block whose panels have left their own
+// factors on T's diagonal: the Gram matrix of the prepared (masked) block in
+// f->Vm, in the storage precision, then pairwise joins of the panel factors.
 template <typename TS>
-static int block_t(ct_factor* f, int64_t mk, int bo, const double* tau, double* T, int64_t ldt, hipStream_t s)
+static int block_t(ct_factor* f, int64_t mk, int bo, double* T, int64_t ldt, hipStream_t s)
 {
     int nz = 1;
     CT_HIP(launch_nt<TS>((const TS*)f->Vm, f->ldvm, (const TS*)f->Vm, f->ldvm, (TS*)f->Wp, bo, bo, bo, mk, false,
                          f->wp_elems * 8 / (int64_t)sizeof(TS), &nz, s));
     CT_HIP((launch_sum_slices<TS, double>((const TS*)f->Wp, (int64_t)bo * bo, nz, (int64_t)bo * bo, f->G, s)));
-    if (bo <= 128) {
-        CT_HIP(launch_t_from_gram(f->G, bo, tau, bo, T, ldt, s));
-    } else {
-        // two halves, each built in LDS, then their coupling block
-        const int n1 = 128, n2 = bo - 128;
-        CT_HIP(launch_t_from_gram(f->G, bo, tau, n1, T, ldt, s));
-        CT_HIP(launch_t_from_gram(f->G + n1 + (int64_t)n1 * bo, bo, tau + n1, n2, T + n1 + (int64_t)n1 * ldt, ldt, s));
-        CT_HIP(launch_t12(f->G + (int64_t)n1 * bo, bo, T, T + n1 + (int64_t)n1 * ldt, ldt, (double*)f->Wq, n1, n2,
-                          T + (int64_t)n1 * ldt, s));
-        CT_HIP(launch_zero_rows<double>(T, ldt, n1, bo, n1, s));     // below the diagonal blocks
-    }
+    CT_HIP(launch_t_join(f->G, bo, T, ldt, (double*)f->Wq, f->nb_in, bo, s));
     return 0;
 }
 
@@ -512,9 +483,9 @@ static int factor_cols(ct_factor* f, TS* C, int64_t c0, int64_t c1, hipStream_t 
             const int bi = (int)std::min<int64_t>(nbi, k0 + bo - p0);
             const int64_t mkp = m - p0;
             TS* Vp = Ab + (p0 - k0) * lda + (p0 - k0);
-            // the panel writes its T straight into the block's T when it is the only panel
-            double* Tp = (bo == bi) ? Tb : f->Tin;
-            const int64_t ldtp = (bo == bi) ? nbo : 32;
+            // the panel writes its factor on the diagonal of the block's T
+            double* Tp = Tb + (p0 - k0) * (1 + (int64_t)nbo);
+            const int64_t ldtp = nbo;
             CT_HIP(launch_panel<TS>(Vp, lda, mkp, bi, f->rw, f->tau + p0, Tp, ldtp, f->part, f->gpart, f->counter,
                                     &f->barrier_base, f->flag, &f->flag_base, f->info, p0, f->err, s));
             const int64_t rest = k0 + bo - (p0 + bi);
@@ -532,7 +503,7 @@ static int factor_cols(ct_factor* f, TS* C, int64_t c0, int64_t c1, hipStream_t 
             if (r) return r;
         }
         if (bo > nbi) {
-            int r = block_t<TS>(f, mk, bo, f->tau + k0, Tb, nbo, s);
+            int r = block_t<TS>(f, mk, bo, Tb, nbo, s);
             if (r) return r;
         }
         if constexpr (sizeof(TS) == 4)
@@ -1082,7 +1053,6 @@ static int init_factor(ct_factor* f, void* A, int64_t m, int64_t n, int64_t lda,
     f->nb_out = nbo;
     f->nblocks = (n + f->nb_out - 1) / f->nb_out;
     f->T_all = (double*)(w + L.T_all);
-    f->Tin = (double*)(w + L.Tin);
     f->part = (double*)(w + L.part);
     f->gpart = (double*)(w + L.gpart);
     f->counter = (uint64_t*)(w + L.words);
@@ -1098,18 +1068,20 @@ static int init_factor(ct_factor* f, void* A, int64_t m, int64_t n, int64_t lda,
     f->ldvm = (m + 15) / 16 * 16;
     f->Ws = w + L.Ws;
     f->Tf = f->f64 ? nullptr : (void*)(w + L.Tf);
-    f->S3 = prec == CT_PREC_BF16X3 && x3_presplit() ? (void*)(w + L.S3) : nullptr;
+    // BF16x3 updates take the reflector block and W' already split into
+    // bfloat16 halves (one split per block instead of one per tile)
+    f->S3 = prec == CT_PREC_BF16X3 ? (void*)(w + L.S3) : nullptr;
     f->barrier_base = 0;
     f->max_nrhs = max_nrhs;
     for (int b = 0; b < 5; ++b) f->solve_plan[b] = NtPlan{b < 2 ? 32 : 128, 1024};
 
     const size_t lds_words = g_dev.lds_max / 8 - panel_aux_words();
     int nbi = 32;
-    int rw = (int)std::min<size_t>(lds_words / nbi, (size_t)panel_max_rows());
+    int rw = (int)(lds_words / nbi);
     if ((rw & 1) == 0) --rw;
     if ((m + rw - 1) / rw > g_dev.cus) {
         nbi = 16;
-        rw = (int)std::min<size_t>(lds_words / nbi, (size_t)panel_max_rows());
+        rw = (int)(lds_words / nbi);
         if ((rw & 1) == 0) --rw;
     }
     if ((m + rw - 1) / rw > g_dev.cus) return fail(-2, "%s", "m too large for a resident panel on this device");

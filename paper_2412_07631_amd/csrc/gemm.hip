@@ -341,139 +341,73 @@ __global__ void __launch_bounds__(256) tw_kernel(const TWp* __restrict__ Wp, int
 }
 
 // ---------------------------------------------------------------------------
-// Compact-WY factor of a reflector block from its Gram matrix G = V^T V:
-//   T_qq = tau_q,  T[p][q] = -tau_q sum_{l=p}^{q-1} T[p][l] G[l][q]  (p < q).
-// One workgroup.  For nb <= 128 T is built in LDS (FP64) and written once;
-// larger blocks build it in place in global memory (L2-resident).
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(512) t_from_gram_kernel(const double* __restrict__ G, int64_t ldg,
-                                                         const double* __restrict__ tau, int nb, double* T,
-                                                         int64_t ldt, int in_lds)
-{
-    extern __shared__ double sh[];
-    const int t = threadIdx.x;
-    double* gq = sh;                              // nb
-    double* Ts = sh + nb;                         // nb x (nb + 1) when in LDS
-    const int lds_ld = nb + 1;
-    double* Tw = in_lds ? Ts : T;
-    const int64_t ld = in_lds ? lds_ld : ldt;
-    for (int e = t; e < nb * nb; e += 512) {
-        const int q = e / nb, p = e - q * nb;
-        Tw[p + (int64_t)q * ld] = 0.0;
-    }
-    __syncthreads();
-    for (int q = 0; q < nb; ++q) {
-        for (int l = t; l < q; l += 512) gq[l] = G[l + (int64_t)q * ldg];
-        __syncthreads();
-        const double tq = tau[q];
-        for (int p = t; p < q; p += 512) {
-            double s0 = 0.0, s1 = 0.0;
-            int l = p;
-            for (; l + 1 < q; l += 2) {
-                s0 += Tw[p + (int64_t)l * ld] * gq[l];
-                s1 += Tw[p + (int64_t)(l + 1) * ld] * gq[l + 1];
-            }
-            if (l < q) s0 += Tw[p + (int64_t)l * ld] * gq[l];
-            Tw[p + (int64_t)q * ld] = -tq * (s0 + s1);
-        }
-        if (t == 0) Tw[q + (int64_t)q * ld] = tq;
-        __threadfence_block();
-        __syncthreads();
-    }
-    if (in_lds)
-        for (int e = t; e < nb * nb; e += 512) {
-            const int q = e / nb, p = e - q * nb;
-            T[p + (int64_t)q * ldt] = Ts[p + q * lds_ld];
-        }
-}
-
-// The same factor for nb <= 128 through its inverse: T^{-1} is upper
-// triangular with diagonal 1 / tau and the strictly upper part of the Gram
-// matrix (for H_1 ... H_nb = I - V T V^T; the two-reflector case reads
-// T = [t1, -t1 g t2; 0, t2] and its inverse [1/t1, g; 0, 1/t2]).  Column q of
-// T solves T^{-1} x = e_q by back-substitution, so every column is
-// independent: one thread per column, no barrier between columns.  G's upper
-// triangle and T are kept packed in LDS (entry (i, j), i <= j, at
-// j (j + 1) / 2 + i), FP64.
-__global__ void __launch_bounds__(128) t_from_gram_inv_kernel(const double* __restrict__ G, int64_t ldg,
-                                                              const double* __restrict__ tau, int nb, double* T,
-                                                              int64_t ldt)
-{
-    extern __shared__ double sh[];
-    const int np = nb * (nb + 1) / 2;
-    double* Gp = sh;
-    double* Xp = sh + np;
-    double* tl = Xp + np;                         // tau
-    const int t = threadIdx.x;
-    for (int j = 0; j < nb; ++j)
-        for (int i = t; i <= j; i += 128) Gp[j * (j + 1) / 2 + i] = G[i + (int64_t)j * ldg];
-    for (int i = t; i < nb; i += 128) tl[i] = tau[i];
-    __syncthreads();
-    if (t < nb) {
-        const int q = t;
-        const int cq = q * (q + 1) / 2;
-        Xp[cq + q] = tl[q];
-        for (int i = q - 1; i >= 0; --i) {
-            double s0 = 0.0, s1 = 0.0;
-            int l = i + 1;
-            for (; l + 1 <= q; l += 2) {
-                s0 += Gp[l * (l + 1) / 2 + i] * Xp[cq + l];
-                s1 += Gp[(l + 1) * (l + 2) / 2 + i] * Xp[cq + l + 1];
-            }
-            if (l <= q) s0 += Gp[l * (l + 1) / 2 + i] * Xp[cq + l];
-            Xp[cq + i] = -tl[i] * (s0 + s1);
-        }
-    }
-    __syncthreads();
-    for (int e = t; e < nb * nb; e += 128) {
-        const int q = e / nb, p = e - q * nb;
-        T[p + (int64_t)q * ldt] = p <= q ? Xp[q * (q + 1) / 2 + p] : 0.0;
-    }
-}
-
-// Compact-WY factor of two consecutive reflector blocks V = [V1 V2] from the
-// factors of each (H1 H2 = I - V T V^T):
+// Compact-WY factor of an outer reflector block from the factors of its
+// panels.  For consecutive groups of reflectors V = [V1 V2] with factors T1,
+// T2 (H1 H2 = I - V T V^T):
 //   T = [ T1   -T1 (V1^T V2) T2 ]
 //       [ 0     T2              ]
-// STEP 0: M = G12 T2 (n1 x n2, ld n1), with G12 = V1^T V2 and T2 upper
-// triangular; STEP 1: T12 = -T1 M, T1 upper triangular.  One output per thread.
+// The panels leave their factors on T's diagonal (width s); one level joins
+// adjacent groups [a, a + s) and [a + s, c), pair i = blockIdx.y, a = 2 s i,
+// using the block's Gram matrix G = V^T V for V1^T V2.
+// STEP 0: M_i = G12 T2 (T2 upper triangular); STEP 1: T12 = -T1 M_i.
+// One output per thread.
+// ---------------------------------------------------------------------------
 template <int STEP>
-__global__ void __launch_bounds__(256) t12_kernel(const double* __restrict__ A, int64_t lda,
-                                                  const double* __restrict__ Tt, int64_t ldt, double* __restrict__ out,
-                                                  int64_t ldo, int n1, int n2)
+__global__ void __launch_bounds__(256) t_join_kernel(const double* __restrict__ G, int64_t ldg, double* T,
+                                                     int64_t ldt, double* M, int sz, int bo)
 {
+    const int a = 2 * sz * blockIdx.y, b = a + sz;
+    const int c = a + 2 * sz < bo ? a + 2 * sz : bo;
+    const int n1 = sz, n2 = c - b;
+    if (n2 <= 0) return;
     const int e = blockIdx.x * 256 + threadIdx.x;
     if (e >= n1 * n2) return;
-    const int i = e % n1, j = e / n1;
+    const int r = e % n1, q = e / n1;
+    double* Mi = M + (size_t)blockIdx.y * sz * sz;          // n1 x n2, ld n1
     double s0 = 0.0, s1 = 0.0;
     if (STEP == 0) {
-        // A = G12 (n1 x n2), Tt = T2: sum over l <= j of G12[i][l] T2[l][j]
+        // M[r][q] = sum_{l <= q} G[a + r][b + l] T[b + l][b + q]
+        const double* g = G + (a + r) + (int64_t)b * ldg;
+        const double* t2 = T + b + (int64_t)(b + q) * ldt;
         int l = 0;
-        for (; l + 1 <= j; l += 2) {
-            s0 += A[i + (int64_t)l * lda] * Tt[l + (int64_t)j * ldt];
-            s1 += A[i + (int64_t)(l + 1) * lda] * Tt[(l + 1) + (int64_t)j * ldt];
+        for (; l + 1 <= q; l += 2) {
+            s0 += g[(int64_t)l * ldg] * t2[l];
+            s1 += g[(int64_t)(l + 1) * ldg] * t2[l + 1];
         }
-        if (l <= j) s0 += A[i + (int64_t)l * lda] * Tt[l + (int64_t)j * ldt];
-        out[i + (int64_t)j * ldo] = s0 + s1;
+        if (l <= q) s0 += g[(int64_t)l * ldg] * t2[l];
+        Mi[r + q * n1] = s0 + s1;
     } else {
-        // A = M (n1 x n2), Tt = T1: -(sum over l >= i of T1[i][l] M[l][j])
-        int l = i;
+        // T[a + r][b + q] = -sum_{l >= r} T[a + r][a + l] M[l][q]
+        const double* t1 = T + (a + r) + (int64_t)a * ldt;
+        const double* mq = Mi + (size_t)q * n1;
+        int l = r;
         for (; l + 1 < n1; l += 2) {
-            s0 += Tt[i + (int64_t)l * ldt] * A[l + (int64_t)j * lda];
-            s1 += Tt[i + (int64_t)(l + 1) * ldt] * A[(l + 1) + (int64_t)j * lda];
+            s0 += t1[(int64_t)l * ldt] * mq[l];
+            s1 += t1[(int64_t)(l + 1) * ldt] * mq[l + 1];
         }
-        if (l < n1) s0 += Tt[i + (int64_t)l * ldt] * A[l + (int64_t)j * lda];
-        out[i + (int64_t)j * ldo] = -(s0 + s1);
+        if (l < n1) s0 += t1[(int64_t)l * ldt] * mq[l];
+        T[(a + r) + (int64_t)(b + q) * ldt] = -(s0 + s1);
     }
 }
 
-hipError_t launch_t12(const double* G12, int64_t ldg, const double* T1, const double* T2, int64_t ldt, double* M,
-                      int n1, int n2, double* T12, hipStream_t s)
+// T[p][q] = 0 for p > q (n x n)
+__global__ void __launch_bounds__(256) tril_zero_kernel(double* T, int64_t ldt, int n)
 {
-    const unsigned blocks = (unsigned)((n1 * n2 + 255) / 256);
-    hipLaunchKernelGGL((t12_kernel<0>), dim3(blocks), dim3(256), 0, s, G12, ldg, T2, ldt, M, (int64_t)n1, n1, n2);
-    hipLaunchKernelGGL((t12_kernel<1>), dim3(blocks), dim3(256), 0, s, (const double*)M, (int64_t)n1, T1, ldt, T12,
-                       ldt, n1, n2);
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= n * n) return;
+    const int p = e % n, q = e / n;
+    if (p > q) T[p + (int64_t)q * ldt] = 0.0;
+}
+
+hipError_t launch_t_join(const double* G, int64_t ldg, double* T, int64_t ldt, double* M, int nb_panel, int bo,
+                         hipStream_t s)
+{
+    hipLaunchKernelGGL(tril_zero_kernel, dim3((unsigned)((bo * bo + 255) / 256)), dim3(256), 0, s, T, ldt, bo);
+    for (int sz = nb_panel; sz < bo; sz *= 2) {
+        const dim3 grid((unsigned)((sz * sz + 255) / 256), (unsigned)((bo + 2 * sz - 1) / (2 * sz)));
+        hipLaunchKernelGGL((t_join_kernel<0>), grid, dim3(256), 0, s, G, ldg, T, ldt, M, sz, bo);
+        hipLaunchKernelGGL((t_join_kernel<1>), grid, dim3(256), 0, s, G, ldg, T, ldt, M, sz, bo);
+    }
     return hipGetLastError();
 }
 
@@ -567,29 +501,6 @@ hipError_t launch_tw(const TWp* Wp, int nz, int nbv, int N, const double* T, int
     hipLaunchKernelGGL((tw_kernel<TWp, TO, OP, SPLIT>), dim3(cdiv(N, 16)), dim3(256), sh, s, Wp, (int64_t)nbv * N,
                        nz, nbv, N, T, ldt, out, out_lo, ldo, desc);
     return hipGetLastError();
-}
-
-hipError_t launch_t_from_gram(const double* G, int64_t ldg, const double* tau, int nb, double* T, int64_t ldt,
-                              hipStream_t s)
-{
-    if (nb <= 128) {
-        const size_t shi = ((size_t)nb * (nb + 1) + nb) * sizeof(double);
-        hipLaunchKernelGGL(t_from_gram_inv_kernel, dim3(1), dim3(128), shi, s, G, ldg, tau, nb, T, ldt);
-        return hipGetLastError();
-    }
-    const int in_lds = nb <= 128 ? 1 : 0;
-    const size_t sh = ((size_t)nb + (in_lds ? (size_t)nb * (nb + 1) : 0)) * sizeof(double);
-    hipLaunchKernelGGL(t_from_gram_kernel, dim3(1), dim3(512), sh, s, G, ldg, tau, nb, T, ldt, in_lds);
-    return hipGetLastError();
-}
-
-hipError_t t_from_gram_set_max_lds(size_t bytes)
-{
-    hipError_t e = hipFuncSetAttribute((const void*)t_from_gram_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)t_from_gram_inv_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)bytes);
 }
 
 template <typename TWp, typename TS>

@@ -52,13 +52,10 @@ struct PanelArgs {
     uint64_t wait_ticks; // time limit of one wait (100 MHz ticks)
 };
 
-// Rows of the panel a thread owns in the update (rows per workgroup <= 256 x this).
-constexpr int kPanelRowsPerThread = 5;
-
 // LDS words besides the panel: red 256, vec 64, wv 32, sc 8, Tl 32*33, gl 32
 constexpr int kPanelAux = 256 + 64 + 32 + 8 + kPanelMax * (kPanelMax + 1) + kPanelMax;
 
-template <typename TS, bool ALL>
+template <typename TS>
 __global__ void __launch_bounds__(256) panel_qr_kernel(PanelArgs<TS> a)
 {
     extern __shared__ double lds[];
@@ -121,41 +118,18 @@ __global__ void __launch_bounds__(256) panel_qr_kernel(PanelArgs<TS> a)
             a.part[((size_t)(j & 1) * a.P + w) * 64 + t] = v;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         }
-        // (2) arrival.  ALL: every workgroup waits until all have arrived and
-        // sums the partials itself, in the same fixed order (one hop).
-        // Otherwise the last workgroup to arrive sums them and publishes the
-        // result; the others wait for its flag (two hops).
+        // (2) arrival; the last workgroup to arrive sums the partials in a
+        // fixed order and publishes them; the others wait for its flag
         if (t == 0) {
             const uint64_t old =
                 __hip_atomic_fetch_add(a.counter, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            sc[4] = (!ALL && old + 1 == target + (uint64_t)a.P) ? 1.0 : 0.0;
+            sc[4] = (old + 1 == target + (uint64_t)a.P) ? 1.0 : 0.0;
         }
         target += (uint64_t)a.P;
         __syncthreads();
         const bool last = sc[4] != 0.0;
         double* res = a.part + (size_t)2 * a.P * 64 + (size_t)(j & 1) * 64;
-        if (ALL) {
-            if (t == 0) {
-                const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-                uint32_t spins = 0;
-                while (__hip_atomic_load(a.counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                    __builtin_amdgcn_s_sleep(1);
-                    if (__builtin_amdgcn_s_memrealtime() - t0 >= a.wait_ticks) {
-                        __hip_atomic_fetch_or(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        sc[5] = 1.0;
-                        break;
-                    }
-                    if ((++spins & 15) == 0 &&
-                        (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1)) {
-                        sc[5] = 1.0;
-                        break;
-                    }
-                }
-            }
-            __syncthreads();
-            if (sc[5] != 0.0) return;      // uniform: the whole workgroup leaves
-        }
-        if (ALL || last) {
+        if (last) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             const int v = t & 63, g = t >> 6;
             const double* base = a.part + (size_t)(j & 1) * a.P * 64 + v;
@@ -179,32 +153,39 @@ __global__ void __launch_bounds__(256) panel_qr_kernel(PanelArgs<TS> a)
             if (t < 64) {
                 const double r = ((red[t] + red[64 + t]) + red[128 + t]) + red[192 + t];
                 vec[t] = r;
-                if (!ALL) {
-                    res[t] = r;
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                }
+                res[t] = r;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             }
-            if (!ALL) {
-                __syncthreads();
-                if (t == 0)
-                    __hip_atomic_store(a.flag, (uint64_t)(a.flag_base + j + 1), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-            }
+            __syncthreads();
+            if (t == 0)
+                __hip_atomic_store(a.flag, (uint64_t)(a.flag_base + j + 1), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         } else {
             if (t == 0) {
-                const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+                // poll the flag; the clock and the error word are read only
+                // every 16 polls, so a normal (microsecond) wait costs neither
+                uint64_t t0 = 0;
                 uint32_t spins = 0;
                 while (__hip_atomic_load(a.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < a.flag_base + j + 1) {
-                    __builtin_amdgcn_s_sleep(1);
-                    if (__builtin_amdgcn_s_memrealtime() - t0 >= a.wait_ticks) {
+                    if (a.wait_ticks == 0) {
                         __hip_atomic_fetch_or(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         sc[5] = 1.0;
                         break;
                     }
-                    if ((++spins & 15) == 0 &&
-                        (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1)) {
-                        sc[5] = 1.0;
-                        break;
+                    __builtin_amdgcn_s_sleep(1);
+                    if ((++spins & 15) == 0) {
+                        const uint64_t now = __builtin_amdgcn_s_memrealtime();
+                        if (spins == 16) {
+                            t0 = now;
+                        } else if (now - t0 >= a.wait_ticks) {
+                            __hip_atomic_fetch_or(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            sc[5] = 1.0;
+                            break;
+                        }
+                        if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1) {
+                            sc[5] = 1.0;
+                            break;
+                        }
                     }
                 }
             }
@@ -256,37 +237,40 @@ __global__ void __launch_bounds__(256) panel_qr_kernel(PanelArgs<TS> a)
                 Tl[j * 33 + j] = sc[2];
             }
         }
-        // (4) apply H_j to this workgroup's rows.  Each thread owns rows
-        // t, t + 256, ...: it forms v there (column j scaled below the pivot,
-        // beta stored at the pivot, where v = 1) and updates those rows of
-        // every later column, so no other thread's rows are touched.
+        // (4) apply H_j to this workgroup's rows: first v (column j scaled,
+        // pivot set to beta), then the rank-1 update with one column per
+        // thread and eight row phases, so the inner loop has no branches
         if (sc[3] == 0.0) {
             const double scl = sc[0], beta = sc[1];
-            double vr[kPanelRowsPerThread];
-#pragma unroll
-            for (int u = 0; u < kPanelRowsPerThread; ++u) {
-                const int r = t + 256 * u;
-                double v = 0.0;
-                if (r < rows) {
-                    const int64_t gr = r0 + r;
-                    if (gr > j) {
-                        v = pan[j * rw + r] * scl;
-                        pan[j * rw + r] = v;
-                    } else if (gr == j) {
-                        pan[j * rw + r] = beta;
-                        v = 1.0;
-                    }
-                }
-                vr[u] = v;
+            for (int r = t; r < rows; r += 256) {
+                const int64_t gr = r0 + r;
+                if (gr > j) pan[j * rw + r] *= scl;
+                else if (gr == j) pan[j * rw + r] = beta;
             }
-            for (int c = j + 1; c < nbp; ++c) {
+            __syncthreads();
+            const int c = t & 31, g = t >> 5;
+            if (c > j && c < nbp) {
                 const double wc = wv[c];
+                const double* vj = pan + j * rw;
                 double* pc = pan + c * rw;
-#pragma unroll
-                for (int u = 0; u < kPanelRowsPerThread; ++u) {
-                    const int r = t + 256 * u;
-                    if (r < rows && r0 + r >= j) pc[r] -= wc * vr[u];
+                int rs = (int)((int64_t)j - r0);
+                if (rs < 0) rs = 0;
+                // the pivot row (gr == j) takes v = 1
+                if (rs < rows && r0 + rs == j && (rs & 7) == g) {
+                    pc[rs] -= wc;
+                    rs += 8;
                 }
+                int r = rs + ((g - rs) & 7);
+                if (r < rows && r0 + r == j) r += 8;
+                for (; r + 24 < rows; r += 32) {
+                    const double v0 = vj[r], v1 = vj[r + 8], v2 = vj[r + 16], v3 = vj[r + 24];
+                    const double x0 = pc[r], x1 = pc[r + 8], x2 = pc[r + 16], x3 = pc[r + 24];
+                    pc[r] = x0 - wc * v0;
+                    pc[r + 8] = x1 - wc * v1;
+                    pc[r + 16] = x2 - wc * v2;
+                    pc[r + 24] = x3 - wc * v3;
+                }
+                for (; r < rows; r += 8) pc[r] -= wc * vj[r];
             }
         }
         __syncthreads();
@@ -303,23 +287,11 @@ __global__ void __launch_bounds__(256) panel_qr_kernel(PanelArgs<TS> a)
 
 // --------------------------------------------------------------- launcher
 static uint64_t g_wait_ticks = kWaitTicks;
-// column reduction: every workgroup sums all partials (1) or the last to
-// arrive sums and publishes (0); CTQR_PANEL_REDUCE=last selects the latter
-static int reduce_all()
-{
-    static int v = -1;
-    if (v < 0) {
-        const char* e = getenv("CTQR_PANEL_REDUCE");
-        v = (e && !strcmp(e, "last")) ? 0 : 1;
-    }
-    return v;
-}
 void panel_set_wait_limit(int64_t ticks) { g_wait_ticks = ticks < 0 ? kWaitTicks : (uint64_t)ticks; }
 
 // LDS: the panel plus the reduction scratch and the T factor.
 size_t panel_lds_bytes(int nbp, int rw) { return ((size_t)nbp * rw + kPanelAux) * sizeof(double); }
 int panel_aux_words() { return kPanelAux; }
-int panel_max_rows() { return 256 * kPanelRowsPerThread - 1; }
 
 template <typename TS>
 hipError_t launch_panel(TS* A, int64_t lda, int64_t mk, int nbp, int rw, double* tau, double* T, int64_t ldt,
@@ -335,10 +307,7 @@ hipError_t launch_panel(TS* A, int64_t lda, int64_t mk, int nbp, int rw, double*
     a.flag = flag; a.flag_base = *flag_base;
     a.wait_ticks = g_wait_ticks;
     const size_t shmem = panel_lds_bytes(nbp, rw);
-    if (reduce_all())
-        hipLaunchKernelGGL((panel_qr_kernel<TS, true>), dim3(a.P), dim3(256), shmem, s, a);
-    else
-        hipLaunchKernelGGL((panel_qr_kernel<TS, false>), dim3(a.P), dim3(256), shmem, s, a);
+    hipLaunchKernelGGL(panel_qr_kernel<TS>, dim3(a.P), dim3(256), shmem, s, a);
     *base += (uint64_t)a.P * (uint64_t)nbp;
     *flag_base += (uint64_t)nbp;
     return hipGetLastError();
@@ -347,8 +316,7 @@ hipError_t launch_panel(TS* A, int64_t lda, int64_t mk, int nbp, int rw, double*
 
 hipError_t panel_set_max_lds(size_t bytes)
 {
-    const void* k[4] = {(const void*)panel_qr_kernel<double, true>, (const void*)panel_qr_kernel<double, false>,
-                        (const void*)panel_qr_kernel<float, true>, (const void*)panel_qr_kernel<float, false>};
+    const void* k[2] = {(const void*)panel_qr_kernel<double>, (const void*)panel_qr_kernel<float>};
     for (const void* f : k) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
@@ -359,10 +327,9 @@ hipError_t panel_set_max_lds(size_t bytes)
 hipError_t panel_max_active(int* per_cu, size_t shmem)
 {
     int a = 0, b = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, (const void*)panel_qr_kernel<float, true>, 256,
-                                                                 shmem);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, (const void*)panel_qr_kernel<float>, 256, shmem);
     if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void*)panel_qr_kernel<double, false>, 256, shmem);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void*)panel_qr_kernel<double>, 256, shmem);
     *per_cu = a < b ? a : b;
     return e;
 }
