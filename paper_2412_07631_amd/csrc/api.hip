@@ -858,6 +858,7 @@ static int trsm_impl(const ct_factor* fc, TS* B, int64_t nrhs, int64_t ldb, hipS
         // product with the stored inverse), then B[0:k0] -= R[0:k0, b] X_b with
         // the row-major copy of the block column; both on the NT kernel
         const NtPlan* plan = &f->solve_plan[bucket_of(nrhs)];
+        const NtPlan diag_plan{32, 1024};     // 128-row products: narrow tiles for more workgroups
         TS* S = (TS*)f->Wq;
         for (int64_t b = nb - 1; b >= 0; --b) {
             const int64_t k0 = b * 128;
@@ -865,7 +866,7 @@ static int trsm_impl(const ct_factor* fc, TS* B, int64_t nrhs, int64_t ldb, hipS
             int nz;
             CT_HIP((launch_copy_block<TS>(B + k0, ldb, S, 128, bo, (int)nrhs, s, desc)));
             CT_HIP(launch_nt<TS>((const TS*)f->RiR + (size_t)b * 128 * 128, 128, S, 128, B + k0, ldb, bo, (int)nrhs,
-                                 bo, false, 0, &nz, s, plan, desc, 0, 1));
+                                 bo, false, 0, &nz, s, &diag_plan, desc, 0, 1));
             if (k0 > 0)
                 CT_HIP(launch_nt<TS>((const TS*)f->Rt + (size_t)128 * 128 * (size_t)(b * (b - 1) / 2), 128, B + k0,
                                      ldb, B, ldb, k0, (int)nrhs, bo, true, 0, &nz, s, plan, desc, 1, 1));
@@ -900,6 +901,28 @@ static int trsm_lt_impl(const ct_factor* fc, TS* Y, int64_t k, int64_t ldy, hipS
     const int64_t n = f->n, lda = f->lda;
     const int tb = g_dev.trsm_block;
     const int64_t nb = (n + tb - 1) / tb;
+    if (f->RiC && !f->st) {
+        // right-looking, first block first: Z_b = R_bb^{-T} Y_b with the stored
+        // inverse, then Y[k0+bo:n] -= R[k0:k0+bo, k0+bo:n]^T Z_b, whose X rows
+        // are the later columns of R read in place (K-contiguous down a column)
+        const NtPlan* plan = &f->solve_plan[bucket_of(k)];
+        const NtPlan diag_plan{32, 1024};
+        const TS* A = (const TS*)f->A;
+        TS* S = (TS*)f->Wq;
+        for (int64_t b = 0; b < nb; ++b) {
+            const int64_t k0 = b * 128;
+            const int bo = (int)std::min<int64_t>(128, n - k0);
+            int nz;
+            CT_HIP((launch_copy_block<TS>(Y + k0, ldy, S, 128, bo, (int)k, s, nullptr)));
+            CT_HIP(launch_nt<TS>((const TS*)f->RiC + (size_t)b * 128 * 128, 128, S, 128, Y + k0, ldy, bo, (int)k, bo,
+                                 false, 0, &nz, s, &diag_plan));
+            const int64_t rest = n - k0 - bo;
+            if (rest > 0)
+                CT_HIP(launch_nt<TS>(A + k0 + (k0 + bo) * lda, lda, Y + k0, ldy, Y + k0 + bo, ldy, rest, (int)k, bo,
+                                     true, 0, &nz, s, plan));
+        }
+        return 0;
+    }
     ColWalk<TS> walk(f, s, 1, false);
     for (int64_t b = 0; b < nb; ++b) {
         const int64_t k0 = b * tb;
