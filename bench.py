@@ -131,7 +131,7 @@ def main():
     ap.add_argument("--nrhs", type=int, default=None, help="slices per batch (default: the workload's)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-cols", type=int, default=1024, help="leading columns in the CPU oracle sample")
+    ap.add_argument("--cpu-cols", type=int, default=2048, help="leading columns in the CPU oracle sample")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 1 GiB device copy first (calibrates profiler byte counters)")
     ap.add_argument("--no-batched", action="store_true",

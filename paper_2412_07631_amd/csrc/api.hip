@@ -61,7 +61,7 @@ hipError_t launch_trsm_diag(const TS* R, int64_t ldr, int bo, TS* B, int64_t ldb
 hipError_t launch_advance_batch(int32_t* desc, hipStream_t s);
 hipError_t trsm_set_max_lds(size_t bytes);
 template <typename TS>
-hipError_t launch_rinv(const TS* A, int64_t lda, int64_t n, TS* RiR, TS* RiC, hipStream_t s);
+hipError_t launch_rinv(const TS* A, int64_t lda, int64_t n, TS* RiR, TS* RiC, double* Ri64, double* M, hipStream_t s);
 template <typename TS>
 hipError_t launch_rt(const TS* A, int64_t lda, int64_t n, TS* Rt, hipStream_t s);
 template <typename TS>
@@ -204,7 +204,7 @@ constexpr int kNbMax = 256;
 static int nb_out_for(int prec) { (void)prec; return kNbMax; }
 
 struct Layout {
-    size_t T_all, part, gpart, words, Wp, Wq, G, Vm, Vt, Ws, Ri, Rt, VtAll, Tf, S3, total;
+    size_t T_all, part, gpart, words, Wp, Wq, G, Vm, Vt, Ws, Ri, Ri64, Rt, VtAll, Tf, S3, total;
     int64_t wp_elems, wq_elems;
 };
 
@@ -230,12 +230,14 @@ static Layout layout(int64_t m, int64_t n, int prec, int64_t max_nrhs, bool r_co
     L.Vm = off; off += up256((size_t)ldm * nbo * 8);
     L.Vt = off; off += up256((size_t)ldm * nbo * 8);
     L.Ws = off; off += up256((size_t)L.wq_elems * 8);
-    // R copies for the solves: 2 inverses per 128-row block, and the block
-    // columns above the diagonal (128^2 nbt (nbt - 1) / 2 elements)
+    // R copies for the solves: 2 inverses per 256-row block (and their FP64
+    // scratch), and the block columns above the diagonal (256^2 nbt (nbt - 1)
+    // / 2 elements)
     const size_t es = prec == CT_PREC_F64 ? 8 : 4;
-    const int64_t nbt = (n + 127) / 128;
-    L.Ri = off; off += r_copies ? up256((size_t)2 * nbt * 128 * 128 * es) : 0;
-    L.Rt = off; off += r_copies ? up256((size_t)128 * 128 * (size_t)(nbt * (nbt - 1) / 2) * es) : 0;
+    const int64_t nbt = (n + 255) / 256;
+    L.Ri = off; off += r_copies ? up256((size_t)2 * nbt * 256 * 256 * es) : 0;
+    L.Ri64 = off; off += r_copies ? up256((size_t)nbt * 256 * 256 * 8) : 0;
+    L.Rt = off; off += r_copies ? up256((size_t)256 * 256 * (size_t)(nbt * (nbt - 1) / 2) * es) : 0;
     // reflector blocks, row-major: block b holds (m - b nbo) rows of nbo
     L.VtAll = off; off += r_copies ? up256((size_t)(nblocks * m - nbo * (nblocks * (nblocks - 1) / 2)) * nbo * es) : 0;
     L.Tf = off; off += prec == CT_PREC_F64 ? 0 : up256((size_t)nblocks * nbo * nbo * 4);
@@ -854,21 +856,22 @@ static int trsm_impl(const ct_factor* fc, TS* B, int64_t nrhs, int64_t ldb, hipS
     const int tb = g_dev.trsm_block;
     const int64_t nb = (n + tb - 1) / tb;
     if (f->Rt) {
-        // per block, last first: X_b = R_bb^{-1} B_b (copy to scratch, then a
-        // product with the stored inverse), then B[0:k0] -= R[0:k0, b] X_b with
-        // the row-major copy of the block column; both on the NT kernel
+        // per 256-row block, last first: X_b = R_bb^{-1} B_b (copy to scratch,
+        // then a product with the stored inverse), then B[0:k0] -= R[0:k0, b] X_b
+        // with the row-major copy of the block column; both on the NT kernel
         const NtPlan* plan = &f->solve_plan[bucket_of(nrhs)];
-        const NtPlan diag_plan{32, 1024};     // 128-row products: narrow tiles for more workgroups
+        const NtPlan diag_plan{32, 1024};     // 256-row products: narrow tiles for more workgroups
         TS* S = (TS*)f->Wq;
-        for (int64_t b = nb - 1; b >= 0; --b) {
-            const int64_t k0 = b * 128;
-            const int bo = (int)std::min<int64_t>(128, n - k0);
+        const int64_t nb2 = (n + 255) / 256;
+        for (int64_t b = nb2 - 1; b >= 0; --b) {
+            const int64_t k0 = b * 256;
+            const int bo = (int)std::min<int64_t>(256, n - k0);
             int nz;
-            CT_HIP((launch_copy_block<TS>(B + k0, ldb, S, 128, bo, (int)nrhs, s, desc)));
-            CT_HIP(launch_nt<TS>((const TS*)f->RiR + (size_t)b * 128 * 128, 128, S, 128, B + k0, ldb, bo, (int)nrhs,
+            CT_HIP((launch_copy_block<TS>(B + k0, ldb, S, 256, bo, (int)nrhs, s, desc)));
+            CT_HIP(launch_nt<TS>((const TS*)f->RiR + (size_t)b * 256 * 256, 256, S, 256, B + k0, ldb, bo, (int)nrhs,
                                  bo, false, 0, &nz, s, &diag_plan, desc, 0, 1));
             if (k0 > 0)
-                CT_HIP(launch_nt<TS>((const TS*)f->Rt + (size_t)128 * 128 * (size_t)(b * (b - 1) / 2), 128, B + k0,
+                CT_HIP(launch_nt<TS>((const TS*)f->Rt + (size_t)256 * 256 * (size_t)(b * (b - 1) / 2), 256, B + k0,
                                      ldb, B, ldb, k0, (int)nrhs, bo, true, 0, &nz, s, plan, desc, 1, 1));
         }
         return 0;
@@ -909,12 +912,13 @@ static int trsm_lt_impl(const ct_factor* fc, TS* Y, int64_t k, int64_t ldy, hipS
         const NtPlan diag_plan{32, 1024};
         const TS* A = (const TS*)f->A;
         TS* S = (TS*)f->Wq;
-        for (int64_t b = 0; b < nb; ++b) {
-            const int64_t k0 = b * 128;
-            const int bo = (int)std::min<int64_t>(128, n - k0);
+        const int64_t nb2 = (n + 255) / 256;
+        for (int64_t b = 0; b < nb2; ++b) {
+            const int64_t k0 = b * 256;
+            const int bo = (int)std::min<int64_t>(256, n - k0);
             int nz;
-            CT_HIP((launch_copy_block<TS>(Y + k0, ldy, S, 128, bo, (int)k, s, nullptr)));
-            CT_HIP(launch_nt<TS>((const TS*)f->RiC + (size_t)b * 128 * 128, 128, S, 128, Y + k0, ldy, bo, (int)k, bo,
+            CT_HIP((launch_copy_block<TS>(Y + k0, ldy, S, 256, bo, (int)k, s, nullptr)));
+            CT_HIP(launch_nt<TS>((const TS*)f->RiC + (size_t)b * 256 * 256, 256, S, 256, Y + k0, ldy, bo, (int)k, bo,
                                  false, 0, &nz, s, &diag_plan));
             const int64_t rest = n - k0 - bo;
             if (rest > 0)
@@ -941,16 +945,7 @@ static int trsm_lt_impl(const ct_factor* fc, TS* Y, int64_t k, int64_t ldy, hipS
             }
             CT_HIP((launch_tw<TS, TS, 3, false>(Wsum, 1, bo, (int)k, nullptr, 0, Y + k0, nullptr, ldy, s)));
         }
-        if (f->RiC) {
-            // Z_b = R_bb^{-T} Y_b with the stored inverse (column-major rows of R_bb^{-T})
-            TS* S = (TS*)f->Wq;
-            int nz;
-            CT_HIP((launch_copy_block<TS>(Y + k0, ldy, S, 128, bo, (int)k, s, nullptr)));
-            CT_HIP(launch_nt<TS>((const TS*)f->RiC + (size_t)b * 128 * 128, 128, S, 128, Y + k0, ldy, bo, (int)k, bo,
-                                 false, 0, &nz, s));
-        } else {
-            CT_HIP((launch_trsm_diag<TS, false>(Rb + k0, lda, bo, Y + k0, ldy, (int)k, s)));
-        }
+        CT_HIP((launch_trsm_diag<TS, false>(Rb + k0, lda, bo, Y + k0, ldy, (int)k, s)));
     }
     return walk.finish();
 }
@@ -1154,14 +1149,16 @@ int ct_qr_factor(void* A, int64_t m, int64_t n, int64_t lda, int prec, double* t
         // solve-side copies of R: diagonal-block inverses and row-major block columns
         const size_t es = f->f64 ? 8 : 4;
         f->RiR = (char*)work + L.Ri;
-        f->RiC = (char*)work + L.Ri + (size_t)((n + 127) / 128) * 128 * 128 * es;
+        f->RiC = (char*)work + L.Ri + (size_t)((n + 255) / 256) * 256 * 256 * es;
         f->Rt = (char*)work + L.Rt;
+        double* Ri64 = (double*)((char*)work + L.Ri64);
+        double* M = (double*)f->Wq;      // free once the factorization is done
         hipError_t e;
         if (f->f64) {
-            e = launch_rinv<double>((const double*)A, lda, n, (double*)f->RiR, (double*)f->RiC, s);
+            e = launch_rinv<double>((const double*)A, lda, n, (double*)f->RiR, (double*)f->RiC, Ri64, M, s);
             if (e == hipSuccess) e = launch_rt<double>((const double*)A, lda, n, (double*)f->Rt, s);
         } else {
-            e = launch_rinv<float>((const float*)A, lda, n, (float*)f->RiR, (float*)f->RiC, s);
+            e = launch_rinv<float>((const float*)A, lda, n, (float*)f->RiR, (float*)f->RiC, Ri64, M, s);
             if (e == hipSuccess) e = launch_rt<float>((const float*)A, lda, n, (float*)f->Rt, s);
         }
         if (e != hipSuccess) {

@@ -8,6 +8,10 @@
 //
 //   ctqr_bench [--n-pix 256] [--views 120] [--bins 640]
 //              [--prec f64|f32|bf16|f16|bf16x3] [--nrhs 16] [--copy-mib 0]
+//              [--stream-gib G --tile-cols 1024]
+// With --stream-gib the matrix is factored from pinned host memory
+// (ct_qr_factor_streamed) with a device buffer of G GiB, and the time
+// includes every host<->device transfer.
 //
 // Scanner: grid width 1, source-isocentre distance 2, source-detector 4, flat
 // detector whose fan covers the circle inscribed in the image (the reading of
@@ -55,6 +59,8 @@ int main(int argc, char** argv)
 {
     int n_pix = 256, views = 120, bins = 640, nrhs = 16;
     long copy_mib = 0;
+    double stream_gib = 0.0;
+    long tile_cols = 1024;
     const char* pname = "bf16x3";
     for (int i = 1; i + 1 < argc; i += 2) {
         if (!strcmp(argv[i], "--n-pix")) n_pix = atoi(argv[i + 1]);
@@ -63,6 +69,8 @@ int main(int argc, char** argv)
         else if (!strcmp(argv[i], "--prec")) pname = argv[i + 1];
         else if (!strcmp(argv[i], "--nrhs")) nrhs = atoi(argv[i + 1]);
         else if (!strcmp(argv[i], "--copy-mib")) copy_mib = atol(argv[i + 1]);
+        else if (!strcmp(argv[i], "--stream-gib")) stream_gib = atof(argv[i + 1]);
+        else if (!strcmp(argv[i], "--tile-cols")) tile_cols = atol(argv[i + 1]);
         else {
             fprintf(stderr, "unknown option %s\n", argv[i]);
             return 2;
@@ -99,6 +107,48 @@ int main(int argc, char** argv)
         HIP_OK(hipFree(b));
         printf("copy probe: %ld MiB read, %ld MiB written\n", copy_mib, copy_mib);
         fflush(stdout);
+    }
+
+    if (stream_gib > 0.0) {
+        // out-of-core: A built on the device, moved to pinned host memory,
+        // then factored from there through a device buffer of stream_gib GiB
+        size_t lo = 0, full = 0;
+        CT_OK(ct_qr_stream_workspace(m, n, lda, prec, nrhs, tile_cols, &lo, &full));
+        size_t wb = (size_t)(stream_gib * (double)(1ull << 30));
+        if (wb < lo) wb = lo;
+        if (wb > full) wb = full;
+        void *Ad, *Ah, *work;
+        double* tau;
+        HIP_OK(hipMalloc(&Ad, (size_t)n * lda * es));
+        CT_OK(ct_build_system(&g, prec == CT_PREC_F64 ? CT_F64 : CT_F32, Ad, lda, s));
+        HIP_OK(hipHostMalloc(&Ah, (size_t)n * lda * es, hipHostMallocDefault));
+        HIP_OK(hipMemcpyAsync(Ah, Ad, (size_t)n * lda * es, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        HIP_OK(hipFree(Ad));
+        HIP_OK(hipMalloc(&tau, (size_t)n * sizeof(double)));
+        HIP_OK(hipMalloc(&work, wb));
+        hipEvent_t e0, e1;
+        HIP_OK(hipEventCreate(&e0));
+        HIP_OK(hipEventCreate(&e1));
+        ct_factor* f = nullptr;
+        HIP_OK(hipEventRecord(e0, s));
+        CT_OK(ct_qr_factor_streamed(Ah, m, n, lda, prec, tau, work, wb, nrhs, tile_cols, &f, s));
+        HIP_OK(hipEventRecord(e1, s));
+        int64_t info = 0, tiles = 0, res = 0;
+        CT_OK(ct_status(f, &info, s));
+        CT_OK(ct_stream_info(f, &tiles, &res, nullptr));
+        float ms = 0;
+        HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+        const double fl = 2.0 * m * (double)n * n - 2.0 * (double)n * n * n / 3.0;
+        printf("streamed: info %lld tiles %lld resident %lld device %.2f GiB of %.2f (A %.2f GiB) qr_ms %.1f "
+               "qr_tflops %.2f\n", (long long)info, (long long)tiles, (long long)res, wb / 1073741824.0,
+               full / 1073741824.0, (double)n * lda * es / 1073741824.0, ms, fl / (ms * 1e-3) / 1e12);
+        CT_OK(ct_factor_destroy(f));
+        HIP_OK(hipFree(work));
+        HIP_OK(hipFree(tau));
+        HIP_OK(hipHostFree(Ah));
+        HIP_OK(hipStreamDestroy(s));
+        return info == 0 ? 0 : 3;
     }
 
     void *A, *work, *B;

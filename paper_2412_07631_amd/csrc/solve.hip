@@ -63,28 +63,29 @@ __global__ void __launch_bounds__(256) trsm_diag_kernel(const TS* __restrict__ R
     }
 }
 
-// Inverses of the diagonal blocks of R, one workgroup per 128-row block.
+// Solve-side copies of R, built once per factorization, for 256-row blocks.
+// Step 1: the inverse of every 128-row diagonal block, one workgroup each.
 // The block (upper triangle) and its inverse are kept packed in LDS as FP64
 // (column-major triangle: entry (i, j), i <= j, at j (j + 1) / 2 + i); thread j
 // computes column j of the inverse by back-substitution against the unit
-// vector e_j, independently of the other columns.  Written in the storage type
-// twice: row-major (RiR, for X_b = R_bb^{-1} C_b) and column-major (RiC, for
-// Z_b = R_bb^{-T} C_b), both 128 x 128 with zeros outside the triangle.
-template <typename TS>
-__global__ void __launch_bounds__(128) rinv_kernel(const TS* __restrict__ A, int64_t lda, int64_t n,
-                                                   TS* __restrict__ RiR, TS* __restrict__ RiC)
+// vector e_j, independently of the other columns.  Written in FP64 to the
+// diagonal of its 256-row block in Ri64 (block k at k * 256^2, ld 256).
+__global__ void __launch_bounds__(128) rinv128_kernel(const void* __restrict__ Av, int f64, int64_t lda, int64_t n,
+                                                      double* __restrict__ Ri64)
 {
     extern __shared__ double tri[];
-    constexpr int B = kTrsmBlock;
+    constexpr int B = 128;
     constexpr int NP = B * (B + 1) / 2;
     double* Rp = tri;
     double* Xp = tri + NP;
     const int64_t k0 = (int64_t)blockIdx.x * B;
     const int bo = (int)((n - k0) < B ? (n - k0) : B);
-    const TS* R = A + k0 + k0 * lda;
     const int t = threadIdx.x;
     for (int j = 0; j < bo; ++j)
-        for (int i = t; i <= j; i += B) Rp[j * (j + 1) / 2 + i] = (double)R[i + (int64_t)j * lda];
+        for (int i = t; i <= j; i += B) {
+            const int64_t e = (k0 + i) + (k0 + j) * lda;
+            Rp[j * (j + 1) / 2 + i] = f64 ? ((const double*)Av)[e] : (double)((const float*)Av)[e];
+        }
     __syncthreads();
     if (t < bo) {
         const int j = t;
@@ -102,41 +103,98 @@ __global__ void __launch_bounds__(128) rinv_kernel(const TS* __restrict__ A, int
         }
     }
     __syncthreads();
-    TS* outR = RiR + (size_t)blockIdx.x * B * B;
-    TS* outC = RiC + (size_t)blockIdx.x * B * B;
+    double* out = Ri64 + (size_t)(blockIdx.x >> 1) * 256 * 256 + (size_t)(blockIdx.x & 1) * B * 257;
     for (int e = t; e < B * B; e += B) {
-        const int i = e / B, j = e % B;          // row-major walk: (i, j) at i * B + j
-        outR[e] = (i <= j && j < bo) ? (TS)Xp[j * (j + 1) / 2 + i] : (TS)0;
-        const int jc = e / B, ic = e % B;        // column-major walk: (ic, jc) at jc * B + ic
-        outC[e] = (ic <= jc && jc < bo) ? (TS)Xp[jc * (jc + 1) / 2 + ic] : (TS)0;
+        const int i = e % B, j = e / B;
+        out[i + (size_t)j * 256] = (i <= j && j < bo) ? Xp[j * (j + 1) / 2 + i] : 0.0;
     }
 }
 
-// Row-major copies of the strictly-above-diagonal part of each block column
-// of R: for block b (columns k0 = 128 b .. k0 + bo), Rt_b[p * 128 + c] =
-// R[p][k0 + c] for rows p < k0 (zero for c >= bo).  Block b starts at element
-// 128 * 128 * b (b - 1) / 2.  Tiles of 32 rows x 128 columns pass through LDS
-// so that both the column-major reads and the row-major writes are coalesced.
+// Step 2: the coupling block of each 256-row block's inverse,
+//   [A B; 0 D]^{-1} = [A^{-1}  -A^{-1} B D^{-1}; 0  D^{-1}],
+// STEP 0: M = B D^{-1} (128 x n2, ld 128), STEP 1: X12 = -A^{-1} M; block
+// k = blockIdx.y, one output per thread.
+template <int STEP>
+__global__ void __launch_bounds__(256) rinv_join_kernel(const void* __restrict__ Av, int f64, int64_t lda, int64_t n,
+                                                        double* __restrict__ Ri64, double* __restrict__ M)
+{
+    const int64_t k0 = (int64_t)blockIdx.y * 256;
+    const int bo = (int)((n - k0) < 256 ? (n - k0) : 256);
+    const int n2 = bo - 128;
+    if (n2 <= 0) return;
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= 128 * n2) return;
+    const int r = e % 128, q = e / 128;
+    double* X = Ri64 + (size_t)blockIdx.y * 256 * 256;
+    double* Mk = M + (size_t)blockIdx.y * 128 * 128;
+    double s0 = 0.0, s1 = 0.0;
+    if (STEP == 0) {
+        const double* Dinv = X + 128 + (size_t)128 * 256;
+        for (int l = 0; l <= q; ++l) {
+            const int64_t ei = (k0 + r) + (k0 + 128 + l) * lda;
+            const double b = f64 ? ((const double*)Av)[ei] : (double)((const float*)Av)[ei];
+            if (l & 1) s1 += b * Dinv[l + (size_t)q * 256];
+            else s0 += b * Dinv[l + (size_t)q * 256];
+        }
+        Mk[r + q * 128] = s0 + s1;
+    } else {
+        const double* mq = Mk + (size_t)q * 128;
+        int l = r;
+        for (; l + 1 < 128; l += 2) {
+            s0 += X[r + (size_t)l * 256] * mq[l];
+            s1 += X[r + (size_t)(l + 1) * 256] * mq[l + 1];
+        }
+        if (l < 128) s0 += X[r + (size_t)l * 256] * mq[l];
+        X[r + (size_t)(128 + q) * 256] = -(s0 + s1);
+    }
+}
+
+// Step 3: the inverses in the storage type, row-major (RiR, for X_b =
+// R_bb^{-1} C_b) and column-major (RiC, for Z_b = R_bb^{-T} C_b), 256 x 256
+// per block with zeros outside the triangle.
+template <typename TS>
+__global__ void __launch_bounds__(256) rinv_store_kernel(const double* __restrict__ Ri64, int64_t n,
+                                                         TS* __restrict__ RiR, TS* __restrict__ RiC)
+{
+    const int64_t k0 = (int64_t)blockIdx.y * 256;
+    const int bo = (int)((n - k0) < 256 ? (n - k0) : 256);
+    const double* X = Ri64 + (size_t)blockIdx.y * 256 * 256;
+    TS* R = RiR + (size_t)blockIdx.y * 256 * 256;
+    TS* C = RiC + (size_t)blockIdx.y * 256 * 256;
+    for (int e = blockIdx.x * 256 + threadIdx.x; e < 256 * 256; e += gridDim.x * 256) {
+        const int i = e / 256, j = e % 256;     // row-major walk: (i, j) at i * 256 + j
+        R[e] = (i <= j && j < bo) ? (TS)X[i + (size_t)j * 256] : (TS)0;
+        const int jc = e / 256, ic = e % 256;   // column-major walk: (ic, jc) at jc * 256 + ic
+        C[e] = (ic <= jc && jc < bo) ? (TS)X[ic + (size_t)jc * 256] : (TS)0;
+    }
+}
+
+// Row-major copies of the part of each 256-column block of R above its
+// diagonal block: for block b (columns k0 = 256 b .. k0 + bo),
+// Rt_b[p * 256 + c] = R[p][k0 + c] for rows p < k0 (zero for c >= bo).  Block b
+// starts at element 256 * 256 * b (b - 1) / 2.  Tiles of 16 rows x 256 columns
+// pass through LDS so that both the column-major reads and the row-major
+// writes are coalesced.
 template <typename TS>
 __global__ void __launch_bounds__(256) rt_kernel(const TS* __restrict__ A, int64_t lda, int64_t n,
                                                  TS* __restrict__ Rt)
 {
-    constexpr int B = kTrsmBlock;
-    __shared__ TS tile[B][33];
+    constexpr int B = 256, TR = 16;
+    __shared__ TS tile[B][TR + 1];
     const int64_t b = blockIdx.y;
     const int64_t k0 = b * B;
-    const int64_t p0 = (int64_t)blockIdx.x * 32;
+    const int64_t p0 = (int64_t)blockIdx.x * TR;
     if (p0 >= k0) return;
     const int bo = (int)((n - k0) < B ? (n - k0) : B);
     const int t = threadIdx.x;
-    for (int e = t; e < B * 32; e += 256) {
-        const int c = e / 32, r = e % 32;        // r fastest: along a column of R
+    for (int e = t; e < B * TR; e += 256) {
+        const int c = e / TR, r = e % TR;        // r fastest: along a column of R
         const int64_t p = p0 + r;
         tile[c][r] = (c < bo && p < k0) ? A[p + (k0 + c) * lda] : (TS)0;
     }
     __syncthreads();
     TS* out = Rt + (size_t)B * B * (size_t)(b * (b - 1) / 2);
-    for (int e = t; e < B * 32; e += 256) {
+    for (int e = t; e < B * TR; e += 256) {
         const int r = e / B, c = e % B;          // c fastest: along a row of Rt
         const int64_t p = p0 + r;
         if (p < k0) out[p * B + c] = tile[c][r];
@@ -437,22 +495,30 @@ hipError_t launch_trsm_diag(const TS* R, int64_t ldr, int bo, TS* B, int64_t ldb
     return hipGetLastError();
 }
 
+// Inverses of the 256-row diagonal blocks of R (RiR row-major, RiC
+// column-major, 256^2 elements per block); Ri64 (n_blocks x 256^2 FP64) and M
+// (n_blocks x 128^2 FP64) are scratch.
 template <typename TS>
-hipError_t launch_rinv(const TS* A, int64_t lda, int64_t n, TS* RiR, TS* RiC, hipStream_t s)
+hipError_t launch_rinv(const TS* A, int64_t lda, int64_t n, TS* RiR, TS* RiC, double* Ri64, double* M, hipStream_t s)
 {
-    const unsigned blocks = (unsigned)((n + kTrsmBlock - 1) / kTrsmBlock);
-    const size_t sh = (size_t)kTrsmBlock * (kTrsmBlock + 1) * sizeof(double);   // two packed triangles
-    hipLaunchKernelGGL(rinv_kernel<TS>, dim3(blocks), dim3(kTrsmBlock), sh, s, A, lda, n, RiR, RiC);
+    const unsigned b128 = (unsigned)((n + 127) / 128), b256 = (unsigned)((n + 255) / 256);
+    const size_t sh = (size_t)128 * 129 * sizeof(double);   // two packed triangles
+    const int f64 = sizeof(TS) == 8;
+    hipLaunchKernelGGL(rinv128_kernel, dim3(b128), dim3(128), sh, s, (const void*)A, f64, lda, n, Ri64);
+    const dim3 gj(128 * 128 / 256, b256);
+    hipLaunchKernelGGL((rinv_join_kernel<0>), gj, dim3(256), 0, s, (const void*)A, f64, lda, n, Ri64, M);
+    hipLaunchKernelGGL((rinv_join_kernel<1>), gj, dim3(256), 0, s, (const void*)A, f64, lda, n, Ri64, M);
+    hipLaunchKernelGGL(rinv_store_kernel<TS>, dim3(64, b256), dim3(256), 0, s, (const double*)Ri64, n, RiR, RiC);
     return hipGetLastError();
 }
 
 template <typename TS>
 hipError_t launch_rt(const TS* A, int64_t lda, int64_t n, TS* Rt, hipStream_t s)
 {
-    const int64_t nb = (n + kTrsmBlock - 1) / kTrsmBlock;
+    const int64_t nb = (n + 255) / 256;
     if (nb < 2) return hipSuccess;
-    const int64_t rows = (nb - 1) * kTrsmBlock;         // rows above the last block
-    hipLaunchKernelGGL(rt_kernel<TS>, dim3((unsigned)((rows + 31) / 32), (unsigned)nb), dim3(256), 0, s, A, lda, n,
+    const int64_t rows = (nb - 1) * 256;                // rows above the last block
+    hipLaunchKernelGGL(rt_kernel<TS>, dim3((unsigned)((rows + 15) / 16), (unsigned)nb), dim3(256), 0, s, A, lda, n,
                        Rt);
     return hipGetLastError();
 }
@@ -469,15 +535,12 @@ hipError_t launch_copy_block(const TS* src, int64_t lds, TS* dst, int64_t ldd, i
 
 hipError_t rinv_set_max_lds(size_t bytes)
 {
-    hipError_t e = hipFuncSetAttribute((const void*)rinv_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)rinv_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)bytes);
+    return hipFuncSetAttribute((const void*)rinv128_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template hipError_t launch_rinv<double>(const double*, int64_t, int64_t, double*, double*, hipStream_t);
-template hipError_t launch_rinv<float>(const float*, int64_t, int64_t, float*, float*, hipStream_t);
+template hipError_t launch_rinv<double>(const double*, int64_t, int64_t, double*, double*, double*, double*,
+                                        hipStream_t);
+template hipError_t launch_rinv<float>(const float*, int64_t, int64_t, float*, float*, double*, double*, hipStream_t);
 template hipError_t launch_rt<double>(const double*, int64_t, int64_t, double*, hipStream_t);
 template hipError_t launch_rt<float>(const float*, int64_t, int64_t, float*, hipStream_t);
 template hipError_t launch_copy_block<double>(const double*, int64_t, double*, int64_t, int, int, hipStream_t,
