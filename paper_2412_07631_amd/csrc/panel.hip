@@ -44,13 +44,17 @@ struct PanelArgs {
     double* part;       // [2][P][64] per-column partials (double buffered), then [2][64] results
     uint64_t* counter;  // arrival counter (monotone)
     uint64_t base;      // its value before this launch
-    uint64_t* flag;     // published-column counter (monotone)
-    uint64_t flag_base; // its value before this launch
+    uint64_t col_base;  // columns factored by earlier launches (parity of the result slots)
     int64_t* info;      // first zero-norm column + 1 (0: none so far)
     int64_t col0;       // global index of the panel's first column
     int32_t* err;
     uint64_t wait_ticks; // time limit of one wait (100 MHz ticks)
 };
+
+// Result slots follow the double-buffered partial rows (2 x 256 x 64) in the
+// part buffer; an empty slot entry holds this NaN bit pattern.
+constexpr size_t kPartRes = (size_t)2 * 256 * 64;
+constexpr uint64_t kEmpty = 0x7FF4C0FFEE5107D5ull;
 
 // LDS words besides the panel: red 256, vec 64, wv 32, sc 8, Tl 32*33, gl 32
 constexpr int kPanelAux = 256 + 64 + 32 + 8 + kPanelMax * (kPanelMax + 1) + kPanelMax;
@@ -119,7 +123,10 @@ __global__ void __launch_bounds__(256) panel_qr_kernel(PanelArgs<TS> a)
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         }
         // (2) arrival; the last workgroup to arrive sums the partials in a
-        // fixed order and publishes them; the others wait for its flag
+        // fixed order and publishes the 64 sums in a result slot; the others
+        // poll that slot.  Two slots alternate by global column parity; a slot
+        // reads as empty (kEmpty bit pattern) until published, and the
+        // publisher empties the other slot, for the next column, first.
         if (t == 0) {
             const uint64_t old =
                 __hip_atomic_fetch_add(a.counter, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -128,45 +135,53 @@ __global__ void __launch_bounds__(256) panel_qr_kernel(PanelArgs<TS> a)
         target += (uint64_t)a.P;
         __syncthreads();
         const bool last = sc[4] != 0.0;
-        double* res = a.part + (size_t)2 * a.P * 64 + (size_t)(j & 1) * 64;
+        const uint64_t gpar = (a.col_base + (uint64_t)j) & 1;
+        uint64_t* slot = (uint64_t*)(a.part + kPartRes) + gpar * 64;
+        uint64_t* other = (uint64_t*)(a.part + kPartRes) + (gpar ^ 1) * 64;
         if (last) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             const int v = t & 63, g = t >> 6;
             const double* base = a.part + (size_t)(j & 1) * a.P * 64 + v;
-            // one round trip: every load of this lane is issued before any is
-            // consumed (P <= 256, so at most 64 per lane, in two halves)
+            // every load of this lane is issued before any is consumed: one
+            // round trip for up to 136 workgroups (136 rows per WG-column of
+            // 4 lanes x 34), a second one for the rest (P <= 256)
             double s = 0.0;
+            {
+                double x[34];
 #pragma unroll
-            for (int half = 0; half < 2; ++half) {
-                if (half == 1 && a.P <= 128) break;
-                double x[32];
-#pragma unroll
-                for (int u = 0; u < 32; ++u) {
-                    const int q = g + 4 * (u + 32 * half);
+                for (int u = 0; u < 34; ++u) {
+                    const int q = g + 4 * u;
                     x[u] = q < a.P ? base[(size_t)q * 64] : 0.0;
                 }
 #pragma unroll
-                for (int u = 0; u < 32; ++u) s += x[u];
+                for (int u = 0; u < 34; ++u) s += x[u];
+            }
+            if (a.P > 136) {
+                double x[30];
+#pragma unroll
+                for (int u = 0; u < 30; ++u) {
+                    const int q = g + 4 * (u + 34);
+                    x[u] = q < a.P ? base[(size_t)q * 64] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 30; ++u) s += x[u];
             }
             red[g * 64 + v] = s;
             __syncthreads();
             if (t < 64) {
                 const double r = ((red[t] + red[64 + t]) + red[128 + t]) + red[192 + t];
                 vec[t] = r;
-                res[t] = r;
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            }
-            __syncthreads();
-            if (t == 0)
-                __hip_atomic_store(a.flag, (uint64_t)(a.flag_base + j + 1), __ATOMIC_RELAXED,
+                __hip_atomic_store(other + t, kEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(slot + t, __builtin_bit_cast(uint64_t, r), __ATOMIC_RELEASE,
                                    __HIP_MEMORY_SCOPE_AGENT);
+            }
         } else {
-            if (t == 0) {
-                // poll the flag; the clock and the error word are read only
-                // every 16 polls, so a normal (microsecond) wait costs neither
-                uint64_t t0 = 0;
+            if (t < 64) {
+                // poll this lane's entry; the clock and the error word are read
+                // only every 16 polls, so a normal (microsecond) wait costs neither
+                uint64_t t0 = 0, bits;
                 uint32_t spins = 0;
-                while (__hip_atomic_load(a.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < a.flag_base + j + 1) {
+                while ((bits = __hip_atomic_load(slot + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == kEmpty) {
                     if (a.wait_ticks == 0) {
                         __hip_atomic_fetch_or(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         sc[5] = 1.0;
@@ -188,11 +203,13 @@ __global__ void __launch_bounds__(256) panel_qr_kernel(PanelArgs<TS> a)
                         }
                     }
                 }
+                // what the publisher wrote before the slot (the emptied
+                // other slot) is visible from here on
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                vec[t] = __builtin_bit_cast(double, bits);
             }
             __syncthreads();
             if (sc[5] != 0.0) return;      // uniform: the whole workgroup leaves
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            if (t < 64) vec[t] = res[t];
         }
         __syncthreads();
         // (3) the reflector, computed alike by the 32 lanes that then form
@@ -295,8 +312,8 @@ int panel_aux_words() { return kPanelAux; }
 
 template <typename TS>
 hipError_t launch_panel(TS* A, int64_t lda, int64_t mk, int nbp, int rw, double* tau, double* T, int64_t ldt,
-                        double* part, double* gpart, uint64_t* counter, uint64_t* base, uint64_t* flag,
-                        uint64_t* flag_base, int64_t* info, int64_t col0, int32_t* err, hipStream_t s)
+                        double* part, double* gpart, uint64_t* counter, uint64_t* base, uint64_t* col_base,
+                        int64_t* info, int64_t col0, int32_t* err, hipStream_t s)
 {
     PanelArgs<TS> a;
     a.A = A; a.lda = lda; a.mk = mk; a.nbp = nbp; a.rw = rw;
@@ -304,12 +321,12 @@ hipError_t launch_panel(TS* A, int64_t lda, int64_t mk, int nbp, int rw, double*
     a.tau = tau; a.T = T; a.ldt = ldt; a.part = part;
     (void)gpart;
     a.counter = counter; a.base = *base; a.info = info; a.col0 = col0; a.err = err;
-    a.flag = flag; a.flag_base = *flag_base;
+    a.col_base = *col_base;
     a.wait_ticks = g_wait_ticks;
     const size_t shmem = panel_lds_bytes(nbp, rw);
     hipLaunchKernelGGL(panel_qr_kernel<TS>, dim3(a.P), dim3(256), shmem, s, a);
     *base += (uint64_t)a.P * (uint64_t)nbp;
-    *flag_base += (uint64_t)nbp;
+    *col_base += (uint64_t)nbp;
     return hipGetLastError();
 }
 
@@ -335,10 +352,23 @@ hipError_t panel_max_active(int* per_cu, size_t shmem)
 }
 
 template hipError_t launch_panel<double>(double*, int64_t, int64_t, int, int, double*, double*, int64_t, double*,
-                                         double*, uint64_t*, uint64_t*, uint64_t*, uint64_t*, int64_t*, int64_t,
-                                         int32_t*, hipStream_t);
+                                         double*, uint64_t*, uint64_t*, uint64_t*, int64_t*, int64_t, int32_t*,
+                                         hipStream_t);
 template hipError_t launch_panel<float>(float*, int64_t, int64_t, int, int, double*, double*, int64_t, double*,
-                                        double*, uint64_t*, uint64_t*, uint64_t*, uint64_t*, int64_t*, int64_t,
-                                        int32_t*, hipStream_t);
+                                        double*, uint64_t*, uint64_t*, uint64_t*, int64_t*, int64_t, int32_t*,
+                                        hipStream_t);
+
+// Empty both result slots (before the first panel of a factorization).
+__global__ void panel_reset_kernel(double* part)
+{
+    uint64_t* s = (uint64_t*)(part + kPartRes);
+    s[threadIdx.x] = kEmpty;
+}
+
+hipError_t panel_reset(double* part, hipStream_t s)
+{
+    hipLaunchKernelGGL(panel_reset_kernel, dim3(1), dim3(128), 0, s, part);
+    return hipGetLastError();
+}
 
 }  // namespace ctqr
