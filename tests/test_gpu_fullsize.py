@@ -7,6 +7,8 @@ any size, against the oracle's own Siddon CSR copy of A (FP64):
   * graph-captured uneven batches (4096 sinograms, sizes 1..512) equal to the
     same batches solved one call at a time;
   * the adjoint's dot-product identity <g, S d> = <S^T g, d>.
+The 128x128 workload (A 23040 x 16384) also runs its FP64 and FP32 paths:
+FP64 least-squares optimality and A = QR, and FP32 within 1e-4 of FP64.
 """
 import numpy as np
 import pytest
@@ -157,3 +159,79 @@ def test_adjoint_dot_product_identity_full_size(big):
     # FP32 products on both sides, each within about kappa(A) u32 (~1e-3) of
     # the exact map; measured 8e-5
     assert rel <= 1e-3
+
+
+# ---------------------------------------------------------------- 128 x 128
+# The 128x128 workload (90 views x 256 bins: A is 23040 x 16384): plain FP32
+# and FP64 paths on the same 64 noisy slices, checked against each other and
+# against the oracle's CSR copy of A by the same properties.
+@pytest.fixture(scope="module")
+def mid():
+    from paper_2412_07631_amd import ctqr
+    sc = synth.workload_scanner("c2_128")
+    csr = O.system_csr(sc)
+    k = 64
+    ids = list(range(k))
+    X_true = synth.phantoms(2, sc.n_pix, ids)
+    B = synth.noisy_sinograms(2, O.csr_matvec(csr, X_true), 5e4, ids)
+    out = {}
+    for name, dt, prec in (("f64", torch.float64, ctqr.PREC_F64), ("f32", torch.float32, ctqr.PREC_F32)):
+        A = torch.empty((sc.n, ld16(sc.m)), dtype=dt, device="cuda")
+        ctqr.build_system(sc, A)
+        f = ctqr.qr_factor(A, sc.m, sc.n, prec, max_nrhs=k)
+        assert ctqr.status(f) == 0
+        Bd = torch.zeros((k, ld16(sc.m)), dtype=dt, device="cuda")
+        Bd[:, :sc.m] = torch.from_numpy(np.ascontiguousarray(B.T)).to("cuda", dt)
+        ctqr.apply_qt(f, Bd)
+        ctqr.trsm_solve(f, Bd)
+        out[name] = (A, f, Bd[:, :sc.n].double().cpu().numpy().T)
+    yield ctqr, sc, csr, B, out
+    out.clear()
+    torch.cuda.empty_cache()
+
+
+def ls_gradient(csr, B, X, m, n):
+    row_ptr, col, val = csr
+    rows = np.repeat(np.arange(m), np.diff(row_ptr))
+    R = B - O.csr_matvec(csr, X)
+    g = np.stack([np.bincount(col, weights=val * R[rows, c], minlength=n) for c in range(X.shape[1])], axis=1)
+    gb = np.stack([np.bincount(col, weights=val * B[rows, c], minlength=n) for c in range(X.shape[1])], axis=1)
+    return np.max(np.linalg.norm(g, axis=0) / np.linalg.norm(gb, axis=0))
+
+
+def test_c2_fp64_solution_is_least_squares_optimal(mid):
+    ctqr, sc, csr, B, out = mid
+    rel = ls_gradient(csr, B, out["f64"][2], sc.m, sc.n)
+    print("FP64 path ||A^T r|| / ||A^T b||: %.3g" % rel)
+    # FP64 Householder is backward stable: the normal-equation residual sits
+    # a few units of FP64 rounding above zero; measured 3.1e-16
+    assert rel <= 1e-12
+
+
+def test_c2_fp32_path_within_1e4_of_fp64(mid):
+    ctqr, sc, csr, B, out = mid
+    X64, X32 = out["f64"][2], out["f32"][2]
+    err = max(np.linalg.norm(X32[:, c] - X64[:, c]) / np.linalg.norm(X64[:, c]) for c in range(X64.shape[1]))
+    print("FP32 vs FP64 max relative image error: %.3g" % err)
+    # FP32 factor and solve: relative error about kappa(A) u32; measured 2.3e-5
+    assert err <= 1e-4
+
+
+def test_c2_qt_a_equals_r(mid):
+    ctqr, sc, csr, B, out = mid
+    A, f, _ = out["f64"]
+    m = sc.m
+    cols = [0, 1, 127, 128, 8191, 16383]
+    Acol = np.stack([column(csr, m, j) for j in cols], axis=1)
+    Bd = torch.zeros((len(cols), ld16(m)), dtype=torch.float64, device="cuda")
+    Bd[:, :m] = torch.from_numpy(np.ascontiguousarray(Acol.T)).to("cuda")
+    ctqr.apply_qt(f, Bd)
+    QtA = Bd[:, :m].cpu().numpy().T
+    worst = 0.0
+    for c, j in enumerate(cols):
+        expect = np.zeros(m)
+        expect[: j + 1] = A[j, : j + 1].cpu().numpy()
+        worst = max(worst, np.linalg.norm(QtA[:, c] - expect) / np.linalg.norm(Acol[:, c]))
+    print("FP64 max ||Q^T a_j - r_j|| / ||a_j||: %.3g" % worst)
+    # backward error of FP64 Householder QR; measured 1.8e-14
+    assert worst <= 1e-13
