@@ -197,11 +197,17 @@ struct ct_factor {
     void* S3 = nullptr;
 };
 
-// Outer block width: the workspace is sized for kNbMax; an in-memory factor
-// uses kNbMax, a streamed one kNbMax when its tiles allow, else 128.
-constexpr int kNbMax = 256;
+// Outer block width.  The trailing update of a block of nbo reflectors reads
+// and writes the remaining columns once, so its arithmetic intensity grows
+// with nbo (2 nbo / 8 flop per FP32 byte); the work inside a block (panels
+// and their rank-32 updates, the block's Gram matrix) grows with it too.
+// Measured on MI355X at 76800 x 65536: BF16x3 QR 3.46 s (256), 3.07 s (512),
+// 3.02 s (768), 2.91 s (1024), 3.08 s (2048); at 23040 x 16384 the width
+// changes little except in FP64 (494 ms at 256, 451 ms at 1024).  A streamed
+// factor uses kNbStream when its column tiles allow, else 128.
+constexpr int kNbStream = 256;
 
-static int nb_out_for(int prec) { (void)prec; return kNbMax; }
+static int nb_out_for(int64_t n) { return n >= 16384 ? 1024 : 256; }
 
 struct Layout {
     size_t T_all, part, gpart, words, Wp, Wq, G, Vm, Vt, Ws, Ri, Ri64, Rt, VtAll, Tf, S3, total;
@@ -210,10 +216,9 @@ struct Layout {
 
 static size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static Layout layout(int64_t m, int64_t n, int prec, int64_t max_nrhs, bool r_copies = true)
+static Layout layout(int64_t m, int64_t n, int prec, int64_t max_nrhs, int nbo, bool r_copies = true)
 {
     Layout L;
-    const int nbo = nb_out_for(prec);
     const int64_t nblocks = (n + nbo - 1) / nbo;
     const int64_t ncap = std::max<int64_t>(n, 64 * std::max<int64_t>(max_nrhs, 1));
     L.wp_elems = (int64_t)nbo * ncap;
@@ -377,6 +382,13 @@ static int larfb_nt(ct_factor* f, int64_t mk, int nbv, const double* T, int64_t 
         int nz1;
         CT_HIP(launch_nt<TS>((const TS*)o.tts, ldt, Wsum, nbv, (TS*)f->Wq, ldw, nbv, nc, nbv, false, 0, &nz1, s, plan,
                              desc, 0, 0));
+    } else if (OPT == 1 && o.tts) {
+        // W' = T W on the NT kernel: T row-major (its transpose, built in the
+        // Gram scratch, which the solves do not otherwise use)
+        int nz1;
+        TS* Tt = (TS*)f->G;
+        CT_HIP((launch_transpose<TS, TS, true, false>((const TS*)o.tts, Tt, nbv, nbv, ldt, nbv, s)));
+        CT_HIP(launch_nt<TS>(Tt, nbv, Wsum, nbv, (TS*)f->Wq, ldw, nbv, nc, nbv, false, 0, &nz1, s, plan, desc, 0, 0));
     } else {
         CT_HIP((launch_tw<TS, TS, OPT, false>(Wsum, 1, nbv, nc, T, ldt, (TS*)f->Wq, nullptr, ldw, s, desc)));
     }
@@ -1054,7 +1066,7 @@ int ct_qr_workspace(int64_t m, int64_t n, int prec, int64_t max_nrhs, size_t* by
     CT_ARG(prec >= CT_PREC_F64 && prec <= CT_PREC_BF16X3, 3, "prec");
     CT_ARG(max_nrhs >= 0, 4, "max_nrhs");
     CT_ARG(bytes != nullptr, 5, "bytes");
-    *bytes = layout(m, n, prec, max_nrhs).total;
+    *bytes = layout(m, n, prec, max_nrhs, nb_out_for(n)).total;
     return 0;
 }
 
@@ -1128,7 +1140,7 @@ int ct_qr_factor(void* A, int64_t m, int64_t n, int64_t lda, int prec, double* t
     CT_ARG(work != nullptr && aligned(work), 7, "work");
     CT_ARG(max_nrhs >= 0, 9, "max_nrhs");
     CT_ARG(f_out != nullptr, 10, "f");
-    const Layout L = layout(m, n, prec, max_nrhs);
+    const Layout L = layout(m, n, prec, max_nrhs, nb_out_for(n));
     CT_ARG(work_bytes >= L.total, 8, "work_bytes (see ct_qr_workspace)");
     int r = device_setup();
     if (r) return r;
@@ -1136,7 +1148,7 @@ int ct_qr_factor(void* A, int64_t m, int64_t n, int64_t lda, int prec, double* t
 
     ct_factor* f = new (std::nothrow) ct_factor();
     if (!f) return fail(-1001, "%s", "out of host memory");
-    r = init_factor(f, A, m, n, lda, prec, tau, (char*)work, L, max_nrhs, kNbMax);
+    r = init_factor(f, A, m, n, lda, prec, tau, (char*)work, L, max_nrhs, nb_out_for(n));
     if (r) {
         delete f;
         return r;
@@ -1186,7 +1198,7 @@ int ct_qr_stream_workspace(int64_t m, int64_t n, int64_t lda, int prec, int64_t 
     CT_ARG(min_bytes != nullptr, 7, "min_bytes");
     const size_t es = prec == CT_PREC_F64 ? 8 : 4;
     const int64_t nt = (n + tile_cols - 1) / tile_cols;
-    const size_t base = layout(m, n, prec, max_nrhs, false).total, tb = tile_bytes(lda, tile_cols, es);
+    const size_t base = layout(m, n, prec, max_nrhs, kNbStream, false).total, tb = tile_bytes(lda, tile_cols, es);
     *min_bytes = base + std::min<int64_t>(nt, kSlots) * tb;
     if (all_resident_bytes) *all_resident_bytes = base + nt * tb;
     return 0;
@@ -1219,7 +1231,7 @@ int ct_qr_factor_streamed(void* A_host, int64_t m, int64_t n, int64_t lda, int p
         }
     }
     hipStream_t s = (hipStream_t)stream;
-    const Layout L = layout(m, n, prec, max_nrhs, false);
+    const Layout L = layout(m, n, prec, max_nrhs, kNbStream, false);
     const size_t es = prec == CT_PREC_F64 ? 8 : 4;
     const size_t tb = tile_bytes(lda, tile_cols, es);
     const int64_t nt = (n + tile_cols - 1) / tile_cols;
@@ -1242,7 +1254,7 @@ int ct_qr_factor_streamed(void* A_host, int64_t m, int64_t n, int64_t lda, int p
         st->nres = (int64_t)((work_bytes - L.total - kSlots * tb) / tb);
         for (int k = 0; k < kSlots; ++k) st->slot[k] = w + L.total + (size_t)st->nres * tb + (size_t)k * tb;
     }
-    r = init_factor(f, w + L.total, m, n, lda, prec, tau, w, L, max_nrhs, tile_cols % kNbMax == 0 ? kNbMax : 128);
+    r = init_factor(f, w + L.total, m, n, lda, prec, tau, w, L, max_nrhs, tile_cols % kNbStream == 0 ? kNbStream : 128);
     if (r) {
         delete st;
         delete f;

@@ -622,6 +622,7 @@ template hipError_t launch_transpose<float, double, true, true>(const float*, do
 template hipError_t launch_transpose<double, double, true, true>(const double*, double*, int64_t, int, int64_t, int64_t, hipStream_t);
 template hipError_t launch_transpose<double, float, false, false>(const double*, float*, int64_t, int, int64_t, int64_t, hipStream_t);
 template hipError_t launch_transpose<double, double, false, false>(const double*, double*, int64_t, int, int64_t, int64_t, hipStream_t);
+template hipError_t launch_transpose<float, float, true, false>(const float*, float*, int64_t, int, int64_t, int64_t, hipStream_t);
 
 template <typename TI, typename TO>
 hipError_t launch_convert(const TI* X, int64_t ldx, TO* Y, int64_t ldy, int64_t rows, int cols, hipStream_t s)

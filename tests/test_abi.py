@@ -62,7 +62,9 @@ def test_stream_workspace_arithmetic():
     diagonal, 128^2 b (b - 1) / 2 elements for b blocks; the row-major
     reflector blocks, (m - 256 k) x 256 elements for outer block k) plus four
     staging tiles; keeping every tile resident needs that workspace plus all
-    tiles (tile = lda x tile_cols elements, 256-B rounded)."""
+    tiles (tile = lda x tile_cols elements, 256-B rounded).  Below 16384
+    columns both factorizations use outer blocks of 256 columns, so their
+    other buffers coincide."""
     from paper_2412_07631_amd import ctqr
     m, n, lda = 3360, 2304, 3360
     nbt = (n + 255) // 256

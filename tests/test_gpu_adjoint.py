@@ -43,9 +43,11 @@ def test_autograd_matches_oracle_adjoint(setup, prec, tol):
     assert err <= tol, err
 
 
-@pytest.mark.parametrize("prec,tol", [("f64", 1e-11), ("f32", 1e-4)])
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-13), ("f32", 1e-5)])
 def test_dot_product_identity(setup, prec, tol):
-    """<x(db), g> = <db, grad_b(g)> on the GPU path itself."""
+    """<x(db), g> = <db, grad_b(g)> on the GPU path itself.  The rounding
+    error of either side is bounded relative to ||x|| ||g|| (respectively
+    ||db|| ||grad_b||), not to the inner product itself, which can cancel."""
     ct, sc, f = setup["ct"], setup["sc"], setup[prec]
     rng = np.random.default_rng(12)
     db = torch.from_numpy(rng.standard_normal((4, sc.m))).to("cuda", f.dtype).requires_grad_(True)
@@ -54,7 +56,11 @@ def test_dot_product_identity(setup, prec, tol):
     lhs = (x.double() * g.double()).sum(dim=1)
     x.backward(g)
     rhs = (db.detach().double() * db.grad.double()).sum(dim=1)
-    assert torch.max(torch.abs(lhs - rhs) / torch.abs(lhs)).item() <= tol
+    scale = torch.minimum(x.detach().double().norm(dim=1) * g.double().norm(dim=1),
+                          db.detach().double().norm(dim=1) * db.grad.double().norm(dim=1))
+    rel = torch.max(torch.abs(lhs - rhs) / scale).item()
+    print("dot-product identity, error / (||x|| ||g||): %.3g" % rel)
+    assert rel <= tol
 
 
 def test_finite_differences_fp32(setup):
