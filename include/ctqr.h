@@ -134,6 +134,13 @@ int ct_stream_inject_failure(int64_t tile);
  * tests: set the limit in 100 MHz ticks for later factorizations (ticks < 0
  * restores the default; 0 makes every wait give up). */
 int ct_debug_wait_limit(int64_t ticks);
+/* A Householder panel (Sec. 2.1, the geqrf step) is factored first from two
+ * Gram reductions (CholeskyQR2 followed by reconstruction of the Householder
+ * vectors, the same V, T, R and tau in exact arithmetic); a rank-deficient or
+ * badly conditioned panel falls back, on the device, to one reduction per
+ * column.  For tests: enable != 0 (default) allows the two-reduction form for
+ * later factorizations, 0 forces the column-wise form.  Always returns 0. */
+int ct_debug_panel_cholesky(int enable);
 
 /* B <- Q^T B (Eq. (solve), first half; ormqr).  B: m x nrhs, same storage
  * type as the factor's A, nrhs <= max_nrhs.  Rows n..m-1 of the result hold

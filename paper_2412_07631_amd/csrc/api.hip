@@ -22,8 +22,10 @@ hipError_t launch_siddon_rows(const double* rays, int64_t r, int32_t N, double W
 template <typename TS>
 hipError_t launch_panel(TS* A, int64_t lda, int64_t mk, int nbp, int rw, double* tau, double* T, int64_t ldt,
                         double* part, double* gpart, uint64_t* counter, uint64_t* base, uint64_t* col_base,
-                        int64_t* info, int64_t col0, int32_t* err, hipStream_t s);
-hipError_t panel_reset(double* part, hipStream_t s);
+                        uint64_t* cq_count, int64_t* info, int64_t col0, int32_t* err, hipStream_t s);
+hipError_t panel_reset(double* part, double* gpart, hipStream_t s);
+void panel_set_cholesky(bool on);
+void panel_set_cus(int cus);
 size_t panel_lds_bytes(int nbp, int rw);
 int panel_aux_words();
 hipError_t panel_set_max_lds(size_t bytes);
@@ -138,6 +140,7 @@ static int device_setup()
     hipDeviceProp_t p;
     CT_HIP(hipGetDeviceProperties(&p, dev));
     g_dev.cus = p.multiProcessorCount;
+    panel_set_cus(g_dev.cus);
     size_t want = 160 * 1024;
     if (p.maxSharedMemoryPerMultiProcessor > 0 && (size_t)p.maxSharedMemoryPerMultiProcessor < want)
         want = p.maxSharedMemoryPerMultiProcessor;
@@ -179,6 +182,7 @@ struct ct_factor {
     void* Ws;          // split-K sums
     uint64_t barrier_base;
     uint64_t col_base;  // panel columns factored so far (parity of the panel's result slots)
+    uint64_t cq_count;  // two-reduction panel launches so far (parity of their result slots)
     NtPlan solve_plan[5];   // per batch-size bucket (<=8, <=32, <=128, <=512, more)
     int rw;            // panel rows per workgroup
     int64_t max_nrhs;
@@ -501,7 +505,7 @@ static int factor_cols(ct_factor* f, TS* C, int64_t c0, int64_t c1, hipStream_t 
             double* Tp = Tb + (p0 - k0) * (1 + (int64_t)nbo);
             const int64_t ldtp = nbo;
             CT_HIP(launch_panel<TS>(Vp, lda, mkp, bi, f->rw, f->tau + p0, Tp, ldtp, f->part, f->gpart, f->counter,
-                                    &f->barrier_base, &f->col_base, f->info, p0, f->err, s));
+                                    &f->barrier_base, &f->col_base, &f->cq_count, f->info, p0, f->err, s));
             const int64_t rest = k0 + bo - (p0 + bi);
             if (rest > 0) {
                 int r = larfb_mode<TS, 0>(f, inner_mode, Vp, lda, mkp, bi, Tp, ldtp, Vp + bi * lda, lda, (int)rest, s);
@@ -1089,6 +1093,7 @@ static int init_factor(ct_factor* f, void* A, int64_t m, int64_t n, int64_t lda,
     f->info = (int64_t*)(w + L.words + 64);
     f->err = (int32_t*)(w + L.words + 128);
     f->col_base = 0;
+    f->cq_count = 0;
     f->Wp = w + L.Wp; f->wp_elems = L.wp_elems;
     f->Wq = w + L.Wq; f->wq_elems = L.wq_elems;
     f->G = (double*)(w + L.G);
@@ -1154,7 +1159,7 @@ int ct_qr_factor(void* A, int64_t m, int64_t n, int64_t lda, int prec, double* t
         return r;
     }
     CT_HIP(hipMemsetAsync((char*)work + L.words, 0, 256, s));
-    CT_HIP(panel_reset(f->part, s));
+    CT_HIP(panel_reset(f->part, f->gpart, s));
     f->VtAll = (char*)work + L.VtAll;
     int rc = f->f64 ? factor_impl<double>(f, s) : factor_impl<float>(f, s);
     if (!rc && g_dev.trsm_block == 128) {
@@ -1287,7 +1292,7 @@ int ct_qr_factor_streamed(void* A_host, int64_t m, int64_t n, int64_t lda, int p
         return cleanup(-1000 - (int)e);
     }
     e = hipMemsetAsync(w + L.words, 0, 256, s);
-    if (e == hipSuccess) e = panel_reset(f->part, s);
+    if (e == hipSuccess) e = panel_reset(f->part, f->gpart, s);
     if (e != hipSuccess) {
         snprintf(g_err, sizeof g_err, "hipMemsetAsync: %s", hipGetErrorString(e));
         return cleanup(-1000 - (int)e);
@@ -1323,6 +1328,12 @@ int ct_stream_info(const ct_factor* f, int64_t* tiles, int64_t* resident, int64_
 int ct_debug_wait_limit(int64_t ticks)
 {
     panel_set_wait_limit(ticks);
+    return 0;
+}
+
+int ct_debug_panel_cholesky(int enable)
+{
+    panel_set_cholesky(enable != 0);
     return 0;
 }
 

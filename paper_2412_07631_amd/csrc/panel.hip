@@ -20,6 +20,25 @@
 // so workgroup 0 grows the compact-WY factor T (Schreiber & Van Loan 1989)
 // one column per step in LDS, T_jj = tau_j, T[0:j, j] = -tau_j T[0:j,0:j] (V^T v_j)[0:j],
 // with no extra pass over the panel: H_0 ... H_{nbp-1} = I - V T V^T.
+//
+// Two-reduction path (panel_cqr_kernel, tried first when the panel fits): the
+// same V, T, R and tau in exact arithmetic from two Gram reductions instead of
+// one per column.  CholeskyQR2 gives the thin factor Q with orthonormal
+// columns: G = A^T A, R1 = chol(G), Q1 = A R1^-1, R2 = chol(Q1^T Q1),
+// Q = Q1 R2^-1, A = Q (R2 R1).  The Householder form follows from the LU
+// factorization without pivoting Q_top - S = L1 U of the top nbp x nbp block,
+// with the sign S_j = -sign of the eliminated diagonal entry (so every pivot
+// has modulus >= 1): V = [L1; Q_bottom U^-1], T = -U S L1^-T, R = S R2 R1
+// (Ballard, Demmel, Grigori, Jacquelin, Knight, Nguyen, "Reconstructing
+// Householder vectors from tall-skinny QR", 2015).  The sign choice is the
+// no-cancellation choice of the column-wise path, so both give the LAPACK
+// convention.  Each workgroup sums a slice of the Gram partials of all
+// workgroups and publishes it; the top block travels with the first
+// reduction, so the small factorizations (two Cholesky, one LU) run
+// redundantly and identically in every workgroup.  A Cholesky pivot below a
+// relative threshold (rank deficiency, or a panel too ill-conditioned for
+// CholeskyQR2 in FP64) sends every workgroup, uniformly, to the column-wise
+// path on the original panel.
 #include "ct_internal.h"
 
 #include <stdlib.h>
@@ -49,6 +68,8 @@ struct PanelArgs {
     int64_t col0;       // global index of the panel's first column
     int32_t* err;
     uint64_t wait_ticks; // time limit of one wait (100 MHz ticks)
+    double* cq;         // two-reduction path: [256][kNV] partials, then [2][kCqSlotLen] result slots
+    uint64_t cq_par;    // parity of this launch among the two-reduction launches
 };
 
 // Result slots follow the double-buffered partial rows (2 x 256 x 64) in the
@@ -59,33 +80,113 @@ constexpr uint64_t kEmpty = 0x7FF4C0FFEE5107D5ull;
 // LDS words besides the panel: red 256, vec 64, wv 32, sc 8, Tl 32*33, gl 32
 constexpr int kPanelAux = 256 + 64 + 32 + 8 + kPanelMax * (kPanelMax + 1) + kPanelMax;
 
-template <typename TS>
-__global__ void __launch_bounds__(256) panel_qr_kernel(PanelArgs<TS> a)
-{
-    extern __shared__ double lds[];
-    const int t = threadIdx.x, w = blockIdx.x;
-    const int nbp = a.nbp, rw = a.rw;
-    double* pan = lds;                        // pan[c * rw + r]
-    double* red = lds + (size_t)nbp * rw;     // 256
-    double* vec = red + 256;                  // 64: s_c then the pivot row
-    double* wv = vec + 64;                    // 32
-    double* sc = wv + 32;                     // 8 scalars
-    double* Tl = sc + 8;                      // 32 x 33 (workgroup 0)
-    double* gl = Tl + kPanelMax * (kPanelMax + 1);  // 32
-    const int64_t r0 = (int64_t)w * rw;
-    const int rows = (int)((a.mk - r0) < (int64_t)rw ? (a.mk - r0) : (int64_t)rw);
+// Two-reduction path: a reduction carries the packed upper triangle of a
+// 32 x 32 Gram matrix (kNV values); the first also carries the panel's top
+// 32 x 32 block (published by workgroup 0, not summed).
+constexpr int kNV = 32 * 33 / 2;
+constexpr int kNA = kNV + 32 * 32;
+constexpr int kCqSlotLen = kNA + kNV;
+constexpr size_t kCqSlot = (size_t)256 * kNV;
+// LDS words of that path besides the 32-column panel and kPanelAux:
+// K1..K4 (32 x 32 each), S, 1/diag, Gram phase partials (36 blocks x 7 x 16)
+constexpr int kGramPh = 7;
+constexpr int kCqAux = 4 * 1024 + 32 + 32 + 36 * kGramPh * 16;
+constexpr double kCholTol1 = 1e-13;   // pivot / diagonal of A^T A
+constexpr double kCholTol2 = 0.25;    // pivot of Q1^T Q1 (close to 1)
 
-    // a wait of an earlier launch gave up: the factorization is already failed
-    if (t == 0) sc[5] = (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1) ? 1.0 : 0.0;
-    __syncthreads();
-    if (sc[5] != 0.0) return;
-    for (int c = 0; c < nbp; ++c)
-        for (int r = t; r < rows; r += 256) pan[c * rw + r] = (double)a.A[(r0 + r) + (int64_t)c * a.lda];
+struct PanelLds {
+    double *pan, *red, *vec, *wv, *sc, *Tl, *gl;
+};
+
+__device__ __forceinline__ PanelLds panel_lds(double* lds, int rw, int ncols)
+{
+    PanelLds L;
+    L.pan = lds;                               // pan[c * rw + r]
+    L.red = lds + (size_t)ncols * rw;          // 256
+    L.vec = L.red + 256;                       // 64: s_c then the pivot row
+    L.wv = L.vec + 64;                         // 32
+    L.sc = L.wv + 32;                          // 8 scalars
+    L.Tl = L.sc + 8;                           // 32 x 33 (workgroup 0)
+    L.gl = L.Tl + kPanelMax * (kPanelMax + 1); // 32
+    return L;
+}
+
+__device__ __forceinline__ void set_err(int32_t* err)
+{
+    __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bounded wait for a published word (anything but the kEmpty pattern).  The
+// clock and the error word are read only every 16 polls, so a normal
+// (microsecond) wait costs neither.  False: the wait gave up (time limit, or
+// an earlier wait of the factorization did).
+__device__ __forceinline__ bool wait_word(uint64_t* p, uint64_t& bits, int32_t* err, uint64_t wait_ticks)
+{
+    uint64_t t0 = 0;
+    uint32_t spins = 0;
+    while ((bits = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == kEmpty) {
+        if (wait_ticks == 0) {
+            set_err(err);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        if ((++spins & 15) == 0) {
+            const uint64_t now = __builtin_amdgcn_s_memrealtime();
+            if (spins == 16) {
+                t0 = now;
+            } else if (now - t0 >= wait_ticks) {
+                set_err(err);
+                return false;
+            }
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1) return false;
+        }
+    }
+    return true;
+}
+
+// The same for the arrival counter: wait until it reaches `target`.
+__device__ __forceinline__ bool wait_count(uint64_t* counter, uint64_t target, int32_t* err, uint64_t wait_ticks)
+{
+    uint64_t t0 = 0;
+    uint32_t spins = 0;
+    while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (wait_ticks == 0) {
+            set_err(err);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        if ((++spins & 15) == 0) {
+            const uint64_t now = __builtin_amdgcn_s_memrealtime();
+            if (spins == 16) {
+                t0 = now;
+            } else if (now - t0 >= wait_ticks) {
+                set_err(err);
+                return false;
+            }
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1) return false;
+        }
+    }
+    return true;
+}
+
+// Column-wise Householder steps on the panel in LDS: one cross-workgroup
+// reduction per column, arrivals counted from `target` on.  False: a wait
+// gave up (every workgroup then leaves).
+template <typename TS>
+__device__ bool column_steps(const PanelArgs<TS>& a, const PanelLds& L, int w, int t, int rows, int64_t r0,
+                             uint64_t target)
+{
+    const int nbp = a.nbp, rw = a.rw;
+    double* pan = L.pan;
+    double* red = L.red;
+    double* vec = L.vec;
+    double* wv = L.wv;
+    double* sc = L.sc;
+    double* Tl = L.Tl;
+    double* gl = L.gl;
     if (w == 0)
         for (int e = t; e < kPanelMax * (kPanelMax + 1); e += 256) Tl[e] = 0.0;
     __syncthreads();
-
-    uint64_t target = a.base;
     for (int j = 0; j < nbp; ++j) {
         // (1) this workgroup's partial Gram row (all columns) and pivot row
         {
@@ -177,39 +278,15 @@ __global__ void __launch_bounds__(256) panel_qr_kernel(PanelArgs<TS> a)
             }
         } else {
             if (t < 64) {
-                // poll this lane's entry; the clock and the error word are read
-                // only every 16 polls, so a normal (microsecond) wait costs neither
-                uint64_t t0 = 0, bits;
-                uint32_t spins = 0;
-                while ((bits = __hip_atomic_load(slot + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == kEmpty) {
-                    if (a.wait_ticks == 0) {
-                        __hip_atomic_fetch_or(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        sc[5] = 1.0;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                    if ((++spins & 15) == 0) {
-                        const uint64_t now = __builtin_amdgcn_s_memrealtime();
-                        if (spins == 16) {
-                            t0 = now;
-                        } else if (now - t0 >= a.wait_ticks) {
-                            __hip_atomic_fetch_or(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            sc[5] = 1.0;
-                            break;
-                        }
-                        if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1) {
-                            sc[5] = 1.0;
-                            break;
-                        }
-                    }
-                }
+                uint64_t bits = 0;
+                if (!wait_word(slot + t, bits, a.err, a.wait_ticks)) sc[5] = 1.0;
                 // what the publisher wrote before the slot (the emptied
                 // other slot) is visible from here on
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 vec[t] = __builtin_bit_cast(double, bits);
             }
             __syncthreads();
-            if (sc[5] != 0.0) return;      // uniform: the whole workgroup leaves
+            if (sc[5] != 0.0) return false;      // uniform: the whole workgroup leaves
         }
         __syncthreads();
         // (3) the reflector, computed alike by the 32 lanes that then form
@@ -292,14 +369,412 @@ __global__ void __launch_bounds__(256) panel_qr_kernel(PanelArgs<TS> a)
         }
         __syncthreads();
     }
+    return true;
+}
 
+template <typename TS>
+__device__ __forceinline__ void load_panel(const PanelArgs<TS>& a, double* pan, int ncols, int t, int rows, int64_t r0)
+{
+    for (int c = 0; c < ncols; ++c)
+        for (int r = t; r < rows; r += 256)
+            pan[c * a.rw + r] = c < a.nbp ? (double)a.A[(r0 + r) + (int64_t)c * a.lda] : 0.0;
+}
+
+// V\R back to the matrix; workgroup 0 also writes T (zero below the diagonal).
+template <typename TS>
+__device__ __forceinline__ void store_panel(const PanelArgs<TS>& a, const PanelLds& L, int w, int t, int rows,
+                                            int64_t r0)
+{
+    const int nbp = a.nbp;
     for (int c = 0; c < nbp; ++c)
-        for (int r = t; r < rows; r += 256) a.A[(r0 + r) + (int64_t)c * a.lda] = (TS)pan[c * rw + r];
+        for (int r = t; r < rows; r += 256) a.A[(r0 + r) + (int64_t)c * a.lda] = (TS)L.pan[c * a.rw + r];
     if (w == 0)
         for (int e = t; e < nbp * nbp; e += 256) {
             const int q = e / nbp, p = e - q * nbp;
-            a.T[p + (int64_t)q * a.ldt] = p <= q ? Tl[q * 33 + p] : 0.0;
+            a.T[p + (int64_t)q * a.ldt] = p <= q ? L.Tl[q * 33 + p] : 0.0;
         }
+}
+
+template <typename TS>
+__global__ void __launch_bounds__(256) panel_qr_kernel(PanelArgs<TS> a)
+{
+    extern __shared__ double lds[];
+    const int t = threadIdx.x, w = blockIdx.x;
+    const PanelLds L = panel_lds(lds, a.rw, a.nbp);
+    const int64_t r0 = (int64_t)w * a.rw;
+    const int rows = (int)((a.mk - r0) < (int64_t)a.rw ? (a.mk - r0) : (int64_t)a.rw);
+
+    // a wait of an earlier launch gave up: the factorization is already failed
+    if (t == 0) L.sc[5] = (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1) ? 1.0 : 0.0;
+    __syncthreads();
+    if (L.sc[5] != 0.0) return;
+    load_panel(a, L.pan, a.nbp, t, rows, r0);
+    __syncthreads();
+    if (!column_steps(a, L, w, t, rows, r0, a.base)) return;
+    store_panel(a, L, w, t, rows, r0);
+}
+
+// ------------------------------------------------- two-reduction panel path
+// Packed upper triangle: entry (i, c), i <= c < 32, at c (c + 1) / 2 + i.
+__device__ __forceinline__ void unpack_ut(int e, int& i, int& c)
+{
+    int cc = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+    if ((cc + 1) * (cc + 2) / 2 <= e) ++cc;
+    if (cc * (cc + 1) / 2 > e) --cc;
+    c = cc;
+    i = e - cc * (cc + 1) / 2;
+}
+
+// This workgroup's Gram partial of the 32 panel columns (rows in LDS) as the
+// packed upper triangle, in pv[0..kNV).  Threads own 4 x 4 blocks of the
+// upper block triangle (36 blocks) over kGramPh row phases; wave 0 then sums
+// the phases.  Ends with a barrier.
+__device__ void gram_partial(const double* pan, int rw, int rows, double* red2, double* pv, int t)
+{
+    if (t < 36 * kGramPh) {
+        const int blk = t % 36, ph = t / 36;
+        int bj = 0;
+        while ((bj + 1) * (bj + 2) / 2 <= blk) ++bj;
+        const int bi = blk - bj * (bj + 1) / 2;
+        const double* pa = pan + (4 * bi) * rw;
+        const double* pc = pan + (4 * bj) * rw;
+        double acc[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+        for (int r = ph; r < rows; r += kGramPh) {
+            double xa[4], xc[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                xa[u] = pa[u * rw + r];
+                xc[u] = pc[u * rw + r];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] += xa[u] * xc[v];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) red2[(ph * 36 + blk) * 16 + u * 4 + v] = acc[u][v];
+    }
+    __syncthreads();
+    for (int e = t; e < kNV; e += 256) {
+        int i, c;
+        unpack_ut(e, i, c);
+        const int bi = i >> 2, bj = c >> 2;
+        const int blk = bj * (bj + 1) / 2 + bi;
+        const int uv = (i & 3) * 4 + (c & 3);
+        double s = 0.0;
+        for (int ph = 0; ph < kGramPh; ++ph) s += red2[(ph * 36 + blk) * 16 + uv];
+        pv[e] = s;
+    }
+    __syncthreads();
+}
+
+// One reduction of the two-reduction path.  pv (LDS) holds this workgroup's
+// packed partial; it goes to the partial buffer, the workgroup arrives, waits
+// for every arrival (counter >= target), sums its slice of entries
+// (e = w + P k) over all partials in a fixed order and publishes them in
+// `slot`; then every one of the `nread` slot entries is read back into LDS
+// through `dst` (packed entries go to the upper triangle of K, column-major
+// ld 32; entries from kNV on to Kt).  False: a wait gave up.
+template <typename TS>
+__device__ bool cq_reduce(const PanelArgs<TS>& a, const double* pv, uint64_t target, uint64_t* slot, int nread,
+                          double* K, double* Kt, double* sc, int w, int t)
+{
+    const int P = a.P;
+    double* part = a.cq;
+    if (t < 64) {
+        for (int e = t; e < kNV; e += 64) part[(size_t)w * kNV + e] = pv[e];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (t == 0) {
+            __hip_atomic_fetch_add(a.counter, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            sc[5] = wait_count(a.counter, target, a.err, a.wait_ticks) ? 0.0 : 1.0;
+        }
+    }
+    __syncthreads();
+    if (sc[5] != 0.0) return false;
+    if (t < 64) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const int ns = (kNV - 1 - w) / P + 1;
+        int p2 = 1;
+        while (p2 < ns) p2 <<= 1;
+        const int gsz = p2 >= 64 ? 1 : 64 / p2;
+        const int ng = 64 / gsz, grp = t / gsz, mem = t % gsz;
+        for (int k0 = 0; k0 < ns; k0 += ng) {
+            const int k = k0 + grp;
+            const int e = w + P * k;
+            double s = 0.0;
+            if (k < ns) {
+#pragma unroll 8
+                for (int q = mem; q < P; q += gsz) s += part[(size_t)q * kNV + e];
+            }
+            for (int o = 1; o < gsz; o <<= 1) s += __shfl_xor(s, o);
+            if (k < ns && mem == 0)
+                __hip_atomic_store(slot + e, __builtin_bit_cast(uint64_t, s), __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    bool ok = true;
+    for (int e = t; e < nread; e += 256) {
+        uint64_t bits = 0;
+        if (!wait_word(slot + e, bits, a.err, a.wait_ticks)) {
+            ok = false;
+            break;
+        }
+        const double v = __builtin_bit_cast(double, bits);
+        if (e < kNV) {
+            int i, c;
+            unpack_ut(e, i, c);
+            K[i + 32 * c] = v;
+        } else {
+            Kt[e - kNV] = v;
+        }
+    }
+    if (!ok) sc[5] = 1.0;
+    __syncthreads();
+    return sc[5] == 0.0;
+}
+
+// Cholesky factor of the symmetric matrix in K (upper triangle, column-major
+// ld 32, n x n leading block): right-looking, the pivot row scaled only at the
+// end.  On success K's upper triangle holds R (R^T R = K) and dv[j] = 1/R_jj.
+// The pivot test reads values every thread sees alike, so the result is
+// uniform.  Diagonal pivots must exceed tol times the original diagonal.
+__device__ bool chol32(double* K, double* dv, double* diag0, int n, double tol, int t)
+{
+    if (t < 32) diag0[t] = t < n ? K[t + 32 * t] : 1.0;
+    int ei[3], ec[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int e = t + 256 * k;
+        if (e < kNV) {
+            unpack_ut(e, ei[k], ec[k]);
+        } else {
+            ei[k] = 32;
+            ec[k] = 32;
+        }
+    }
+    __syncthreads();
+    for (int j = 0; j < n; ++j) {
+        const double d = K[j + 32 * j];
+        if (!(d > tol * diag0[j]) || !(d < 1.0e300)) return false;
+        const double id = 1.0 / d;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int i = ei[k], c = ec[k];
+            if (i > j && c < n) K[i + 32 * c] -= K[j + 32 * i] * K[j + 32 * c] * id;
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < kNV; e += 256) {
+        int i, c;
+        unpack_ut(e, i, c);
+        if (c < n) {
+            const double rd = sqrt(K[i + 32 * i]);
+            // the diagonal entry is read by the other entries of its row: the
+            // row is finished from its untouched pivot value, written last
+            if (i != c) K[i + 32 * c] = K[i + 32 * c] / rd;
+        }
+    }
+    __syncthreads();
+    if (t < 32) {
+        if (t < n) {
+            const double rd = sqrt(K[t + 32 * t]);
+            K[t + 32 * t] = rd;
+            dv[t] = 1.0 / rd;
+        } else {
+            dv[t] = 0.0;
+        }
+    }
+    __syncthreads();
+    return true;
+}
+
+// x (one row of 32, registers) <- x M^-1, M upper triangular (column-major
+// ld 32, dv = 1/diag, zero beyond the leading n x n block).
+__device__ __forceinline__ void row_times_inv(double (&x)[32], const double* M, const double* dv)
+{
+#pragma unroll
+    for (int l = 0; l < 32; ++l) {
+        x[l] *= dv[l];
+#pragma unroll
+        for (int c = l + 1; c < 32; ++c) x[c] -= x[l] * M[l + 32 * c];
+    }
+}
+
+// Rows [lo, hi) of a column-major row block (ld) times M^-1, in place.
+__device__ __forceinline__ void rows_times_inv(double* X, int ld, int lo, int hi, const double* M, const double* dv,
+                                               int t, int nthreads)
+{
+    for (int r = lo + t; r < hi; r += nthreads) {
+        double x[32];
+#pragma unroll
+        for (int c = 0; c < 32; ++c) x[c] = X[c * ld + r];
+        row_times_inv(x, M, dv);
+#pragma unroll
+        for (int c = 0; c < 32; ++c) X[c * ld + r] = x[c];
+    }
+}
+
+template <typename TS>
+__global__ void __launch_bounds__(256) panel_cqr_kernel(PanelArgs<TS> a)
+{
+    extern __shared__ double lds[];
+    const int t = threadIdx.x, w = blockIdx.x;
+    const int nbp = a.nbp, rw = a.rw, P = a.P;
+    const PanelLds L = panel_lds(lds, rw, 32);
+    double* K1 = L.gl + kPanelMax;   // G, then R1
+    double* K2 = K1 + 1024;          // Q1^T Q1, then R2
+    double* K3 = K2 + 1024;          // top 32 x 32 block of A, of Q1, of Q, then L1 \ U
+    double* K4 = K3 + 1024;          // U R2
+    double* Sv = K4 + 1024;          // S
+    double* dv = Sv + 32;            // 1 / diagonal of the current triangular factor
+    double* red2 = dv + 32;          // Gram phase partials
+    double* sc = L.sc;
+    double* pan = L.pan;
+    const int64_t r0 = (int64_t)w * rw;
+    const int rows = (int)((a.mk - r0) < (int64_t)rw ? (a.mk - r0) : (int64_t)rw);
+
+    if (t == 0) sc[5] = (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1) ? 1.0 : 0.0;
+    __syncthreads();
+    if (sc[5] != 0.0) return;
+    // Nothing in this launch reads the other parity's result slots: empty
+    // them for the next two-reduction launch.  The column-wise path expects
+    // the slot of parity col_base + nbp empty at its next launch.
+    {
+        uint64_t* o = (uint64_t*)(a.cq + kCqSlot) + (a.cq_par ^ 1) * kCqSlotLen;
+        for (int e = w * 256 + t; e < kCqSlotLen; e += P * 256)
+            __hip_atomic_store(o + e, kEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (w == 0 && t < 64) {
+            uint64_t* cs = (uint64_t*)(a.part + kPartRes) + ((a.col_base + (uint64_t)nbp) & 1) * 64;
+            __hip_atomic_store(cs + t, kEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    load_panel(a, pan, 32, t, rows, r0);
+    for (int e = t; e < 4 * 1024; e += 256) K1[e] = 0.0;
+    __syncthreads();
+    uint64_t* slotA = (uint64_t*)(a.cq + kCqSlot) + a.cq_par * kCqSlotLen;
+    uint64_t* slotB = slotA + kNA;
+    // the panel's top 32 x 32 block, from workgroup 0 (whose rows they are)
+    if (w == 0)
+        for (int e = t; e < 1024; e += 256) {
+            const int r = e & 31, c = e >> 5;
+            const double v = r < rows ? pan[c * rw + r] : 0.0;
+            __hip_atomic_store(slotA + kNV + e, __builtin_bit_cast(uint64_t, v), __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+
+    int res = 0;     // 1: done; 0: fall back after one reduction; 2: after two
+    do {
+        // (A) G = A^T A and the top block
+        // (K4 is free until the LU: it carries this workgroup's partials)
+        gram_partial(pan, rw, rows, red2, K4, t);
+        if (!cq_reduce(a, K4, a.base + (uint64_t)P, slotA, kNA, K1, K3, sc, w, t)) return;
+        if (!chol32(K1, dv, Sv, nbp, kCholTol1, t)) {
+            res = 0;
+            break;
+        }
+        // Q1 = A R1^-1 on this workgroup's rows and on the top block
+        rows_times_inv(pan, rw, 0, rows, K1, dv, t, 256);
+        __syncthreads();
+        rows_times_inv(K3, 32, 0, 32, K1, dv, t, 256);
+        // (B) Q1^T Q1
+        gram_partial(pan, rw, rows, red2, K4, t);
+        if (!cq_reduce(a, K4, a.base + 2 * (uint64_t)P, slotB, kNV, K2, nullptr, sc, w, t)) return;
+        if (!chol32(K2, dv, Sv, nbp, kCholTol2, t)) {
+            res = 2;
+            break;
+        }
+        // top block of Q = Q1 R2^-1
+        rows_times_inv(K3, 32, 0, 32, K2, dv, t, 256);
+        __syncthreads();
+        // LU of Q_top - S (leading nbp x nbp), right-looking, the pivot column
+        // scaled at the end; S_j = -sign of the eliminated diagonal entry
+        for (int j = 0; j < nbp; ++j) {
+            const double q = K3[j + 32 * j];
+            const double sj = q >= 0.0 ? -1.0 : 1.0;
+            const double ip = 1.0 / (q - sj);
+            if (t == 0) Sv[j] = sj;
+            for (int e = t; e < 1024; e += 256) {
+                const int i = e & 31, c = e >> 5;
+                if (i > j && c > j && i < nbp && c < nbp) K3[e] -= K3[i + 32 * j] * K3[j + 32 * c] * ip;
+            }
+            __syncthreads();
+        }
+        // U_jj = q_jj - S_j; L_ij = K_ij / U_jj (i > j)
+        for (int e = t; e < 1024; e += 256) {
+            const int i = e & 31, c = e >> 5;
+            if (i > c && i < nbp) K3[e] = K3[e] / (K3[c + 32 * c] - Sv[c]);
+        }
+        __syncthreads();
+        if (t < 32) K3[t + 32 * t] = t < nbp ? K3[t + 32 * t] - Sv[t] : 1.0;
+        __syncthreads();
+        // K4 = U R2 (upper triangular), dv = its inverse diagonal
+        for (int e = t; e < kNV; e += 256) {
+            int i, c;
+            unpack_ut(e, i, c);
+            double s = 0.0;
+            if (c < nbp)
+                for (int l = i; l <= c; ++l) s += K3[i + 32 * l] * K2[l + 32 * c];
+            K4[i + 32 * c] = s;
+        }
+        __syncthreads();
+        if (t < 32) dv[t] = t < nbp ? 1.0 / K4[t + 32 * t] : 0.0;
+        __syncthreads();
+        // V = Q1 (U R2)^-1 on rows nbp.. of the panel
+        {
+            const int lo = r0 >= nbp ? 0 : (int)(nbp - r0);
+            rows_times_inv(pan, rw, lo < rows ? lo : rows, rows, K4, dv, t, 256);
+        }
+        __syncthreads();
+        if (w == 0) {
+            // top rows: V below the diagonal, R = S R2 R1 on and above it
+            for (int e = t; e < nbp * nbp; e += 256) {
+                const int i = e % nbp, c = e / nbp;
+                double v;
+                if (i > c) {
+                    v = K3[i + 32 * c];
+                } else {
+                    double s = 0.0;
+                    for (int l = i; l <= c; ++l) s += K2[i + 32 * l] * K1[l + 32 * c];
+                    v = Sv[i] * s;
+                }
+                pan[c * rw + i] = v;
+            }
+            // T = -U S L1^-T, row i by thread i:
+            //   T[i][c] = -U[i][c] S_c - sum_{l=i}^{c-1} T[i][l] L1[c][l]
+            if (t < nbp) {
+                const int i = t;
+                for (int c = 0; c < 32; ++c) L.Tl[c * 33 + i] = 0.0;
+                for (int c = i; c < nbp; ++c) {
+                    double s = -K3[i + 32 * c] * Sv[c];
+                    for (int l = i; l < c; ++l) s -= L.Tl[l * 33 + i] * K3[c + 32 * l];
+                    L.Tl[c * 33 + i] = s;
+                }
+                a.tau[i] = L.Tl[i * 33 + i];
+            }
+        }
+        __syncthreads();
+        res = 1;
+    } while (false);
+
+    if (res == 1) {
+        store_panel(a, L, w, t, rows, r0);
+        // arrivals the column-wise path would have made: the counter advances
+        // by the same amount whichever path a launch takes
+        if (t == 0) __hip_atomic_fetch_add(a.counter, (uint64_t)nbp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    // fall back on the column-wise path from the original panel
+    if (res == 0 && t == 0) __hip_atomic_fetch_add(a.counter, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    load_panel(a, pan, nbp, t, rows, r0);
+    __syncthreads();
+    if (!column_steps(a, L, w, t, rows, r0, a.base + 2 * (uint64_t)P)) return;
+    store_panel(a, L, w, t, rows, r0);
 }
 
 // --------------------------------------------------------------- launcher
@@ -310,22 +785,46 @@ void panel_set_wait_limit(int64_t ticks) { g_wait_ticks = ticks < 0 ? kWaitTicks
 size_t panel_lds_bytes(int nbp, int rw) { return ((size_t)nbp * rw + kPanelAux) * sizeof(double); }
 int panel_aux_words() { return kPanelAux; }
 
+// Two-reduction path: 32 panel columns, the column-wise scratch and its own.
+static size_t cqr_lds_bytes(int rw) { return ((size_t)32 * rw + kPanelAux + kCqAux) * sizeof(double); }
+static size_t g_lds_max = 64 * 1024;
+static bool g_cqr = true;
+static int g_cus = 256;
+void panel_set_cholesky(bool on) { g_cqr = on; }
+void panel_set_cus(int cus) { g_cus = cus < 1 ? 1 : (cus > 256 ? 256 : cus); }
+
 template <typename TS>
 hipError_t launch_panel(TS* A, int64_t lda, int64_t mk, int nbp, int rw, double* tau, double* T, int64_t ldt,
                         double* part, double* gpart, uint64_t* counter, uint64_t* base, uint64_t* col_base,
-                        int64_t* info, int64_t col0, int32_t* err, hipStream_t s)
+                        uint64_t* cq_count, int64_t* info, int64_t col0, int32_t* err, hipStream_t s)
 {
     PanelArgs<TS> a;
-    a.A = A; a.lda = lda; a.mk = mk; a.nbp = nbp; a.rw = rw;
-    a.P = (int)((mk + rw - 1) / rw);
+    a.A = A; a.lda = lda; a.mk = mk; a.nbp = nbp;
     a.tau = tau; a.T = T; a.ldt = ldt; a.part = part;
-    (void)gpart;
     a.counter = counter; a.base = *base; a.info = info; a.col0 = col0; a.err = err;
     a.col_base = *col_base;
     a.wait_ticks = g_wait_ticks;
-    const size_t shmem = panel_lds_bytes(nbp, rw);
-    hipLaunchKernelGGL(panel_qr_kernel<TS>, dim3(a.P), dim3(256), shmem, s, a);
-    *base += (uint64_t)a.P * (uint64_t)nbp;
+    a.cq = gpart;
+    a.cq_par = *cq_count & 1;
+    // the two-reduction path spreads the rows over one workgroup per compute
+    // unit (at most 256; odd row counts keep the column-major LDS panel free
+    // of bank conflicts); workgroup 0 must hold the top nbp rows
+    int64_t rq = (mk + g_cus - 1) / g_cus;
+    if (rq < 33) rq = 33;
+    if ((rq & 1) == 0) ++rq;
+    const bool cq = g_cqr && nbp <= 32 && cqr_lds_bytes((int)rq) <= g_lds_max;
+    if (cq) {
+        a.rw = (int)rq;
+        a.P = (int)((mk + rq - 1) / rq);
+        hipLaunchKernelGGL(panel_cqr_kernel<TS>, dim3(a.P), dim3(256), cqr_lds_bytes(a.rw), s, a);
+        *base += (uint64_t)a.P * (uint64_t)(2 + nbp);
+        *cq_count += 1;
+    } else {
+        a.rw = rw;
+        a.P = (int)((mk + rw - 1) / rw);
+        hipLaunchKernelGGL(panel_qr_kernel<TS>, dim3(a.P), dim3(256), panel_lds_bytes(nbp, rw), s, a);
+        *base += (uint64_t)a.P * (uint64_t)nbp;
+    }
     *col_base += (uint64_t)nbp;
     return hipGetLastError();
 }
@@ -333,11 +832,13 @@ hipError_t launch_panel(TS* A, int64_t lda, int64_t mk, int nbp, int rw, double*
 
 hipError_t panel_set_max_lds(size_t bytes)
 {
-    const void* k[2] = {(const void*)panel_qr_kernel<double>, (const void*)panel_qr_kernel<float>};
+    const void* k[4] = {(const void*)panel_qr_kernel<double>, (const void*)panel_qr_kernel<float>,
+                        (const void*)panel_cqr_kernel<double>, (const void*)panel_cqr_kernel<float>};
     for (const void* f : k) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
     }
+    g_lds_max = bytes;
     return hipSuccess;
 }
 
@@ -352,22 +853,24 @@ hipError_t panel_max_active(int* per_cu, size_t shmem)
 }
 
 template hipError_t launch_panel<double>(double*, int64_t, int64_t, int, int, double*, double*, int64_t, double*,
-                                         double*, uint64_t*, uint64_t*, uint64_t*, int64_t*, int64_t, int32_t*,
-                                         hipStream_t);
+                                         double*, uint64_t*, uint64_t*, uint64_t*, uint64_t*, int64_t*, int64_t,
+                                         int32_t*, hipStream_t);
 template hipError_t launch_panel<float>(float*, int64_t, int64_t, int, int, double*, double*, int64_t, double*,
-                                        double*, uint64_t*, uint64_t*, uint64_t*, int64_t*, int64_t, int32_t*,
-                                        hipStream_t);
+                                        double*, uint64_t*, uint64_t*, uint64_t*, uint64_t*, int64_t*, int64_t,
+                                        int32_t*, hipStream_t);
 
-// Empty both result slots (before the first panel of a factorization).
-__global__ void panel_reset_kernel(double* part)
+// Empty every result slot (before the first panel of a factorization): the
+// column-wise path's two, and both parities of the two-reduction path's.
+__global__ void __launch_bounds__(256) panel_reset_kernel(double* part, double* gpart)
 {
-    uint64_t* s = (uint64_t*)(part + kPartRes);
-    s[threadIdx.x] = kEmpty;
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e < 128) ((uint64_t*)(part + kPartRes))[e] = kEmpty;
+    if (e < 2 * kCqSlotLen) ((uint64_t*)(gpart + kCqSlot))[e] = kEmpty;
 }
 
-hipError_t panel_reset(double* part, hipStream_t s)
+hipError_t panel_reset(double* part, double* gpart, hipStream_t s)
 {
-    hipLaunchKernelGGL(panel_reset_kernel, dim3(1), dim3(128), 0, s, part);
+    hipLaunchKernelGGL(panel_reset_kernel, dim3((2 * kCqSlotLen + 255) / 256), dim3(256), 0, s, part, gpart);
     return hipGetLastError();
 }
 

@@ -58,6 +58,7 @@ _sig("ct_qr_resume", [_vp, _vp])
 _sig("ct_stream_info", [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)])
 _sig("ct_stream_inject_failure", [_i64])
 _sig("ct_debug_wait_limit", [_i64])
+_sig("ct_debug_panel_cholesky", [ctypes.c_int])
 _sig("ct_apply_qt", [_vp, _vp, _i64, _i64, _vp])
 _sig("ct_trsm_solve", [_vp, _vp, _i64, _i64, _vp])
 _sig("ct_solve_backward", [_vp, _vp, _i64, _i64, _vp, _i64, _vp])
@@ -237,6 +238,12 @@ def debug_wait_limit(ticks: int):
     """Time limit (100 MHz ticks) of one cross-workgroup wait of the panels;
     negative restores the default."""
     _check(_lib.ct_debug_wait_limit(ticks))
+
+
+def debug_panel_cholesky(enable: bool):
+    """Allow (default) or forbid the two-reduction panel form for later
+    factorizations; forbidden, every panel takes one reduction per column."""
+    _check(_lib.ct_debug_panel_cholesky(1 if enable else 0))
 
 
 def apply_qt(f: Factor, B: torch.Tensor, nrhs: int = None, stream=None):

@@ -104,8 +104,17 @@ def test_residual_kernel_f64(ct):
 
 
 # ------------------------------------------------------------ factorization
+@pytest.fixture(params=["two-reduction", "column-wise"])
+def panel_path(request, ct):
+    """Panels factored from two Gram reductions (the default) or forced onto
+    one reduction per column."""
+    ct.debug_panel_cholesky(request.param == "two-reduction")
+    yield request.param
+    ct.debug_panel_cholesky(True)
+
+
 @pytest.mark.parametrize("name", ["c1", "ragged", "multi"])
-def test_qr_f64_matches_oracle(ct, name):
+def test_qr_f64_matches_oracle(ct, name, panel_path):
     sc, A, VR, tau = problem(name)
     Ad = gpu_system(ct, sc, torch.float64)
     f = ct.qr_factor(Ad, sc.m, sc.n, ct.PREC_F64, max_nrhs=8)
@@ -120,6 +129,23 @@ def test_qr_f64_matches_oracle(ct, name):
     assert np.max(np.abs(f.tau.cpu().numpy() - tau)) <= 1e-12
 
 
+@pytest.mark.parametrize("name", ["ragged", "multi"])
+def test_qr_f32_matches_oracle(ct, name, panel_path):
+    """FP32 storage, FP32 updates, FP64 panels: R against the oracle's within
+    the FP32 rounding of the updates (kappa(A) u32 ~ 1e-5 here)."""
+    sc, A, VR, tau = problem(name)
+    Ad = gpu_system(ct, sc, torch.float32)
+    f = ct.qr_factor(Ad, sc.m, sc.n, ct.PREC_F32, max_nrhs=8)
+    assert ct.status(f) == 0
+    VRg = from_dev(Ad, sc.m)
+    n = sc.n
+    R, Rg = np.triu(VR[:n]), np.triu(VRg[:n])
+    err = np.max(np.abs(Rg - R)) / np.max(np.abs(R))
+    print("FP32 R max error / max |R|: %.3g" % err)
+    assert err <= 1e-4
+    assert np.max(np.abs(f.tau.cpu().numpy() - tau)) <= 1e-4
+
+
 def test_qr_f64_bitwise_reproducible(ct):
     sc, _, _, _ = problem("multi")
     outs = []
@@ -131,7 +157,7 @@ def test_qr_f64_bitwise_reproducible(ct):
     assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
 
 
-def test_rank_deficient_column_reported(ct):
+def test_rank_deficient_column_reported(ct, panel_path):
     sc = synth.scanner(*GEOMS["ragged"])
     Ad = gpu_system(ct, sc, torch.float64)
     Ad[17].zero_()
