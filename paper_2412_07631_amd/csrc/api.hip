@@ -28,6 +28,7 @@ void panel_set_cholesky(bool on);
 void panel_set_cus(int cus);
 size_t panel_lds_bytes(int nbp, int rw);
 int panel_aux_words();
+size_t panel_scratch_words();
 hipError_t panel_set_max_lds(size_t bytes);
 hipError_t panel_max_active(int* per_cu, size_t shmem);
 void panel_set_wait_limit(int64_t ticks);
@@ -167,7 +168,7 @@ struct ct_factor {
     // workspace partition
     double* T_all;     // nblocks x nb_out x nb_out
     double* part;      // 2 x 256 x 64
-    double* gpart;     // 256 x 1024
+    double* gpart;     // the two-reduction panels' polled scratch
     uint64_t* counter;
     int64_t* info;
     int32_t* err;
@@ -230,7 +231,7 @@ static Layout layout(int64_t m, int64_t n, int prec, int64_t max_nrhs, int nbo, 
     size_t off = 0;
     L.T_all = off; off += up256((size_t)nblocks * nbo * nbo * 8);
     L.part = off; off += up256(2 * 256 * 64 * 8 + 2 * 64 * 8);
-    L.gpart = off; off += up256(256 * 1024 * 8);
+    L.gpart = off; off += up256(panel_scratch_words() * 8);
     L.words = off; off += 256;
     L.Wp = off; off += up256((size_t)L.wp_elems * 8);
     L.Wq = off; off += up256((size_t)L.wq_elems * 8);

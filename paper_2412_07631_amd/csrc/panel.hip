@@ -68,7 +68,7 @@ struct PanelArgs {
     int64_t col0;       // global index of the panel's first column
     int32_t* err;
     uint64_t wait_ticks; // time limit of one wait (100 MHz ticks)
-    double* cq;         // two-reduction path: [256][kNV] partials, then [2][kCqSlotLen] result slots
+    double* cq;         // two-reduction path scratch (kCqWords)
     uint64_t cq_par;    // parity of this launch among the two-reduction launches
 };
 
@@ -82,11 +82,15 @@ constexpr int kPanelAux = 256 + 64 + 32 + 8 + kPanelMax * (kPanelMax + 1) + kPan
 
 // Two-reduction path: a reduction carries the packed upper triangle of a
 // 32 x 32 Gram matrix (kNV values); the first also carries the panel's top
-// 32 x 32 block (published by workgroup 0, not summed).
+// 32 x 32 block (published by workgroup 0, not summed).  The scratch buffer
+// holds the partials of both reductions for both launch parities, then the
+// result slots of both parities; every word reads as kEmpty until written.
 constexpr int kNV = 32 * 33 / 2;
 constexpr int kNA = kNV + 32 * 32;
 constexpr int kCqSlotLen = kNA + kNV;
-constexpr size_t kCqSlot = (size_t)256 * kNV;
+constexpr size_t kCqPartLen = (size_t)256 * kNV;
+constexpr size_t kCqSlot = 4 * kCqPartLen;
+constexpr size_t kCqWords = kCqSlot + 2 * (size_t)kCqSlotLen;
 // LDS words of that path besides the 32-column panel and kPanelAux:
 // K1..K4 (32 x 32 each), S, 1/diag, Gram phase partials (36 blocks x 7 x 16)
 constexpr int kGramPh = 7;
@@ -372,12 +376,22 @@ __device__ bool column_steps(const PanelArgs<TS>& a, const PanelLds& L, int w, i
     return true;
 }
 
+// Rows of the panel into LDS as FP64 (columns from nbp to ncols as zeros);
+// every load of a row is issued before any is stored.
 template <typename TS>
 __device__ __forceinline__ void load_panel(const PanelArgs<TS>& a, double* pan, int ncols, int t, int rows, int64_t r0)
 {
-    for (int c = 0; c < ncols; ++c)
-        for (int r = t; r < rows; r += 256)
-            pan[c * a.rw + r] = c < a.nbp ? (double)a.A[(r0 + r) + (int64_t)c * a.lda] : 0.0;
+    for (int r = t; r < rows; r += 256) {
+        const TS* src = a.A + (r0 + r);
+        // unconditional loads (columns past nbp reread the last one), so the
+        // compiler issues all 32 before waiting
+        TS v[32];
+#pragma unroll
+        for (int c = 0; c < 32; ++c) v[c] = src[(int64_t)(c < a.nbp ? c : a.nbp - 1) * a.lda];
+#pragma unroll
+        for (int c = 0; c < 32; ++c)
+            if (c < ncols) pan[c * a.rw + r] = c < a.nbp ? (double)v[c] : 0.0;
+    }
 }
 
 // V\R back to the matrix; workgroup 0 also writes T (zero below the diagonal).
@@ -427,8 +441,8 @@ __device__ __forceinline__ void unpack_ut(int e, int& i, int& c)
 
 // This workgroup's Gram partial of the 32 panel columns (rows in LDS) as the
 // packed upper triangle, in pv[0..kNV).  Threads own 4 x 4 blocks of the
-// upper block triangle (36 blocks) over kGramPh row phases; wave 0 then sums
-// the phases.  Ends with a barrier.
+// upper block triangle (36 blocks) over kGramPh row phases; the phases are
+// then summed per entry.  Ends with a barrier.
 __device__ void gram_partial(const double* pan, int rw, int rows, double* red2, double* pv, int t)
 {
     if (t < 36 * kGramPh) {
@@ -474,147 +488,260 @@ __device__ void gram_partial(const double* pan, int rw, int rows, double* red2, 
     __syncthreads();
 }
 
-// One reduction of the two-reduction path.  pv (LDS) holds this workgroup's
-// packed partial; it goes to the partial buffer, the workgroup arrives, waits
-// for every arrival (counter >= target), sums its slice of entries
-// (e = w + P k) over all partials in a fixed order and publishes them in
-// `slot`; then every one of the `nread` slot entries is read back into LDS
-// through `dst` (packed entries go to the upper triangle of K, column-major
-// ld 32; entries from kNV on to Kt).  False: a wait gave up.
+// Wave-uniform bounded poll: loads the NW words p[i] (i < n, compile-time
+// bound NW) until none holds kEmpty in any lane of the wave; their bits go
+// to v.  False: the wait gave up (time limit, or an earlier wait did).
+template <int NW>
+__device__ __forceinline__ bool poll_words(uint64_t* const (&p)[NW], int n, uint64_t (&v)[NW], int32_t* err,
+                                           uint64_t wait_ticks)
+{
+    uint64_t t0 = 0;
+    uint32_t spins = 0;
+    for (;;) {
+        bool all = true;
+#pragma unroll
+        for (int i = 0; i < NW; ++i)
+            if (i < n) {
+                v[i] = __hip_atomic_load(p[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                all = all && v[i] != kEmpty;
+            }
+        if (__all(all)) return true;
+        if (wait_ticks == 0) {
+            set_err(err);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        if ((++spins & 15) == 0) {
+            const uint64_t now = __builtin_amdgcn_s_memrealtime();
+            if (spins == 16) {
+                t0 = now;
+            } else if (now - t0 >= wait_ticks) {
+                set_err(err);
+                return false;
+            }
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1) return false;
+        }
+    }
+}
+
+// One reduction of the two-reduction path.  Each workgroup writes its packed
+// partial (pv, LDS) to its row of `part`, one polled word per entry; wave 0
+// sums the workgroup's slice of entries (e = w + P k) over every partial in a
+// fixed order and publishes the sums in `slot`; then the nread slot entries
+// come back into LDS (packed entries to the upper triangle of K, row-major
+// ld 32; entries from kNV on to Kt).  No counter, no fence: every word is
+// its own flag.  False: a wait gave up.
 template <typename TS>
-__device__ bool cq_reduce(const PanelArgs<TS>& a, const double* pv, uint64_t target, uint64_t* slot, int nread,
+__device__ bool cq_reduce(const PanelArgs<TS>& a, const double* pv, double* part, uint64_t* slot, int nread,
                           double* K, double* Kt, double* sc, int w, int t)
 {
     const int P = a.P;
-    double* part = a.cq;
+    uint64_t* pw = (uint64_t*)part;
+    for (int e = t; e < kNV; e += 256)
+        __hip_atomic_store(pw + (size_t)w * kNV + e, __builtin_bit_cast(uint64_t, pv[e]), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
     if (t < 64) {
-        for (int e = t; e < kNV; e += 64) part[(size_t)w * kNV + e] = pv[e];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        if (t == 0) {
-            __hip_atomic_fetch_add(a.counter, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            sc[5] = wait_count(a.counter, target, a.err, a.wait_ticks) ? 0.0 : 1.0;
-        }
-    }
-    __syncthreads();
-    if (sc[5] != 0.0) return false;
-    if (t < 64) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        // lanes in groups of gsz, one slice entry per group and round; lane
+        // `mem` of a group adds the partials q = mem + gsz i
         const int ns = (kNV - 1 - w) / P + 1;
         int p2 = 1;
         while (p2 < ns) p2 <<= 1;
         const int gsz = p2 >= 64 ? 1 : 64 / p2;
         const int ng = 64 / gsz, grp = t / gsz, mem = t % gsz;
+        const int nq = mem < P ? (P - mem + gsz - 1) / gsz : 0;    // <= 24 (gsz >= P / 24 here)
         for (int k0 = 0; k0 < ns; k0 += ng) {
             const int k = k0 + grp;
-            const int e = w + P * k;
-            double s = 0.0;
-            if (k < ns) {
-#pragma unroll 8
-                for (int q = mem; q < P; q += gsz) s += part[(size_t)q * kNV + e];
+            const int e = w + P * (k < ns ? k : 0);
+            constexpr int NW = 24;
+            uint64_t* ptr[NW];
+            uint64_t bits[NW];
+#pragma unroll
+            for (int i = 0; i < NW; ++i) ptr[i] = pw + (size_t)(mem + gsz * i) * kNV + e;
+            if (!poll_words<NW>(ptr, k < ns ? nq : 0, bits, a.err, a.wait_ticks)) {
+                sc[5] = 1.0;
+                break;
             }
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < NW; ++i)
+                if (i < nq && k < ns) s += __builtin_bit_cast(double, bits[i]);
             for (int o = 1; o < gsz; o <<= 1) s += __shfl_xor(s, o);
             if (k < ns && mem == 0)
-                __hip_atomic_store(slot + e, __builtin_bit_cast(uint64_t, s), __ATOMIC_RELEASE,
+                __hip_atomic_store(slot + e, __builtin_bit_cast(uint64_t, s), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
         }
     }
-    bool ok = true;
-    for (int e = t; e < nread; e += 256) {
-        uint64_t bits = 0;
-        if (!wait_word(slot + e, bits, a.err, a.wait_ticks)) {
-            ok = false;
-            break;
+    {
+        constexpr int NW = (kNA + 255) / 256;
+        uint64_t* ptr[NW];
+        uint64_t bits[NW];
+        int n = 0;
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+            const int e = t + 256 * i;
+            ptr[i] = slot + (e < nread ? e : 0);
+            if (e < nread) n = i + 1;
         }
-        const double v = __builtin_bit_cast(double, bits);
-        if (e < kNV) {
-            int i, c;
-            unpack_ut(e, i, c);
-            K[i + 32 * c] = v;
+        if (!poll_words<NW>(ptr, n, bits, a.err, a.wait_ticks)) {
+            sc[5] = 1.0;
         } else {
-            Kt[e - kNV] = v;
+#pragma unroll
+            for (int i = 0; i < NW; ++i) {
+                const int e = t + 256 * i;
+                if (e < nread) {
+                    const double v = __builtin_bit_cast(double, bits[i]);
+                    if (e < kNV) {
+                        int r, c;
+                        unpack_ut(e, r, c);
+                        K[r * 32 + c] = v;
+                    } else {
+                        Kt[e - kNV] = v;
+                    }
+                }
+            }
         }
     }
-    if (!ok) sc[5] = 1.0;
     __syncthreads();
     return sc[5] == 0.0;
 }
 
-// Cholesky factor of the symmetric matrix in K (upper triangle, column-major
-// ld 32, n x n leading block): right-looking, the pivot row scaled only at the
-// end.  On success K's upper triangle holds R (R^T R = K) and dv[j] = 1/R_jj.
-// The pivot test reads values every thread sees alike, so the result is
-// uniform.  Diagonal pivots must exceed tol times the original diagonal.
-__device__ bool chol32(double* K, double* dv, double* diag0, int n, double tol, int t)
+// Value of v in lane `lane` (uniform lane index), for every lane.
+__device__ __forceinline__ double bcast(double v, int lane)
 {
-    if (t < 32) diag0[t] = t < n ? K[t + 32 * t] : 1.0;
-    int ei[3], ec[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const int e = t + 256 * k;
-        if (e < kNV) {
-            unpack_ut(e, ei[k], ec[k]);
-        } else {
-            ei[k] = 32;
-            ec[k] = 32;
-        }
-    }
-    __syncthreads();
-    for (int j = 0; j < n; ++j) {
-        const double d = K[j + 32 * j];
-        if (!(d > tol * diag0[j]) || !(d < 1.0e300)) return false;
-        const double id = 1.0 / d;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const int i = ei[k], c = ec[k];
-            if (i > j && c < n) K[i + 32 * c] -= K[j + 32 * i] * K[j + 32 * c] * id;
-        }
-        __syncthreads();
-    }
-    for (int e = t; e < kNV; e += 256) {
-        int i, c;
-        unpack_ut(e, i, c);
-        if (c < n) {
-            const double rd = sqrt(K[i + 32 * i]);
-            // the diagonal entry is read by the other entries of its row: the
-            // row is finished from its untouched pivot value, written last
-            if (i != c) K[i + 32 * c] = K[i + 32 * c] / rd;
-        }
-    }
-    __syncthreads();
-    if (t < 32) {
-        if (t < n) {
-            const double rd = sqrt(K[t + 32 * t]);
-            K[t + 32 * t] = rd;
-            dv[t] = 1.0 / rd;
-        } else {
-            dv[t] = 0.0;
-        }
-    }
-    __syncthreads();
-    return true;
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// x (one row of 32, registers) <- x M^-1, M upper triangular (column-major
-// ld 32, dv = 1/diag, zero beyond the leading n x n block).
+// Cholesky factor of the symmetric matrix in K (upper triangle, row-major
+// ld 32, n x n leading block, zero elsewhere), by wave 0 in registers: lane i
+// holds row i (lanes 32..63 repeat 0..31), right-looking, the pivot row
+// broadcast from its lane, no barrier inside.  On success K's upper triangle
+// holds R (R^T R = K) and dv[j] = 1/R_jj (0 past n).  Pivots must exceed tol
+// times the original diagonal; the test reads broadcast values, so the
+// outcome is the same in every lane and, through flag, every thread.
+__device__ bool chol32(double* K, double* dv, double* flag, int n, double tol, int t)
+{
+    if (t < 64) {
+        const int i = t & 31;
+        double a[32];
+#pragma unroll
+        for (int c = 0; c < 32; ++c) a[c] = c >= i ? K[i * 32 + c] : K[c * 32 + i];
+        const double g0 = K[i * 33];
+        bool ok = true;
+#pragma unroll
+        for (int j = 0; j < 32; ++j) {
+            if (j < n && ok) {
+                const double d = bcast(a[j], j);
+                if (!(d > tol * bcast(g0, j)) || !(d < 1.0e300)) {
+                    ok = false;
+                } else {
+                    const double f = i > j ? a[j] / d : 0.0;
+#pragma unroll
+                    for (int c = j + 1; c < 32; ++c) a[c] -= f * bcast(a[c], j);
+                }
+            }
+        }
+        if (t < 32) {
+            if (ok && i < n) {
+                // this row's pivot (register chosen without a dynamic index)
+                double ai = 0.0;
+#pragma unroll
+                for (int c = 0; c < 32; ++c) ai = c == i ? a[c] : ai;
+                const double rd = sqrt(ai);
+                const double ir = 1.0 / rd;
+#pragma unroll
+                for (int c = 0; c < 32; ++c)
+                    if (c > i) K[i * 32 + c] = c < n ? a[c] * ir : 0.0;
+                K[i * 33] = rd;
+                dv[i] = ir;
+            } else if (i >= n) {
+                dv[i] = 0.0;
+            }
+            if (t == 0) flag[0] = ok ? 1.0 : 0.0;
+        }
+    }
+    __syncthreads();
+    return flag[0] != 0.0;
+}
+
+// LU without pivoting of Q - S on the leading n x n block of K (column-major
+// ld 32), S_j = -sign of the eliminated diagonal entry, by wave 0 in
+// registers (lane i holds row i).  Leaves the unit lower factor's
+// multipliers below the diagonal, U on and above it (U_jj = q_jj - S_j),
+// S in Sv; diagonal entries past n are set to 1.
+__device__ void lu32(double* K, double* Sv, int n, int t)
+{
+    if (t < 64) {
+        const int i = t & 31;
+        double a[32];
+#pragma unroll
+        for (int c = 0; c < 32; ++c) a[c] = K[i + 32 * c];
+        double si = 0.0;
+#pragma unroll
+        for (int j = 0; j < 32; ++j) {
+            if (j < n) {
+                const double q = bcast(a[j], j);
+                const double sj = q >= 0.0 ? -1.0 : 1.0;
+                if (i == j) si = sj;
+                const double l = (i > j && i < n) ? a[j] / (q - sj) : 0.0;
+                if (i > j && i < n) a[j] = l;
+#pragma unroll
+                for (int c = j + 1; c < 32; ++c) a[c] -= l * bcast(a[c], j);
+            }
+        }
+        if (t < 32) {
+#pragma unroll
+            for (int c = 0; c < 32; ++c) K[i + 32 * c] = c == i ? (i < n ? a[c] - si : 1.0) : a[c];
+            Sv[i] = si;
+        }
+    }
+    __syncthreads();
+}
+
+// x (one row of 32, registers) <- x M^-1, M upper triangular (row-major
+// ld 32, 16-byte aligned; dv = 1/diag, zero beyond the leading block; UNIT:
+// unit diagonal, dv unused).  Right-looking, so a step's updates are
+// independent; each row of M comes in as 16-byte loads issued one step
+// ahead, so a step waits on LDS once, not once per product.
+template <bool UNIT>
 __device__ __forceinline__ void row_times_inv(double (&x)[32], const double* M, const double* dv)
 {
+    const double2* M2 = (const double2*)M;
+    double2 m[16];
+    double d = UNIT ? 1.0 : dv[0];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) m[k] = M2[k];
 #pragma unroll
     for (int l = 0; l < 32; ++l) {
-        x[l] *= dv[l];
+        double2 mn[16];
+        double dn = 1.0;
+        if (l + 1 < 32) {
 #pragma unroll
-        for (int c = l + 1; c < 32; ++c) x[c] -= x[l] * M[l + 32 * c];
+            for (int k = (l + 2) / 2; k < 16; ++k) mn[k] = M2[(l + 1) * 16 + k];
+            if (!UNIT) dn = dv[l + 1];
+        }
+        if (!UNIT) x[l] *= d;
+#pragma unroll
+        for (int c = l + 1; c < 32; ++c) x[c] -= x[l] * ((c & 1) ? m[c >> 1].y : m[c >> 1].x);
+        if (l + 1 < 32) {
+#pragma unroll
+            for (int k = (l + 2) / 2; k < 16; ++k) m[k] = mn[k];
+            d = dn;
+        }
     }
 }
 
-// Rows [lo, hi) of a column-major row block (ld) times M^-1, in place.
-__device__ __forceinline__ void rows_times_inv(double* X, int ld, int lo, int hi, const double* M, const double* dv,
-                                               int t, int nthreads)
+// Rows u, u + nt, ... (< n) of X (column-major, ld) times M^-1, in place.
+__device__ __forceinline__ void rows_times_inv(double* X, int ld, int n, const double* M, const double* dv, int u,
+                                               int nt)
 {
-    for (int r = lo + t; r < hi; r += nthreads) {
+    for (int r = u; r < n; r += nt) {
         double x[32];
 #pragma unroll
         for (int c = 0; c < 32; ++c) x[c] = X[c * ld + r];
-        row_times_inv(x, M, dv);
+        row_times_inv<false>(x, M, dv);
 #pragma unroll
         for (int c = 0; c < 32; ++c) X[c * ld + r] = x[c];
     }
@@ -627,10 +754,10 @@ __global__ void __launch_bounds__(256) panel_cqr_kernel(PanelArgs<TS> a)
     const int t = threadIdx.x, w = blockIdx.x;
     const int nbp = a.nbp, rw = a.rw, P = a.P;
     const PanelLds L = panel_lds(lds, rw, 32);
-    double* K1 = L.gl + kPanelMax;   // G, then R1
-    double* K2 = K1 + 1024;          // Q1^T Q1, then R2
-    double* K3 = K2 + 1024;          // top 32 x 32 block of A, of Q1, of Q, then L1 \ U
-    double* K4 = K3 + 1024;          // U R2
+    double* K1 = L.gl + kPanelMax;   // G, then R1 (row-major upper)
+    double* K2 = K1 + 1024;          // Q1^T Q1, then R2 (row-major upper)
+    double* K3 = K2 + 1024;          // top 32 x 32 block of A, of Q1, of Q, then L1 \ U (column-major)
+    double* K4 = K3 + 1024;          // this workgroup's Gram partials, then U R2 (row-major upper)
     double* Sv = K4 + 1024;          // S
     double* dv = Sv + 32;            // 1 / diagonal of the current triangular factor
     double* red2 = dv + 32;          // Gram phase partials
@@ -638,15 +765,27 @@ __global__ void __launch_bounds__(256) panel_cqr_kernel(PanelArgs<TS> a)
     double* pan = L.pan;
     const int64_t r0 = (int64_t)w * rw;
     const int rows = (int)((a.mk - r0) < (int64_t)rw ? (a.mk - r0) : (int64_t)rw);
+    const uint64_t par = a.cq_par;
+    double* partA = a.cq + (par * 2 + 0) * kCqPartLen;
+    double* partB = a.cq + (par * 2 + 1) * kCqPartLen;
+    uint64_t* slotA = (uint64_t*)(a.cq + kCqSlot) + par * kCqSlotLen;
+    uint64_t* slotB = slotA + kNA;
 
     if (t == 0) sc[5] = (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1) ? 1.0 : 0.0;
     __syncthreads();
     if (sc[5] != 0.0) return;
-    // Nothing in this launch reads the other parity's result slots: empty
-    // them for the next two-reduction launch.  The column-wise path expects
-    // the slot of parity col_base + nbp empty at its next launch.
+    // Nothing in this launch reads the other parity's words: empty this
+    // workgroup's partial rows and its share of the result slots there, for
+    // the next two-reduction launch.  The column-wise path expects the slot
+    // of parity col_base + nbp empty at its next launch.
     {
-        uint64_t* o = (uint64_t*)(a.cq + kCqSlot) + (a.cq_par ^ 1) * kCqSlotLen;
+        uint64_t* q0 = (uint64_t*)(a.cq + ((par ^ 1) * 2 + 0) * kCqPartLen) + (size_t)w * kNV;
+        uint64_t* q1 = (uint64_t*)(a.cq + ((par ^ 1) * 2 + 1) * kCqPartLen) + (size_t)w * kNV;
+        for (int e = t; e < kNV; e += 256) {
+            __hip_atomic_store(q0 + e, kEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(q1 + e, kEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        uint64_t* o = (uint64_t*)(a.cq + kCqSlot) + (par ^ 1) * kCqSlotLen;
         for (int e = w * 256 + t; e < kCqSlotLen; e += P * 256)
             __hip_atomic_store(o + e, kEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (w == 0 && t < 64) {
@@ -657,78 +796,61 @@ __global__ void __launch_bounds__(256) panel_cqr_kernel(PanelArgs<TS> a)
     load_panel(a, pan, 32, t, rows, r0);
     for (int e = t; e < 4 * 1024; e += 256) K1[e] = 0.0;
     __syncthreads();
-    uint64_t* slotA = (uint64_t*)(a.cq + kCqSlot) + a.cq_par * kCqSlotLen;
-    uint64_t* slotB = slotA + kNA;
     // the panel's top 32 x 32 block, from workgroup 0 (whose rows they are)
     if (w == 0)
         for (int e = t; e < 1024; e += 256) {
             const int r = e & 31, c = e >> 5;
             const double v = r < rows ? pan[c * rw + r] : 0.0;
-            __hip_atomic_store(slotA + kNV + e, __builtin_bit_cast(uint64_t, v), __ATOMIC_RELEASE,
+            __hip_atomic_store(slotA + kNV + e, __builtin_bit_cast(uint64_t, v), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         }
 
-    int res = 0;     // 1: done; 0: fall back after one reduction; 2: after two
+    bool done = false;
     do {
         // (A) G = A^T A and the top block
-        // (K4 is free until the LU: it carries this workgroup's partials)
         gram_partial(pan, rw, rows, red2, K4, t);
-        if (!cq_reduce(a, K4, a.base + (uint64_t)P, slotA, kNA, K1, K3, sc, w, t)) return;
-        if (!chol32(K1, dv, Sv, nbp, kCholTol1, t)) {
-            res = 0;
-            break;
-        }
+        if (!cq_reduce(a, K4, partA, slotA, kNA, K1, K3, sc, w, t)) return;
+        if (!chol32(K1, dv, sc + 6, nbp, kCholTol1, t)) break;
         // Q1 = A R1^-1 on this workgroup's rows and on the top block
-        rows_times_inv(pan, rw, 0, rows, K1, dv, t, 256);
+        // (the top block's 32 rows go to threads idle in the panel rows'
+        // last batch, when there are enough)
+        {
+            const int tail = rows & 255;
+            const int t3 = rows < 256 ? rows : (tail == 0 ? 256 : tail);
+            rows_times_inv(pan, rw, rows, K1, dv, t, 256);
+            if (t3 + 32 <= 256) {
+                if (t >= t3 && t < t3 + 32) rows_times_inv(K3, 32, 32, K1, dv, t - t3, 32);
+            } else {
+                __syncthreads();
+                if (t < 32) rows_times_inv(K3, 32, 32, K1, dv, t, 32);
+            }
+        }
         __syncthreads();
-        rows_times_inv(K3, 32, 0, 32, K1, dv, t, 256);
         // (B) Q1^T Q1
         gram_partial(pan, rw, rows, red2, K4, t);
-        if (!cq_reduce(a, K4, a.base + 2 * (uint64_t)P, slotB, kNV, K2, nullptr, sc, w, t)) return;
-        if (!chol32(K2, dv, Sv, nbp, kCholTol2, t)) {
-            res = 2;
-            break;
-        }
+        if (!cq_reduce(a, K4, partB, slotB, kNV, K2, nullptr, sc, w, t)) return;
+        if (!chol32(K2, dv, sc + 6, nbp, kCholTol2, t)) break;
         // top block of Q = Q1 R2^-1
-        rows_times_inv(K3, 32, 0, 32, K2, dv, t, 256);
+        if (t < 32) rows_times_inv(K3, 32, 32, K2, dv, t, 32);
         __syncthreads();
-        // LU of Q_top - S (leading nbp x nbp), right-looking, the pivot column
-        // scaled at the end; S_j = -sign of the eliminated diagonal entry
-        for (int j = 0; j < nbp; ++j) {
-            const double q = K3[j + 32 * j];
-            const double sj = q >= 0.0 ? -1.0 : 1.0;
-            const double ip = 1.0 / (q - sj);
-            if (t == 0) Sv[j] = sj;
-            for (int e = t; e < 1024; e += 256) {
-                const int i = e & 31, c = e >> 5;
-                if (i > j && c > j && i < nbp && c < nbp) K3[e] -= K3[i + 32 * j] * K3[j + 32 * c] * ip;
-            }
-            __syncthreads();
-        }
-        // U_jj = q_jj - S_j; L_ij = K_ij / U_jj (i > j)
-        for (int e = t; e < 1024; e += 256) {
-            const int i = e & 31, c = e >> 5;
-            if (i > c && i < nbp) K3[e] = K3[e] / (K3[c + 32 * c] - Sv[c]);
-        }
-        __syncthreads();
-        if (t < 32) K3[t + 32 * t] = t < nbp ? K3[t + 32 * t] - Sv[t] : 1.0;
-        __syncthreads();
-        // K4 = U R2 (upper triangular), dv = its inverse diagonal
+        // LU of Q_top - S (leading nbp x nbp)
+        lu32(K3, Sv, nbp, t);
+        // K4 = U R2 (upper triangular, row-major), dv = its inverse diagonal
         for (int e = t; e < kNV; e += 256) {
             int i, c;
             unpack_ut(e, i, c);
             double s = 0.0;
             if (c < nbp)
-                for (int l = i; l <= c; ++l) s += K3[i + 32 * l] * K2[l + 32 * c];
-            K4[i + 32 * c] = s;
+                for (int l = i; l <= c; ++l) s += K3[i + 32 * l] * K2[l * 32 + c];
+            K4[i * 32 + c] = s;
         }
         __syncthreads();
-        if (t < 32) dv[t] = t < nbp ? 1.0 / K4[t + 32 * t] : 0.0;
+        if (t < 32) dv[t] = t < nbp ? 1.0 / K4[t * 33] : 0.0;
         __syncthreads();
         // V = Q1 (U R2)^-1 on rows nbp.. of the panel
         {
-            const int lo = r0 >= nbp ? 0 : (int)(nbp - r0);
-            rows_times_inv(pan, rw, lo < rows ? lo : rows, rows, K4, dv, t, 256);
+            const int lo = r0 >= nbp ? 0 : (int)(nbp - r0 < rows ? nbp - r0 : rows);
+            rows_times_inv(pan + lo, rw, rows - lo, K4, dv, t, 256);
         }
         __syncthreads();
         if (w == 0) {
@@ -740,40 +862,40 @@ __global__ void __launch_bounds__(256) panel_cqr_kernel(PanelArgs<TS> a)
                     v = K3[i + 32 * c];
                 } else {
                     double s = 0.0;
-                    for (int l = i; l <= c; ++l) s += K2[i + 32 * l] * K1[l + 32 * c];
+                    for (int l = i; l <= c; ++l) s += K2[i * 32 + l] * K1[l * 32 + c];
                     v = Sv[i] * s;
                 }
                 pan[c * rw + i] = v;
             }
-            // T = -U S L1^-T, row i by thread i:
-            //   T[i][c] = -U[i][c] S_c - sum_{l=i}^{c-1} T[i][l] L1[c][l]
+            // T = -U S L1^-T: row i of T solves T_i L1^T = -(U S)_i, and
+            // L1^T read row-major is K3 (column-major L1) itself
             if (t < nbp) {
                 const int i = t;
-                for (int c = 0; c < 32; ++c) L.Tl[c * 33 + i] = 0.0;
-                for (int c = i; c < nbp; ++c) {
-                    double s = -K3[i + 32 * c] * Sv[c];
-                    for (int l = i; l < c; ++l) s -= L.Tl[l * 33 + i] * K3[c + 32 * l];
-                    L.Tl[c * 33 + i] = s;
-                }
-                a.tau[i] = L.Tl[i * 33 + i];
+                double x[32];
+#pragma unroll
+                for (int c = 0; c < 32; ++c) x[c] = (c >= i && c < nbp) ? -K3[i + 32 * c] * Sv[c] : 0.0;
+                row_times_inv<true>(x, K3, nullptr);
+#pragma unroll
+                for (int c = 0; c < 32; ++c) L.Tl[c * 33 + i] = x[c];
+                a.tau[i] = x[i];
             }
         }
         __syncthreads();
-        res = 1;
+        done = true;
     } while (false);
 
-    if (res == 1) {
+    if (done) {
         store_panel(a, L, w, t, rows, r0);
-        // arrivals the column-wise path would have made: the counter advances
-        // by the same amount whichever path a launch takes
+        // the arrivals the column-wise path would have made: the counter
+        // advances by P nbp whichever path a launch takes
         if (t == 0) __hip_atomic_fetch_add(a.counter, (uint64_t)nbp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return;
     }
-    // fall back on the column-wise path from the original panel
-    if (res == 0 && t == 0) __hip_atomic_fetch_add(a.counter, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // Cholesky breakdown (every workgroup alike): the column-wise path from
+    // the original panel
     load_panel(a, pan, nbp, t, rows, r0);
     __syncthreads();
-    if (!column_steps(a, L, w, t, rows, r0, a.base + 2 * (uint64_t)P)) return;
+    if (!column_steps(a, L, w, t, rows, r0, a.base)) return;
     store_panel(a, L, w, t, rows, r0);
 }
 
@@ -784,6 +906,7 @@ void panel_set_wait_limit(int64_t ticks) { g_wait_ticks = ticks < 0 ? kWaitTicks
 // LDS: the panel plus the reduction scratch and the T factor.
 size_t panel_lds_bytes(int nbp, int rw) { return ((size_t)nbp * rw + kPanelAux) * sizeof(double); }
 int panel_aux_words() { return kPanelAux; }
+size_t panel_scratch_words() { return kCqWords; }
 
 // Two-reduction path: 32 panel columns, the column-wise scratch and its own.
 static size_t cqr_lds_bytes(int rw) { return ((size_t)32 * rw + kPanelAux + kCqAux) * sizeof(double); }
@@ -792,6 +915,20 @@ static bool g_cqr = true;
 static int g_cus = 256;
 void panel_set_cholesky(bool on) { g_cqr = on; }
 void panel_set_cus(int cus) { g_cus = cus < 1 ? 1 : (cus > 256 ? 256 : cus); }
+
+// The slice sums of the two-reduction path hold at most 24 partials per lane
+// (the same arithmetic as the kernel's lane grouping).
+static bool cq_lanes_ok(int P)
+{
+    for (int w = 0; w < P; ++w) {
+        const int ns = (kNV - 1 - w) / P + 1;
+        int p2 = 1;
+        while (p2 < ns) p2 <<= 1;
+        const int gsz = p2 >= 64 ? 1 : 64 / p2;
+        if ((P + gsz - 1) / gsz > 24) return false;
+    }
+    return true;
+}
 
 template <typename TS>
 hipError_t launch_panel(TS* A, int64_t lda, int64_t mk, int nbp, int rw, double* tau, double* T, int64_t ldt,
@@ -812,12 +949,15 @@ hipError_t launch_panel(TS* A, int64_t lda, int64_t mk, int nbp, int rw, double*
     int64_t rq = (mk + g_cus - 1) / g_cus;
     if (rq < 33) rq = 33;
     if ((rq & 1) == 0) ++rq;
-    const bool cq = g_cqr && nbp <= 32 && cqr_lds_bytes((int)rq) <= g_lds_max;
+    // (at most 448 rows: the row-pair solves then need at most 224 threads
+    // for the panel rows plus 16 for the top block)
+    const bool cq = g_cqr && nbp <= 32 && rq <= 448 && cqr_lds_bytes((int)rq) <= g_lds_max &&
+                    cq_lanes_ok((int)((mk + rq - 1) / rq));
     if (cq) {
         a.rw = (int)rq;
         a.P = (int)((mk + rq - 1) / rq);
         hipLaunchKernelGGL(panel_cqr_kernel<TS>, dim3(a.P), dim3(256), cqr_lds_bytes(a.rw), s, a);
-        *base += (uint64_t)a.P * (uint64_t)(2 + nbp);
+        *base += (uint64_t)a.P * (uint64_t)nbp;
         *cq_count += 1;
     } else {
         a.rw = rw;
@@ -859,18 +999,19 @@ template hipError_t launch_panel<float>(float*, int64_t, int64_t, int, int, doub
                                         double*, uint64_t*, uint64_t*, uint64_t*, uint64_t*, int64_t*, int64_t,
                                         int32_t*, hipStream_t);
 
-// Empty every result slot (before the first panel of a factorization): the
-// column-wise path's two, and both parities of the two-reduction path's.
+// Empty every polled word (before the first panel of a factorization): the
+// column-wise path's two result slots, and all of the two-reduction path's
+// scratch.
 __global__ void __launch_bounds__(256) panel_reset_kernel(double* part, double* gpart)
 {
-    const int e = blockIdx.x * 256 + threadIdx.x;
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (e < 128) ((uint64_t*)(part + kPartRes))[e] = kEmpty;
-    if (e < 2 * kCqSlotLen) ((uint64_t*)(gpart + kCqSlot))[e] = kEmpty;
+    for (size_t i = e; i < kCqWords; i += (size_t)gridDim.x * 256) ((uint64_t*)gpart)[i] = kEmpty;
 }
 
 hipError_t panel_reset(double* part, double* gpart, hipStream_t s)
 {
-    hipLaunchKernelGGL(panel_reset_kernel, dim3((2 * kCqSlotLen + 255) / 256), dim3(256), 0, s, part, gpart);
+    hipLaunchKernelGGL(panel_reset_kernel, dim3(256), dim3(256), 0, s, part, gpart);
     return hipGetLastError();
 }
 
