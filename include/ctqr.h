@@ -141,6 +141,13 @@ int ct_debug_wait_limit(int64_t ticks);
  * column.  For tests: enable != 0 (default) allows the two-reduction form for
  * later factorizations, 0 forces the column-wise form.  Always returns 0. */
 int ct_debug_panel_cholesky(int enable);
+/* The factorization groups reflectors in outer blocks of nb_out columns (its
+ * trailing update is one compact-WY block product, Sec. 2.1); nb_out is 1024
+ * from 16384 columns up, else 256.  For tests: force nb_out (a multiple of 32 up to 2048) for
+ * later workspace queries and factorizations, or restore the default with 0.
+ * A factor must be created and used under the same setting.  Returns -1
+ * (argument 1 invalid) for other values. */
+int ct_debug_block_width(int nb_out);
 
 /* B <- Q^T B (Eq. (solve), first half; ormqr).  B: m x nrhs, same storage
  * type as the factor's A, nrhs <= max_nrhs.  Rows n..m-1 of the result hold

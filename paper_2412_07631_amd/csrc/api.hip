@@ -52,7 +52,9 @@ hipError_t launch_prep_v(const T* V, int64_t ldv, int64_t mk, int nb, T* Vm, int
 template <typename T>
 hipError_t launch_nt(const T* X, int64_t ldx, const T* Y, int64_t ldy, T* out, int64_t ldo, int64_t P, int Q,
                      int64_t K, bool sub, int64_t ocap, int* nz_out, hipStream_t s, const NtPlan* plan = nullptr,
-                     const int32_t* desc = nullptr, int desc_y = 0, int desc_out = 0, int maskx = 0);
+                     const int32_t* desc = nullptr, int desc_y = 0, int desc_out = 0, int maskx = 0,
+                     int tout = 0);
+extern NtPlan g_nt_default;
 template <int MODE>
 hipError_t launch_nt_lp(const void* X, int64_t ldx, const void* Y, int64_t ldy, float* out, int64_t ldo, int64_t P,
                         int Q, int64_t K, bool sub, int64_t ocap, int* nz_out, hipStream_t s,
@@ -212,7 +214,8 @@ struct ct_factor {
 // factor uses kNbStream when its column tiles allow, else 128.
 constexpr int kNbStream = 256;
 
-static int nb_out_for(int64_t n) { return n >= 16384 ? 1024 : 256; }
+static int g_nb_force = 0;   // test hook: forced outer block width (0: by size)
+static int nb_out_for(int64_t n) { return g_nb_force ? g_nb_force : (n >= 16384 ? 1024 : 256); }
 
 struct Layout {
     size_t T_all, part, gpart, words, Wp, Wq, G, Vm, Vt, Ws, Ri, Ri64, Rt, VtAll, Tf, S3, total;
@@ -359,8 +362,17 @@ static int larfb_nt(ct_factor* f, int64_t mk, int nbv, const double* T, int64_t 
     {
         ProfScope ps(timed ? 0 : -1, fl, ((double)mk * nbv + (double)mk * nc) * sizeof(TS) + (double)nbv * nc * sizeof(TS), s);
         if constexpr (MODE == M_F64 || MODE == M_F32) {
-            CT_HIP(launch_nt<TS>((const TS*)o.vm, o.ldvm, C, ldc, (TS*)f->Wp, nbv, nbv, nc, mk, false,
-                                 f->wp_elems * 8 / (int64_t)sizeof(TS), &nz, s, plan, desc, 1, 0, o.mask));
+            if (nbv <= 32 && !desc && !o.mask) {
+                // narrow block: W^T = C^T V with C on the 128-row side of the
+                // tile and the block on its 32-column side, stored transposed
+                // (so W lands column-major as below)
+                const NtPlan p32{32, plan ? plan->split_target : g_nt_default.split_target};
+                CT_HIP(launch_nt<TS>(C, ldc, (const TS*)o.vm, o.ldvm, (TS*)f->Wp, nbv, nc, nbv, mk, false,
+                                     f->wp_elems * 8 / (int64_t)sizeof(TS), &nz, s, &p32, nullptr, 0, 0, 0, 1));
+            } else {
+                CT_HIP(launch_nt<TS>((const TS*)o.vm, o.ldvm, C, ldc, (TS*)f->Wp, nbv, nbv, nc, mk, false,
+                                     f->wp_elems * 8 / (int64_t)sizeof(TS), &nz, s, plan, desc, 1, 0, o.mask));
+            }
         } else {
             if (o.mask) return fail(-1, "%s", "internal: masked operand on the low-precision kernel");
             if (MODE == M_BF16X3 && f->S3) {
@@ -460,14 +472,16 @@ static int trailing_mode(int prec)
 // Compact-WY factor of an outer block whose panels have left their own
 // factors on T's diagonal: the Gram matrix of the prepared (masked) block in
 // f->Vm, in the storage precision, then pairwise joins of the panel factors.
+// join0: width of the diagonal blocks of T that are already complete (the
+// panels', or those of sub-blocks factored earlier).
 template <typename TS>
-static int block_t(ct_factor* f, int64_t mk, int bo, double* T, int64_t ldt, hipStream_t s)
+static int block_t(ct_factor* f, int64_t mk, int bo, double* T, int64_t ldt, hipStream_t s, int join0)
 {
     int nz = 1;
     CT_HIP(launch_nt<TS>((const TS*)f->Vm, f->ldvm, (const TS*)f->Vm, f->ldvm, (TS*)f->Wp, bo, bo, bo, mk, false,
                          f->wp_elems * 8 / (int64_t)sizeof(TS), &nz, s));
     CT_HIP((launch_sum_slices<TS, double>((const TS*)f->Wp, (int64_t)bo * bo, nz, (int64_t)bo * bo, f->G, s)));
-    CT_HIP(launch_t_join(f->G, bo, T, ldt, (double*)f->Wq, f->nb_in, bo, s));
+    CT_HIP(launch_t_join(f->G, bo, T, ldt, (double*)f->Wq, join0, bo, s));
     return 0;
 }
 
@@ -522,7 +536,7 @@ static int factor_cols(ct_factor* f, TS* C, int64_t c0, int64_t c1, hipStream_t 
             if (r) return r;
         }
         if (bo > nbi) {
-            int r = block_t<TS>(f, mk, bo, Tb, nbo, s);
+            int r = block_t<TS>(f, mk, bo, Tb, nbo, s, nbi);
             if (r) return r;
         }
         if constexpr (sizeof(TS) == 4)
@@ -1335,6 +1349,13 @@ int ct_debug_wait_limit(int64_t ticks)
 int ct_debug_panel_cholesky(int enable)
 {
     panel_set_cholesky(enable != 0);
+    return 0;
+}
+
+int ct_debug_block_width(int nb_out)
+{
+    CT_ARG(nb_out == 0 || (nb_out >= 32 && nb_out <= 2048 && nb_out % 32 == 0), 1, "nb_out (0, or a multiple of 32 up to 2048)");
+    g_nb_force = nb_out;
     return 0;
 }
 

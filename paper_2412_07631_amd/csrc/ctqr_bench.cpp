@@ -8,7 +8,7 @@
 //
 //   ctqr_bench [--n-pix 256] [--views 120] [--bins 640]
 //              [--prec f64|f32|bf16|f16|bf16x3] [--nrhs 16] [--copy-mib 0]
-//              [--stream-gib G --tile-cols 1024]
+//              [--stream-gib G --tile-cols 1024] [--nb-out 0]
 // With --stream-gib the matrix is factored from pinned host memory
 // (ct_qr_factor_streamed) with a device buffer of G GiB, and the time
 // includes every host<->device transfer.
@@ -61,6 +61,7 @@ int main(int argc, char** argv)
     long copy_mib = 0;
     double stream_gib = 0.0;
     long tile_cols = 1024;
+    int nb_out = 0;
     const char* pname = "bf16x3";
     for (int i = 1; i + 1 < argc; i += 2) {
         if (!strcmp(argv[i], "--n-pix")) n_pix = atoi(argv[i + 1]);
@@ -71,12 +72,14 @@ int main(int argc, char** argv)
         else if (!strcmp(argv[i], "--copy-mib")) copy_mib = atol(argv[i + 1]);
         else if (!strcmp(argv[i], "--stream-gib")) stream_gib = atof(argv[i + 1]);
         else if (!strcmp(argv[i], "--tile-cols")) tile_cols = atol(argv[i + 1]);
+        else if (!strcmp(argv[i], "--nb-out")) nb_out = atoi(argv[i + 1]);
         else {
             fprintf(stderr, "unknown option %s\n", argv[i]);
             return 2;
         }
     }
     const int prec = prec_of(pname);
+    CT_OK(ct_debug_block_width(nb_out));
     ct_geometry g;
     memset(&g, 0, sizeof g);
     g.n_pix = n_pix;

@@ -50,6 +50,9 @@ struct NtArgs {
     // and Xlo / Ylo the low parts, same leading dimension
     const void* Xlo;
     const void* Ylo;
+    // non-subtracting form only: store element (p, q) at q + p ldo (the
+    // transpose; a slice then spans P ldo elements)
+    int tout;
 };
 
 __device__ __forceinline__ void apply_desc(const NtArgs& a, int& Q, const char*& Y, size_t ysz, char*& out, size_t osz)
@@ -262,7 +265,13 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_kernel(NtArgs a)
         for (int j = 0; j < NJ; ++j) {
             const int q = q0 + wq + 16 * j + c;
             if (q >= Qe) continue;
-            if constexpr (!F64) {
+            if (!SUB && a.tout) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t p = F64 ? p0 + wp + 16 * i + g + 4 * r : p0 + wp + 16 * i + 4 * g + r;
+                    if (p < a.P) O[q + p * a.ldo] = (T)acc[i][j][r];
+                }
+            } else if constexpr (!F64) {
                 const int64_t pb = p0 + wp + 16 * i + 4 * g;
                 T* d = O + pb + (int64_t)q * a.ldo;
                 accv_t v = acc[i][j];
@@ -339,7 +348,7 @@ NtPlan g_nt_default = {128, 1024};
 template <typename T>
 hipError_t launch_nt(const T* X, int64_t ldx, const T* Y, int64_t ldy, T* out, int64_t ldo, int64_t P, int Q,
                      int64_t K, bool sub, int64_t ocap, int* nz_out, hipStream_t s, const NtPlan* plan,
-                     const int32_t* desc, int desc_y, int desc_out, int maskx)
+                     const int32_t* desc, int desc_y, int desc_out, int maskx, int tout)
 {
     constexpr int BK = LdsTraits<T>::BK;
     const NtPlan pl = plan ? *plan : g_nt_default;
@@ -349,9 +358,10 @@ hipError_t launch_nt(const T* X, int64_t ldx, const T* Y, int64_t ldy, T* out, i
     a.P = P; a.Q = Q; a.K = K; a.sub = sub ? 1 : 0;
     a.desc = desc; a.desc_y = desc_y; a.desc_out = desc_out;
     a.maskx = maskx;
+    a.tout = sub ? 0 : tout;
     a.tiles_p = (int)((P + kBP - 1) / kBP);
     a.tiles_q = (Q + bq - 1) / bq;
-    a.ostride = ldo * (int64_t)Q;
+    a.ostride = a.tout ? ldo * P : ldo * (int64_t)Q;
     const int tiles = a.tiles_p * a.tiles_q;
     int nz = 1;
     if (!sub) {
@@ -385,10 +395,10 @@ template hipError_t launch_prep_v<double>(const double*, int64_t, int64_t, int, 
                                           hipStream_t);
 template hipError_t launch_nt<float>(const float*, int64_t, const float*, int64_t, float*, int64_t, int64_t, int,
                                      int64_t, bool, int64_t, int*, hipStream_t, const NtPlan*, const int32_t*, int,
-                                     int, int);
+                                     int, int, int);
 template hipError_t launch_nt<double>(const double*, int64_t, const double*, int64_t, double*, int64_t, int64_t, int,
                                       int64_t, bool, int64_t, int*, hipStream_t, const NtPlan*, const int32_t*, int,
-                                      int, int);
+                                      int, int, int);
 
 
 // ---------------------------------------------------------------------------
@@ -669,7 +679,7 @@ hipError_t launch_nt_lp(const void* X, int64_t ldx, const void* Y, int64_t ldy, 
     NtArgs a;
     a.X = X; a.ldx = ldx; a.Y = Y; a.ldy = ldy; a.out = out; a.ldo = ldo;
     a.P = P; a.Q = Q; a.K = K; a.sub = sub ? 1 : 0;
-    a.desc = nullptr; a.desc_y = 0; a.desc_out = 0; a.maskx = 0;
+    a.desc = nullptr; a.desc_y = 0; a.desc_out = 0; a.maskx = 0; a.tout = 0;
     a.Xlo = Xlo; a.Ylo = Ylo;
     a.tiles_p = (int)((P + kBP - 1) / kBP);
     a.tiles_q = (Q + kBQ - 1) / kBQ;

@@ -59,6 +59,7 @@ _sig("ct_stream_info", [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.
 _sig("ct_stream_inject_failure", [_i64])
 _sig("ct_debug_wait_limit", [_i64])
 _sig("ct_debug_panel_cholesky", [ctypes.c_int])
+_sig("ct_debug_block_width", [ctypes.c_int])
 _sig("ct_apply_qt", [_vp, _vp, _i64, _i64, _vp])
 _sig("ct_trsm_solve", [_vp, _vp, _i64, _i64, _vp])
 _sig("ct_solve_backward", [_vp, _vp, _i64, _i64, _vp, _i64, _vp])
@@ -244,6 +245,12 @@ def debug_panel_cholesky(enable: bool):
     """Allow (default) or forbid the two-reduction panel form for later
     factorizations; forbidden, every panel takes one reduction per column."""
     _check(_lib.ct_debug_panel_cholesky(1 if enable else 0))
+
+
+def debug_block_width(nb_out: int):
+    """Force the outer block width of later factorizations (0 restores the
+    size-based default)."""
+    _check(_lib.ct_debug_block_width(nb_out))
 
 
 def apply_qt(f: Factor, B: torch.Tensor, nrhs: int = None, stream=None):

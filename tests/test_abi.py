@@ -41,6 +41,17 @@ def test_argument_errors_without_gpu():
     assert lib.ct_qr_workspace(1920, 1024, 0, 4, ctypes.byref(b)) == 0 and b.value > 1920 * 8
     lib.ct_factor_destroy.argtypes = [ctypes.c_void_p]
     assert lib.ct_factor_destroy(None) == 0
+    # the block-width hook takes 0 or a multiple of 32 up to 2048, and the
+    # workspace follows the width (T of every outer block grows with it)
+    for bad in (16, 100, 4096, -32):
+        assert lib.ct_debug_block_width(bad) == -1
+    ws = {}
+    for nb in (256, 1024):
+        assert lib.ct_debug_block_width(nb) == 0
+        assert lib.ct_qr_workspace(4096, 2048, 1, 4, ctypes.byref(b)) == 0
+        ws[nb] = b.value
+    assert lib.ct_debug_block_width(0) == 0
+    assert ws[1024] > ws[256]
 
 
 def test_binding_marshals_without_gpu():

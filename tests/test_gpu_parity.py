@@ -146,6 +146,34 @@ def test_qr_f32_matches_oracle(ct, name, panel_path):
     assert np.max(np.abs(f.tau.cpu().numpy() - tau)) <= 1e-4
 
 
+@pytest.mark.parametrize("nb", [64, 96, 512, 768, 1024])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_qr_block_widths_match_oracle(ct, nb, prec):
+    """Outer reflector blocks of other widths (ragged last blocks, more join
+    levels of the compact-WY factor): R and a solve against the oracle."""
+    sc, A, VR, tau = problem("multi")
+    ct.debug_block_width(nb)
+    try:
+        dt = torch.float64 if prec == "f64" else torch.float32
+        Ad = gpu_system(ct, sc, dt)
+        f = ct.qr_factor(Ad, sc.m, sc.n, ct.PREC_NAMES[prec], max_nrhs=8)
+        assert ct.status(f) == 0
+        VRg = from_dev(Ad, sc.m)
+        n = sc.n
+        R, Rg = np.triu(VR[:n]), np.triu(VRg[:n])
+        tol = 1e-12 if prec == "f64" else 1e-4
+        assert np.max(np.abs(Rg - R)) / np.max(np.abs(R)) <= tol
+        _, P, B = sinograms(sc, A, 1, 3, 1e5)
+        Bd = to_dev(B, dt)
+        ct.apply_qt(f, Bd)
+        ct.trsm_solve(f, Bd)
+        err = max_col_rel(from_dev(Bd, n), O.solve(VR, tau, B))
+        print("nb %d %s: solve max rel err %.3g" % (nb, prec, err))
+        assert err <= (1e-10 if prec == "f64" else 1e-4)
+    finally:
+        ct.debug_block_width(0)
+
+
 def test_qr_f64_bitwise_reproducible(ct):
     sc, _, _, _ = problem("multi")
     outs = []
