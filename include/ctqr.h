@@ -211,6 +211,26 @@ int ct_status(const ct_factor* f, int64_t* info, void* stream);
 
 int ct_factor_destroy(ct_factor* f);
 
+/* Checkpoint of a factor held in device memory (the factor is reused for
+ * every later batch of sinograms, Sec. 2): ct_factor_save waits for the
+ * stream, then writes V\R (m x n, without the lda padding), tau, the
+ * compact-WY factor T of every outer block and a 64-bit checksum to the host
+ * file `path` (overwritten).  A factor whose factorization failed (ct_status
+ * < 0) is not saved.  Returns -2 when the file cannot be written.
+ * ct_factor_file_info reads a file's header: m, n, prec and the work bytes a
+ * load with max_nrhs needs (any pointer may be NULL except path); -1 for a
+ * file that is not a factor file.
+ * ct_factor_load reads the file into the caller's A (lda >= m, a multiple of
+ * 16), tau (n) and work (work_bytes from ct_factor_file_info), rebuilds the
+ * solve-side copies, waits for the stream and returns a handle equivalent to
+ * the saved one: the solves give bitwise the same results.  -1 for a
+ * missing, truncated or corrupted file (checksum) or one saved on a device
+ * with another panel width. */
+int ct_factor_save(const ct_factor* f, const char* path, void* stream);
+int ct_factor_file_info(const char* path, int64_t max_nrhs, int64_t* m, int64_t* n, int* prec, size_t* work_bytes);
+int ct_factor_load(const char* path, void* A, int64_t lda, double* tau, void* work, size_t work_bytes,
+                   int64_t max_nrhs, ct_factor** f, void* stream);
+
 /* Graph-captured solve over a device batch descriptor, for many batches of
  * uneven size sharing one factor.  desc is a device int32 array: desc[0] = k,
  * the index of the batch the next launch solves; desc[2+2k] and desc[3+2k]

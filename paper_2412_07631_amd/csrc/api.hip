@@ -5,6 +5,7 @@
 #include "ct_internal.h"
 #include "../../include/ctqr.h"
 
+#include <stdarg.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -104,9 +105,12 @@ using namespace ctqr;
 // ------------------------------------------------------------ error handling
 static thread_local char g_err[512] = "";
 
-static int fail(int code, const char* fmt, const char* what)
+__attribute__((format(printf, 2, 3))) static int fail(int code, const char* fmt, ...)
 {
-    snprintf(g_err, sizeof g_err, fmt, what);
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
     return code;
 }
 
@@ -1146,7 +1150,268 @@ static int init_factor(ct_factor* f, void* A, int64_t m, int64_t n, int64_t lda,
 // nres resident tiles, then the staging slots (none when every tile is resident).
 static size_t tile_bytes(int64_t lda, int64_t wt, size_t es) { return up256((size_t)lda * wt * es); }
 
+// Solve-side copies of R of an in-memory factor (diagonal-block inverses and
+// row-major block columns), from V\R in place.
+static int r_copies(ct_factor* f, char* work, const Layout& L, hipStream_t s)
+{
+    if (g_dev.trsm_block != 128) return 0;
+    const int64_t n = f->n, lda = f->lda;
+    const size_t es = f->f64 ? 8 : 4;
+    f->RiR = work + L.Ri;
+    f->RiC = work + L.Ri + (size_t)((n + 255) / 256) * 256 * 256 * es;
+    f->Rt = work + L.Rt;
+    double* Ri64 = (double*)(work + L.Ri64);
+    double* M = (double*)f->Wq;      // free once the factorization is done
+    hipError_t e;
+    if (f->f64) {
+        e = launch_rinv<double>((const double*)f->A, lda, n, (double*)f->RiR, (double*)f->RiC, Ri64, M, s);
+        if (e == hipSuccess) e = launch_rt<double>((const double*)f->A, lda, n, (double*)f->Rt, s);
+    } else {
+        e = launch_rinv<float>((const float*)f->A, lda, n, (float*)f->RiR, (float*)f->RiC, Ri64, M, s);
+        if (e == hipSuccess) e = launch_rt<float>((const float*)f->A, lda, n, (float*)f->Rt, s);
+    }
+    if (e != hipSuccess) return fail(-1000 - (int)e, "R copies: %s", hipGetErrorString(e));
+    return 0;
+}
+
+// The per-block solve copies a factorization writes as it goes: the
+// row-major reflector blocks and T in the storage type.
+template <typename TS>
+static int block_copies(ct_factor* f, hipStream_t s)
+{
+    const int nbo = f->nb_out;
+    for (int64_t b = 0; b < f->nblocks; ++b) {
+        const int64_t k0 = b * nbo;
+        const int bo = (int)std::min<int64_t>(nbo, f->n - k0);
+        TS* Ab = (TS*)f->A + k0 * f->lda + k0;
+        int r = prep_block<TS>(f, Ab, f->lda, f->m - k0, bo, s, (TS*)f->VtAll + vt_offset(f, b));
+        if (r) return r;
+        if constexpr (sizeof(TS) == 4) {
+            const double* Tb = f->T_all + (size_t)b * nbo * nbo;
+            CT_HIP((launch_convert<double, float>(Tb, nbo, (float*)f->Tf + (size_t)b * nbo * nbo, nbo, bo, bo, s)));
+        }
+    }
+    return 0;
+}
+
+// ------------------------------------------------------------- checkpoints
+// File: a fixed header, the m x n matrix V\R column by column (m elements
+// each, storage type), tau (n FP64), T of every outer block (nb_out^2 FP64
+// each), then a 64-bit checksum of everything before it.
+struct FactorFileHeader {
+    char magic[8];          // "CTQRFAC1"
+    int64_t m, n, prec, nb_out, nb_in, info, es, reserved;
+};
+static const char kFactorMagic[8] = {'C', 'T', 'Q', 'R', 'F', 'A', 'C', '1'};
+constexpr size_t kChunk = (size_t)64 << 20;
+
+// order-dependent 64-bit checksum of a byte stream (multiply-xorshift of
+// 8-byte words, a tail padded with zeros)
+struct Checksum {
+    uint64_t h = 0x9E3779B97F4A7C15ull;
+    void add(const void* p, size_t bytes)
+    {
+        const unsigned char* c = (const unsigned char*)p;
+        size_t i = 0;
+        for (; i + 8 <= bytes; i += 8) {
+            uint64_t w;
+            memcpy(&w, c + i, 8);
+            mix(w);
+        }
+        if (i < bytes) {
+            uint64_t w = 0;
+            memcpy(&w, c + i, bytes - i);
+            mix(w);
+        }
+    }
+    void mix(uint64_t w)
+    {
+        h ^= w;
+        h *= 0xBF58476D1CE4E5B9ull;
+        h ^= h >> 31;
+    }
+};
+
+static int read_header(FILE* fp, FactorFileHeader& hd)
+{
+    if (fread(&hd, sizeof hd, 1, fp) != 1) return fail(-1, "%s", "invalid argument path (not a factor file)");
+    if (memcmp(hd.magic, kFactorMagic, 8) != 0) return fail(-1, "%s", "invalid argument path (not a factor file)");
+    if (hd.m <= 0 || hd.n <= 0 || hd.n > hd.m || hd.prec < CT_PREC_F64 || hd.prec > CT_PREC_BF16X3 ||
+        hd.nb_out < 32 || hd.nb_out > 2048 || hd.es != (hd.prec == CT_PREC_F64 ? 8 : 4))
+        return fail(-1, "%s", "invalid argument path (inconsistent factor file header)");
+    return 0;
+}
+
 extern "C" {
+
+int ct_factor_save(const ct_factor* f, const char* path, void* stream)
+{
+    CT_ARG(f != nullptr && f->st == nullptr, 1, "f (a factor held in device memory)");
+    CT_ARG(path != nullptr, 2, "path");
+    hipStream_t s = (hipStream_t)stream;
+    int64_t info = 0;
+    int r = ct_status(f, &info, stream);
+    if (r) return r;
+    FILE* fp = fopen(path, "wb");
+    if (!fp) return fail(-2, "invalid argument path (cannot open %s for writing)", path);
+    FactorFileHeader hd;
+    memset(&hd, 0, sizeof hd);
+    memcpy(hd.magic, kFactorMagic, 8);
+    hd.m = f->m; hd.n = f->n; hd.prec = f->prec; hd.nb_out = f->nb_out; hd.nb_in = f->nb_in; hd.info = info;
+    hd.es = f->f64 ? 8 : 4;
+    Checksum ck;
+    std::vector<char> buf;
+    bool ok = fwrite(&hd, sizeof hd, 1, fp) == 1;
+    ck.add(&hd, sizeof hd);
+    hipError_t e = hipSuccess;
+    auto put = [&](const void* dev, size_t bytes) {
+        for (size_t o = 0; ok && o < bytes; o += kChunk) {
+            const size_t nb = std::min(kChunk, bytes - o);
+            buf.resize(nb);
+            e = hipMemcpy(buf.data(), (const char*)dev + o, nb, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) { ok = false; break; }
+            ck.add(buf.data(), nb);
+            ok = fwrite(buf.data(), 1, nb, fp) == nb;
+        }
+    };
+    // the matrix, column groups of at most kChunk bytes (m elements a column)
+    const size_t colb = (size_t)f->m * hd.es;
+    const int64_t cols = std::max<int64_t>(1, (int64_t)(kChunk / colb));
+    for (int64_t j0 = 0; ok && j0 < f->n; j0 += cols) {
+        const int64_t nc = std::min<int64_t>(cols, f->n - j0);
+        buf.resize(nc * colb);
+        e = hipMemcpy2D(buf.data(), colb, (const char*)f->A + (size_t)j0 * f->lda * hd.es, (size_t)f->lda * hd.es,
+                        colb, nc, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) { ok = false; break; }
+        ck.add(buf.data(), nc * colb);
+        ok = fwrite(buf.data(), 1, nc * colb, fp) == nc * colb;
+    }
+    if (ok) put(f->tau, (size_t)f->n * 8);
+    if (ok) put(f->T_all, (size_t)f->nblocks * f->nb_out * f->nb_out * 8);
+    if (ok) ok = fwrite(&ck.h, 8, 1, fp) == 1;
+    const bool closed = fclose(fp) == 0;
+    (void)s;
+    if (e != hipSuccess) return fail(-1000 - (int)e, "save: %s", hipGetErrorString(e));
+    if (!ok || !closed) return fail(-2, "invalid argument path (write to %s failed)", path);
+    return 0;
+}
+
+int ct_factor_file_info(const char* path, int64_t max_nrhs, int64_t* m, int64_t* n, int* prec, size_t* work_bytes)
+{
+    CT_ARG(path != nullptr, 1, "path");
+    CT_ARG(max_nrhs >= 0, 2, "max_nrhs");
+    FILE* fp = fopen(path, "rb");
+    if (!fp) return fail(-1, "invalid argument path (cannot open %s)", path);
+    FactorFileHeader hd;
+    const int r = read_header(fp, hd);
+    fclose(fp);
+    if (r) return r;
+    if (m) *m = hd.m;
+    if (n) *n = hd.n;
+    if (prec) *prec = (int)hd.prec;
+    if (work_bytes) *work_bytes = layout(hd.m, hd.n, (int)hd.prec, max_nrhs, (int)hd.nb_out).total;
+    return 0;
+}
+
+int ct_factor_load(const char* path, void* A, int64_t lda, double* tau, void* work, size_t work_bytes,
+                   int64_t max_nrhs, ct_factor** f_out, void* stream)
+{
+    CT_ARG(path != nullptr, 1, "path");
+    CT_ARG(A != nullptr && aligned(A), 2, "A");
+    CT_ARG(tau != nullptr, 4, "tau");
+    CT_ARG(work != nullptr && aligned(work), 5, "work");
+    CT_ARG(max_nrhs >= 0, 7, "max_nrhs");
+    CT_ARG(f_out != nullptr, 8, "f");
+    FILE* fp = fopen(path, "rb");
+    if (!fp) return fail(-1, "invalid argument path (cannot open %s)", path);
+    FactorFileHeader hd;
+    int r = read_header(fp, hd);
+    if (r) {
+        fclose(fp);
+        return r;
+    }
+    const Layout L = layout(hd.m, hd.n, (int)hd.prec, max_nrhs, (int)hd.nb_out);
+    if (!(lda >= hd.m && lda % 16 == 0)) {
+        fclose(fp);
+        return fail(-3, "%s", "invalid argument lda (need >= m of the file, a multiple of 16)");
+    }
+    if (work_bytes < L.total) {
+        fclose(fp);
+        return fail(-6, "%s", "invalid argument work_bytes (see ct_factor_file_info)");
+    }
+    r = device_setup();
+    if (r) {
+        fclose(fp);
+        return r;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    ct_factor* f = new (std::nothrow) ct_factor();
+    if (!f) {
+        fclose(fp);
+        return fail(-1001, "%s", "out of host memory");
+    }
+    r = init_factor(f, A, hd.m, hd.n, lda, (int)hd.prec, tau, (char*)work, L, max_nrhs, (int)hd.nb_out);
+    if (!r && f->nb_in != hd.nb_in)
+        r = fail(-1, "invalid argument path (saved with panels of %lld columns, this device uses %d)",
+                 (long long)hd.nb_in, f->nb_in);
+    Checksum ck;
+    ck.add(&hd, sizeof hd);
+    std::vector<char> buf;
+    hipError_t e = hipSuccess;
+    bool ok = r == 0;
+    auto get = [&](void* dev, size_t bytes) {
+        for (size_t o = 0; ok && o < bytes; o += kChunk) {
+            const size_t nb = std::min(kChunk, bytes - o);
+            buf.resize(nb);
+            ok = fread(buf.data(), 1, nb, fp) == nb;
+            if (!ok) break;
+            ck.add(buf.data(), nb);
+            e = hipMemcpy((char*)dev + o, buf.data(), nb, hipMemcpyHostToDevice);
+            if (e != hipSuccess) ok = false;
+        }
+    };
+    const size_t colb = (size_t)hd.m * hd.es;
+    const int64_t cols = std::max<int64_t>(1, (int64_t)(kChunk / colb));
+    for (int64_t j0 = 0; ok && j0 < hd.n; j0 += cols) {
+        const int64_t nc = std::min<int64_t>(cols, hd.n - j0);
+        buf.resize(nc * colb);
+        ok = fread(buf.data(), 1, nc * colb, fp) == nc * colb;
+        if (!ok) break;
+        ck.add(buf.data(), nc * colb);
+        e = hipMemcpy2D((char*)A + (size_t)j0 * lda * hd.es, (size_t)lda * hd.es, buf.data(), colb, colb, nc,
+                        hipMemcpyHostToDevice);
+        if (e != hipSuccess) ok = false;
+    }
+    if (ok) get(tau, (size_t)hd.n * 8);
+    if (ok) get(f->T_all, (size_t)f->nblocks * f->nb_out * f->nb_out * 8);
+    uint64_t want = 0;
+    if (ok) ok = fread(&want, 8, 1, fp) == 1 && want == ck.h;
+    fclose(fp);
+    if (r || e != hipSuccess || !ok) {
+        delete f;
+        if (r) return r;
+        if (e != hipSuccess) return fail(-1000 - (int)e, "load: %s", hipGetErrorString(e));
+        return fail(-1, "%s", "invalid argument path (truncated or corrupted factor file)");
+    }
+    // status words: info from the file, no failed wait
+    int64_t words[2] = {hd.info, 0};
+    CT_HIP(hipMemsetAsync((char*)work + L.words, 0, 256, s));
+    CT_HIP(hipMemcpyAsync(f->info, words, 8, hipMemcpyHostToDevice, s));
+    CT_HIP(panel_reset(f->part, f->gpart, s));
+    f->VtAll = (char*)work + L.VtAll;
+    int rc = f->f64 ? block_copies<double>(f, s) : block_copies<float>(f, s);
+    if (!rc) rc = r_copies(f, (char*)work, L, s);
+    if (!rc) {
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) rc = fail(-1000 - (int)e, "load: %s", hipGetErrorString(e));
+    }
+    if (rc) {
+        delete f;
+        return rc;
+    }
+    *f_out = f;
+    return 0;
+}
 
 int ct_qr_factor(void* A, int64_t m, int64_t n, int64_t lda, int prec, double* tau, void* work, size_t work_bytes,
                  int64_t max_nrhs, ct_factor** f_out, void* stream)
@@ -1177,27 +1442,7 @@ int ct_qr_factor(void* A, int64_t m, int64_t n, int64_t lda, int prec, double* t
     CT_HIP(panel_reset(f->part, f->gpart, s));
     f->VtAll = (char*)work + L.VtAll;
     int rc = f->f64 ? factor_impl<double>(f, s) : factor_impl<float>(f, s);
-    if (!rc && g_dev.trsm_block == 128) {
-        // solve-side copies of R: diagonal-block inverses and row-major block columns
-        const size_t es = f->f64 ? 8 : 4;
-        f->RiR = (char*)work + L.Ri;
-        f->RiC = (char*)work + L.Ri + (size_t)((n + 255) / 256) * 256 * 256 * es;
-        f->Rt = (char*)work + L.Rt;
-        double* Ri64 = (double*)((char*)work + L.Ri64);
-        double* M = (double*)f->Wq;      // free once the factorization is done
-        hipError_t e;
-        if (f->f64) {
-            e = launch_rinv<double>((const double*)A, lda, n, (double*)f->RiR, (double*)f->RiC, Ri64, M, s);
-            if (e == hipSuccess) e = launch_rt<double>((const double*)A, lda, n, (double*)f->Rt, s);
-        } else {
-            e = launch_rinv<float>((const float*)A, lda, n, (float*)f->RiR, (float*)f->RiC, Ri64, M, s);
-            if (e == hipSuccess) e = launch_rt<float>((const float*)A, lda, n, (float*)f->Rt, s);
-        }
-        if (e != hipSuccess) {
-            snprintf(g_err, sizeof g_err, "R copies: %s", hipGetErrorString(e));
-            rc = -1000 - (int)e;
-        }
-    }
+    if (!rc) rc = r_copies(f, (char*)work, L, s);
     if (rc) {
         delete f;
         return rc;

@@ -60,6 +60,10 @@ _sig("ct_stream_inject_failure", [_i64])
 _sig("ct_debug_wait_limit", [_i64])
 _sig("ct_debug_panel_cholesky", [ctypes.c_int])
 _sig("ct_debug_block_width", [ctypes.c_int])
+_sig("ct_factor_save", [_vp, ctypes.c_char_p, _vp])
+_sig("ct_factor_file_info", [ctypes.c_char_p, _i64, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                             ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_sz)])
+_sig("ct_factor_load", [ctypes.c_char_p, _vp, _i64, _vp, _vp, _sz, _i64, ctypes.POINTER(_vp), _vp])
 _sig("ct_apply_qt", [_vp, _vp, _i64, _i64, _vp])
 _sig("ct_trsm_solve", [_vp, _vp, _i64, _i64, _vp])
 _sig("ct_solve_backward", [_vp, _vp, _i64, _i64, _vp, _i64, _vp])
@@ -183,6 +187,32 @@ def qr_factor(A: torch.Tensor, m: int, n: int, prec: int, max_nrhs: int = 512, s
     h = _vp()
     _check(_lib.ct_qr_factor(_ptr(A), m, n, A.shape[1], prec, _ptr(tau), _ptr(work), work.numel(), max_nrhs,
                              ctypes.byref(h), _stream(stream)))
+    return Factor(h, A, tau, work, m, n, prec, max_nrhs)
+
+
+def factor_save(f: Factor, path: str, stream=None):
+    """Write the factor (V\\R, tau, T, checksum) to a host file."""
+    _check(_lib.ct_factor_save(f.handle, os.fsencode(path), _stream(stream)))
+
+
+def factor_file_info(path: str, max_nrhs: int = 512):
+    """(m, n, prec, work bytes for max_nrhs) of a saved factor."""
+    m, n, p, b = _i64(0), _i64(0), ctypes.c_int(0), _sz(0)
+    _check(_lib.ct_factor_file_info(os.fsencode(path), max_nrhs, ctypes.byref(m), ctypes.byref(n), ctypes.byref(p),
+                                    ctypes.byref(b)))
+    return m.value, n.value, p.value, b.value
+
+
+def factor_load(path: str, max_nrhs: int = 512, device="cuda", stream=None) -> Factor:
+    """Load a saved factor into new device buffers."""
+    m, n, prec, wb = factor_file_info(path, max_nrhs)
+    dt = torch.float64 if prec == PREC_F64 else torch.float32
+    A = torch.empty((n, ld16(m)), dtype=dt, device=device)
+    tau = torch.zeros(n, dtype=torch.float64, device=device)
+    work = torch.empty(wb, dtype=torch.uint8, device=device)
+    h = _vp()
+    _check(_lib.ct_factor_load(os.fsencode(path), _ptr(A), A.shape[1], _ptr(tau), _ptr(work), work.numel(),
+                               max_nrhs, ctypes.byref(h), _stream(stream)))
     return Factor(h, A, tau, work, m, n, prec, max_nrhs)
 
 

@@ -118,3 +118,41 @@ def test_streamed_factor_argument_errors_without_gpu():
     with __import__("pytest").raises(TypeError):
         import torch
         ctqr.qr_factor_streamed(torch.zeros((4, 16)), 16, 4, ctqr.PREC_F32, tile_cols=128)
+
+
+def test_factor_file_header_checks_without_gpu(tmp_path):
+    """ct_factor_file_info / ct_factor_load refuse what is not a factor file,
+    and report the workspace of a well-formed header before any device work."""
+    import struct
+    lib = ctypes.CDLL(LIB)
+    lib.ct_factor_file_info.argtypes = [ctypes.c_char_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_size_t)]
+    lib.ct_factor_load.argtypes = [ctypes.c_char_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64,
+                                   ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]
+    lib.ct_qr_workspace.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int64,
+                                    ctypes.POINTER(ctypes.c_size_t)]
+    m, n, p, b = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int(0), ctypes.c_size_t(0)
+    info = lambda path: lib.ct_factor_file_info(path.encode(), 8, ctypes.byref(m), ctypes.byref(n),
+                                                ctypes.byref(p), ctypes.byref(b))
+    assert info(str(tmp_path / "missing.bin")) == -1
+    junk = tmp_path / "junk.bin"
+    junk.write_bytes(b"not a factor file at all, just text" * 4)
+    assert info(str(junk)) == -1
+    # header: magic, m, n, prec, nb_out, nb_in, info, element size, reserved
+    hdr = tmp_path / "hdr.bin"
+    hdr.write_bytes(b"CTQRFAC1" + struct.pack("<8q", 3360, 2304, 1, 256, 32, 0, 4, 0))
+    assert info(str(hdr)) == 0 and (m.value, n.value, p.value) == (3360, 2304, 1)
+    w = ctypes.c_size_t(0)
+    assert lib.ct_qr_workspace(3360, 2304, 1, 8, ctypes.byref(w)) == 0
+    assert b.value == w.value          # the same blocking as a fresh factorization
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"CTQRFAC1" + struct.pack("<8q", 3360, 2304, 1, 256, 32, 0, 8, 0))   # wrong element size
+    assert info(str(bad)) == -1
+    h = ctypes.c_void_p(0)
+    # too small a workspace and a bad lda are refused before any device work
+    assert lib.ct_factor_load(str(hdr).encode(), ctypes.c_void_p(256), 3360, ctypes.c_void_p(256),
+                              ctypes.c_void_p(256), 1024, 8, ctypes.byref(h), None) == -6
+    assert lib.ct_factor_load(str(hdr).encode(), ctypes.c_void_p(256), 3000, ctypes.c_void_p(256),
+                              ctypes.c_void_p(256), 1 << 40, 8, ctypes.byref(h), None) == -3
