@@ -54,7 +54,7 @@ template <typename T>
 hipError_t launch_nt(const T* X, int64_t ldx, const T* Y, int64_t ldy, T* out, int64_t ldo, int64_t P, int Q,
                      int64_t K, bool sub, int64_t ocap, int* nz_out, hipStream_t s, const NtPlan* plan = nullptr,
                      const int32_t* desc = nullptr, int desc_y = 0, int desc_out = 0, int maskx = 0,
-                     int tout = 0);
+                     int tout = 0, int upper = 0);
 extern NtPlan g_nt_default;
 template <int MODE>
 hipError_t launch_nt_lp(const void* X, int64_t ldx, const void* Y, int64_t ldy, float* out, int64_t ldo, int64_t P,
@@ -370,7 +370,9 @@ static int larfb_nt(ct_factor* f, int64_t mk, int nbv, const double* T, int64_t 
                 // narrow block: W^T = C^T V with C on the 128-row side of the
                 // tile and the block on its 32-column side, stored transposed
                 // (so W lands column-major as below)
-                const NtPlan p32{32, plan ? plan->split_target : g_nt_default.split_target};
+                // (half the default split target: a narrow product has at
+                // most 8 tiles, and its split-K sums cost a pass of their own)
+                const NtPlan p32{32, plan ? plan->split_target : g_nt_default.split_target / 2};
                 CT_HIP(launch_nt<TS>(C, ldc, (const TS*)o.vm, o.ldvm, (TS*)f->Wp, nbv, nc, nbv, mk, false,
                                      f->wp_elems * 8 / (int64_t)sizeof(TS), &nz, s, &p32, nullptr, 0, 0, 0, 1));
             } else {
@@ -398,7 +400,13 @@ static int larfb_nt(ct_factor* f, int64_t mk, int nbv, const double* T, int64_t 
                                           desc, nbv)));
         Wsum = (const TS*)f->Ws;
     }
-    if (OPT == 0 && o.tts) {
+    if (OPT == 0 && o.tts && MODE == M_BF16X3 && !desc) {
+        // W' = T^T W in the update's own arithmetic (BF16x3, operands split
+        // when staged): row p of T^T is column p of T
+        int nz1;
+        CT_HIP(launch_nt_lp<M_BF16X3>(o.tts, ldt, Wsum, nbv, (float*)f->Wq, ldw, nbv, nc, nbv, false, 0, &nz1, s,
+                                      nullptr, nullptr));
+    } else if (OPT == 0 && o.tts) {
         // W' = T^T W on the NT kernel: row p of T^T is column p of T
         int nz1;
         CT_HIP(launch_nt<TS>((const TS*)o.tts, ldt, Wsum, nbv, (TS*)f->Wq, ldw, nbv, nc, nbv, false, 0, &nz1, s, plan,
@@ -482,8 +490,9 @@ template <typename TS>
 static int block_t(ct_factor* f, int64_t mk, int bo, double* T, int64_t ldt, hipStream_t s, int join0)
 {
     int nz = 1;
+    // the joins read V1^T V2 blocks above the diagonal only
     CT_HIP(launch_nt<TS>((const TS*)f->Vm, f->ldvm, (const TS*)f->Vm, f->ldvm, (TS*)f->Wp, bo, bo, bo, mk, false,
-                         f->wp_elems * 8 / (int64_t)sizeof(TS), &nz, s));
+                         f->wp_elems * 8 / (int64_t)sizeof(TS), &nz, s, nullptr, nullptr, 0, 0, 0, 0, 1));
     CT_HIP((launch_sum_slices<TS, double>((const TS*)f->Wp, (int64_t)bo * bo, nz, (int64_t)bo * bo, f->G, s)));
     CT_HIP(launch_t_join(f->G, bo, T, ldt, (double*)f->Wq, join0, bo, s));
     return 0;

@@ -53,6 +53,9 @@ struct NtArgs {
     // non-subtracting form only: store element (p, q) at q + p ldo (the
     // transpose; a slice then spans P ldo elements)
     int tout;
+    // only tiles that reach the diagonal or above it (a Gram matrix whose
+    // lower triangle nobody reads); the others stay unwritten
+    int upper;
 };
 
 __device__ __forceinline__ void apply_desc(const NtArgs& a, int& Q, const char*& Y, size_t ysz, char*& out, size_t osz)
@@ -106,6 +109,7 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_kernel(NtArgs a)
 
     int tp, tq;
     if (!tile_of(blockIdx.x, a.tiles_p, a.tiles_q, tp, tq)) return;
+    if (a.upper && (int64_t)tp * kBP >= (int64_t)(tq + 1) * BQ) return;
     const int64_t p0 = (int64_t)tp * kBP;
     const int q0 = tq * BQ;
     const int64_t kbeg = (int64_t)blockIdx.y * a.kslice;
@@ -348,7 +352,7 @@ NtPlan g_nt_default = {128, 1024};
 template <typename T>
 hipError_t launch_nt(const T* X, int64_t ldx, const T* Y, int64_t ldy, T* out, int64_t ldo, int64_t P, int Q,
                      int64_t K, bool sub, int64_t ocap, int* nz_out, hipStream_t s, const NtPlan* plan,
-                     const int32_t* desc, int desc_y, int desc_out, int maskx, int tout)
+                     const int32_t* desc, int desc_y, int desc_out, int maskx, int tout, int upper)
 {
     constexpr int BK = LdsTraits<T>::BK;
     const NtPlan pl = plan ? *plan : g_nt_default;
@@ -359,6 +363,7 @@ hipError_t launch_nt(const T* X, int64_t ldx, const T* Y, int64_t ldy, T* out, i
     a.desc = desc; a.desc_y = desc_y; a.desc_out = desc_out;
     a.maskx = maskx;
     a.tout = sub ? 0 : tout;
+    a.upper = sub ? 0 : upper;
     a.tiles_p = (int)((P + kBP - 1) / kBP);
     a.tiles_q = (Q + bq - 1) / bq;
     a.ostride = a.tout ? ldo * P : ldo * (int64_t)Q;
@@ -395,10 +400,10 @@ template hipError_t launch_prep_v<double>(const double*, int64_t, int64_t, int, 
                                           hipStream_t);
 template hipError_t launch_nt<float>(const float*, int64_t, const float*, int64_t, float*, int64_t, int64_t, int,
                                      int64_t, bool, int64_t, int*, hipStream_t, const NtPlan*, const int32_t*, int,
-                                     int, int, int);
+                                     int, int, int, int);
 template hipError_t launch_nt<double>(const double*, int64_t, const double*, int64_t, double*, int64_t, int64_t, int,
                                       int64_t, bool, int64_t, int*, hipStream_t, const NtPlan*, const int32_t*, int,
-                                      int, int, int);
+                                      int, int, int, int);
 
 
 // ---------------------------------------------------------------------------
@@ -679,7 +684,7 @@ hipError_t launch_nt_lp(const void* X, int64_t ldx, const void* Y, int64_t ldy, 
     NtArgs a;
     a.X = X; a.ldx = ldx; a.Y = Y; a.ldy = ldy; a.out = out; a.ldo = ldo;
     a.P = P; a.Q = Q; a.K = K; a.sub = sub ? 1 : 0;
-    a.desc = nullptr; a.desc_y = 0; a.desc_out = 0; a.maskx = 0; a.tout = 0;
+    a.desc = nullptr; a.desc_y = 0; a.desc_out = 0; a.maskx = 0; a.tout = 0; a.upper = 0;
     a.Xlo = Xlo; a.Ylo = Ylo;
     a.tiles_p = (int)((P + kBP - 1) / kBP);
     a.tiles_q = (Q + kBQ - 1) / kBQ;
