@@ -26,6 +26,7 @@
 
 typedef struct {
     int32_t n_pix, n_angles, n_det;
+    int32_t projector;              /* 0: Siddon, 1: Joseph */
     double grid_width, sid, sdd, det_length, angle0;
 } orc_geometry;
 
@@ -135,6 +136,74 @@ int64_t orc_siddon_ray(double x0, double y0, double x1, double y1, int32_t N,
     return cnt;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Joseph (1982) interpolating projector, the one the paper builds A with    */
+/* (Sec. 3.1).  The ray is sampled once per pixel-centre line across its     */
+/* dominant axis (x when |dx| >= |dy|): at the centre line of pixel column   */
+/* ix it sits at height y; the image there is the linear interpolation of    */
+/* the two pixels of that column whose centres bracket y (zero outside the   */
+/* grid), and each sample stands for the ray length over one pixel width     */
+/* along the dominant axis, h |p1 - p0| / |dx|.  So pixel (ix, iy) gets      */
+/* (1 - f) h |p1-p0|/|dx| and pixel (ix, iy+1) gets f h |p1-p0|/|dx|, with   */
+/* iy = floor(fy), f = fy - iy, fy = (y - lo)/h - 1/2.  Samples outside the  */
+/* segment [p0, p1] are skipped; zero weights are not emitted.               */
+/* Returns the number of (pixel, weight) pairs written (at most 2N).         */
+/* ------------------------------------------------------------------------ */
+int64_t orc_joseph_ray(double x0, double y0, double x1, double y1, int32_t N, double W,
+                       int32_t* pix, double* wt)
+{
+    const double dx = x1 - x0, dy = y1 - y0;
+    const double lo = -0.5 * W, h = W / (double)N;
+    const int xmajor = fabs(dx) >= fabs(dy);
+    const double dmaj = xmajor ? dx : dy, dmin = xmajor ? dy : dx;
+    const double pmaj = xmajor ? x0 : y0, pmin = xmajor ? y0 : x0;
+    if (dmaj == 0.0) return 0;
+    const double scale = h * sqrt(dx * dx + dy * dy) / fabs(dmaj);
+    int64_t cnt = 0;
+    for (int32_t k = 0; k < N; ++k) {
+        const double c = lo + ((double)k + 0.5) * h;       /* centre line of pixel column / row k */
+        const double a = (c - pmaj) / dmaj;
+        if (a < 0.0 || a > 1.0) continue;
+        const double q = pmin + a * dmin;                  /* position across the dominant axis */
+        const double fq = (q - lo) / h - 0.5;
+        const double fl = floor(fq);
+        const double f = fq - fl;
+        const int64_t i0 = (int64_t)fl;
+        for (int e = 0; e < 2; ++e) {
+            const int64_t i = i0 + e;
+            const double w = (e == 0 ? 1.0 - f : f) * scale;
+            if (i < 0 || i >= N || !(w > 0.0)) continue;
+            pix[cnt] = xmajor ? (int32_t)(i * N + k) : (int32_t)((int64_t)k * N + i);
+            wt[cnt] = w;
+            ++cnt;
+        }
+    }
+    return cnt;
+}
+
+/* One ray of the geometry's projector: (pixel, weight) pairs, count returned */
+static int64_t orc_ray(const orc_geometry* g, const double* p, int32_t* pix, double* len, double* work)
+{
+    if (g->projector == 1) return orc_joseph_ray(p[0], p[1], p[2], p[3], g->n_pix, g->grid_width, pix, len);
+    return orc_siddon_ray(p[0], p[1], p[2], p[3], g->n_pix, g->grid_width, pix, len, work);
+}
+
+/* Joseph rows for an explicit list of rays (r x 4), dense row-major r x N^2. */
+void orc_joseph_rows(const double* rays, int64_t r, int32_t N, double W, double* rows)
+{
+    const int64_t n = (int64_t)N * N;
+    int32_t* pix = (int32_t*)malloc(sizeof(int32_t) * (size_t)(2 * N + 8));
+    double* wt = (double*)malloc(sizeof(double) * (size_t)(2 * N + 8));
+    for (int64_t i = 0; i < r; ++i) {
+        double* row = rows + i * n;
+        memset(row, 0, sizeof(double) * (size_t)n);
+        const double* p = rays + 4 * i;
+        const int64_t c = orc_joseph_ray(p[0], p[1], p[2], p[3], N, W, pix, wt);
+        for (int64_t t = 0; t < c; ++t) row[pix[t]] += wt[t];
+    }
+    free(pix); free(wt);
+}
+
 /* Rows of A for an explicit list of rays (r x 4), dense row-major r x N^2. */
 void orc_siddon_rows(const double* rays, int64_t r, int32_t N, double W, double* rows)
 {
@@ -172,7 +241,7 @@ void orc_system_dense(const orc_geometry* g, double* A, int64_t lda)
 #pragma omp for schedule(static)
         for (int64_t i = 0; i < m; ++i) {
             const double* p = rays + 4 * i;
-            const int64_t c = orc_siddon_ray(p[0], p[1], p[2], p[3], N, g->grid_width, pix, len, work);
+            const int64_t c = orc_ray(g, p, pix, len, work);
             for (int64_t t = 0; t < c; ++t) A[i + (int64_t)pix[t] * lda] += len[t];
         }
         free(work); free(pix); free(len);
@@ -195,7 +264,7 @@ int64_t orc_system_csr(const orc_geometry* g, int64_t* row_ptr, int32_t* col, do
     row_ptr[0] = 0;
     for (int64_t i = 0; i < m; ++i) {
         const double* p = rays + 4 * i;
-        int64_t c = orc_siddon_ray(p[0], p[1], p[2], p[3], N, g->grid_width, pix, len, work);
+        int64_t c = orc_ray(g, p, pix, len, work);
         /* insertion sort by column so that each row lists ascending pixels */
         for (int64_t a = 1; a < c; ++a) {
             int32_t kp = pix[a]; double kl = len[a]; int64_t b = a - 1;

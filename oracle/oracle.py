@@ -9,7 +9,9 @@ arithmetic).
 Functions and the passages they follow:
   rays / system_dense / system_csr / siddon_rows -- the weights matrix A of
       Eq. (system): a_ij = length of ray i inside pixel j (Siddon's exact
-      intersection lengths; the fan-beam scan of Table 1).
+      intersection lengths; the fan-beam scan of Table 1); with a scanner's
+      projector = 1, system_dense / system_csr use joseph_ray / joseph_rows,
+      Joseph's interpolating projector (the one Sec. 3.1 builds A with).
   householder_qr -- Eq. (qr), unblocked Householder with the LAPACK sign rule.
   apply_qt / back_substitute / solve -- Eq. (solve): C = Q^T B, X = R^{-1} C.
   apply_q / forward_substitute_rt / adjoint -- the transpose of the solve map,
@@ -43,7 +45,7 @@ _i32p = ctypes.POINTER(ctypes.c_int32)
 
 
 class _Geom(ctypes.Structure):
-    _fields_ = [("n_pix", _i32), ("n_angles", _i32), ("n_det", _i32),
+    _fields_ = [("n_pix", _i32), ("n_angles", _i32), ("n_det", _i32), ("projector", _i32),
                 ("grid_width", ctypes.c_double), ("sid", ctypes.c_double),
                 ("sdd", ctypes.c_double), ("det_length", ctypes.c_double),
                 ("angle0", ctypes.c_double)]
@@ -69,6 +71,9 @@ def _load():
             lib.orc_siddon_ray.argtypes = [ctypes.c_double] * 4 + [_i32, ctypes.c_double, _i32p, _dp, _dp]
             lib.orc_siddon_ray.restype = _i64
             lib.orc_siddon_rows.argtypes = [_dp, _i64, _i32, ctypes.c_double, _dp]
+            lib.orc_joseph_ray.argtypes = [ctypes.c_double] * 4 + [_i32, ctypes.c_double, _i32p, _dp]
+            lib.orc_joseph_ray.restype = _i64
+            lib.orc_joseph_rows.argtypes = [_dp, _i64, _i32, ctypes.c_double, _dp]
             lib.orc_system_dense.argtypes = [ctypes.POINTER(_Geom), _dp, _i64]
             lib.orc_system_csr.argtypes = [ctypes.POINTER(_Geom), _i64p, _i32p, _dp, _i64]
             lib.orc_system_csr.restype = _i64
@@ -89,8 +94,8 @@ def _ptr(a: np.ndarray, t=_dp):
 
 
 def _geom(s) -> _Geom:
-    return _Geom(int(s.n_pix), int(s.n_angles), int(s.n_det), float(s.grid_width),
-                 float(s.sid), float(s.sdd), float(s.det_length), float(s.angle0))
+    return _Geom(int(s.n_pix), int(s.n_angles), int(s.n_det), int(getattr(s, "projector", 0)),
+                 float(s.grid_width), float(s.sid), float(s.sdd), float(s.det_length), float(s.angle0))
 
 
 def _f64_colmajor(a) -> np.ndarray:
@@ -126,6 +131,26 @@ def siddon_rows(ray_list, n_pix: int, grid_width: float = 1.0) -> np.ndarray:
     r = np.ascontiguousarray(np.asarray(ray_list, dtype=np.float64).reshape(-1, 4))
     out = np.empty((r.shape[0], n_pix * n_pix), dtype=np.float64)
     lib.orc_siddon_rows(_ptr(r), r.shape[0], int(n_pix), float(grid_width), _ptr(out))
+    return out
+
+
+def joseph_ray(x0, y0, x1, y1, n_pix: int, grid_width: float = 1.0):
+    """(pixel indices, weights) of one ray under Joseph's projector."""
+    lib = _load()
+    cap = 2 * n_pix + 8
+    pix = np.empty(cap, dtype=np.int32)
+    wt = np.empty(cap, dtype=np.float64)
+    c = lib.orc_joseph_ray(float(x0), float(y0), float(x1), float(y1), int(n_pix), float(grid_width),
+                           _ptr(pix, _i32p), _ptr(wt))
+    return pix[:c].copy(), wt[:c].copy()
+
+
+def joseph_rows(ray_list, n_pix: int, grid_width: float = 1.0) -> np.ndarray:
+    """Dense rows (r x N^2) of Joseph's A for explicit rays (r x 4 end points)."""
+    lib = _load()
+    r = np.ascontiguousarray(np.asarray(ray_list, dtype=np.float64).reshape(-1, 4))
+    out = np.empty((r.shape[0], n_pix * n_pix), dtype=np.float64)
+    lib.orc_joseph_rows(_ptr(r), r.shape[0], int(n_pix), float(grid_width), _ptr(out))
     return out
 
 

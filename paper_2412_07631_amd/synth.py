@@ -42,6 +42,7 @@ class Scanner:
     sdd: float
     det_length: float
     angle0: float = 0.0
+    projector: int = 0          # 0: Siddon's exact lengths, 1: Joseph's interpolation
 
     @property
     def m(self) -> int:
@@ -56,7 +57,7 @@ class Scanner:
 
 
 def scanner(n_pix: int, n_angles: int, n_det: int, grid_width: float = 1.0,
-            angle0: float = 0.0) -> Scanner:
+            angle0: float = 0.0, projector: int = 0) -> Scanner:
     """The scanner reading used for every workload.
 
     Source-to-isocentre distance 2W; source-to-detector twice that (the 75 cm /
@@ -71,7 +72,7 @@ def scanner(n_pix: int, n_angles: int, n_det: int, grid_width: float = 1.0,
     sdd = 2.0 * sid
     half_fan = math.asin(W / (2.0 * sid))
     det_length = 2.0 * sdd * math.tan(half_fan)
-    return Scanner(n_pix, n_angles, n_det, W, sid, sdd, det_length, float(angle0))
+    return Scanner(n_pix, n_angles, n_det, W, sid, sdd, det_length, float(angle0), int(projector))
 
 
 # Workloads: image side, views, bins, slices, incident photons per bin.
