@@ -140,6 +140,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the uneven-batch graph solve and the adjoint leg on the same factor")
     ap.add_argument("--batched-total", type=int, default=4096, help="sinograms in the uneven-batch leg")
+    ap.add_argument("--projector", default="siddon", choices=["siddon", "joseph"],
+                    help="system matrix: Siddon's exact lengths or Joseph's interpolation")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -152,6 +154,9 @@ def main():
 
     w = synth.WORKLOADS[args.workload]
     sc = synth.workload_scanner(args.workload)
+    if args.projector == "joseph":
+        import dataclasses
+        sc = dataclasses.replace(sc, projector=1)
     m, n = sc.m, sc.n
     nrhs = args.nrhs or w["slices"]
     prec = ctqr.PREC_NAMES[args.prec]
@@ -333,7 +338,7 @@ def main():
         "config": {"workload": "%s: %dx%d image, %d views x %d bins (m=%d, n=%d), %d noisy slices, I0=%g"
                                % (args.workload, sc.n_pix, sc.n_pix, sc.n_angles, sc.n_det, m, n, nrhs, w["I0"]),
                    "global_batch": nrhs, "precision": args.prec, "refine_steps": args.refine,
-                   "refine_method": args.method},
+                   "refine_method": args.method, "projector": args.projector},
         "qr_ms": qr_ms / args.steps,
         "qr_tflops_frac_of_peak": qr_tflops / peak,
         "slices_per_s": slices_per_s,

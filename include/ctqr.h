@@ -43,11 +43,20 @@ extern "C" {
  * j = iy * n_pix + ix.  View k is at angle angle0 + 2 pi k / n_angles; the
  * flat detector of length det_length is centred on the line through the
  * isocentre at distance sdd from the source; ray i = k * n_det + d runs from
- * the source to the centre of bin d. */
+ * the source to the centre of bin d.
+ * projector: CT_PROJ_SIDDON (0) -- a_ij is the exact length of ray i inside
+ * pixel j (Siddon 1985); CT_PROJ_JOSEPH (1) -- Joseph's interpolating
+ * projector (Joseph 1982), which the paper builds A with (Sec. 3.1): the ray
+ * is sampled once per pixel-centre line across its dominant axis, the image
+ * there is linearly interpolated between the two pixels whose centres
+ * bracket the ray (zero outside the grid), and each sample weighs one pixel
+ * width along the dominant axis, h |p1 - p0| / |d_dominant|. */
 typedef struct ct_geometry {
-    int32_t n_pix, n_angles, n_det, reserved;
+    int32_t n_pix, n_angles, n_det, projector;
     double grid_width, sid, sdd, det_length, angle0;
 } ct_geometry;
+
+enum { CT_PROJ_SIDDON = 0, CT_PROJ_JOSEPH = 1 };
 
 /* Storage types of A and of the sinogram blocks */
 enum { CT_F64 = 0, CT_F32 = 1 };
@@ -64,10 +73,12 @@ enum { CT_PREC_F64 = 0, CT_PREC_F32 = 1, CT_PREC_BF16 = 2, CT_PREC_F16 = 3, CT_P
 
 typedef struct ct_factor ct_factor; /* opaque, host-side */
 
-/* Assemble the dense system matrix (Eq. (system)) with Siddon's exact
- * ray-pixel intersection lengths.  A: m x n (m = n_angles * n_det,
- * n = n_pix^2), dtype CT_F64 or CT_F32 (FP64 lengths rounded to nearest),
- * leading dimension lda >= m.  Every entry of A[0:m, 0:n] is written. */
+/* Assemble the dense system matrix (Eq. (system)) with the geometry's
+ * projector (Siddon's exact ray-pixel intersection lengths, or Joseph's
+ * interpolation weights).  A: m x n (m = n_angles * n_det, n = n_pix^2),
+ * dtype CT_F64 or CT_F32 (FP64 weights rounded to nearest), leading
+ * dimension lda >= m.  Every entry of A[0:m, 0:n] is written.  An unknown
+ * projector is argument error -1. */
 int ct_build_system(const ct_geometry* g, int dtype, void* A, int64_t lda, void* stream);
 
 /* FP64 CSR copy of the same matrix, used for FP64 residuals.  row_ptr has
@@ -280,7 +291,7 @@ const char* ct_last_error(void);
 
 /* Rows of A for explicit rays (host arrays): rays_host r x 4 (x0, y0, x1, y1)
  * row-major, rows_host r x n_pix^2 row-major.  Synchronous; computed on the
- * GPU with the same walk as ct_build_system. */
+ * GPU with the same Siddon walk as ct_build_system. */
 int ct_siddon_rows(const double* rays_host, int64_t r, int32_t n_pix, double grid_width, double* rows_host);
 
 #ifdef __cplusplus

@@ -1071,11 +1071,13 @@ int ct_build_system(const ct_geometry* g, int dtype, void* A, int64_t lda, void*
     CT_ARG(g->n_pix > 0 && g->n_angles > 0 && g->n_det > 0, 1, "g (sizes)");
     CT_ARG(g->grid_width > 0 && g->sdd > 0 && g->sid > 0.5 * g->grid_width * 1.4142135623730951, 1,
            "g (source must lie outside the image)");
+    CT_ARG(g->projector == CT_PROJ_SIDDON || g->projector == CT_PROJ_JOSEPH, 1, "g (projector)");
     CT_ARG(dtype == CT_F64 || dtype == CT_F32, 2, "dtype");
     CT_ARG(A != nullptr && aligned(A), 3, "A");
     const int64_t m = (int64_t)g->n_angles * g->n_det;
     CT_ARG(lda >= m && lda % 16 == 0, 4, "lda");
-    GeomDev gd{g->n_pix, g->n_angles, g->n_det, g->grid_width, g->sid, g->sdd, g->det_length, g->angle0};
+    GeomDev gd{g->n_pix, g->n_angles, g->n_det, g->grid_width, g->sid, g->sdd, g->det_length, g->angle0,
+               g->projector};
     CT_HIP(launch_siddon_dense(gd, dtype, A, lda, (hipStream_t)stream));
     return 0;
 }
@@ -1083,10 +1085,12 @@ int ct_build_system(const ct_geometry* g, int dtype, void* A, int64_t lda, void*
 int ct_build_csr(const ct_geometry* g, int64_t* row_ptr, int32_t* col, double* val, int64_t nnz_cap, void* stream)
 {
     CT_ARG(g != nullptr && g->n_pix > 0 && g->n_angles > 0 && g->n_det > 0, 1, "g");
+    CT_ARG(g->projector == CT_PROJ_SIDDON || g->projector == CT_PROJ_JOSEPH, 1, "g (projector)");
     CT_ARG(row_ptr != nullptr, 2, "row_ptr");
     CT_ARG((col == nullptr) == (val == nullptr), 3, "col/val (both or neither)");
     CT_ARG(col == nullptr || nnz_cap > 0, 5, "nnz_cap");
-    GeomDev gd{g->n_pix, g->n_angles, g->n_det, g->grid_width, g->sid, g->sdd, g->det_length, g->angle0};
+    GeomDev gd{g->n_pix, g->n_angles, g->n_det, g->grid_width, g->sid, g->sdd, g->det_length, g->angle0,
+               g->projector};
     CT_HIP(launch_siddon_csr(gd, row_ptr, col, val, nnz_cap, (hipStream_t)stream));
     return 0;
 }

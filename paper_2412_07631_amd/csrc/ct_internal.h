@@ -50,6 +50,7 @@ constexpr uint64_t kWaitTicks = 50000000ull;
 struct GeomDev {
     int32_t n_pix, n_angles, n_det;
     double W, sid, sdd, det_length, angle0;
+    int32_t proj;      // 0: Siddon's exact lengths, 1: Joseph's interpolation
 };
 
 // Launch plan of the LDS-tiled NT update kernel: tile width along the

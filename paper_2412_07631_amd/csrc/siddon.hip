@@ -1,5 +1,7 @@
 // Assembly of the fan-beam system matrix A (Eq. (system): a_ij is the length
-// of ray i inside pixel j) by Siddon's ray-driven walk (Siddon 1985).
+// of ray i inside pixel j) by Siddon's ray-driven walk (Siddon 1985), or, as a
+// second mode, by Joseph's interpolating projector (Joseph 1982), the one the
+// paper builds A with (Sec. 3.1).
 //
 // One lane per ray; the 64 lanes of a wavefront take 64 consecutive detector
 // bins of one view, so their writes land on 64 consecutive rows of the
@@ -100,6 +102,46 @@ __device__ inline void siddon_walk(double x0, double y0, double x1, double y1, i
     }
 }
 
+// Joseph's projector: the ray is sampled once per pixel-centre line across
+// its dominant axis (x when |dx| >= |dy|); there the image is linearly
+// interpolated between the two pixels of that column (row) whose centres
+// bracket the ray, zero outside the grid, and the sample stands for one pixel
+// width along the dominant axis, h |p1 - p0| / |d_dominant|.  Calls
+// emit(pixel, weight) for every positive weight (at most 2N).
+template <typename Emit>
+__device__ inline void joseph_walk(double x0, double y0, double x1, double y1, int N, double W, Emit emit)
+{
+#pragma clang fp contract(off)
+    const double dx = x1 - x0, dy = y1 - y0;
+    const double lo = -0.5 * W, h = W / (double)N;
+    const bool xmajor = fabs(dx) >= fabs(dy);
+    const double dmaj = xmajor ? dx : dy, dmin = xmajor ? dy : dx;
+    const double pmaj = xmajor ? x0 : y0, pmin = xmajor ? y0 : x0;
+    if (dmaj == 0.0) return;
+    const double scale = h * sqrt(dx * dx + dy * dy) / fabs(dmaj);
+    for (int k = 0; k < N; ++k) {
+        const double c = lo + ((double)k + 0.5) * h;
+        const double a = (c - pmaj) / dmaj;
+        if (a < 0.0 || a > 1.0) continue;
+        const double q = pmin + a * dmin;
+        const double fq = (q - lo) / h - 0.5;
+        const double fl = floor(fq);
+        const double f = fq - fl;
+        const int i0 = (int)fl;
+        const double w0 = (1.0 - f) * scale, w1 = f * scale;
+        if (i0 >= 0 && i0 < N && w0 > 0.0) emit(xmajor ? i0 * N + k : k * N + i0, w0);
+        if (i0 + 1 >= 0 && i0 + 1 < N && w1 > 0.0) emit(xmajor ? (i0 + 1) * N + k : k * N + i0 + 1, w1);
+    }
+}
+
+// The geometry's projector.
+template <typename Emit>
+__device__ inline void ray_walk(const GeomDev& g, double x0, double y0, double x1, double y1, Emit emit)
+{
+    if (g.proj == 1) joseph_walk(x0, y0, x1, y1, g.n_pix, g.W, emit);
+    else siddon_walk(x0, y0, x1, y1, g.n_pix, g.W, emit);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) fill_zero_kernel(T* A, int64_t lda, int64_t m, int64_t n)
 {
@@ -119,7 +161,7 @@ __global__ void __launch_bounds__(64) siddon_dense_kernel(GeomDev g, T* A, int64
     double x0, y0, x1, y1;
     ray_points(g, i, x0, y0, x1, y1);
     T* row = A + i;
-    siddon_walk(x0, y0, x1, y1, g.n_pix, g.W, [&](int j, double len) { row[(int64_t)j * lda] = (T)len; });
+    ray_walk(g, x0, y0, x1, y1, [&](int j, double len) { row[(int64_t)j * lda] = (T)len; });
 }
 
 __global__ void __launch_bounds__(64) siddon_count_kernel(GeomDev g, int64_t* counts)
@@ -130,7 +172,7 @@ __global__ void __launch_bounds__(64) siddon_count_kernel(GeomDev g, int64_t* co
     double x0, y0, x1, y1;
     ray_points(g, i, x0, y0, x1, y1);
     int64_t c = 0;
-    siddon_walk(x0, y0, x1, y1, g.n_pix, g.W, [&](int, double) { ++c; });
+    ray_walk(g, x0, y0, x1, y1, [&](int, double) { ++c; });
     counts[i + 1] = c;
 }
 
@@ -182,7 +224,7 @@ __global__ void __launch_bounds__(64) siddon_csr_kernel(GeomDev g, const int64_t
     double x0, y0, x1, y1;
     ray_points(g, i, x0, y0, x1, y1);
     int64_t p = row_ptr[i];
-    siddon_walk(x0, y0, x1, y1, g.n_pix, g.W, [&](int j, double len) {
+    ray_walk(g, x0, y0, x1, y1, [&](int j, double len) {
         col[p] = j;
         val[p] = len;
         ++p;

@@ -35,7 +35,7 @@ _sz = ctypes.c_size_t
 
 
 class Geometry(ctypes.Structure):
-    _fields_ = [("n_pix", _i32), ("n_angles", _i32), ("n_det", _i32), ("reserved", _i32),
+    _fields_ = [("n_pix", _i32), ("n_angles", _i32), ("n_det", _i32), ("projector", _i32),
                 ("grid_width", ctypes.c_double), ("sid", ctypes.c_double), ("sdd", ctypes.c_double),
                 ("det_length", ctypes.c_double), ("angle0", ctypes.c_double)]
 
@@ -130,7 +130,8 @@ def colmajor(rows: int, cols: int, dtype, device="cuda", zero=False):
 
 def geometry(s) -> Geometry:
     """Geometry from any object with the ct_geometry fields (e.g. synth.Scanner)."""
-    return Geometry(int(s.n_pix), int(s.n_angles), int(s.n_det), 0, float(s.grid_width), float(s.sid),
+    return Geometry(int(s.n_pix), int(s.n_angles), int(s.n_det), int(getattr(s, "projector", 0)),
+                    float(s.grid_width), float(s.sid),
                     float(s.sdd), float(s.det_length), float(s.angle0))
 
 

@@ -103,6 +103,64 @@ def test_residual_kernel_f64(ct):
     assert np.max(np.abs(R - (B - A @ X))) <= 1e-12
 
 
+# ---------------------------------------------------- Joseph's projector
+JOSEPH = {"small": (32, 30, 64), "multi": (48, 40, 84)}
+_jcache = {}
+
+
+def joseph_problem(name):
+    if name not in _jcache:
+        sc = synth.scanner(*JOSEPH[name], projector=1)
+        A = O.system_dense(sc)
+        _jcache[name] = (sc, A)
+    return _jcache[name]
+
+
+@pytest.mark.parametrize("name", ["small", "multi"])
+def test_joseph_dense_and_csr_match_oracle(ct, name):
+    sc, A = joseph_problem(name)
+    Ag = from_dev(gpu_system(ct, sc, torch.float64), sc.m)
+    assert np.max(np.abs(Ag - A)) <= 1e-14
+    Af = gpu_system(ct, sc, torch.float32)[:, : sc.m].cpu().numpy().T
+    ref = A.astype(np.float32)
+    assert np.all(np.abs(Af.astype(np.float64) - ref.astype(np.float64)) <= np.spacing(ref))
+    row_ptr, col, val = ct.build_csr(sc)
+    rp, c, v = row_ptr.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy()
+    D = np.zeros_like(A)
+    for i in range(sc.m):
+        D[i, c[rp[i]:rp[i + 1]]] = v[rp[i]:rp[i + 1]]
+    assert np.max(np.abs(D - A)) <= 1e-14
+
+
+def test_joseph_system_through_the_whole_path(ct):
+    """QR, solve and refinement on Joseph's A: R, V, tau and x against the
+    oracle (FP64), and the BF16x3 factor refined to the FP64 solution."""
+    sc, A = joseph_problem("multi")
+    VR, tau, info = O.householder_qr(A)
+    assert info == 0
+    Ad = gpu_system(ct, sc, torch.float64)
+    f = ct.qr_factor(Ad, sc.m, sc.n, ct.PREC_F64, max_nrhs=8)
+    assert ct.status(f) == 0
+    VRg = from_dev(Ad, sc.m)
+    R, Rg = np.triu(VR[: sc.n]), np.triu(VRg[: sc.n])
+    assert np.max(np.abs(Rg - R)) / np.max(np.abs(R)) <= 1e-12
+    assert np.max(np.abs(f.tau.cpu().numpy() - tau)) <= 1e-12
+    _, P, B = sinograms(sc, A, 1, 4, 1e5)
+    Xs = O.solve(VR, tau, B)
+    Bd = to_dev(B, torch.float64)
+    ct.apply_qt(f, Bd)
+    ct.trsm_solve(f, Bd)
+    assert max_col_rel(from_dev(Bd, sc.n), Xs) <= 1e-10
+    A32 = gpu_system(ct, sc, torch.float32)
+    f3 = ct.qr_factor(A32, sc.m, sc.n, ct.PREC_BF16X3, max_nrhs=8)
+    sp = ct.SparseA(sc)
+    Xd = torch.zeros((4, ld16(sc.n)), dtype=torch.float64, device="cuda")
+    ct.solve_refined(f3, sp, to_dev(B, torch.float64), Xd, 4, ct.REFINE_SNE)
+    err = max_col_rel(from_dev(Xd, sc.n), Xs)
+    print("Joseph A, BF16x3 + 4 SNE: max rel err %.3g" % err)
+    assert err <= 1e-10
+
+
 # ------------------------------------------------------------ factorization
 @pytest.fixture(params=["two-reduction", "column-wise"])
 def panel_path(request, ct):
