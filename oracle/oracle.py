@@ -17,6 +17,8 @@ Functions and the passages they follow:
   apply_q / forward_substitute_rt / adjoint -- the transpose of the solve map,
       grad_b = Q [R^{-T} g; 0].
   rank_report -- the full-column-rank condition of Sec. 3.1.
+  snr / mse / psnr / ssim -- the image-quality metrics of Sec. 3.1,
+      Eqs. (snr), (mse), (psnr), (ssim), with an optional crop.
 
 Every function here has a pin in tests/test_oracle_*.py (values fixed by the
 paper, closed forms, brute force at tiny sizes, exact rational arithmetic or
@@ -292,3 +294,63 @@ def rank_report(VR) -> dict:
     ratio = float(d.min() / d.max()) if d.max() > 0 else 0.0
     return {"min_rjj": float(d.min()), "max_rjj": float(d.max()), "ratio": ratio,
             "numerically_deficient": bool(d.min() <= n * np.finfo(np.float64).eps * d.max())}
+
+
+# ----------------------------------------------------------- image quality
+# Sec. 3.1 "Image quality metrics", Eqs. (snr), (mse), (psnr), (ssim).  Images
+# are N x N with pixel (ix, iy) at index iy * N + ix (iy = 0 is the bottom row,
+# y = -W/2).  Readings where the paper is silent: MAX of Eq. (psnr) is the
+# largest pixel of the reference image; SSIM uses every 7 x 7 window of the
+# image (no padding), window means and sample (co)variances (divisor 48), and
+# c1 = (0.01 L)^2, c2 = (0.03 L)^2 with L the reference's dynamic range
+# (max - min); the image's SSIM is the mean over its windows.  A crop keeps
+# the pixels iy in [bottom, N - top), ix in [left, N - right).
+
+def _crop(img, N, crop):
+    a = np.asarray(img, dtype=np.float64).reshape(N, N)          # [iy, ix]
+    if crop is None:
+        return a
+    bottom, top, left, right = (int(v) for v in crop)
+    return a[bottom:N - top, left:N - right]
+
+
+def snr(ref, img, N, crop=None) -> float:
+    """Eq. (snr): 10 log10 (sum I0^2 / sum (I0 - I)^2), in dB."""
+    r, x = _crop(ref, N, crop), _crop(img, N, crop)
+    num = sum(float(v) ** 2 for v in r.ravel())
+    den = sum(float(a - b) ** 2 for a, b in zip(r.ravel(), x.ravel()))
+    return 10.0 * np.log10(num / den) if den > 0 else float("inf")
+
+
+def mse(ref, img, N, crop=None) -> float:
+    """Eq. (mse): mean of (I0 - I)^2 over the (cropped) image."""
+    r, x = _crop(ref, N, crop), _crop(img, N, crop)
+    return sum(float(a - b) ** 2 for a, b in zip(r.ravel(), x.ravel())) / r.size
+
+
+def psnr(ref, img, N, crop=None) -> float:
+    """Eq. (psnr): 10 log10 (MAX_I0^2 / MSE), MAX_I0 the reference's largest pixel."""
+    e = mse(ref, img, N, crop)
+    mx = float(np.max(_crop(ref, N, crop)))
+    return 10.0 * np.log10(mx * mx / e) if e > 0 else float("inf")
+
+
+def ssim(ref, img, N, crop=None, window: int = 7) -> float:
+    """Eq. (ssim) per window x (reference) and y (image), averaged over all
+    window positions; written out window by window."""
+    r, x = _crop(ref, N, crop), _crop(img, N, crop)
+    L = float(np.max(r) - np.min(r))
+    c1, c2 = (0.01 * L) ** 2, (0.03 * L) ** 2
+    k = window
+    total, count = 0.0, 0
+    for i in range(r.shape[0] - k + 1):
+        for j in range(r.shape[1] - k + 1):
+            a = r[i:i + k, j:j + k].ravel()
+            b = x[i:i + k, j:j + k].ravel()
+            mu_a, mu_b = sum(a) / a.size, sum(b) / b.size
+            va = sum((v - mu_a) ** 2 for v in a) / (a.size - 1)
+            vb = sum((v - mu_b) ** 2 for v in b) / (b.size - 1)
+            cov = sum((u - mu_a) * (v - mu_b) for u, v in zip(a, b)) / (a.size - 1)
+            total += ((2 * mu_a * mu_b + c1) * (2 * cov + c2)) / ((mu_a ** 2 + mu_b ** 2 + c1) * (va + vb + c2))
+            count += 1
+    return total / count
