@@ -257,7 +257,8 @@ def main():
         ctqr.trsm_solve(f64, B64)
         ev[3].record(stream)
         torch.cuda.synchronize()
-        X64 = B64[:, :n].cpu().numpy().T.copy()
+        X64d = B64[:, :n].contiguous()
+        X64 = X64d.cpu().numpy().T.copy()
         errs = np.linalg.norm(Xm - X64, axis=0) / np.linalg.norm(X64, axis=0)
         fp64 = {"qr_tflops": qr_flops(m, n) / (ev[0].elapsed_time(ev[1]) * 1e-3) / 1e12,
                 "qr_ms": ev[0].elapsed_time(ev[1]),
@@ -267,6 +268,32 @@ def main():
         del A64, B64, f64
         log("fp64 path: qr %.1f ms (%.2f TFLOP/s), solve %.1f slices/s; mixed vs fp64 max rel err %.3g" % (
             fp64["qr_ms"], fp64["qr_tflops"], fp64["slices_per_s"], fp64["rel_err_max"]))
+
+    # -------------------------------- image quality against the phantoms
+    # full image and the edge crop (the 512^2 margins of 130 rows at the
+    # bottom and 100 pixels elsewhere, scaled to the image size)
+    Np = sc.n_pix
+    crop = (round(130 * Np / 512), round(100 * Np / 512), round(100 * Np / 512), round(100 * Np / 512))
+    qev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def metrics(Xd, c):
+        q = ctqr.quality(Xd, Xtd, Np, crop=c).cpu().numpy()
+        return {"snr_db": float(q[:, 0].mean()), "mse": float(q[:, 1].mean()), "psnr_db": float(q[:, 2].mean()),
+                "ssim": float(q[:, 3].mean())}
+
+    qev[0].record(stream)
+    ctqr.quality(X, Xtd, Np)
+    qev[1].record(stream)
+    torch.cuda.synchronize()
+    quality = {"crop_bottom_top_left_right": list(crop), "kernel_ms": qev[0].elapsed_time(qev[1]),
+               "slices": nrhs, "refined": metrics(X, None), "refined_cropped": metrics(X, crop)}
+    if fp64 is not None:
+        quality["fp64"] = metrics(X64d, None)
+        quality["fp64_cropped"] = metrics(X64d, crop)
+        del X64d
+    log("quality (mean over %d slices): refined SNR %.2f dB, SSIM %.4f; cropped SSIM %.4f; %.2f ms" % (
+        nrhs, quality["refined"]["snr_db"], quality["refined"]["ssim"], quality["refined_cropped"]["ssim"],
+        quality["kernel_ms"]))
 
     # ------------------------------------- uneven batches and the adjoint
     batched = None
@@ -347,6 +374,7 @@ def main():
         "residual_rel_final": float(np.max(rnorm[-1] / bnorm)),
         "ls_grad_norm_by_step": [float(np.max(gnorm[s])) for s in range(args.refine + 1)],
         "fp64_path": fp64,
+        "quality": quality,
         "batched": batched,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -289,6 +289,22 @@ int ct_profile_end(ct_profile* out);
 
 const char* ct_last_error(void);
 
+/* Image quality of k reconstructed slices against reference images
+ * (Sec. 3.1, Eqs. (snr), (mse), (psnr), (ssim)), FP64 on the device.  X and
+ * ref: slice s at X + s * ldx (ref + s * ldr), n_pix^2 pixels each, pixel
+ * (ix, iy) at iy * n_pix + ix (iy = 0 the bottom row).  crop_host: NULL, or
+ * 4 host margins in pixels (bottom, top, left, right) that leave at least
+ * window x window pixels (the paper's cropped variant drops the image's
+ * edges).  out (device, k x 4): SNR (dB); MSE; PSNR (dB, MAX = the largest
+ * reference pixel of the crop); SSIM, the mean over every window x window
+ * window of the crop with window means, sample (co)variances (divisor
+ * window^2 - 1), c1 = (0.01 L)^2 and c2 = (0.03 L)^2, L the reference's
+ * max - min over the crop.  An exact reconstruction gives SNR = PSNR = inf.
+ * k = 0 does nothing (the pointers may then be NULL).  Bad arguments return
+ * their 1-based position (negated) and launch nothing. */
+int ct_quality(const double* X, int64_t ldx, const double* ref, int64_t ldr, int32_t n_pix, int64_t k,
+               const int32_t* crop_host, int32_t window, double* out, void* stream);
+
 /* Rows of A for explicit rays (host arrays): rays_host r x 4 (x0, y0, x1, y1)
  * row-major, rows_host r x n_pix^2 row-major.  Synchronous; computed on the
  * GPU with the same Siddon walk as ct_build_system. */

@@ -26,6 +26,8 @@ hipError_t launch_panel(TS* A, int64_t lda, int64_t mk, int nbp, int rw, double*
                         uint64_t* cq_count, int64_t* info, int64_t col0, int32_t* err, hipStream_t s);
 hipError_t panel_reset(double* part, double* gpart, hipStream_t s);
 void panel_set_cholesky(bool on);
+hipError_t launch_quality(const double* X, int64_t ldx, const double* R, int64_t ldr, int N, int64_t k,
+                          const int* crop, int win, double* out, hipStream_t s);
 void panel_set_cus(int cus);
 size_t panel_lds_bytes(int nbp, int rw);
 int panel_aux_words();
@@ -1601,6 +1603,28 @@ int ct_stream_info(const ct_factor* f, int64_t* tiles, int64_t* resident, int64_
 int ct_debug_wait_limit(int64_t ticks)
 {
     panel_set_wait_limit(ticks);
+    return 0;
+}
+
+int ct_quality(const double* X, int64_t ldx, const double* ref, int64_t ldr, int32_t n_pix, int64_t k,
+               const int32_t* crop_host, int32_t window, double* out, void* stream)
+{
+    CT_ARG(X != nullptr || k == 0, 1, "X");
+    CT_ARG(n_pix > 0 && ldx >= (int64_t)n_pix * n_pix, 2, "ldx");
+    CT_ARG(ref != nullptr || k == 0, 3, "ref");
+    CT_ARG(ldr >= (int64_t)n_pix * n_pix, 4, "ldr");
+    CT_ARG(n_pix > 0, 5, "n_pix");
+    CT_ARG(k >= 0 && k <= 2147483647, 6, "k");
+    int crop[4] = {0, 0, 0, 0};
+    if (crop_host)
+        for (int i = 0; i < 4; ++i) crop[i] = crop_host[i];
+    CT_ARG(window >= 2, 8, "window");
+    CT_ARG(crop[0] >= 0 && crop[1] >= 0 && crop[2] >= 0 && crop[3] >= 0 && n_pix - crop[0] - crop[1] >= window &&
+               n_pix - crop[2] - crop[3] >= window,
+           7, "crop_host (non-negative margins leaving at least window x window pixels)");
+    CT_ARG(out != nullptr || k == 0, 9, "out");
+    if (k == 0) return 0;
+    CT_HIP(launch_quality(X, ldx, ref, ldr, n_pix, k, crop, window, out, (hipStream_t)stream));
     return 0;
 }
 

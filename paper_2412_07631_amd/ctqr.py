@@ -60,6 +60,7 @@ _sig("ct_stream_inject_failure", [_i64])
 _sig("ct_debug_wait_limit", [_i64])
 _sig("ct_debug_panel_cholesky", [ctypes.c_int])
 _sig("ct_debug_block_width", [ctypes.c_int])
+_sig("ct_quality", [_vp, _i64, _vp, _i64, _i32, _i64, _vp, _i32, _vp, _vp])
 _sig("ct_factor_save", [_vp, ctypes.c_char_p, _vp])
 _sig("ct_factor_file_info", [ctypes.c_char_p, _i64, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
                              ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_sz)])
@@ -282,6 +283,21 @@ def debug_block_width(nb_out: int):
     """Force the outer block width of later factorizations (0 restores the
     size-based default)."""
     _check(_lib.ct_debug_block_width(nb_out))
+
+
+def quality(X: torch.Tensor, ref: torch.Tensor, n_pix: int, crop=None, window: int = 7, stream=None) -> torch.Tensor:
+    """(k, 4) FP64 tensor of SNR (dB), MSE, PSNR (dB), SSIM of the k slices
+    (rows) of X against those of ref; crop = (bottom, top, left, right)."""
+    if X.dtype != torch.float64 or ref.dtype != torch.float64:
+        raise TypeError("X and ref must be float64")
+    k = X.shape[0]
+    out = torch.empty((max(k, 1), 4), dtype=torch.float64, device=X.device)
+    c = None
+    if crop is not None:
+        c = (ctypes.c_int32 * 4)(*[int(v) for v in crop])
+    _check(_lib.ct_quality(_ptr(X), X.shape[1], _ptr(ref), ref.shape[1], n_pix, k, c, window, _ptr(out),
+                           _stream(stream)))
+    return out[:k]
 
 
 def apply_qt(f: Factor, B: torch.Tensor, nrhs: int = None, stream=None):
