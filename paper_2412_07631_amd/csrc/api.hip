@@ -77,6 +77,7 @@ template <typename TS>
 hipError_t launch_copy_block(const TS* src, int64_t lds, TS* dst, int64_t ldd, int rows, int cols, hipStream_t s,
                              const int32_t* desc);
 hipError_t rinv_set_max_lds(size_t bytes);
+hipError_t launch_diag_x3(const float* Ri, float* B, int64_t ldb, int bo, int nrhs, hipStream_t s);
 hipError_t launch_residual(const int64_t* row_ptr, const int32_t* col, const double* val, int64_t m, const double* X,
                            int64_t ldx, const double* B, int64_t ldb, double* R, int64_t ldr, int nrhs,
                            hipStream_t s);
@@ -221,6 +222,7 @@ struct ct_factor {
 constexpr int kNbStream = 256;
 
 static int g_nb_force = 0;   // test hook: forced outer block width (0: by size)
+static bool g_x3_refine = true;   // BF16x3 block updates in the refinement of a BF16x3 factor
 static int nb_out_for(int64_t n) { return g_nb_force ? g_nb_force : (n >= 16384 ? 1024 : 256); }
 
 struct Layout {
@@ -859,9 +861,12 @@ static int stream_factor(ct_factor* f, hipStream_t s)
 
 // B <- Q^T B (transpose) or B <- Q B, block by block, in the factor's storage
 // precision.  desc: optional device batch descriptor (graph-captured solves).
+// x3 (Q^T only, FP32 storage, no batch descriptor): both block products on
+// the bfloat16 MFMA in BF16x3, the block first copied out of the factored
+// matrix with its unit diagonal and zeros (that kernel reads no mask).
 template <typename TS>
 static int apply_qt_impl(const ct_factor* fc, TS* B, int64_t nrhs, int64_t ldb, hipStream_t s, bool transpose,
-                         const int32_t* desc = nullptr)
+                         const int32_t* desc = nullptr, bool x3 = false)
 {
     ct_factor* f = const_cast<ct_factor*>(fc);
     const int nbo = f->nb_out;
@@ -886,6 +891,18 @@ static int apply_qt_impl(const ct_factor* fc, TS* B, int64_t nrhs, int64_t ldb, 
             ops = VOps{f->Vm, f->ldvm, 0, f->Vt, ldvt_of(bo), t_storage<TS>(f, b)};
         }
         op = &ops;
+        if constexpr (sizeof(TS) == 4)
+            if (x3 && transpose && !desc && f->VtAll) {
+                r = prep_block<TS>(f, Vb + k0, f->lda, f->m - k0, bo, s);
+                if (r) return r;
+                ops.vm = f->Vm;
+                ops.ldvm = f->ldvm;
+                ops.mask = 0;
+                r = larfb_nt<TS, 0, M_BF16X3>(f, f->m - k0, bo, Tb, nbo, B + k0, ldb, (int)nrhs, s, false, nullptr,
+                                              nullptr, op);
+                if (r) return r;
+                continue;
+            }
         r = transpose ? larfb_nt<TS, 0>(f, f->m - k0, bo, Tb, nbo, B + k0, ldb, (int)nrhs, s, false, plan, desc, op)
                       : larfb_nt<TS, 1>(f, f->m - k0, bo, Tb, nbo, B + k0, ldb, (int)nrhs, s, false, plan, desc, op);
         if (r) return r;
@@ -893,9 +910,11 @@ static int apply_qt_impl(const ct_factor* fc, TS* B, int64_t nrhs, int64_t ldb, 
     return walk.finish();
 }
 
+// x3: the diagonal steps and block-column updates on the bfloat16 MFMA in
+// BF16x3 (FP32 storage only, no batch descriptor).
 template <typename TS>
 static int trsm_impl(const ct_factor* fc, TS* B, int64_t nrhs, int64_t ldb, hipStream_t s,
-                     const int32_t* desc = nullptr)
+                     const int32_t* desc = nullptr, bool x3 = false)
 {
     ct_factor* f = const_cast<ct_factor*>(fc);
     const int64_t n = f->n, lda = f->lda;
@@ -913,12 +932,26 @@ static int trsm_impl(const ct_factor* fc, TS* B, int64_t nrhs, int64_t ldb, hipS
             const int64_t k0 = b * 256;
             const int bo = (int)std::min<int64_t>(256, n - k0);
             int nz;
-            CT_HIP((launch_copy_block<TS>(B + k0, ldb, S, 256, bo, (int)nrhs, s, desc)));
-            CT_HIP(launch_nt<TS>((const TS*)f->RiR + (size_t)b * 256 * 256, 256, S, 256, B + k0, ldb, bo, (int)nrhs,
-                                 bo, false, 0, &nz, s, &diag_plan, desc, 0, 1));
-            if (k0 > 0)
-                CT_HIP(launch_nt<TS>((const TS*)f->Rt + (size_t)256 * 256 * (size_t)(b * (b - 1) / 2), 256, B + k0,
-                                     ldb, B, ldb, k0, (int)nrhs, bo, true, 0, &nz, s, plan, desc, 1, 1));
+            bool done = false;
+            if constexpr (sizeof(TS) == 4)
+                if (x3 && !desc) {
+                    CT_HIP(launch_diag_x3((const float*)f->RiR + (size_t)b * 256 * 256, B + k0, ldb, bo, (int)nrhs, s));
+                    done = true;
+                }
+            if (!done) {
+                CT_HIP((launch_copy_block<TS>(B + k0, ldb, S, 256, bo, (int)nrhs, s, desc)));
+                CT_HIP(launch_nt<TS>((const TS*)f->RiR + (size_t)b * 256 * 256, 256, S, 256, B + k0, ldb, bo,
+                                     (int)nrhs, bo, false, 0, &nz, s, &diag_plan, desc, 0, 1));
+            }
+            if (k0 == 0) continue;
+            const TS* Rtb = (const TS*)f->Rt + (size_t)256 * 256 * (size_t)(b * (b - 1) / 2);
+            if constexpr (sizeof(TS) == 4)
+                if (x3 && !desc) {
+                    CT_HIP(launch_nt_lp<M_BF16X3>(Rtb, 256, B + k0, ldb, B, ldb, k0, (int)nrhs, bo, true, 0, &nz, s,
+                                                  nullptr, nullptr));
+                    continue;
+                }
+            CT_HIP(launch_nt<TS>(Rtb, 256, B + k0, ldb, B, ldb, k0, (int)nrhs, bo, true, 0, &nz, s, plan, desc, 1, 1));
         }
         return 0;
     }
@@ -944,7 +977,7 @@ static int trsm_impl(const ct_factor* fc, TS* B, int64_t nrhs, int64_t ldb, hipS
 // Y[0:n] <- R^{-T} Y[0:n]: forward substitution on the lower-triangular R^T,
 // diagonal-block solves alternating with GEMM updates from the rows above.
 template <typename TS>
-static int trsm_lt_impl(const ct_factor* fc, TS* Y, int64_t k, int64_t ldy, hipStream_t s)
+static int trsm_lt_impl(const ct_factor* fc, TS* Y, int64_t k, int64_t ldy, hipStream_t s, bool x3 = false)
 {
     ct_factor* f = const_cast<ct_factor*>(fc);
     const int64_t n = f->n, lda = f->lda;
@@ -963,13 +996,27 @@ static int trsm_lt_impl(const ct_factor* fc, TS* Y, int64_t k, int64_t ldy, hipS
             const int64_t k0 = b * 256;
             const int bo = (int)std::min<int64_t>(256, n - k0);
             int nz;
-            CT_HIP((launch_copy_block<TS>(Y + k0, ldy, S, 256, bo, (int)k, s, nullptr)));
-            CT_HIP(launch_nt<TS>((const TS*)f->RiC + (size_t)b * 256 * 256, 256, S, 256, Y + k0, ldy, bo, (int)k, bo,
-                                 false, 0, &nz, s, &diag_plan));
+            bool done = false;
+            if constexpr (sizeof(TS) == 4)
+                if (x3) {
+                    CT_HIP(launch_diag_x3((const float*)f->RiC + (size_t)b * 256 * 256, Y + k0, ldy, bo, (int)k, s));
+                    done = true;
+                }
+            if (!done) {
+                CT_HIP((launch_copy_block<TS>(Y + k0, ldy, S, 256, bo, (int)k, s, nullptr)));
+                CT_HIP(launch_nt<TS>((const TS*)f->RiC + (size_t)b * 256 * 256, 256, S, 256, Y + k0, ldy, bo, (int)k,
+                                     bo, false, 0, &nz, s, &diag_plan));
+            }
             const int64_t rest = n - k0 - bo;
-            if (rest > 0)
-                CT_HIP(launch_nt<TS>(A + k0 + (k0 + bo) * lda, lda, Y + k0, ldy, Y + k0 + bo, ldy, rest, (int)k, bo,
-                                     true, 0, &nz, s, plan));
+            if (rest <= 0) continue;
+            if constexpr (sizeof(TS) == 4)
+                if (x3) {
+                    CT_HIP(launch_nt_lp<M_BF16X3>(A + k0 + (k0 + bo) * lda, lda, Y + k0, ldy, Y + k0 + bo, ldy, rest,
+                                                  (int)k, bo, true, 0, &nz, s, nullptr, nullptr));
+                    continue;
+                }
+            CT_HIP(launch_nt<TS>(A + k0 + (k0 + bo) * lda, lda, Y + k0, ldy, Y + k0 + bo, ldy, rest, (int)k, bo, true, 0,
+                                 &nz, s, plan));
         }
         return 0;
     }
@@ -1024,12 +1071,15 @@ static int refined_impl(const ct_factor* f, const ct_sparse* sp, const double* B
     double* Np = (double*)p;                            // column-norm partials (256 x nrhs)
     const bool have_csc = sp->col_ptr && sp->row && sp->cval;
     const int nr = (int)nrhs;
+    // a BF16x3 factor's corrections are solved with BF16x3 block updates:
+    // the FP64 residual, not the correction's arithmetic, sets the accuracy
+    const bool x3 = f->prec == CT_PREC_BF16X3 && g_x3_refine;
     CT_HIP((launch_transpose<double, double, true, false>(B, Bt, m, nr, ldb, lt, s)));
     // x_0 = R~^{-1} Q~^T b
     CT_HIP((launch_convert<double, TS>(B, ldb, C, ld, m, nr, s)));
-    int r = ct_apply_qt(f, C, nrhs, ld, s);
+    int r = apply_qt_impl<TS>(f, C, nrhs, ld, s, true, nullptr, x3);
     if (r) return r;
-    r = ct_trsm_solve(f, C, nrhs, ld, s);
+    r = trsm_impl<TS>(f, C, nrhs, ld, s, nullptr, x3);
     if (r) return r;
     CT_HIP((launch_convert<TS, double>(C, ld, X, ldx, n, nr, s)));
     CT_HIP((launch_transpose<TS, double, true, false>(C, Xt, n, nr, ld, lt, s)));
@@ -1046,15 +1096,15 @@ static int refined_impl(const ct_factor* f, const ct_sparse* sp, const double* B
         if (method == CT_REFINE_SNE) {
             // x += R~^{-1} R~^{-T} (A^T r)
             CT_HIP((launch_transpose<double, TS, false, false>(St, C, n, nr, ld, lt, s)));
-            r = trsm_lt_impl<TS>(f, C, nrhs, ld, s);
+            r = trsm_lt_impl<TS>(f, C, nrhs, ld, s, x3);
             if (r) return r;
         } else {
             // x += R~^{-1} Q~^T r
             CT_HIP((launch_transpose<double, TS, false, false>(Rt, C, m, nr, ld, lt, s)));
-            r = ct_apply_qt(f, C, nrhs, ld, s);
+            r = apply_qt_impl<TS>(f, C, nrhs, ld, s, true, nullptr, x3);
             if (r) return r;
         }
-        r = ct_trsm_solve(f, C, nrhs, ld, s);
+        r = trsm_impl<TS>(f, C, nrhs, ld, s, nullptr, x3);
         if (r) return r;
         CT_HIP((launch_accumulate<TS>(X, ldx, C, ld, n, nr, s)));
         CT_HIP((launch_transpose<TS, double, true, true>(C, Xt, n, nr, ld, lt, s)));
@@ -1626,6 +1676,13 @@ int ct_quality(const double* X, int64_t ldx, const double* ref, int64_t ldr, int
     if (k == 0) return 0;
     CT_HIP(launch_quality(X, ldx, ref, ldr, n_pix, k, crop, window, out, (hipStream_t)stream));
     return 0;
+}
+
+int ct_debug_refine_x3(int enable)
+{
+    const int was = g_x3_refine ? 1 : 0;
+    g_x3_refine = enable != 0;
+    return was;
 }
 
 int ct_debug_panel_cholesky(int enable)

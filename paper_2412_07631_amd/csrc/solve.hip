@@ -533,6 +533,104 @@ hipError_t launch_copy_block(const TS* src, int64_t lds, TS* dst, int64_t ldd, i
     return hipGetLastError();
 }
 
+// One diagonal step of a blocked triangular solve with a stored inverse
+// block, B[0:bo, q] <- Ri B[0:bo, q] (Ri: bo x bo of a 256 x 256 row-major
+// array), in BF16x3 on the bfloat16 MFMA: each FP32 operand is split into
+// bfloat16 halves and the product formed as hi*hi + hi*lo + lo*hi with FP32
+// accumulation.  Workgroup w takes slices 16w .. 16w + 15, stages them in LDS
+// (split), then writes its results in place: no other workgroup reads them.
+// Wave v computes rows 64v .. 64v + 63.  FULL: bo = 256 (no guards).
+template <bool FULL>
+__global__ void __launch_bounds__(256) diag_x3_kernel(const float* __restrict__ Ri, float* __restrict__ B, int64_t ldb,
+                                                      int bo, int nrhs)
+{
+    constexpr int LDK = 256 + 8;                  // 528-byte rows: conflict-free 16-byte lane reads
+    __shared__ __attribute__((aligned(16))) __bf16 Bh[16 * LDK];
+    __shared__ __attribute__((aligned(16))) __bf16 Bl[16 * LDK];
+    const int t = threadIdx.x;
+    const int q0 = blockIdx.x * 16;
+    const int lane = t & 63, wv = t >> 6;
+    const int c = lane & 15, g = lane >> 4;
+    // this lane's 8 consecutive K values of row 64 wv + 16 i + c at K offset kk
+    auto load_a = [&](int kk, float (&a)[4][8]) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int p = 64 * wv + 16 * i + c;
+            const int k = kk + 8 * g;
+            if (FULL || (p < bo && k + 8 <= bo)) {
+                const f4_t u = *(const f4_t*)(Ri + (int64_t)p * 256 + k);
+                const f4_t w = *(const f4_t*)(Ri + (int64_t)p * 256 + k + 4);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    a[i][e] = u[e];
+                    a[i][4 + e] = w[e];
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) a[i][e] = (p < bo && k + e < bo) ? Ri[(int64_t)p * 256 + k + e] : 0.f;
+            }
+        }
+    };
+    float an[4][8];
+    load_a(0, an);
+    float bv[16];
+#pragma unroll
+    for (int qs = 0; qs < 16; ++qs) {
+        const int q = q0 + qs;
+        bv[qs] = (q < nrhs && (FULL || t < bo)) ? B[(int64_t)q * ldb + t] : 0.f;
+    }
+#pragma unroll
+    for (int qs = 0; qs < 16; ++qs) {
+        const __bf16 h = (__bf16)bv[qs];
+        Bh[qs * LDK + t] = h;
+        Bl[qs * LDK + t] = (__bf16)(bv[qs] - (float)h);
+    }
+    __syncthreads();
+    f4_t acc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = f4_t{0.f, 0.f, 0.f, 0.f};
+    for (int kk = 0; kk < bo; kk += 32) {
+        float a[4][8];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) a[i][e] = an[i][e];
+        if (kk + 32 < bo) load_a(kk + 32, an);     // next K step's operands in flight
+        const bf8_t bh = *(const bf8_t*)&Bh[c * LDK + kk + 8 * g];
+        const bf8_t bl = *(const bf8_t*)&Bl[c * LDK + kk + 8 * g];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            bf8_t ah, al;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                ah[e] = (__bf16)a[i][e];
+                al[e] = (__bf16)(a[i][e] - (float)ah[e]);
+            }
+            acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[i], 0, 0, 0);
+            acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[i], 0, 0, 0);
+            acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[i], 0, 0, 0);
+        }
+    }
+    const int q = q0 + c;
+    if (q >= nrhs) return;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int p = 64 * wv + 16 * i + 4 * g + r;
+            if (p < bo) B[(int64_t)q * ldb + p] = acc[i][r];
+        }
+}
+
+hipError_t launch_diag_x3(const float* Ri, float* B, int64_t ldb, int bo, int nrhs, hipStream_t s)
+{
+    if (nrhs <= 0 || bo <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((nrhs + 15) / 16));
+    if (bo == 256) hipLaunchKernelGGL(diag_x3_kernel<true>, grid, dim3(256), 0, s, Ri, B, ldb, bo, nrhs);
+    else hipLaunchKernelGGL(diag_x3_kernel<false>, grid, dim3(256), 0, s, Ri, B, ldb, bo, nrhs);
+    return hipGetLastError();
+}
+
 hipError_t rinv_set_max_lds(size_t bytes)
 {
     return hipFuncSetAttribute((const void*)rinv128_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);

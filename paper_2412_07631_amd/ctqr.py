@@ -60,6 +60,7 @@ _sig("ct_stream_inject_failure", [_i64])
 _sig("ct_debug_wait_limit", [_i64])
 _sig("ct_debug_panel_cholesky", [ctypes.c_int])
 _sig("ct_debug_block_width", [ctypes.c_int])
+_sig("ct_debug_refine_x3", [ctypes.c_int])
 _sig("ct_quality", [_vp, _i64, _vp, _i64, _i32, _i64, _vp, _i32, _vp, _vp])
 _sig("ct_factor_save", [_vp, ctypes.c_char_p, _vp])
 _sig("ct_factor_file_info", [ctypes.c_char_p, _i64, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
@@ -283,6 +284,12 @@ def debug_block_width(nb_out: int):
     """Force the outer block width of later factorizations (0 restores the
     size-based default)."""
     _check(_lib.ct_debug_block_width(nb_out))
+
+
+def debug_refine_x3(enable: bool) -> bool:
+    """BF16x3 block updates in the refinement's triangular solves of a BF16x3
+    factor (default on); returns the previous setting."""
+    return bool(_lib.ct_debug_refine_x3(1 if enable else 0))
 
 
 def quality(X: torch.Tensor, ref: torch.Tensor, n_pix: int, crop=None, window: int = 7, stream=None) -> torch.Tensor:

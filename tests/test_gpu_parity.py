@@ -306,7 +306,7 @@ def refined(ct, prec, name, nrhs, steps, method, cfg=3):
     _, P, B = sinograms(sc, A, cfg, nrhs, 5e4)
     Xs = O.solve(VR, tau, B)
     Ad = gpu_system(ct, sc, torch.float64 if prec == "f64" else torch.float32)
-    f = ct.qr_factor(Ad, sc.m, sc.n, ct.PREC_NAMES[prec], max_nrhs=8)
+    f = ct.qr_factor(Ad, sc.m, sc.n, ct.PREC_NAMES[prec], max_nrhs=max(8, nrhs))
     assert ct.status(f) == 0
     sp = ct.SparseA(sc)
     Bd = to_dev(B, torch.float64)
@@ -327,6 +327,25 @@ def test_refined_sne_parity(ct, prec, steps, tol):
     print("SNE", prec, "steps", steps, "max rel err %.3g" % err, "||A^T r||:", ["%.3g" % v for v in gn])
     assert err <= tol
     assert gn[-1] < gn[0]
+
+
+@pytest.mark.parametrize("name,nrhs", [("multi", 6), ("ragged", 37)])
+def test_refined_bf16x3_block_updates_on_and_off(ct, name, nrhs):
+    """The refinement of a BF16x3 factor solves its corrections with BF16x3
+    diagonal steps and block updates by default; with FP32 ones instead it
+    reaches the same FP64 oracle images, and both converge step by step
+    (ragged: a last diagonal block of 132 rows, 37 slices over three
+    workgroups of 16)."""
+    was = ct.debug_refine_x3(False)
+    try:
+        err32, _, g32 = refined(ct, "bf16x3", name, nrhs, 4, ct.REFINE_SNE)
+    finally:
+        ct.debug_refine_x3(was)
+    assert was
+    err3, _, g3 = refined(ct, "bf16x3", name, nrhs, 4, ct.REFINE_SNE)
+    print("bf16x3 refine, FP32 updates %.3g, BF16x3 updates %.3g" % (err32, err3), g32, g3)
+    assert err3 <= 1e-10 and err32 <= 1e-10
+    assert all(b < a for a, b in zip(g3[:3], g3[1:4]))
 
 
 def test_refined_qr_method_stalls_at_its_fixed_point(ct):
