@@ -159,13 +159,15 @@ int ct_debug_panel_cholesky(int enable);
  * A factor must be created and used under the same setting.  Returns -1
  * (argument 1 invalid) for other values. */
 int ct_debug_block_width(int nb_out);
-/* The corrections of ct_solve_refined on a CT_PREC_BF16X3 factor solve their
- * triangular systems with the 256-row block-column updates in BF16x3 (the
- * precision of the factor's own trailing updates; the FP64 residual sets the
- * final accuracy).  For tests and comparisons: enable = 0 makes later calls
- * use FP32 products there, != 0 restores the default.  Returns the previous
- * setting. */
-int ct_debug_refine_x3(int enable);
+/* ct_solve_refined on a CT_PREC_BF16X3 factor runs the products of its
+ * solves (Q^T blocks, the triangular solves' diagonal steps and 256-row
+ * block-column updates) in BF16x3, the precision of the factor's own trailing
+ * updates, when it solves 48 slices or more (fewer: FP32 products, whose
+ * fewer launches cost less there); the FP64 residual sets the final
+ * accuracy.  For tests and comparisons, mode 0 makes later calls always use
+ * FP32 products, 2 always BF16x3, 1 restores the default.  Returns the
+ * previous mode, or -1 (argument 1 invalid) for another value. */
+int ct_debug_refine_x3(int mode);
 
 /* B <- Q^T B (Eq. (solve), first half; ormqr).  B: m x nrhs, same storage
  * type as the factor's A, nrhs <= max_nrhs.  Rows n..m-1 of the result hold
@@ -218,9 +220,8 @@ int ct_refine_workspace(int64_t m, int64_t n, int64_t nrhs, size_t* bytes);
  * B: m x nrhs FP64 (unchanged), X: n x nrhs FP64 (output).  If not NULL,
  * res_norms receives ||r_s||_2 and grad_norms ||A^T r_s||_2 (the latter needs
  * the CSC copy) for s = 0..steps, (steps + 1) x nrhs, step-major.  On a
- * CT_PREC_BF16X3 factor the triangular solves of the corrections use BF16x3
- * block updates (see ct_debug_refine_x3); the first solve and every other
- * factor use the storage precision. */
+ * CT_PREC_BF16X3 factor the solves inside use BF16x3 products from 48 slices
+ * up (see ct_debug_refine_x3); other factors use their storage precision. */
 int ct_solve_refined(const ct_factor* f, const ct_sparse* A, const double* B, int64_t ldb, double* X,
                      int64_t ldx, int64_t nrhs, int32_t steps, int32_t method, void* scratch,
                      size_t scratch_bytes, double* res_norms, double* grad_norms, void* stream);

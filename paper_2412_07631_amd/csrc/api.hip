@@ -222,7 +222,11 @@ struct ct_factor {
 constexpr int kNbStream = 256;
 
 static int g_nb_force = 0;   // test hook: forced outer block width (0: by size)
-static bool g_x3_refine = true;   // BF16x3 block updates in the refinement of a BF16x3 factor
+// BF16x3 products in the refinement of a BF16x3 factor: 0 never, 1 from
+// kX3MinSlices slices (below that the extra launches cost more than the
+// products save), 2 always
+static int g_x3_refine = 1;
+constexpr int64_t kX3MinSlices = 48;
 static int nb_out_for(int64_t n) { return g_nb_force ? g_nb_force : (n >= 16384 ? 1024 : 256); }
 
 struct Layout {
@@ -1073,7 +1077,7 @@ static int refined_impl(const ct_factor* f, const ct_sparse* sp, const double* B
     const int nr = (int)nrhs;
     // a BF16x3 factor's corrections are solved with BF16x3 block updates:
     // the FP64 residual, not the correction's arithmetic, sets the accuracy
-    const bool x3 = f->prec == CT_PREC_BF16X3 && g_x3_refine;
+    const bool x3 = f->prec == CT_PREC_BF16X3 && (g_x3_refine == 2 || (g_x3_refine == 1 && nrhs >= kX3MinSlices));
     CT_HIP((launch_transpose<double, double, true, false>(B, Bt, m, nr, ldb, lt, s)));
     // x_0 = R~^{-1} Q~^T b
     CT_HIP((launch_convert<double, TS>(B, ldb, C, ld, m, nr, s)));
@@ -1678,10 +1682,11 @@ int ct_quality(const double* X, int64_t ldx, const double* ref, int64_t ldr, int
     return 0;
 }
 
-int ct_debug_refine_x3(int enable)
+int ct_debug_refine_x3(int mode)
 {
-    const int was = g_x3_refine ? 1 : 0;
-    g_x3_refine = enable != 0;
+    if (mode < 0 || mode > 2) return fail(-1, "%s", "invalid argument mode (0, 1 or 2)");
+    const int was = g_x3_refine;
+    g_x3_refine = mode;
     return was;
 }
 

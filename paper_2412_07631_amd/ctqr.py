@@ -286,10 +286,13 @@ def debug_block_width(nb_out: int):
     _check(_lib.ct_debug_block_width(nb_out))
 
 
-def debug_refine_x3(enable: bool) -> bool:
-    """BF16x3 block updates in the refinement's triangular solves of a BF16x3
-    factor (default on); returns the previous setting."""
-    return bool(_lib.ct_debug_refine_x3(1 if enable else 0))
+def debug_refine_x3(mode: int) -> int:
+    """BF16x3 products in the refinement of a BF16x3 factor: 0 never, 1 from
+    48 slices (default), 2 always; returns the previous mode."""
+    r = _lib.ct_debug_refine_x3(int(mode))
+    if r < 0:
+        _check(r)
+    return r
 
 
 def quality(X: torch.Tensor, ref: torch.Tensor, n_pix: int, crop=None, window: int = 7, stream=None) -> torch.Tensor:

@@ -52,6 +52,11 @@ def test_argument_errors_without_gpu():
         ws[nb] = b.value
     assert lib.ct_debug_block_width(0) == 0
     assert ws[1024] > ws[256]
+    # the refinement-precision hook takes modes 0..2 and returns the previous one
+    assert lib.ct_debug_refine_x3(3) == -1 and lib.ct_debug_refine_x3(-1) == -1
+    assert lib.ct_debug_refine_x3(2) == 1
+    assert lib.ct_debug_refine_x3(0) == 2
+    assert lib.ct_debug_refine_x3(1) == 0
 
 
 def test_binding_marshals_without_gpu():

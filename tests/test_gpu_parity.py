@@ -331,18 +331,19 @@ def test_refined_sne_parity(ct, prec, steps, tol):
 
 @pytest.mark.parametrize("name,nrhs", [("multi", 6), ("ragged", 37)])
 def test_refined_bf16x3_block_updates_on_and_off(ct, name, nrhs):
-    """The refinement of a BF16x3 factor solves its corrections with BF16x3
-    diagonal steps and block updates by default; with FP32 ones instead it
+    """The refinement of a BF16x3 factor runs its solves' products in BF16x3
+    (by default from 48 slices); with FP32 ones instead it
     reaches the same FP64 oracle images, and both converge step by step
     (ragged: a last diagonal block of 132 rows, 37 slices over three
-    workgroups of 16)."""
-    was = ct.debug_refine_x3(False)
+    workgroups of 16; both forced, whatever the slice count)."""
+    was = ct.debug_refine_x3(0)
     try:
         err32, _, g32 = refined(ct, "bf16x3", name, nrhs, 4, ct.REFINE_SNE)
+        ct.debug_refine_x3(2)
+        err3, _, g3 = refined(ct, "bf16x3", name, nrhs, 4, ct.REFINE_SNE)
     finally:
         ct.debug_refine_x3(was)
-    assert was
-    err3, _, g3 = refined(ct, "bf16x3", name, nrhs, 4, ct.REFINE_SNE)
+    assert was == 1
     print("bf16x3 refine, FP32 updates %.3g, BF16x3 updates %.3g" % (err32, err3), g32, g3)
     assert err3 <= 1e-10 and err32 <= 1e-10
     assert all(b < a for a, b in zip(g3[:3], g3[1:4]))
