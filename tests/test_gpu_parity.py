@@ -349,6 +349,23 @@ def test_refined_bf16x3_block_updates_on_and_off(ct, name, nrhs):
     assert all(b < a for a, b in zip(g3[:3], g3[1:4]))
 
 
+def test_refined_qr_method_bf16x3_products(ct):
+    """The Q~^T-correction refinement of a BF16x3 factor with BF16x3 products
+    (every step applies Q~^T in BF16x3) reaches the same fixed point as with
+    FP32 products: the two fixed points lie at the same distance, within a
+    factor of 3, from the least-squares solution."""
+    was = ct.debug_refine_x3(0)
+    try:
+        e32, _, g32 = refined(ct, "bf16x3", "ragged", 37, 4, ct.REFINE_QR)
+        ct.debug_refine_x3(2)
+        e3, _, g3 = refined(ct, "bf16x3", "ragged", 37, 4, ct.REFINE_QR)
+    finally:
+        ct.debug_refine_x3(was)
+    print("QR-method refine, FP32 products %.3g, BF16x3 products %.3g" % (e32, e3), g32[-1], g3[-1])
+    assert np.isfinite(e3) and e3 <= 3 * e32 + 1e-12 and e32 <= 3 * e3 + 1e-12
+    assert g3[-1] < g3[0]
+
+
 def test_refined_qr_method_stalls_at_its_fixed_point(ct):
     """x += R~^{-1} Q~^T r converges to Q~^T r = 0, not to A^T r = 0: with an
     FP32 factor and noisy data the image error stops far above the SNE one."""
