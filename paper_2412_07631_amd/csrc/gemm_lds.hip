@@ -585,7 +585,12 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_lp_kernel(NtArgs a)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f4_t{0, 0, 0, 0};
 
+    // the wave raises its issue priority for its MFMAs, so that while one
+    // workgroup of the CU stages its next K step the other keeps the matrix
+    // cores fed (measured: W = V^T C 317 -> 343 TFLOP/s at the first trailing
+    // update of the 256^2 factorization)
     auto compute = [&]() {
+        __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 32) {
             v8 bh[4], bl[4];
@@ -609,6 +614,7 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_lp_kernel(NtArgs a)
                 }
             }
         }
+        __builtin_amdgcn_s_setprio(0);
     };
 
     // the subtracting epilogue's C tile is fetched during the last K step,
