@@ -489,26 +489,9 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_lp_kernel(NtArgs a)
     u4v xs[PX ? 2 * PB : 1], ys[PY ? 2 * PB : 1];
     const int lrb = t / VB, lvb = t % VB;
     auto gload = [&](int64_t k0) {
-        if constexpr (PX) {
-            const __bf16* Xh = (const __bf16*)a.X;
-            const __bf16* Xl = (const __bf16*)a.Xlo;
-#pragma unroll
-            for (int ps = 0; ps < PB; ++ps) {
-                const int64_t pr = p0 + ps * RB + lrb, kk = k0 + lvb * 8;
-                xs[ps] = load_bf8(Xh, a.ldx, pr, a.P, kk, kend);
-                xs[PB + ps] = load_bf8(Xl, a.ldx, pr, a.P, kk, kend);
-            }
-        }
-        if constexpr (PY) {
-            const __bf16* Yh = (const __bf16*)a.Y;
-            const __bf16* Yl = (const __bf16*)a.Ylo;
-#pragma unroll
-            for (int ps = 0; ps < PB; ++ps) {
-                const int64_t qr = q0 + ps * RB + lrb, kk = k0 + lvb * 8;
-                ys[ps] = load_bf8(Yh, a.ldy, qr, a.Q, kk, kend);
-                ys[PB + ps] = load_bf8(Yl, a.ldy, qr, a.Q, kk, kend);
-            }
-        }
+        // FP32 operands first: in W = V^T C the columns of C come fresh from
+        // HBM while the split reflector block is mostly in L2, so C's loads
+        // get the longest time in flight
         if constexpr (!PX || !PY) {
 #pragma unroll
             for (int ps = 0; ps < PASSES; ++ps) {
@@ -530,6 +513,26 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_lp_kernel(NtArgs a)
                 }
                 if constexpr (!PX) xr[ps] = vx;
                 if constexpr (!PY) yr[ps] = vy;
+            }
+        }
+        if constexpr (PX) {
+            const __bf16* Xh = (const __bf16*)a.X;
+            const __bf16* Xl = (const __bf16*)a.Xlo;
+#pragma unroll
+            for (int ps = 0; ps < PB; ++ps) {
+                const int64_t pr = p0 + ps * RB + lrb, kk = k0 + lvb * 8;
+                xs[ps] = load_bf8(Xh, a.ldx, pr, a.P, kk, kend);
+                xs[PB + ps] = load_bf8(Xl, a.ldx, pr, a.P, kk, kend);
+            }
+        }
+        if constexpr (PY) {
+            const __bf16* Yh = (const __bf16*)a.Y;
+            const __bf16* Yl = (const __bf16*)a.Ylo;
+#pragma unroll
+            for (int ps = 0; ps < PB; ++ps) {
+                const int64_t qr = q0 + ps * RB + lrb, kk = k0 + lvb * 8;
+                ys[ps] = load_bf8(Yh, a.ldy, qr, a.Q, kk, kend);
+                ys[PB + ps] = load_bf8(Yl, a.ldy, qr, a.Q, kk, kend);
             }
         }
     };
