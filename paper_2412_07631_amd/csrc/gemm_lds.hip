@@ -594,6 +594,9 @@ __global__ void __launch_bounds__(256, 2) gemm_nt_lp_kernel(NtArgs a)
     // update of the 256^2 factorization)
     auto compute = [&]() {
         __builtin_amdgcn_s_setprio(1);
+        // scheduler hint: interleave the fragment reads with the MFMAs
+        // (QR at 256^2 2.15 -> 2.12 s measured on one box)
+        __builtin_amdgcn_iglp_opt(0);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 32) {
             v8 bh[4], bl[4];
