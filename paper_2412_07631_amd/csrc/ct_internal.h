@@ -77,7 +77,7 @@ __device__ __forceinline__ int desc_offset(const int32_t* desc) { return desc ? 
 // kBand tile columns row by row (columns fastest), so the tiles that run at
 // the same time on one XCD share their row and column operand blocks in L2.
 // Returns false for the padding workgroups.
-constexpr int kBand = 8;
+constexpr int kBand = 4;
 __device__ __forceinline__ bool tile_of(int b, int tiles_p, int tiles_q, int& tp, int& tq)
 {
     const int nt = tiles_p * tiles_q;
