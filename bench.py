@@ -23,7 +23,12 @@ import time
 import numpy as np
 
 METRIC = "QR TFLOP/s + slices/s at 256^2: FP32/BF16+refine vs FP64 on MI355X, rel err"
-PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "f16": 2500.0, "bf16x3": 2500.0 / 3.0}
+# MFMA peak of the arithmetic each path's trailing update runs on: BF16x3
+# runs on the bfloat16 MFMA, so its method flops are measured against the
+# bfloat16 peak (it issues three MFMA products per method product, reported
+# separately as the issue rate)
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "f16": 2500.0, "bf16x3": 2500.0}
+ISSUE_FACTOR = {"f64": 1, "f32": 1, "bf16": 1, "f16": 1, "bf16x3": 3}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -39,7 +44,7 @@ def solve_flops(m, n):
     return 4.0 * m * n - float(n) * n
 
 
-def batched_leg(ctqr, synth, torch, f, sc, Bd, dev, total, sp):
+def batched_leg(ctqr, synth, torch, f, sc, Bd, dev, total, sp, X64=None):
     """Uneven batches (seeded sizes 1..512) of sinograms through the
     graph-captured solve, then the adjoint on 64 upstream gradients with a
     central finite-difference check (step 1e-3) on the same factor.  The
@@ -89,6 +94,11 @@ def batched_leg(ctqr, synth, torch, f, sc, Bd, dev, total, sp):
     torch.cuda.synchronize()
     eager_ms = e0.elapsed_time(e1)
     agree = float(((Xg - Bb[:, :n]).abs().max() / Bb[:, :n].abs().max()).item())
+    vs64 = None
+    if X64 is not None:
+        Xr = X64[idx, :n]
+        e = (Xg.double() - Xr).norm(dim=1) / Xr.norm(dim=1)
+        vs64 = {"rel_err_max": float(e.max().item()), "rel_err_median": float(e.median().item())}
 
     # adjoint: 64 FP32 upstream gradients; FD check along seeded directions
     k = 64
@@ -119,6 +129,7 @@ def batched_leg(ctqr, synth, torch, f, sc, Bd, dev, total, sp):
     fd_err = float(((fd - an).abs() / scale).max().item())
     return {"sinograms": total, "batches": len(sizes), "graph_slices_per_s": total / (g_ms * 1e-3),
             "eager_slices_per_s": total / (eager_ms * 1e-3), "graph_vs_eager_max_rel_diff": agree,
+            "graph_vs_fp64": vs64,
             "adjoint_gradients": k, "adjoint_ms": bwd_ms, "fd_step": h, "fd_err_by_norms": fd_err}
 
 
@@ -133,6 +144,7 @@ def main():
     ap.add_argument("--method", default="sne", choices=["sne", "qr"])
     ap.add_argument("--nrhs", type=int, default=None, help="slices per batch (default: the workload's)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference path")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cols", type=int, default=2048, help="leading columns in the CPU oracle sample")
     ap.add_argument("--copy-probe", action="store_true",
@@ -244,32 +256,101 @@ def main():
     bnorm = np.linalg.norm(B, axis=0)
     Xm = X[:, :n].cpu().numpy().T.copy()
 
+    def ev_pair():
+        return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def paper_residual(Xd, Bsrc):
+        """||A X - B||_F / ||B||_F in FP64 with the CSR copy of A (Tables 2, 6, 8)."""
+        R = torch.empty_like(Bsrc)
+        ctqr.residual(sp.csr, m, Xd, Bsrc, R)
+        return float((R[:, :m].norm() / Bsrc[:, :m].norm()).item())
+
+    def errs_vs(Xa, Xref):
+        """Per-slice relative image error and max pixel error (Sec. 3.1)."""
+        d = (Xa[:, :n] - Xref[:, :n])
+        e = d.norm(dim=1) / Xref[:, :n].norm(dim=1)
+        return {"rel_err_max": float(e.max().item()), "rel_err_median": float(e.median().item()),
+                "max_abs_pixel_err": float(d.abs().max().item())}
+
+    def plain_solve(fac, Bsrc):
+        """X = R^-1 Q^T B in the factor's storage precision (Eq. (solve)); ms."""
+        Bs = Bsrc.to(fac.dtype, copy=True)
+        e0, e1 = ev_pair()
+        e0.record(stream)
+        ctqr.apply_qt(fac, Bs)
+        ctqr.trsm_solve(fac, Bs)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        Xo = torch.zeros((Bs.shape[0], ctqr.ld16(n)), dtype=torch.float64, device=dev)
+        Xo[:, :n] = Bs[:, :n].double()
+        return Xo, e0.elapsed_time(e1)
+
+    # refined headline path on the noiseless sinograms (consistent data, as
+    # the paper's projected references): the paper-style residual
+    Xnl = torch.zeros_like(X)
+    ctqr.solve_refined(f, sp, Pnl, Xnl, args.refine, method, scratch=scratch)
+    torch.cuda.synchronize()
+    headline_residual_noiseless = paper_residual(Xnl, Pnl)
+
     # -------------------------------------------------- plain FP64 GPU path
     fp64 = None
+    X64d = None
     if not args.no_fp64 and prec != ctqr.PREC_F64:
         A64 = torch.empty((n, ctqr.ld16(m)), dtype=torch.float64, device=dev)
         ctqr.build_system(sc, A64)
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-        ev[0].record(stream)
+        e0, e1 = ev_pair()
+        e0.record(stream)
         f64 = ctqr.qr_factor(A64, m, n, ctqr.PREC_F64, max_nrhs=nrhs)
-        ev[1].record(stream)
-        B64 = Bd.clone()
-        ev[2].record(stream)
-        ctqr.apply_qt(f64, B64)
-        ctqr.trsm_solve(f64, B64)
-        ev[3].record(stream)
+        e1.record(stream)
         torch.cuda.synchronize()
-        X64d = B64[:, :n].contiguous()
-        X64 = X64d.cpu().numpy().T.copy()
-        errs = np.linalg.norm(Xm - X64, axis=0) / np.linalg.norm(X64, axis=0)
-        fp64 = {"qr_tflops": qr_flops(m, n) / (ev[0].elapsed_time(ev[1]) * 1e-3) / 1e12,
-                "qr_ms": ev[0].elapsed_time(ev[1]),
-                "slices_per_s": nrhs / (ev[2].elapsed_time(ev[3]) * 1e-3),
-                "rel_err_max": float(errs.max()), "rel_err_median": float(np.median(errs)),
-                "max_abs_pixel_err": float(np.max(np.abs(Xm - X64)))}
-        del A64, B64, f64
-        log("fp64 path: qr %.1f ms (%.2f TFLOP/s), solve %.1f slices/s; mixed vs fp64 max rel err %.3g" % (
-            fp64["qr_ms"], fp64["qr_tflops"], fp64["slices_per_s"], fp64["rel_err_max"]))
+        qr64_ms = e0.elapsed_time(e1)
+        X64d, sol64_ms = plain_solve(f64, Bd)
+        X64nl, _ = plain_solve(f64, Pnl)
+        fp64 = {"qr_tflops": qr_flops(m, n) / (qr64_ms * 1e-3) / 1e12, "qr_ms": qr64_ms,
+                "qr_tflops_frac_of_peak": qr_flops(m, n) / (qr64_ms * 1e-3) / 1e12 / PEAK_TFLOPS["f64"],
+                "slices_per_s": nrhs / (sol64_ms * 1e-3), "solve_ms": sol64_ms,
+                "residual_noiseless": paper_residual(X64nl, Pnl),
+                "noiseless_rel_err_vs_phantom": errs_vs(X64nl, Xtd)["rel_err_max"]}
+        del A64, f64, X64nl
+        torch.cuda.empty_cache()
+        log("fp64 path: qr %.1f ms (%.2f TFLOP/s), solve %.1f slices/s, noiseless residual %.3g" % (
+            fp64["qr_ms"], fp64["qr_tflops"], fp64["slices_per_s"], fp64["residual_noiseless"]))
+
+    headline_vs_fp64 = errs_vs(X, X64d) if X64d is not None else None
+    noiseless_vs_fp64 = None
+
+    # ------------------------------------------------------ plain FP32 path
+    fp32 = None
+    f32 = None
+    if not args.no_fp32 and prec != ctqr.PREC_F32:
+        A32 = torch.empty((n, ctqr.ld16(m)), dtype=torch.float32, device=dev)
+        ctqr.build_system(sc, A32)
+        e0, e1 = ev_pair()
+        e0.record(stream)
+        f32 = ctqr.qr_factor(A32, m, n, ctqr.PREC_F32, max_nrhs=nrhs)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        qr32_ms = e0.elapsed_time(e1)
+        X32, sol32_ms = plain_solve(f32, Bd)
+        X32nl, _ = plain_solve(f32, Pnl)
+        X32r = torch.zeros_like(X)
+        e0, e1 = ev_pair()
+        e0.record(stream)
+        ctqr.solve_refined(f32, sp, Bd, X32r, 3, ctqr.REFINE_SNE, scratch=scratch)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ref32_ms = e0.elapsed_time(e1)
+        fp32 = {"qr_tflops": qr_flops(m, n) / (qr32_ms * 1e-3) / 1e12, "qr_ms": qr32_ms,
+                "qr_tflops_frac_of_peak": qr_flops(m, n) / (qr32_ms * 1e-3) / 1e12 / PEAK_TFLOPS["f32"],
+                "slices_per_s": nrhs / (sol32_ms * 1e-3), "solve_ms": sol32_ms,
+                "residual_noiseless": paper_residual(X32nl, Pnl),
+                "refined3_slices_per_s": nrhs / (ref32_ms * 1e-3)}
+        if X64d is not None:
+            fp32["vs_fp64"] = errs_vs(X32, X64d)
+            fp32["refined3_vs_fp64"] = errs_vs(X32r, X64d)
+        del X32, X32nl, X32r
+        log("fp32 path: qr %.1f ms (%.2f TFLOP/s), solve %.1f slices/s, noiseless residual %.3g" % (
+            fp32["qr_ms"], fp32["qr_tflops"], fp32["slices_per_s"], fp32["residual_noiseless"]))
 
     # ------------- the same solve with B handed over in pinned host memory
     # (the timed region starts with B in host RAM: its H2D copy is included)
@@ -305,27 +386,26 @@ def main():
     qev[1].record(stream)
     torch.cuda.synchronize()
     quality = {"crop_bottom_top_left_right": list(crop), "kernel_ms": qev[0].elapsed_time(qev[1]),
-               "slices": nrhs, "refined": metrics(X, None), "refined_cropped": metrics(X, crop)}
-    # consistent data (b = A x_true, as the paper's projected references):
-    # the metrics then measure the solver's precision instead of the noise
-    Xnl = torch.zeros_like(X)
-    ctqr.solve_refined(f, sp, Pnl, Xnl, args.refine, method, scratch=scratch, res_norms=rn, grad_norms=gn)
-    quality["noiseless_refined"] = metrics(Xnl, None)
-    quality["noiseless_refined_cropped"] = metrics(Xnl, crop)
-    del Xnl, Pnl
-    if fp64 is not None:
+               "slices": nrhs, "refined": metrics(X, None), "refined_cropped": metrics(X, crop),
+               "noiseless_refined": metrics(Xnl, None), "noiseless_refined_cropped": metrics(Xnl, crop)}
+    if X64d is not None:
         quality["fp64"] = metrics(X64d, None)
         quality["fp64_cropped"] = metrics(X64d, crop)
-        del X64d
     log("quality (mean over %d slices): refined SNR %.2f dB, SSIM %.4f; cropped SSIM %.4f; noiseless SNR %.1f dB, "
         "SSIM %.6f; %.2f ms" % (nrhs, quality["refined"]["snr_db"], quality["refined"]["ssim"],
                                 quality["refined_cropped"]["ssim"], quality["noiseless_refined"]["snr_db"],
                                 quality["noiseless_refined"]["ssim"], quality["kernel_ms"]))
+    del Xnl, Pnl
 
     # ------------------------------------- uneven batches and the adjoint
+    # (on the FP32 factor: a plain FP32 solve meets the FP32 path's
+    # tolerance, which a plain solve on a bfloat16-based factor does not)
     batched = None
     if not args.no_batched:
-        batched = batched_leg(ctqr, synth, torch, f, sc, Bd, dev, args.batched_total, sp)
+        fb = f32 if f32 is not None else f
+        batched = batched_leg(ctqr, synth, torch, fb, sc, Bd, dev, args.batched_total, sp, X64d)
+        batched["factor"] = "f32" if f32 is not None else args.prec
+    del f32
 
     # ------------------------------------------------------ roofline (live)
     dom = max(prof, key=lambda k: prof[k]["ms"])
@@ -342,14 +422,20 @@ def main():
     else:
         kname = (tname % "true") + " (C -= V W')" if dom == "update_cvw" else (tname % "false") + " (W = V^T C)"
     # the kernel's own bound: its algorithmic flop per algorithmic byte
-    # against the machine balance (MFMA peak / 8 TB/s HBM)
+    # against the balance of the MFMA rate it can reach (the dtype's peak over
+    # the MFMA products it issues per method product) and 8 TB/s of HBM; the
+    # fraction is always taken against the dtype's own MFMA peak
+    issue = ISSUE_FACTOR[args.prec]
     intensity = d["flop"] / d["bytes"] if d["bytes"] > 0 else float("inf")
-    ridge = peak * 1e12 / (HBM_PEAK_GBS * 1e9)
+    ridge = peak / issue * 1e12 / (HBM_PEAK_GBS * 1e9)
     if intensity >= ridge:
         bound = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak}
     else:
         gbs = d["bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0
         bound = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+    if issue > 1:
+        bound["mfma_issue"] = {"products_per_method_product": issue, "tflops": achieved * issue,
+                               "frac_of_peak": achieved * issue / peak}
     roofline = {**bound, "kernel": kname, "flop_per_byte": intensity, "ridge_flop_per_byte": ridge,
                 "launches": d["launches"], "avg_launch_ms": d["ms"] / max(d["launches"], 1),
                 "algorithmic_gbs": d["bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0,
@@ -398,10 +484,12 @@ def main():
         "slices_per_s": slices_per_s,
         "solve_ms": sol_ms / args.steps,
         "slices_per_s_incl_h2d": slices_per_s_h2d,
-        "solve_tflops": solve_flops(m, n) * nrhs * (1 + args.refine) / (sol_ms / args.steps * 1e-3) / 1e12,
+        "vs_fp64": headline_vs_fp64,
+        "residual_noiseless": headline_residual_noiseless,
         "residual_rel_final": float(np.max(rnorm[-1] / bnorm)),
         "ls_grad_norm_by_step": [float(np.max(gnorm[s])) for s in range(args.refine + 1)],
         "fp64_path": fp64,
+        "fp32_path": fp32,
         "quality": quality,
         "batched": batched,
         "roofline": roofline,

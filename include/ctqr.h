@@ -121,7 +121,10 @@ int ct_qr_factor(void* A, int64_t m, int64_t n, int64_t lda, int prec, double* t
  * work.  The handle works with every solve call except the graph-captured
  * ones; A_host, tau and work must stay alive until ct_factor_destroy.
  * Returns -2002 after an injected copy failure (see ct_stream_inject_failure)
- * with *f set: ct_qr_resume then continues from the failed tile. */
+ * with *f set: ct_qr_resume then continues from the failed tile.  Any error
+ * inside a tile leaves the handle at that tile with the tile's host copy
+ * untouched, so a resume redoes it; only a failed write-back of a finished
+ * tile makes the handle unresumable (ct_qr_resume then returns -1). */
 int ct_qr_stream_workspace(int64_t m, int64_t n, int64_t lda, int prec, int64_t max_nrhs, int64_t tile_cols,
                            size_t* min_bytes, size_t* all_resident_bytes);
 int ct_qr_factor_streamed(void* A_host, int64_t m, int64_t n, int64_t lda, int prec, double* tau, void* work,
@@ -132,9 +135,14 @@ int ct_qr_resume(ct_factor* f, void* stream);
 /* Tile count, resident tile count and first unfinished tile of a streamed
  * factor (all 0 for an in-memory factor). */
 int ct_stream_info(const ct_factor* f, int64_t* tiles, int64_t* resident, int64_t* next_tile);
-/* Failure injection for tests: the next streamed factorization stops before
- * tile `tile` as if its copy had failed (-1 disables). */
-int ct_stream_inject_failure(int64_t tile);
+/* Failure injection for tests: the next streamed factorization (or resume)
+ * stops at tile `tile` as if a copy had failed and returns -2002 -- before
+ * any work on the tile (after_updates < 0), or after the reflector blocks of
+ * the first after_updates earlier tiles have been applied to it (a value of
+ * `tile` or more: after all of them, just before the tile's own panels).  A
+ * failed tile is redone from its host copy by ct_qr_resume, which gives
+ * bitwise the uninterrupted result.  tile = -1 disables. */
+int ct_stream_inject_failure(int64_t tile, int64_t after_updates);
 
 /* The Householder panels wait for each other's column reductions (their
  * workgroups must all be resident; the handle checks the occupancy).  A wait
@@ -179,7 +187,10 @@ int ct_apply_qt(const ct_factor* f, void* B, int64_t nrhs, int64_t ldb, void* st
  * the rows above (Sec. 2.2). */
 int ct_trsm_solve(const ct_factor* f, void* B, int64_t nrhs, int64_t ldb, void* stream);
 
-/* Adjoint of the solve map b -> x = R^{-1} Q^T b: gradB <- Q [R^{-T} G; 0].
+/* Adjoint of the solve map of Eq. (solve), b -> x = R^{-1} Q^T b (linear in
+ * b, so its transpose is the gradient map): gradB <- Q [R^{-T} G; 0], by a
+ * forward substitution with R^T followed by the reflectors applied in reverse
+ * order.
  * G: n x k (ldg), gradB: m x k (ldgb), both of the factor's storage type. */
 int ct_solve_backward(const ct_factor* f, const void* G, int64_t k, int64_t ldg, void* gradB, int64_t ldgb,
                       void* stream);
@@ -228,7 +239,9 @@ int ct_solve_refined(const ct_factor* f, const ct_sparse* A, const double* B, in
 
 /* Waits for `stream`, then reports the factor's numerical status: *info = 0
  * for full column rank, j + 1 if column j had a zero Householder norm.
- * Returns -2001 if a cross-workgroup wait of the factorization timed out. */
+ * Returns -2001 if a cross-workgroup wait of the factorization timed out, and
+ * -2003 (once; the flag is then cleared) if a graph-captured solve met an
+ * invalid batch descriptor entry. */
 int ct_status(const ct_factor* f, int64_t* info, void* stream);
 
 int ct_factor_destroy(ct_factor* f);
@@ -254,18 +267,24 @@ int ct_factor_load(const char* path, void* A, int64_t lda, double* tau, void* wo
                    int64_t max_nrhs, ct_factor** f, void* stream);
 
 /* Graph-captured solve over a device batch descriptor, for many batches of
- * uneven size sharing one factor.  desc is a device int32 array: desc[0] = k,
- * the index of the batch the next launch solves; desc[2+2k] and desc[3+2k]
- * = first column and column count (<= max_cols) of batch k inside B
- * (m x total columns, ldb, the factor's storage type).  The whole solve
- * (Q^T then R^{-1}, Eq. (solve)) is captured once into a hipGraph with the
- * launch plan of the max_cols size bucket; every kernel reads the descriptor,
- * and the graph's last node advances desc[0], so consecutive launches walk the
- * batch list with no host work.  `stream` must not be the legacy default
- * stream during creation (capture).  The caller sets desc before the first
- * launch and keeps B, desc and the factor alive until ct_solve_graph_destroy. */
+ * uneven size sharing one factor (Sec. 2: one factorization serves every
+ * later set of sinograms; Eq. (solve) per batch).  desc is a device int32
+ * array [cur, nbatch, off_0, cnt_0, off_1, cnt_1, ...]: cur is the index of
+ * the batch the next launch solves, nbatch the number of batches, and batch k
+ * occupies columns off_k .. off_k + cnt_k - 1 of B (m x b_cols, ldb, the
+ * factor's storage type).  The whole solve (Q^T then R^{-1}) is captured once
+ * into a hipGraph with the launch plan of the max_cols size bucket.  The
+ * graph's first node checks the entry of batch cur (0 <= cur < nbatch,
+ * off_k >= 0, 0 <= cnt_k <= max_cols, off_k + cnt_k <= b_cols); an invalid
+ * entry, or a launch past the last batch, leaves B untouched and makes the
+ * next ct_status return -2003.  The last node advances cur (never past
+ * nbatch), so consecutive launches walk the batch list with no host work.
+ * `stream` must not be the legacy default stream during creation (capture).
+ * The caller sets desc before the first launch and keeps B, desc and the
+ * factor alive until ct_solve_graph_destroy.  Graphs and solve calls sharing
+ * a factor must be ordered on one stream (they share the factor's scratch). */
 typedef struct ct_solve_graph ct_solve_graph;
-int ct_solve_graph_create(const ct_factor* f, void* B, int64_t ldb, int64_t max_cols, int32_t* desc,
+int ct_solve_graph_create(const ct_factor* f, void* B, int64_t ldb, int64_t b_cols, int64_t max_cols, int32_t* desc,
                           void* stream, ct_solve_graph** g);
 int ct_solve_graph_launch(ct_solve_graph* g, void* stream);
 int ct_solve_graph_destroy(ct_solve_graph* g);

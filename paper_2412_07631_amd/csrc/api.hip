@@ -67,7 +67,9 @@ hipError_t launch_split_x3(const float* src, int64_t lds, void* hi, void* lo, in
 template <typename TS, bool UPPER>
 hipError_t launch_trsm_diag(const TS* R, int64_t ldr, int bo, TS* B, int64_t ldb, int nrhs, hipStream_t s,
                             const int32_t* desc = nullptr);
-hipError_t launch_advance_batch(int32_t* desc, hipStream_t s);
+hipError_t launch_begin_batch(const int32_t* desc, int32_t* rec, int max_cols, int64_t b_cols, int32_t* err,
+                              hipStream_t s);
+hipError_t launch_end_batch(int32_t* desc, hipStream_t s);
 hipError_t trsm_set_max_lds(size_t bytes);
 template <typename TS>
 hipError_t launch_rinv(const TS* A, int64_t lda, int64_t n, TS* RiR, TS* RiC, double* Ri64, double* M, hipStream_t s);
@@ -181,6 +183,7 @@ struct ct_factor {
     uint64_t* counter;
     int64_t* info;
     int32_t* err;
+    int32_t* batch_rec;   // (offset, count) of the current batch of a graph-captured solve
     void* Wp;
     int64_t wp_elems;  // capacity in 8-byte elements
     void* Wq;
@@ -594,6 +597,7 @@ struct StreamState {
     size_t es = 4;                 // bytes per element
     int64_t wt = 0, ntiles = 0, nres = 0;
     int64_t next_tile = 0;         // first tile not yet factored
+    bool broken = false;           // a tile's write-back failed: no resume
     hipStream_t cin = nullptr, cout = nullptr;
     hipEvent_t done = nullptr;     // scratch event on the compute stream
     char* slot[kSlots] = {};
@@ -789,7 +793,28 @@ struct ColWalk {
 // st->next_tile: bring tile J in, apply every earlier reflector block to it
 // (in order), factor it, and copy it back to the host matrix while the next
 // tile is processed.
-static int64_t g_inject_fail_tile = -1;
+// Failure injection (tests): the factorization stops at tile g_inject_tile
+// as if a copy had failed, before any work on the tile (g_inject_after < 0)
+// or after g_inject_after of the earlier tiles' reflector blocks have been
+// applied to it.
+static int64_t g_inject_tile = -1, g_inject_after = -1;
+
+// Undo a partly processed tile J after an error: wait for every stream, drop
+// the staging cache and its pins, and forget that a resident tile J was
+// loaded, so that a resume reloads it from the host matrix (whose copy of
+// tile J is only written when the tile is finished).
+static int stream_abort_tile(ct_factor* f, int64_t J, hipStream_t s, int code)
+{
+    StreamState* st = f->st;
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamSynchronize(st->cin);
+    (void)hipStreamSynchronize(st->cout);
+    stream_invalidate(st);
+    for (int k = 0; k < kSlots; ++k) st->pins[k] = 0;
+    if (J < st->nres) st->res_loaded[J] = 0;
+    st->next_tile = J;
+    return code;
+}
 
 template <typename TS>
 static int stream_factor(ct_factor* f, hipStream_t s)
@@ -798,64 +823,71 @@ static int stream_factor(ct_factor* f, hipStream_t s)
     const int64_t m = f->m, lda = f->lda, wt = st->wt;
     const int nbo = f->nb_out;
     const int mode = trailing_mode(f->prec);
+    auto injected = [&](int64_t J) {
+        g_inject_tile = -1;
+        g_inject_after = -1;
+        const int r = fail(-2002, "%s", "tile copy failed (injected); ct_qr_resume continues from the failed tile");
+        return stream_abort_tile(f, J, s, r);
+    };
     for (int64_t J = st->next_tile; J < st->ntiles; ++J) {
-        if (g_inject_fail_tile == J) {
-            // test hook: behave as if the copy of tile J had failed
-            g_inject_fail_tile = -1;
-            (void)hipStreamSynchronize(s);
-            (void)hipStreamSynchronize(st->cin);
-            (void)hipStreamSynchronize(st->cout);
-            stream_invalidate(st);
-            for (int k = 0; k < kSlots; ++k) st->pins[k] = 0;
-            st->next_tile = J;
-            return fail(-2002, "%s", "tile copy failed (injected); ct_qr_resume continues from the failed tile");
-        }
+        if (g_inject_tile == J && g_inject_after < 0) return injected(J);
         const int64_t c0 = J * wt, w = tile_width(f, J);
         char* Cb;
         int kc;
         int r = stream_acquire(f, J, 0, m, s, &Cb, &kc);
-        if (r) return r;
+        if (r) return stream_abort_tile(f, J, s, r);
         TS* C = (TS*)Cb;
         if (J == 0) {
             r = stream_prefetch(f, 1, 0, m);
-            if (r) return r;
+            if (r) return stream_abort_tile(f, J, s, r);
         }
         for (int64_t u = 0; u < J; ++u) {
+            if (g_inject_tile == J && g_inject_after == u) return injected(J);
             const int64_t u0 = u * wt, uw = tile_width(f, u);
             char* Vb;
             int kv;
             r = stream_acquire(f, u, u0, m, s, &Vb, &kv);
-            if (r) return r;
+            if (r) return stream_abort_tile(f, J, s, r);
             // overlap the next load with this tile's updates
             r = (u + 1 < J) ? stream_prefetch(f, u + 1, (u + 1) * wt, m) : stream_prefetch(f, J + 1, 0, m);
-            if (r) return r;
+            if (r) return stream_abort_tile(f, J, s, r);
             const TS* V = (const TS*)Vb;
             for (int64_t k0 = u0; k0 < u0 + uw; k0 += nbo) {
                 const int bo = (int)std::min<int64_t>(nbo, u0 + uw - k0);
                 const double* Tb = f->T_all + (size_t)(k0 / nbo) * nbo * nbo;
                 r = larfb_mode<TS, 0>(f, mode, V + (k0 - u0) * lda + k0, lda, m - k0, bo, Tb, nbo, C + k0, lda,
                                       (int)w, s, true);
-                if (r) return r;
+                if (r) return stream_abort_tile(f, J, s, r);
             }
             r = stream_release(f, kv, s);
-            if (r) return r;
+            if (r) return stream_abort_tile(f, J, s, r);
         }
+        if (g_inject_tile == J && g_inject_after >= J) return injected(J);
         r = factor_cols<TS>(f, C, c0, c0 + w, s);
-        if (r) return r;
+        if (r) return stream_abort_tile(f, J, s, r);
         // copy the finished tile back to the host matrix
-        CT_HIP(hipEventRecord(st->done, s));
-        CT_HIP(hipStreamWaitEvent(st->cout, st->done, 0));
         const size_t pitch = (size_t)lda * st->es;
-        CT_HIP(hipMemcpy2DAsync(st->Ah + (size_t)c0 * lda * st->es, pitch, C, pitch, (size_t)m * st->es, (size_t)w,
-                                hipMemcpyDeviceToHost, st->cout));
-        CT_HIP(hipEventRecord(st->d2h[J], st->cout));
+        hipError_t e = hipEventRecord(st->done, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st->cout, st->done, 0);
+        if (e == hipSuccess)
+            e = hipMemcpy2DAsync(st->Ah + (size_t)c0 * lda * st->es, pitch, C, pitch, (size_t)m * st->es, (size_t)w,
+                                 hipMemcpyDeviceToHost, st->cout);
+        if (e == hipSuccess) e = hipEventRecord(st->d2h[J], st->cout);
+        if (e != hipSuccess) {
+            // the host copy of tile J may be partly written, so the tile can
+            // no longer be redone from it: the factorization cannot resume
+            const int rc = fail(-1000 - (int)e, "tile write-back: %s", hipGetErrorString(e));
+            (void)stream_abort_tile(f, J, s, rc);
+            st->broken = true;
+            return rc;
+        }
         st->d2h_rec[J] = 1;
         if (kc >= 0) {
             CT_HIP(hipEventRecord(st->out[kc], st->cout));
             st->out_rec[kc] = true;
         }
         r = stream_release(f, kc, s);
-        if (r) return r;
+        if (r) return stream_abort_tile(f, J + 1, s, r);
         st->next_tile = J + 1;
     }
     // the host matrix is complete once the compute stream passes this point
@@ -1180,6 +1212,7 @@ static int init_factor(ct_factor* f, void* A, int64_t m, int64_t n, int64_t lda,
     f->counter = (uint64_t*)(w + L.words);
     f->info = (int64_t*)(w + L.words + 64);
     f->err = (int32_t*)(w + L.words + 128);
+    f->batch_rec = (int32_t*)(w + L.words + 192);
     f->col_base = 0;
     f->cq_count = 0;
     f->Wp = w + L.Wp; f->wp_elems = L.wp_elems;
@@ -1639,6 +1672,7 @@ int ct_qr_factor_streamed(void* A_host, int64_t m, int64_t n, int64_t lda, int p
 int ct_qr_resume(ct_factor* f, void* stream)
 {
     CT_ARG(f != nullptr && f->st != nullptr, 1, "f (a streamed factor)");
+    CT_ARG(!f->st->broken, 1, "f (a tile's write-back to the host matrix failed; the factorization cannot resume)");
     if (f->st->next_tile >= f->st->ntiles) return 0;
     hipStream_t s = (hipStream_t)stream;
     return f->f64 ? stream_factor<double>(f, s) : stream_factor<float>(f, s);
@@ -1703,9 +1737,10 @@ int ct_debug_block_width(int nb_out)
     return 0;
 }
 
-int ct_stream_inject_failure(int64_t tile)
+int ct_stream_inject_failure(int64_t tile, int64_t after_updates)
 {
-    g_inject_fail_tile = tile;
+    g_inject_tile = tile;
+    g_inject_after = tile < 0 ? -1 : after_updates;
     return 0;
 }
 
@@ -1824,6 +1859,12 @@ int ct_status(const ct_factor* f, int64_t* info, void* stream)
     CT_HIP(hipStreamSynchronize(s));
     *info = words[0];
     if (err & 1) return fail(-2001, "%s", "a cross-workgroup wait timed out during the factorization");
+    if (err & 4) {
+        // reported once: the word is cleared for later launches
+        CT_HIP(hipMemsetAsync(f->err, 0, 4, s));
+        CT_HIP(hipStreamSynchronize(s));
+        return fail(-2003, "%s", "a graph-captured solve met an invalid batch descriptor entry and solved nothing");
+    }
     return 0;
 }
 
@@ -1840,29 +1881,37 @@ struct ct_solve_graph {
     hipGraphExec_t exec;
 };
 
-int ct_solve_graph_create(const ct_factor* f, void* B, int64_t ldb, int64_t max_cols, int32_t* desc, void* stream,
-                          ct_solve_graph** out)
+int ct_solve_graph_create(const ct_factor* f, void* B, int64_t ldb, int64_t b_cols, int64_t max_cols, int32_t* desc,
+                          void* stream, ct_solve_graph** out)
 {
     CT_ARG(f != nullptr, 1, "f");
     CT_ARG(B != nullptr && aligned(B), 2, "B");
     CT_ARG(ldb >= f->m && ldb % 16 == 0, 3, "ldb");
-    CT_ARG(max_cols > 0 && max_cols <= f->max_nrhs, 4, "max_cols (1..max_nrhs)");
-    CT_ARG(desc != nullptr, 5, "desc");
-    CT_ARG(stream != nullptr, 6, "stream (capture needs a created stream)");
-    CT_ARG(out != nullptr, 7, "g");
+    CT_ARG(b_cols > 0, 4, "b_cols");
+    CT_ARG(max_cols > 0 && max_cols <= f->max_nrhs && max_cols <= b_cols, 5, "max_cols (1..min(max_nrhs, b_cols))");
+    CT_ARG(desc != nullptr, 6, "desc");
+    CT_ARG(stream != nullptr, 7, "stream (capture needs a created stream)");
+    CT_ARG(out != nullptr, 8, "g");
     CT_ARG(f->st == nullptr, 1, "f (graph-captured solves need a factor held in device memory)");
     hipStream_t s = (hipStream_t)stream;
     ct_solve_graph* g = new (std::nothrow) ct_solve_graph();
     if (!g) return fail(-1001, "%s", "out of host memory");
     CT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    int r = f->f64 ? apply_qt_impl<double>(f, (double*)B, max_cols, ldb, s, true, desc)
-                   : apply_qt_impl<float>(f, (float*)B, max_cols, ldb, s, true, desc);
+    const int32_t* rec = f->batch_rec;
+    int r = 0;
+    {
+        hipError_t e = launch_begin_batch(desc, f->batch_rec, (int)max_cols, b_cols, f->err, s);
+        if (e != hipSuccess) r = fail(-1000 - (int)e, "begin batch: %s", hipGetErrorString(e));
+    }
     if (!r)
-        r = f->f64 ? trsm_impl<double>(f, (double*)B, max_cols, ldb, s, desc)
-                   : trsm_impl<float>(f, (float*)B, max_cols, ldb, s, desc);
+        r = f->f64 ? apply_qt_impl<double>(f, (double*)B, max_cols, ldb, s, true, rec)
+                   : apply_qt_impl<float>(f, (float*)B, max_cols, ldb, s, true, rec);
+    if (!r)
+        r = f->f64 ? trsm_impl<double>(f, (double*)B, max_cols, ldb, s, rec)
+                   : trsm_impl<float>(f, (float*)B, max_cols, ldb, s, rec);
     if (!r) {
-        hipError_t e = launch_advance_batch(desc, s);
-        if (e != hipSuccess) r = -1000 - (int)e;
+        hipError_t e = launch_end_batch(desc, s);
+        if (e != hipSuccess) r = fail(-1000 - (int)e, "end batch: %s", hipGetErrorString(e));
     }
     hipGraph_t graph = nullptr;
     hipError_t ee = hipStreamEndCapture(s, &graph);

@@ -61,15 +61,17 @@ struct NtPlan {
     int split_target;
 };
 
-// Batch descriptor of a graph-captured solve: desc[0] = index of the current
-// batch, desc[2 + 2k], desc[3 + 2k] = column offset and count of batch k.
-__device__ __forceinline__ int desc_count(const int32_t* desc, int n)
+// Batch record of a graph-captured solve: the graph's first node checks the
+// caller's descriptor entry of the current batch and writes rec[0] = column
+// offset, rec[1] = column count (0 for an invalid entry or a launch past the
+// last batch); every solve kernel of the graph reads only this record.
+__device__ __forceinline__ int desc_count(const int32_t* rec, int n)
 {
-    if (!desc) return n;
-    const int c = desc[3 + 2 * desc[0]];
+    if (!rec) return n;
+    const int c = rec[1];
     return c < n ? c : n;
 }
-__device__ __forceinline__ int desc_offset(const int32_t* desc) { return desc ? desc[2 + 2 * desc[0]] : 0; }
+__device__ __forceinline__ int desc_offset(const int32_t* rec) { return rec ? rec[0] : 0; }
 
 // Output tile of workgroup b in the NT update kernels.  The hardware places
 // workgroup b on XCD b % 8; with the grid padded to a multiple of 8, each XCD
@@ -95,7 +97,7 @@ __device__ __forceinline__ bool tile_of(int b, int tiles_p, int tiles_q, int& tp
 __host__ __forceinline__ int padded_tiles(int nt) { return (nt + 7) / 8 * 8; }
 
 struct ErrWord {
-    // bit 0: barrier spin limit hit; bit 1: CSR capacity exceeded; bit 2: invalid batch descriptor
+    // bit 0: barrier spin limit hit; bit 1: CSR capacity exceeded; bit 2: invalid batch descriptor entry
     int32_t flags;
 };
 

@@ -38,9 +38,9 @@ struct NtArgs {
     int64_t K, kslice;
     int tiles_p, tiles_q;
     int sub;         // 0: out = acc (split slice z at out + z*ostride), 1: out -= acc
-    // optional device batch descriptor (desc[0] = current batch k; batch k
-    // has column offset desc[2+2k] and count desc[3+2k]): Q is clipped to the
-    // count, and Y (desc_y) or out (desc_out) start at the offset
+    // optional batch record of a graph-captured solve (desc[0] = column
+    // offset, desc[1] = column count of the current batch): Q is clipped to
+    // the count, and Y (desc_y) or out (desc_out) start at the offset
     const int32_t* desc;
     int desc_y, desc_out;
     // X is a reflector block read in place (column p of the block from its
@@ -61,8 +61,7 @@ struct NtArgs {
 __device__ __forceinline__ void apply_desc(const NtArgs& a, int& Q, const char*& Y, size_t ysz, char*& out, size_t osz)
 {
     if (a.desc) {
-        const int cur = a.desc[0];
-        const int off = a.desc[2 + 2 * cur], cnt = a.desc[3 + 2 * cur];
+        const int off = a.desc[0], cnt = a.desc[1];
         if (cnt < Q) Q = cnt;
         if (a.desc_y) Y += (size_t)off * a.ldy * ysz;
         if (a.desc_out) out += (size_t)off * a.ldo * osz;

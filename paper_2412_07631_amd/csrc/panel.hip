@@ -953,20 +953,32 @@ hipError_t launch_panel(TS* A, int64_t lda, int64_t mk, int nbp, int rw, double*
     // for the panel rows plus 16 for the top block)
     const bool cq = g_cqr && nbp <= 32 && rq <= 448 && cqr_lds_bytes((int)rq) <= g_lds_max &&
                     cq_lanes_ok((int)((mk + rq - 1) / rq));
+    // Every workgroup of a panel waits for the others' published sums, so all
+    // of them must be resident at once.  A cooperative launch guarantees that
+    // or refuses the grid (hipErrorCooperativeLaunchTooLarge) instead of
+    // scheduling part of it, which would leave the waits to time out.
+    void* kargs[] = {&a};
+    hipError_t e = hipErrorCooperativeLaunchTooLarge;
     if (cq) {
         a.rw = (int)rq;
         a.P = (int)((mk + rq - 1) / rq);
-        hipLaunchKernelGGL(panel_cqr_kernel<TS>, dim3(a.P), dim3(256), cqr_lds_bytes(a.rw), s, a);
-        *base += (uint64_t)a.P * (uint64_t)nbp;
-        *cq_count += 1;
-    } else {
+        e = hipLaunchCooperativeKernel((const void*)panel_cqr_kernel<TS>, dim3(a.P), dim3(256), kargs,
+                                       (unsigned)cqr_lds_bytes(a.rw), s);
+        if (e == hipSuccess) *cq_count += 1;
+        else if (e == hipErrorCooperativeLaunchTooLarge) (void)hipGetLastError();
+        else return e;
+    }
+    if (e != hipSuccess) {
+        // the column-wise form (one reduction per column, smaller LDS panel)
         a.rw = rw;
         a.P = (int)((mk + rw - 1) / rw);
-        hipLaunchKernelGGL(panel_qr_kernel<TS>, dim3(a.P), dim3(256), panel_lds_bytes(nbp, rw), s, a);
-        *base += (uint64_t)a.P * (uint64_t)nbp;
+        e = hipLaunchCooperativeKernel((const void*)panel_qr_kernel<TS>, dim3(a.P), dim3(256), kargs,
+                                       (unsigned)panel_lds_bytes(nbp, rw), s);
+        if (e != hipSuccess) return e;
     }
+    *base += (uint64_t)a.P * (uint64_t)nbp;
     *col_base += (uint64_t)nbp;
-    return hipGetLastError();
+    return hipSuccess;
 }
 
 
@@ -982,6 +994,8 @@ hipError_t panel_set_max_lds(size_t bytes)
     return hipSuccess;
 }
 
+// Workgroups of the column-wise panel kernel (at `shmem` bytes of LDS) that
+// one compute unit holds at once, the smaller of the two storage types.
 hipError_t panel_max_active(int* per_cu, size_t shmem)
 {
     int a = 0, b = 0;

@@ -19,9 +19,8 @@ __global__ void __launch_bounds__(256) trsm_diag_kernel(const TS* __restrict__ R
 {
     extern __shared__ double Rs[];
     if (desc) {
-        const int cur = desc[0];
-        B += (int64_t)desc[2 + 2 * cur] * ldb;
-        if (desc[3 + 2 * cur] < nrhs) nrhs = desc[3 + 2 * cur];
+        B += (int64_t)desc_offset(desc) * ldb;
+        nrhs = desc_count(desc, nrhs);
     }
     if (blockIdx.x * 4 >= nrhs) return;
     const int ld = bo + 1;
@@ -646,12 +645,43 @@ template hipError_t launch_copy_block<double>(const double*, int64_t, double*, i
 template hipError_t launch_copy_block<float>(const float*, int64_t, float*, int64_t, int, int, hipStream_t,
                                              const int32_t*);
 
-// Advance the batch cursor of a graph-captured solve (last node of the graph).
-__global__ void advance_batch_kernel(int32_t* desc) { desc[0] += 1; }
-
-hipError_t launch_advance_batch(int32_t* desc, hipStream_t s)
+// First node of a graph-captured solve: check the caller's descriptor
+// [cur, nbatch, off_0, cnt_0, off_1, cnt_1, ...] at the current batch and
+// write the batch record rec = (offset, count) that the solve kernels read.
+// An entry outside 0 <= off, 0 <= cnt <= max_cols, off + cnt <= b_cols, or a
+// launch past the last batch, gives count 0 (the launch solves nothing) and
+// sets bit 2 of the error word.
+__global__ void begin_batch_kernel(const int32_t* desc, int32_t* rec, int max_cols, int64_t b_cols, int32_t* err)
 {
-    hipLaunchKernelGGL(advance_batch_kernel, dim3(1), dim3(1), 0, s, desc);
+    const int cur = desc[0], nb = desc[1];
+    int off = 0, cnt = 0;
+    bool ok = cur >= 0 && cur < nb;
+    if (ok) {
+        off = desc[2 + 2 * cur];
+        cnt = desc[3 + 2 * cur];
+        ok = off >= 0 && cnt >= 0 && cnt <= max_cols && (int64_t)off + cnt <= b_cols;
+    }
+    rec[0] = ok ? off : 0;
+    rec[1] = ok ? cnt : 0;
+    if (!ok) __hip_atomic_fetch_or(err, 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Last node: advance the batch cursor, never past the batch count.
+__global__ void end_batch_kernel(int32_t* desc)
+{
+    if (desc[0] >= 0 && desc[0] < desc[1]) desc[0] += 1;
+}
+
+hipError_t launch_begin_batch(const int32_t* desc, int32_t* rec, int max_cols, int64_t b_cols, int32_t* err,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(begin_batch_kernel, dim3(1), dim3(1), 0, s, desc, rec, max_cols, b_cols, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_end_batch(int32_t* desc, hipStream_t s)
+{
+    hipLaunchKernelGGL(end_batch_kernel, dim3(1), dim3(1), 0, s, desc);
     return hipGetLastError();
 }
 

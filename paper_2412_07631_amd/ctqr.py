@@ -56,7 +56,7 @@ _sig("ct_qr_factor_streamed", [_vp, _i64, _i64, _i64, ctypes.c_int, _vp, _vp, _s
                                _vp])
 _sig("ct_qr_resume", [_vp, _vp])
 _sig("ct_stream_info", [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)])
-_sig("ct_stream_inject_failure", [_i64])
+_sig("ct_stream_inject_failure", [_i64, _i64])
 _sig("ct_debug_wait_limit", [_i64])
 _sig("ct_debug_panel_cholesky", [ctypes.c_int])
 _sig("ct_debug_block_width", [ctypes.c_int])
@@ -89,7 +89,7 @@ class Profile(ctypes.Structure):
 _sig("ct_profile_begin", [])
 _sig("ct_profile_end", [ctypes.POINTER(Profile)])
 _sig("ct_status", [_vp, ctypes.POINTER(_i64), _vp])
-_sig("ct_solve_graph_create", [_vp, _vp, _i64, _i64, _vp, _vp, ctypes.POINTER(_vp)])
+_sig("ct_solve_graph_create", [_vp, _vp, _i64, _i64, _i64, _vp, _vp, ctypes.POINTER(_vp)])
 _sig("ct_solve_graph_launch", [_vp, _vp])
 _sig("ct_solve_graph_destroy", [_vp])
 _sig("ct_autotune_solve", [_vp, _vp, _i64, _i64, ctypes.c_char_p, _vp])
@@ -264,8 +264,11 @@ def stream_info(f: Factor):
     return a.value, b.value, c.value
 
 
-def inject_failure(tile: int):
-    _check(_lib.ct_stream_inject_failure(tile))
+def inject_failure(tile: int, after_updates: int = -1):
+    """Make the next streamed factorization stop at `tile` as if a copy had
+    failed: before the tile's work (after_updates < 0) or after the reflector
+    blocks of that many earlier tiles have been applied to it."""
+    _check(_lib.ct_stream_inject_failure(tile, after_updates))
 
 
 def debug_wait_limit(ticks: int):
@@ -380,8 +383,9 @@ def solve_refined(f: Factor, sp: SparseA, B: torch.Tensor, X: torch.Tensor, step
 
 def batch_descriptor(sizes, device="cuda"):
     """Device descriptor for a list of batch sizes laid out back to back:
-    [current batch, 0, offset_0, count_0, offset_1, count_1, ...] (int32)."""
-    d = [0, 0]
+    [current batch, batch count, offset_0, count_0, offset_1, count_1, ...]
+    (int32)."""
+    d = [0, len(sizes)]
     off = 0
     for c in sizes:
         d += [off, int(c)]
@@ -399,8 +403,8 @@ class SolveGraph:
         self.stream = st
         h = _vp()
         with torch.cuda.stream(st):
-            _check(_lib.ct_solve_graph_create(f.handle, _ptr(B), B.shape[1], int(max_cols), _ptr(desc),
-                                              _vp(st.cuda_stream), ctypes.byref(h)))
+            _check(_lib.ct_solve_graph_create(f.handle, _ptr(B), B.shape[1], B.shape[0], int(max_cols),
+                                              _ptr(desc), _vp(st.cuda_stream), ctypes.byref(h)))
         self.handle = h
 
     def launch(self, stream=None):

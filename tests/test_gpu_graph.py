@@ -90,3 +90,42 @@ def test_autotuner_keeps_results_correct(setup, tmp_path):
     ctqr.trsm_solve(f, Bd)
     X = Bd[:, :sc.n].double().cpu().numpy().T
     assert max_col_rel(X, O.solve(VR, tau, B[:, :9])) <= 1e-4
+
+
+def test_graph_launch_past_end_and_invalid_entry_solve_nothing(setup):
+    """A launch after the last batch, and one whose entry lies outside B or
+    exceeds the graph's column cap, leave B untouched; ct_status then reports
+    -2003 once.  The cursor never moves past the batch count."""
+    ctqr, sc, A, VR, tau, f, B = setup
+    cols = 12
+    Bd = torch.zeros((cols, ld16(sc.m)), dtype=torch.float32, device="cuda")
+    Bd[:, :sc.m] = torch.from_numpy(np.ascontiguousarray(B[:, :cols].T)).to("cuda", torch.float32)
+    desc = ctqr.batch_descriptor([4, 8])
+    g = ctqr.SolveGraph(f, Bd, 8, desc)
+    for _ in range(2):
+        g.launch(g.stream)
+    g.stream.synchronize()
+    assert int(desc[0].item()) == 2
+    assert ctqr.status(f) == 0
+    solved = Bd.clone()
+    # two launches past the end: nothing changes, the cursor stays at 2
+    for _ in range(2):
+        g.launch(g.stream)
+    g.stream.synchronize()
+    assert int(desc[0].item()) == 2
+    assert torch.equal(Bd, solved)
+    with pytest.raises(ctqr.CtError) as ei:
+        ctqr.status(f)
+    assert ei.value.code == -2003
+    assert ctqr.status(f) == 0                     # reported once
+    # entries outside B (offset + count > columns) or above the cap of 8
+    for bad in ([[6, 7]], [[0, 9]], [[-1, 2]]):
+        d = torch.tensor([0, 1] + bad[0], dtype=torch.int32, device="cuda")
+        gb = ctqr.SolveGraph(f, Bd, 8, d)
+        gb.launch(gb.stream)
+        gb.stream.synchronize()
+        assert torch.equal(Bd, solved), bad
+        assert int(d[0].item()) == 1
+        with pytest.raises(ctqr.CtError) as ei:
+            ctqr.status(f)
+        assert ei.value.code == -2003

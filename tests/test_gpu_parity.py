@@ -190,7 +190,8 @@ def test_qr_f64_matches_oracle(ct, name, panel_path):
 @pytest.mark.parametrize("name", ["ragged", "multi"])
 def test_qr_f32_matches_oracle(ct, name, panel_path):
     """FP32 storage, FP32 updates, FP64 panels: R against the oracle's within
-    the FP32 rounding of the updates (kappa(A) u32 ~ 1e-5 here)."""
+    the FP32 rounding of the updates.  kappa(A) u32 is about 8e-6 for these
+    systems (kappa 134 at 3360 x 2304); measured 3e-7..4e-7."""
     sc, A, VR, tau = problem(name)
     Ad = gpu_system(ct, sc, torch.float32)
     f = ct.qr_factor(Ad, sc.m, sc.n, ct.PREC_F32, max_nrhs=8)
@@ -199,9 +200,10 @@ def test_qr_f32_matches_oracle(ct, name, panel_path):
     n = sc.n
     R, Rg = np.triu(VR[:n]), np.triu(VRg[:n])
     err = np.max(np.abs(Rg - R)) / np.max(np.abs(R))
-    print("FP32 R max error / max |R|: %.3g" % err)
-    assert err <= 1e-4
-    assert np.max(np.abs(f.tau.cpu().numpy() - tau)) <= 1e-4
+    etau = float(np.max(np.abs(f.tau.cpu().numpy() - tau)))
+    print("FP32 R max error / max |R|: %.3g, tau %.3g" % (err, etau))
+    assert err <= 4e-6
+    assert etau <= 1e-5
 
 
 @pytest.mark.parametrize("nb", [64, 96, 512, 768, 1024])

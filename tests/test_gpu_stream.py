@@ -145,6 +145,30 @@ def test_streamed_resume_after_injected_failure(ct):
     assert torch.equal(Ah, ref) and torch.equal(f.tau.cpu(), f0.tau.cpu())
 
 
+@pytest.mark.parametrize("resident,tile,after", [(4, 3, 2), (4, 6, 4), (1, 5, 5), (1, 7, 0)])
+def test_streamed_resume_after_failure_inside_a_tile(ct, resident, tile, after):
+    """A failure injected after some earlier reflector blocks have been
+    applied to a tile -- a resident one (tile < resident) or one held in a
+    staging slot -- leaves the tile partly updated on the device; the resume
+    redoes it from its untouched host copy and gives bitwise the
+    uninterrupted factor."""
+    sc, _, _, _ = problem("multi")
+    dev_bytes = budget(ct, sc, ct.PREC_F64, 256, resident, 1)
+    ref = host_system(ct, sc, torch.float64)
+    f0 = ct.qr_factor_streamed(ref, sc.m, sc.n, ct.PREC_F64, tile_cols=256, device_bytes=dev_bytes, max_nrhs=1)
+    assert ct.status(f0) == 0 and ct.stream_info(f0)[1] == resident
+    Ah = host_system(ct, sc, torch.float64)
+    ct.inject_failure(tile, after)
+    with pytest.raises(ct.CtError) as ei:
+        ct.qr_factor_streamed(Ah, sc.m, sc.n, ct.PREC_F64, tile_cols=256, device_bytes=dev_bytes, max_nrhs=1)
+    assert ei.value.code == -2002
+    f = ei.value.factor
+    assert ct.stream_info(f)[2] == tile
+    ct.qr_resume(f)
+    assert ct.status(f) == 0 and ct.stream_info(f)[2] == ct.stream_info(f)[0]
+    assert torch.equal(Ah, ref) and torch.equal(f.tau.cpu(), f0.tau.cpu())
+
+
 def test_streamed_rank_deficient_column_reported(ct):
     sc, _, _, _ = problem("ragged")
     Ah = host_system(ct, sc, torch.float64)
