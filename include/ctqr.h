@@ -237,6 +237,21 @@ int ct_solve_refined(const ct_factor* f, const ct_sparse* A, const double* B, in
                      int64_t ldx, int64_t nrhs, int32_t steps, int32_t method, void* scratch,
                      size_t scratch_bytes, double* res_norms, double* grad_norms, void* stream);
 
+/* ct_solve_refined without a scratch argument, for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and errors as
+ * ct_solve_refined, whose kernels it runs; its scratch is a statically
+ * allocated 128 MiB device array, one per GPU, held until the process ends
+ * (up to 40 slices at 256^2 with 76800 rays, 160 at 128^2 with 23040).
+ * A call whose ct_refine_workspace size exceeds 128 MiB returns -7 (nrhs) and
+ * launches nothing.  The call itself allocates nothing (no hipMalloc, no
+ * library allocation).  Every call on a GPU shares that GPU's array: calls
+ * that overlap on one GPU (different streams or host threads without
+ * ordering) race on it and must be serialized by the caller. */
+int ct_solve_refined_noalloc(const ct_factor* f, const ct_sparse* A, const double* B, int64_t ldb, double* X,
+                             int64_t ldx, int64_t nrhs, int32_t steps, int32_t method, double* res_norms,
+                             double* grad_norms, void* stream);
+
 /* Waits for `stream`, then reports the factor's numerical status: *info = 0
  * for full column rank, j + 1 if column j had a zero Householder norm.
  * Returns -2001 if a cross-workgroup wait of the factorization timed out, and

@@ -11,6 +11,7 @@
 #include <string.h>
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1845,6 +1846,59 @@ int ct_solve_refined(const ct_factor* f, const ct_sparse* sp, const double* B, i
                                          grad_norms, s)
                   : refined_impl<float>(f, sp, B, ldb, X, ldx, nrhs, steps, method, (char*)scratch, res_norms,
                                         grad_norms, s);
+}
+
+}  // extern "C"
+
+// Scratch of ct_solve_refined_noalloc: one statically allocated array per
+// device (the loader reserves it with the code object; it lives until the
+// process ends).  Host code never uses the symbol itself as an address: the
+// device address comes from hipGetSymbolAddress, once per device, with that
+// device current.
+constexpr size_t kStaticScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+static int static_scratch(void** out)
+{
+    int dev = 0;
+    CT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(-2004, "device %d beyond the static scratch table", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        CT_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(-2004, "%s", "static scratch has no device address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return 0;
+}
+
+extern "C" {
+
+int ct_solve_refined_noalloc(const ct_factor* f, const ct_sparse* sp, const double* B, int64_t ldb, double* X,
+                             int64_t ldx, int64_t nrhs, int32_t steps, int32_t method, double* res_norms,
+                             double* grad_norms, void* stream)
+{
+    CT_ARG(f != nullptr, 1, "f");
+    CT_ARG(nrhs >= 0 && nrhs <= f->max_nrhs, 7, "nrhs (0..max_nrhs)");
+    size_t need = 0;
+    ct_refine_workspace(f->m, f->n, nrhs, &need);
+    if (need > kStaticScratchBytes)
+        return fail(-7, "invalid argument nrhs: %lld slices need %zu bytes of scratch, above the %zu-byte static "
+                        "scratch of ct_solve_refined_noalloc", (long long)nrhs, need, kStaticScratchBytes);
+    void* ptr = nullptr;
+    int r = static_scratch(&ptr);
+    if (r) return r;
+    // every word of the scratch is written before it is read (the slice
+    // blocks by transposes and products, the norm partials by their first
+    // pass), so nothing left by an earlier call needs clearing
+    return ct_solve_refined(f, sp, B, ldb, X, ldx, nrhs, steps, method, ptr, kStaticScratchBytes, res_norms,
+                            grad_norms, stream);
 }
 
 int ct_status(const ct_factor* f, int64_t* info, void* stream)

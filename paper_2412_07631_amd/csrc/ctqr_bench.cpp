@@ -146,6 +146,7 @@ int main(int argc, char** argv)
         printf("streamed: info %lld tiles %lld resident %lld device %.2f GiB of %.2f (A %.2f GiB) qr_ms %.1f "
                "qr_tflops %.2f\n", (long long)info, (long long)tiles, (long long)res, wb / 1073741824.0,
                full / 1073741824.0, (double)n * lda * es / 1073741824.0, ms, fl / (ms * 1e-3) / 1e12);
+        fflush(stdout);
         CT_OK(ct_factor_destroy(f));
         HIP_OK(hipFree(work));
         HIP_OK(hipFree(tau));
@@ -194,6 +195,7 @@ int main(int argc, char** argv)
     const double fl = 2.0 * m * (double)n * n - 2.0 * (double)n * n * n / 3.0;
     printf("info %lld qr_ms %.1f qr_tflops %.2f solve_ms %.2f\n", (long long)info, qr_ms, fl / (qr_ms * 1e-3) / 1e12,
            sol_ms);
+    fflush(stdout);
     CT_OK(ct_factor_destroy(f));
     HIP_OK(hipFree(A));
     HIP_OK(hipFree(tau));

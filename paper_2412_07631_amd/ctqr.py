@@ -81,6 +81,10 @@ class Sparse(ctypes.Structure):
 
 _sig("ct_solve_refined", [_vp, ctypes.POINTER(Sparse), _vp, _i64, _vp, _i64, _i64, _i32, _i32, _vp, _sz, _vp, _vp,
                           _vp])
+_sig("ct_solve_refined_noalloc", [_vp, ctypes.POINTER(Sparse), _vp, _i64, _vp, _i64, _i64, _i32, _i32, _vp, _vp,
+                                  _vp])
+
+
 class Profile(ctypes.Structure):
     _fields_ = [("launches", _i64 * 2), ("ms", ctypes.c_double * 2), ("flop", ctypes.c_double * 2),
                 ("bytes", ctypes.c_double * 2)]
@@ -378,6 +382,17 @@ def solve_refined(f: Factor, sp: SparseA, B: torch.Tensor, X: torch.Tensor, step
     _check(_lib.ct_solve_refined(f.handle, ctypes.byref(sp.struct), _ptr(B), B.shape[1], _ptr(X), X.shape[1], nrhs,
                                  int(steps), int(method), _ptr(scratch), scratch.numel(), _ptr(res_norms),
                                  _ptr(grad_norms), _stream(stream)))
+    return X
+
+
+def solve_refined_noalloc(f: Factor, sp: SparseA, B: torch.Tensor, X: torch.Tensor, steps: int,
+                          method: int = REFINE_SNE, nrhs: int = None, res_norms: torch.Tensor = None,
+                          grad_norms: torch.Tensor = None, stream=None):
+    """solve_refined with the library's static scratch (allocates nothing)."""
+    nrhs = B.shape[0] if nrhs is None else nrhs
+    _check(_lib.ct_solve_refined_noalloc(f.handle, ctypes.byref(sp.struct), _ptr(B), B.shape[1], _ptr(X), X.shape[1],
+                                         nrhs, int(steps), int(method), _ptr(res_norms), _ptr(grad_norms),
+                                         _stream(stream)))
     return X
 
 
