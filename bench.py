@@ -416,9 +416,12 @@ def main():
              "bf16": "gemm_nt_lp_kernel<2, %s, false, false>", "f16": "gemm_nt_lp_kernel<3, %s, false, false>",
              "bf16x3": "gemm_nt_lp_kernel<4, %s>"}[args.prec]
     if args.prec == "bf16x3":
-        # both operands of C -= V W' and V of W = V^T C arrive split into bfloat16 halves
-        kname = (tname % "true, true, true") + " (C -= V W')" if dom == "update_cvw" else \
-            (tname % "false, true, false") + " (W = V^T C)"
+        # 1024-wide blocks: the direct-to-LDS kernel on 256 x 256 tiles; both
+        # operands of C -= V W' arrive split into bfloat16 halves, V of
+        # W = V^T C too, while C is split as it is read
+        tname = "gemm_x3_dl_kernel<DlCfg<8, 4, 2, 4, 2, 1>, %s>"
+        kname = (tname % "true, false") + " (C -= V W')" if dom == "update_cvw" else \
+            (tname % "false, true") + " (W = V^T C)"
     else:
         kname = (tname % "true") + " (C -= V W')" if dom == "update_cvw" else (tname % "false") + " (W = V^T C)"
     # the kernel's own bound: its algorithmic flop per algorithmic byte

@@ -63,6 +63,13 @@ template <int MODE>
 hipError_t launch_nt_lp(const void* X, int64_t ldx, const void* Y, int64_t ldy, float* out, int64_t ldo, int64_t P,
                         int Q, int64_t K, bool sub, int64_t ocap, int* nz_out, hipStream_t s,
                         const void* Xlo = nullptr, const void* Ylo = nullptr);
+hipError_t launch_nt_x3dl(const void* Xh, const void* Xl, int64_t ldx, const void* Yh, const void* Yl, int64_t ldy,
+                          float* out, int64_t ldo, int64_t P, int Q, int64_t K, bool sub, int64_t ocap, int* nz_out,
+                          hipStream_t s);
+// the direct-to-LDS BF16x3 products take blocks of at least this many
+// reflectors (narrower ones would leave most of a 256-row tile empty)
+constexpr int kX3dlMinWidth = 256;
+void nt_set_cus(int cus);
 hipError_t launch_split_x3(const float* src, int64_t lds, void* hi, void* lo, int64_t ldd, int64_t rows, int64_t cols,
                            hipStream_t s);
 template <typename TS, bool UPPER>
@@ -154,6 +161,7 @@ static int device_setup()
     CT_HIP(hipGetDeviceProperties(&p, dev));
     g_dev.cus = p.multiProcessorCount;
     panel_set_cus(g_dev.cus);
+    nt_set_cus(g_dev.cus);
     size_t want = 160 * 1024;
     if (p.maxSharedMemoryPerMultiProcessor > 0 && (size_t)p.maxSharedMemoryPerMultiProcessor < want)
         want = p.maxSharedMemoryPerMultiProcessor;
@@ -398,8 +406,12 @@ static int larfb_nt(ct_factor* f, int64_t mk, int nbv, const double* T, int64_t 
                 char* hi = (char*)f->S3;
                 char* lo = hi + (size_t)o.ldvm * nbv * 2;
                 CT_HIP(launch_split_x3((const float*)o.vm, o.ldvm, hi, lo, o.ldvm, mk, nbv, s));
-                CT_HIP(launch_nt_lp<M_BF16X3>(hi, o.ldvm, C, ldc, (float*)f->Wp, nbv, nbv, nc, mk, false,
-                                              f->wp_elems * 2, &nz, s, lo, nullptr));
+                if (nbv >= kX3dlMinWidth)
+                    CT_HIP(launch_nt_x3dl(hi, lo, o.ldvm, C, nullptr, ldc, (float*)f->Wp, nbv, nbv, nc, mk, false,
+                                          f->wp_elems * 2, &nz, s));
+                else
+                    CT_HIP(launch_nt_lp<M_BF16X3>(hi, o.ldvm, C, ldc, (float*)f->Wp, nbv, nbv, nc, mk, false,
+                                                  f->wp_elems * 2, &nz, s, lo, nullptr));
             } else {
                 CT_HIP((nt_any<TS, MODE>((const TS*)o.vm, o.ldvm, C, ldc, (TS*)f->Wp, nbv, nbv, nc, mk, false,
                                          f->wp_elems * 8 / (int64_t)sizeof(TS), &nz, s)));
@@ -448,7 +460,10 @@ static int larfb_nt(ct_factor* f, int64_t mk, int nbv, const double* T, int64_t 
             char* wl = wh + (size_t)ldw * nc * 2;
             CT_HIP(launch_split_x3((const float*)o.vt, o.ldvt, vh, vl, o.ldvt, o.ldvt, mk, s));
             CT_HIP(launch_split_x3((const float*)f->Wq, ldw, wh, wl, ldw, ldw, nc, s));
-            CT_HIP(launch_nt_lp<M_BF16X3>(vh, o.ldvt, wh, ldw, C, ldc, mk, nc, nbv, true, 0, &nz2, s, vl, wl));
+            if (nbv >= kX3dlMinWidth)
+                CT_HIP(launch_nt_x3dl(vh, vl, o.ldvt, wh, wl, ldw, C, ldc, mk, nc, nbv, true, 0, &nz2, s));
+            else
+                CT_HIP(launch_nt_lp<M_BF16X3>(vh, o.ldvt, wh, ldw, C, ldc, mk, nc, nbv, true, 0, &nz2, s, vl, wl));
         } else
             CT_HIP((nt_any<TS, MODE>((const TS*)o.vt, o.ldvt, (const TS*)f->Wq, ldw, C, ldc, mk, nc, nbv, true, 0,
                                      &nz2, s)));

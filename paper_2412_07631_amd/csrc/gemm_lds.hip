@@ -766,4 +766,378 @@ template hipError_t launch_nt_lp<M_F16>(const void*, int64_t, const void*, int64
 template hipError_t launch_nt_lp<M_BF16X3>(const void*, int64_t, const void*, int64_t, float*, int64_t, int64_t, int,
                                            int64_t, bool, int64_t, int*, hipStream_t, const void*, const void*);
 
+
+// ---------------------------------------------------------------------------
+// BF16x3 NT product whose two operands both come split into bfloat16 high and
+// low planes (the block-reflector update C -= V W' of the factorization, and
+// W = V^T C when the trailing matrix is kept split as well), staged into LDS
+// by direct global->LDS loads (global_load_lds_dwordx4): no staging
+// registers and no conversion.
+//
+// A stage holds, for each half of each operand, the tile's rows as 64-byte
+// records (K step 32) in 1 KB blocks of 16 rows; one load instruction of a
+// wavefront fills one block (lane l writes bytes 16 l .. 16 l + 15), and lane
+// l fetches chunk (l & 3) ^ ((r >> 1) & 3) of row r = l >> 2, so that the
+// sixteen rows a fragment read touches spread over all banks.  The stages
+// form a ring: while one is multiplied the next ones are in flight, and one
+// barrier per K step both publishes a landed stage and frees the stage read
+// in the previous step.
+template <int WTP_, int WTQ_, int WVP_, int WVQ_, int ST_, int CH_>
+struct DlCfg {
+    static constexpr int WTP = WTP_, WTQ = WTQ_;       // 16 x 16 blocks of one wavefront (P, Q)
+    static constexpr int WVP = WVP_, WVQ = WVQ_;       // wavefronts along P, Q
+    static constexpr int ST = ST_;                     // LDS stages
+    static constexpr int CH = CH_;                     // row blocks per chunk of the subtracting epilogue
+    static constexpr int NW = WVP * WVQ, NT = 64 * NW;
+    static constexpr int BP = 16 * WTP * WVP, BQ = 16 * WTQ * WVQ, BK = 32;
+    static constexpr int XHALF = BP * BK * 2, YHALF = BQ * BK * 2;
+    static constexpr int STAGE = 2 * XHALF + 2 * YHALF;
+    static constexpr int XBLK = 2 * BP / 16, YBLK = 2 * BQ / 16;   // 1 KB blocks per stage
+    static constexpr int LPW = (XBLK + YBLK) / NW;                 // load instructions per wavefront per stage
+    static_assert((XBLK + YBLK) % NW == 0, "stage blocks must split evenly over the wavefronts");
+    static_assert(WTP % CH == 0, "epilogue chunks");
+    static constexpr int LDS = ST * STAGE;
+};
+// 256 x 128 tile, 8 wavefronts of 64 x 64, 3 stages (144 KB of LDS)
+using DlSmall = DlCfg<4, 4, 4, 2, 3, 4>;
+// 256 x 256 tile, 8 wavefronts of 128 x 64, 2 stages (128 KB): a quarter less
+// LDS traffic per MFMA than 64 x 64 wavefront tiles
+using DlBig = DlCfg<8, 4, 2, 4, 2, 1>;
+
+// Row records of a stage (the 16-byte chunks of a row are permuted by an XOR
+// with a function of the row's place in its 16-row group, so that the rows a
+// fragment read touches spread over all LDS banks):
+//   bfloat16 halves: 64-byte rows, 16 rows per 1 KB block
+//   FP32 operand:   128-byte rows, 8 rows per 1 KB block
+__device__ __forceinline__ int dl_swz16(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+__device__ __forceinline__ int dl_swz32(int r) { return (r ^ (r >> 3)) & 7; }
+
+constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | 0xF70; }
+
+// YF32: Y is FP32 (the trailing matrix in W = V^T C), loaded into LDS as is
+// and split into its bfloat16 halves when the fragments are read
+// (hi = bf16(y), lo = bf16(y - hi), round to nearest even, as everywhere).
+template <class CF, bool SUB, bool YF32>
+__global__ void __launch_bounds__(CF::NT, 1) gemm_x3_dl_kernel(NtArgs a)
+{
+    extern __shared__ __attribute__((aligned(1024))) char dl_lds[];
+    int tp, tq;
+    if (!tile_of(blockIdx.x, a.tiles_p, a.tiles_q, tp, tq)) return;
+    const int64_t p0 = (int64_t)tp * CF::BP;
+    const int q0 = tq * CF::BQ;
+    const int64_t kbeg = (int64_t)blockIdx.y * a.kslice;
+    int64_t kend = kbeg + a.kslice;
+    if (kend > a.K) kend = a.K;
+
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+
+    // this lane's part of the wavefront's load instructions (wavefront wv
+    // fills blocks LPW wv .. LPW wv + LPW - 1 of the stage: X's high half,
+    // X's low half, then Y); rows past P / Q read the last row (the products
+    // they feed are not stored).  src: byte address at k = 0; ksh: log2 of
+    // the element size; kk0: the first k of this lane's chunk.
+    const char* src[CF::LPW];
+    int dst[CF::LPW], ksh[CF::LPW], kk0[CF::LPW];
+#pragma unroll
+    for (int i = 0; i < CF::LPW; ++i) {
+        const int idx = CF::LPW * wv + i;
+        if (idx < CF::XBLK) {
+            const int h = idx / (CF::BP / 16), rb = idx % (CF::BP / 16);
+            const int r = lane >> 2, ch = (lane & 3) ^ dl_swz16(r);
+            int64_t p = p0 + rb * 16 + r;
+            if (p >= a.P) p = a.P - 1;
+            src[i] = (const char*)(h ? a.Xlo : a.X) + (p * a.ldx + ch * 8) * 2;
+            dst[i] = h * CF::XHALF + rb * 1024;
+            ksh[i] = 1;
+            kk0[i] = ch * 8;
+        } else if constexpr (!YF32) {
+            const int y = idx - CF::XBLK, h = y / (CF::BQ / 16), rb = y % (CF::BQ / 16);
+            const int r = lane >> 2, ch = (lane & 3) ^ dl_swz16(r);
+            int q = q0 + rb * 16 + r;
+            if (q >= a.Q) q = a.Q - 1;
+            src[i] = (const char*)(h ? a.Ylo : a.Y) + ((int64_t)q * a.ldy + ch * 8) * 2;
+            dst[i] = 2 * CF::XHALF + h * CF::YHALF + rb * 1024;
+            ksh[i] = 1;
+            kk0[i] = ch * 8;
+        } else {
+            const int blk = idx - CF::XBLK;            // 8 rows of 128 bytes
+            const int r = lane >> 3, ch = (lane & 7) ^ dl_swz32((blk & 1) * 8 + r);
+            int q = q0 + blk * 8 + r;
+            if (q >= a.Q) q = a.Q - 1;
+            src[i] = (const char*)a.Y + ((int64_t)q * a.ldy + ch * 4) * 4;
+            dst[i] = 2 * CF::XHALF + blk * 1024;
+            ksh[i] = 2;
+            kk0[i] = ch * 4;
+        }
+    }
+    auto issue = [&](int stage, int64_t k0) {
+        char* base = dl_lds + stage * CF::STAGE;
+#pragma unroll
+        for (int i = 0; i < CF::LPW; ++i)
+            __builtin_amdgcn_global_load_lds((const void*)(src[i] + (k0 << ksh[i])),
+                                             (__attribute__((address_space(3))) void*)(base + dst[i]), 16, 0, 0);
+    };
+
+    const int c = lane & 15, g = lane >> 4;
+    const int wp = (wv / CF::WVQ) * 16 * CF::WTP, wq = (wv % CF::WVQ) * 16 * CF::WTQ;
+    const int xfrag = (c * 4 + (g ^ dl_swz16(c))) * 16;
+    const int yfrag0 = YF32 ? (c >> 3) * 1024 + (c & 7) * 128 + 16 * ((2 * g) ^ dl_swz32(c))
+                            : (c * 4 + (g ^ dl_swz16(c))) * 16;
+    const int yfrag1 = YF32 ? (c >> 3) * 1024 + (c & 7) * 128 + 16 * ((2 * g + 1) ^ dl_swz32(c)) : 0;
+    f4_t acc[CF::WTP][CF::WTQ];
+#pragma unroll
+    for (int i = 0; i < CF::WTP; ++i)
+#pragma unroll
+        for (int j = 0; j < CF::WTQ; ++j) acc[i][j] = f4_t{0, 0, 0, 0};
+
+    auto compute = [&](int stage) {
+        const char* base = dl_lds + stage * CF::STAGE;
+        __builtin_amdgcn_s_setprio(1);
+        __builtin_amdgcn_iglp_opt(0);
+        bf8_t bh[CF::WTQ], bl[CF::WTQ];
+#pragma unroll
+        for (int j = 0; j < CF::WTQ; ++j) {
+            if constexpr (YF32) {
+                const char* yb = base + 2 * CF::XHALF + (wq + 16 * j) * 128;
+                const f4_t y0 = *(const f4_t*)(yb + yfrag0);
+                const f4_t y1 = *(const f4_t*)(yb + yfrag1);
+                // pairs: one packed conversion gives both high halves, whose
+                // FP32 values are the packed word's halves moved into place
+                typedef __bf16 bf2_t __attribute__((ext_vector_type(2)));
+                typedef float f2_t __attribute__((ext_vector_type(2)));
+                u4v hp, lp;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const f2_t yv = e < 2 ? f2_t{y0[2 * e], y0[2 * e + 1]} : f2_t{y1[2 * e - 4], y1[2 * e - 3]};
+                    const uint32_t h = __builtin_bit_cast(uint32_t, __builtin_convertvector(yv, bf2_t));
+                    const f2_t hf = {__uint_as_float(h << 16), __uint_as_float(h & 0xffff0000u)};
+                    hp[e] = h;
+                    lp[e] = __builtin_bit_cast(uint32_t, __builtin_convertvector(yv - hf, bf2_t));
+                }
+                bh[j] = __builtin_bit_cast(bf8_t, hp);
+                bl[j] = __builtin_bit_cast(bf8_t, lp);
+            } else {
+                const int rb = (wq >> 4) + j;
+                bh[j] = *(const bf8_t*)(base + 2 * CF::XHALF + rb * 1024 + yfrag0);
+                bl[j] = *(const bf8_t*)(base + 2 * CF::XHALF + CF::YHALF + rb * 1024 + yfrag0);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < CF::WTP; ++i) {
+            const int rb = (wp >> 4) + i;
+            const bf8_t ah = *(const bf8_t*)(base + rb * 1024 + xfrag);
+            const bf8_t al = *(const bf8_t*)(base + CF::XHALF + rb * 1024 + xfrag);
+#pragma unroll
+            for (int j = 0; j < CF::WTQ; ++j) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+            }
+        }
+        __builtin_amdgcn_s_setprio(0);
+    };
+
+    // a last K step shorter than 32: plain loads with zero fill, written to
+    // the same layout by each lane for its own chunk
+    auto tail_stage = [&](int stage, int64_t k0) {
+        char* base = dl_lds + stage * CF::STAGE;
+#pragma unroll
+        for (int i = 0; i < CF::LPW; ++i) {
+            const char* sp = src[i] + (k0 << ksh[i]);
+            const int64_t kk = k0 + kk0[i];
+            const int ne = 16 >> ksh[i];                // elements per chunk
+            u4v v = {0, 0, 0, 0};
+            if (kk + ne <= kend) {
+                v = *(const u4v*)sp;
+            } else if (kk < kend) {
+                if (ksh[i] == 1) {
+                    uint16_t e[8];
+                    for (int u = 0; u < 8; ++u) e[u] = kk + u < kend ? ((const uint16_t*)sp)[u] : (uint16_t)0;
+                    v[0] = e[0] | ((uint32_t)e[1] << 16);
+                    v[1] = e[2] | ((uint32_t)e[3] << 16);
+                    v[2] = e[4] | ((uint32_t)e[5] << 16);
+                    v[3] = e[6] | ((uint32_t)e[7] << 16);
+                } else {
+                    for (int u = 0; u < 4; ++u) v[u] = kk + u < kend ? ((const uint32_t*)sp)[u] : 0u;
+                }
+            }
+            *(u4v*)(base + dst[i] + lane * 16) = v;
+        }
+    };
+
+    // the subtracting epilogue reads C in chunks of CH row blocks; the first
+    // chunk is fetched during the last K step
+    constexpr int CH = SUB ? CF::CH : 1;
+    f4_t cpre[CH][CF::WTQ];
+    auto load_c = [&](int i0) {
+        if constexpr (SUB) {
+            const float* O = (const float*)a.out;
+#pragma unroll
+            for (int ii = 0; ii < CH; ++ii)
+#pragma unroll
+                for (int j = 0; j < CF::WTQ; ++j) {
+                    const int q = q0 + wq + 16 * j + c;
+                    const int64_t pb = p0 + wp + 16 * (i0 + ii) + 4 * g;
+                    f4_t v = {0, 0, 0, 0};
+                    if (q < a.Q) {
+                        const float* d = O + pb + (int64_t)q * a.ldo;
+                        if (pb + 3 < a.P && (((uintptr_t)d & 15) == 0)) v = *(const f4_t*)d;
+                        else
+                            for (int r = 0; r < 4; ++r)
+                                if (pb + r < a.P) v[r] = d[r];
+                    }
+                    cpre[ii][j] = v;
+                }
+        }
+    };
+
+    const int64_t klen = kend > kbeg ? kend - kbeg : 0;
+    const int nsteps = (int)(klen / CF::BK);
+    const bool has_tail = klen % CF::BK != 0;
+#pragma unroll
+    for (int sgi = 0; sgi + 1 < CF::ST; ++sgi)
+        if (sgi < nsteps) issue(sgi, kbeg + (int64_t)sgi * CF::BK);
+    int stage = 0;
+    for (int it = 0; it < nsteps; ++it) {
+        // this wavefront's loads of step it have landed (with three stages,
+        // those of step it + 1 may still be in flight); after the barrier
+        // everyone's have, and every wavefront is done with step it - 1,
+        // whose buffer is refilled next.  (An explicit wait and a bare
+        // s_barrier: a workgroup fence would wait for every load in flight.)
+        if (CF::ST >= 3 && it + 1 < nsteps) __builtin_amdgcn_s_waitcnt(vmcnt_imm(CF::LPW));
+        else __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        if (it + CF::ST - 1 < nsteps) {
+            int nb = stage + CF::ST - 1;
+            if (nb >= CF::ST) nb -= CF::ST;
+            issue(nb, kbeg + (int64_t)(it + CF::ST - 1) * CF::BK);
+        }
+        if (SUB && it + 1 == nsteps && !has_tail) load_c(0);
+        compute(stage);
+        stage = stage + 1 == CF::ST ? 0 : stage + 1;
+    }
+    if (has_tail) {
+        __syncthreads();
+        tail_stage(stage, kbeg + (int64_t)nsteps * CF::BK);
+        __syncthreads();
+        if (SUB) load_c(0);
+        compute(stage);
+    } else if (SUB && nsteps == 0) {
+        load_c(0);
+    }
+
+    float* O = (float*)a.out;
+    if (!SUB) O += (int64_t)blockIdx.y * a.ostride;
+#pragma unroll
+    for (int i0 = 0; i0 < CF::WTP; i0 += CH) {
+        if (SUB && i0 > 0) load_c(i0);
+#pragma unroll
+        for (int ii = 0; ii < CH; ++ii)
+#pragma unroll
+            for (int j = 0; j < CF::WTQ; ++j) {
+                const int q = q0 + wq + 16 * j + c;
+                const int64_t pb = p0 + wp + 16 * (i0 + ii) + 4 * g;
+                if (q >= a.Q || pb >= a.P) continue;
+                float* d = O + pb + (int64_t)q * a.ldo;
+                f4_t v = acc[i0 + ii][j];
+                if constexpr (SUB) v = cpre[ii][j] - v;
+                if (pb + 3 < a.P && (((uintptr_t)d & 15) == 0)) {
+                    *(f4_t*)d = v;
+                } else {
+                    for (int r = 0; r < 4; ++r)
+                        if (pb + r < a.P) d[r] = v[r];
+                }
+            }
+    }
+}
+
+template <class CF>
+static hipError_t dl_set_lds()
+{
+    static bool done = false;
+    if (done) return hipSuccess;
+    const void* k[3] = {(const void*)gemm_x3_dl_kernel<CF, true, false>, (const void*)gemm_x3_dl_kernel<CF, false, false>,
+                        (const void*)gemm_x3_dl_kernel<CF, false, true>};
+    for (const void* f : k) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, CF::LDS);
+        if (e != hipSuccess) return e;
+    }
+    done = true;
+    return hipSuccess;
+}
+
+int g_x3dl_cfg = 1;   // 0: 256 x 128 tiles, 1: 256 x 256 tiles
+static int g_nt_cus = 256;
+void nt_set_cus(int cus) { if (cus > 0) g_nt_cus = cus; }
+
+// Split-K factor for a launch of `tiles` tiles (one workgroup per CU): the
+// smallest that fills the CUs' last round to at least 90 % (or the best one
+// up to 8), keeping at least 16 K steps per slice.
+static int dl_split(int tiles, int64_t K, int bk)
+{
+    int best = 1;
+    double best_eff = 0.0;
+    for (int nz = 1; nz <= 8 && K / nz >= 16 * bk; ++nz) {
+        const int64_t w = (int64_t)tiles * nz;
+        const int64_t rounds = (w + g_nt_cus - 1) / g_nt_cus;
+        const double eff = (double)w / (double)(rounds * g_nt_cus);
+        if (eff > best_eff + 1e-9) { best_eff = eff; best = nz; }
+        if (eff >= 0.9) break;
+    }
+    return best;
+}
+
+template <class CF>
+static hipError_t launch_x3dl_cfg(NtArgs& a, bool sub, bool yf32, int64_t ocap, int* nz_out, hipStream_t s)
+{
+    hipError_t e = dl_set_lds<CF>();
+    if (e != hipSuccess) return e;
+    a.tiles_p = (int)((a.P + CF::BP - 1) / CF::BP);
+    a.tiles_q = (a.Q + CF::BQ - 1) / CF::BQ;
+    a.ostride = a.ldo * (int64_t)a.Q;
+    const int tiles = a.tiles_p * a.tiles_q;
+    int nz = 1;
+    if (!sub) {
+        nz = dl_split(tiles, a.K, CF::BK);
+        while (nz > 1 && (int64_t)nz * a.ostride > ocap) --nz;
+    }
+    int64_t ks = (a.K + nz - 1) / nz;
+    ks = (ks + CF::BK - 1) / CF::BK * CF::BK;
+    nz = (int)((a.K + ks - 1) / ks);
+    if (nz < 1) nz = 1;
+    a.kslice = ks;
+    *nz_out = nz;
+    const dim3 grid(padded_tiles(tiles), nz);
+    if (sub)
+        hipLaunchKernelGGL((gemm_x3_dl_kernel<CF, true, false>), grid, dim3(CF::NT), CF::LDS, s, a);
+    else if (yf32)
+        hipLaunchKernelGGL((gemm_x3_dl_kernel<CF, false, true>), grid, dim3(CF::NT), CF::LDS, s, a);
+    else
+        hipLaunchKernelGGL((gemm_x3_dl_kernel<CF, false, false>), grid, dim3(CF::NT), CF::LDS, s, a);
+    return hipGetLastError();
+}
+
+// out (+)= X Y^T with X = Xhi + Xlo (P x K) and Y = Yhi + Ylo (Q x K), the
+// four planes bfloat16 -- or, with Yl null and not sub, Y given in FP32 at Yh
+// and split as it is read -- all K-contiguous, leading dimensions multiples
+// of 8 elements, 16-byte aligned bases.  sub: out -= X Y^T (no split-K);
+// otherwise split-K partials at out + z ldo Q, as launch_nt_lp.
+hipError_t launch_nt_x3dl(const void* Xh, const void* Xl, int64_t ldx, const void* Yh, const void* Yl, int64_t ldy,
+                          float* out, int64_t ldo, int64_t P, int Q, int64_t K, bool sub, int64_t ocap, int* nz_out,
+                          hipStream_t s)
+{
+    if (sub && !Yl) return hipErrorInvalidValue;
+    NtArgs a;
+    a.X = Xh; a.Xlo = Xl; a.ldx = ldx; a.Y = Yh; a.Ylo = Yl; a.ldy = ldy; a.out = out; a.ldo = ldo;
+    a.P = P; a.Q = Q; a.K = K; a.sub = sub ? 1 : 0;
+    a.desc = nullptr; a.desc_y = 0; a.desc_out = 0; a.maskx = 0; a.tout = 0; a.upper = 0;
+    const bool yf32 = !Yl;
+    if (g_x3dl_cfg == 1) return launch_x3dl_cfg<DlBig>(a, sub, yf32, ocap, nz_out, s);
+    return launch_x3dl_cfg<DlSmall>(a, sub, yf32, ocap, nz_out, s);
+}
+
 }  // namespace ctqr
