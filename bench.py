@@ -140,7 +140,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c3_256")
     ap.add_argument("--prec", default="bf16x3", choices=["f64", "f32", "bf16", "f16", "bf16x3"])
-    ap.add_argument("--refine", type=int, default=4, help="refinement steps")
+    ap.add_argument("--refine", type=int, default=6, help="refinement steps at most")
+    ap.add_argument("--tol", type=float, default=1e-8,
+                    help="stop rule: end the refinement once every slice's correction is at most tol relative to "
+                         "its image (0: always run --refine steps); the stated bound of the mixed path's image "
+                         "error against the FP64 path")
     ap.add_argument("--method", default="sne", choices=["sne", "qr"])
     ap.add_argument("--nrhs", type=int, default=None, help="slices per batch (default: the workload's)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference path")
@@ -214,6 +218,8 @@ def main():
     rn = torch.zeros((args.refine + 1) * nrhs, dtype=torch.float64, device=dev)
     gn = torch.zeros((args.refine + 1) * nrhs, dtype=torch.float64, device=dev)
 
+    steps_taken = []
+
     def step(record):
         e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         ctqr.build_system(sc, A)
@@ -222,8 +228,10 @@ def main():
         f = ctqr.qr_factor(A, m, n, prec, max_nrhs=nrhs)
         e[1].record(stream)
         e[2].record(stream)
-        ctqr.solve_refined(f, sp_step, Bd, X, args.refine, method, scratch=scratch, res_norms=rn, grad_norms=gn)
+        taken = ctqr.solve_refined(f, sp_step, Bd, X, args.refine, method, scratch=scratch, res_norms=rn,
+                                   grad_norms=gn, tol=args.tol)
         e[3].record(stream)
+        steps_taken.append(taken)
         info = ctqr.status(f)
         if info != 0:
             raise RuntimeError("factorization reports rank deficiency at column %d" % (info - 1))
@@ -251,8 +259,9 @@ def main():
     sol_ms = sum(t[1] for t in times)
     qr_tflops = qr_flops(m, n) * args.steps / (qr_ms * 1e-3) / 1e12
     slices_per_s = nrhs * args.steps / (sol_ms * 1e-3)
-    rnorm = rn.view(args.refine + 1, nrhs).cpu().numpy()
-    gnorm = gn.view(args.refine + 1, nrhs).cpu().numpy()
+    taken = steps_taken[-1]
+    rnorm = rn.view(args.refine + 1, nrhs).cpu().numpy()[: taken + 1]
+    gnorm = gn.view(args.refine + 1, nrhs).cpu().numpy()[: taken + 1]
     bnorm = np.linalg.norm(B, axis=0)
     Xm = X[:, :n].cpu().numpy().T.copy()
 
@@ -288,7 +297,7 @@ def main():
     # refined headline path on the noiseless sinograms (consistent data, as
     # the paper's projected references): the paper-style residual
     Xnl = torch.zeros_like(X)
-    ctqr.solve_refined(f, sp, Pnl, Xnl, args.refine, method, scratch=scratch)
+    ctqr.solve_refined(f, sp, Pnl, Xnl, args.refine, method, scratch=scratch, tol=args.tol)
     torch.cuda.synchronize()
     headline_residual_noiseless = paper_residual(Xnl, Pnl)
 
@@ -317,6 +326,17 @@ def main():
             fp64["qr_ms"], fp64["qr_tflops"], fp64["slices_per_s"], fp64["residual_noiseless"]))
 
     headline_vs_fp64 = errs_vs(X, X64d) if X64d is not None else None
+    # the headline path's error against the FP64 path after each number of
+    # refinement steps (untimed; s = 0 is the plain low-precision solve)
+    err_by_step = None
+    if X64d is not None:
+        err_by_step = []
+        Xs_ = torch.zeros_like(X)
+        for s_ in range(args.refine + 1):
+            ctqr.solve_refined(f, sp, Bd, Xs_, s_, method, scratch=scratch)
+            err_by_step.append(errs_vs(Xs_, X64d)["rel_err_max"])
+        del Xs_
+        log("error against the FP64 path by refinement step: " + " ".join("%.2e" % v for v in err_by_step))
     noiseless_vs_fp64 = None
 
     # ------------------------------------------------------ plain FP32 path
@@ -361,7 +381,7 @@ def main():
     torch.cuda.synchronize()
     hev[0].record(stream)
     Bd2.copy_(Bh, non_blocking=True)
-    ctqr.solve_refined(f, sp, Bd2, X, args.refine, method, scratch=scratch, res_norms=rn, grad_norms=gn)
+    ctqr.solve_refined(f, sp, Bd2, X, args.refine, method, scratch=scratch, tol=args.tol)
     hev[1].record(stream)
     torch.cuda.synchronize()
     h2d_ms = hev[0].elapsed_time(hev[1])
@@ -480,17 +500,20 @@ def main():
         "data": "synthetic (seeded random-ellipse phantoms, Poisson noise)",
         "config": {"workload": "%s: %dx%d image, %d views x %d bins (m=%d, n=%d), %d noisy slices, I0=%g"
                                % (args.workload, sc.n_pix, sc.n_pix, sc.n_angles, sc.n_det, m, n, nrhs, w["I0"]),
-                   "global_batch": nrhs, "precision": args.prec, "refine_steps": args.refine,
-                   "refine_method": args.method, "projector": args.projector},
+                   "global_batch": nrhs, "precision": args.prec, "refine_steps_max": args.refine,
+                   "refine_tol": args.tol, "refine_method": args.method, "projector": args.projector},
         "qr_ms": qr_ms / args.steps,
         "qr_tflops_frac_of_peak": qr_tflops / peak,
         "slices_per_s": slices_per_s,
         "solve_ms": sol_ms / args.steps,
         "slices_per_s_incl_h2d": slices_per_s_h2d,
+        "refine_steps_taken": steps_taken,
         "vs_fp64": headline_vs_fp64,
+        "vs_fp64_rel_err_by_step": err_by_step,
+        "slices_per_s_vs_fp64_path": slices_per_s / fp64["slices_per_s"] if fp64 else None,
         "residual_noiseless": headline_residual_noiseless,
         "residual_rel_final": float(np.max(rnorm[-1] / bnorm)),
-        "ls_grad_norm_by_step": [float(np.max(gnorm[s])) for s in range(args.refine + 1)],
+        "ls_grad_norm_by_step": [float(np.max(gnorm[s])) for s in range(len(gnorm))],
         "fp64_path": fp64,
         "fp32_path": fp32,
         "quality": quality,

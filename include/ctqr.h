@@ -205,11 +205,34 @@ int ct_residual(const int64_t* row_ptr, const int32_t* col, const double* val, i
 int ct_build_csc(int64_t m, int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
                  int64_t* col_ptr, int32_t* row, double* cval, int32_t* work, void* stream);
 
-/* The FP64 sparse copies of A used by the refinement (device arrays). */
+/* Grouped copy of a sparse matrix (CSR, or CSC as the rows of A^T) for FP64
+ * products with many slices: consecutive rows taken `group` at a time (1, 2,
+ * 4 or 8; adjacent rays of a view cross nearly the same pixels, adjacent
+ * pixels of an image row are crossed by nearly the same rays), each group
+ * storing the sorted distinct column indices of its rows once and, for each
+ * of them, `group` weights (zero where a row has no entry; repeated entries
+ * summed).  A product then reads each slice row of the dense operand once per
+ * group instead of once per stored entry.
+ *   gptr: ceil(rows / group) + 1 entries; gidx: count entries; gval:
+ *   count * group, weight of row g * group + r at gval[(gptr[g] + k) * group + r]
+ *   for the k-th column of group g.
+ * Two calls: with gidx = gval = NULL it fills gptr, waits for the stream and
+ * sets *count (work: one device int32 of scratch); then with gidx / gval of
+ * count (and count * group) entries it fills them.  Returns -2005 if a group
+ * holds more than 8192 stored entries (use a smaller group). */
+int ct_group_sparse(int64_t rows, const int64_t* ptr, const int32_t* idx, const double* val, int32_t group,
+                    int64_t* gptr, int32_t* gidx, double* gval, int64_t* count, int32_t* work, void* stream);
+
+/* The FP64 sparse copies of A used by the refinement (device arrays).  The
+ * grouped copies are optional (group_r / group_c = 0: the products use the
+ * CSR / CSC copies entry by entry). */
 typedef struct ct_sparse {
     int64_t m, n, nnz;
     const int64_t* row_ptr; const int32_t* col; const double* val;   /* CSR of A  */
     const int64_t* col_ptr; const int32_t* row; const double* cval;  /* CSC of A (may be NULL for CT_REFINE_QR) */
+    int32_t group_r, group_c;                                         /* rows per group of the grouped copies */
+    const int64_t* grow_ptr; const int32_t* grow_col; const double* grow_val;  /* grouped CSR (rays) */
+    const int64_t* gcol_ptr; const int32_t* gcol_row; const double* gcol_val;  /* grouped CSC (pixels) */
 } ct_sparse;
 
 /* Refinement steps (the correction is computed with the factor Q~ R~ in its
@@ -227,15 +250,23 @@ enum { CT_REFINE_QR = 0, CT_REFINE_SNE = 1 };
 int ct_refine_workspace(int64_t m, int64_t n, int64_t nrhs, size_t* bytes);
 
 /* Reconstruction with iterative refinement on the FP64 residual r = b - A x:
- *   x_0 = R~^{-1} Q~^T b, then `steps` refinement steps of kind `method`.
- * B: m x nrhs FP64 (unchanged), X: n x nrhs FP64 (output).  If not NULL,
- * res_norms receives ||r_s||_2 and grad_norms ||A^T r_s||_2 (the latter needs
- * the CSC copy) for s = 0..steps, (steps + 1) x nrhs, step-major.  On a
- * CT_PREC_BF16X3 factor the solves inside use BF16x3 products from 48 slices
- * up (see ct_debug_refine_x3); other factors use their storage precision. */
+ *   x_0 = R~^{-1} Q~^T b, then up to `steps` refinement steps of kind `method`.
+ * B: m x nrhs FP64 (unchanged), X: n x nrhs FP64 (output).
+ * Stop rule: with tol > 0, after each step the correction d of every slice is
+ * compared with the updated image, and the refinement ends once
+ * max_j ||d_j||_2 / ||x_j||_2 <= tol (each step contracts the error by
+ * roughly kappa(A) u_factor, so the image error after that step is a small
+ * fraction of tol).  Checking it waits for the stream once per step.
+ * tol = 0 runs all `steps` without waiting.  steps_done (host, may be NULL)
+ * receives the number of steps taken.  If not NULL, res_norms receives
+ * ||r_s||_2 and grad_norms ||A^T r_s||_2 (the latter needs the CSC copy) for
+ * s = 0..steps_done, (steps + 1) x nrhs, step-major; later rows are not
+ * written.  On a CT_PREC_BF16X3 factor the solves inside use BF16x3 products
+ * from 48 slices up (see ct_debug_refine_x3); other factors use their
+ * storage precision. */
 int ct_solve_refined(const ct_factor* f, const ct_sparse* A, const double* B, int64_t ldb, double* X,
-                     int64_t ldx, int64_t nrhs, int32_t steps, int32_t method, void* scratch,
-                     size_t scratch_bytes, double* res_norms, double* grad_norms, void* stream);
+                     int64_t ldx, int64_t nrhs, int32_t steps, int32_t method, double tol, void* scratch,
+                     size_t scratch_bytes, double* res_norms, double* grad_norms, int32_t* steps_done, void* stream);
 
 /* ct_solve_refined without a scratch argument, for callers that cannot
  * allocate device memory (code under graph capture, tight serving loops,
@@ -249,8 +280,8 @@ int ct_solve_refined(const ct_factor* f, const ct_sparse* A, const double* B, in
  * that overlap on one GPU (different streams or host threads without
  * ordering) race on it and must be serialized by the caller. */
 int ct_solve_refined_noalloc(const ct_factor* f, const ct_sparse* A, const double* B, int64_t ldb, double* X,
-                             int64_t ldx, int64_t nrhs, int32_t steps, int32_t method, double* res_norms,
-                             double* grad_norms, void* stream);
+                             int64_t ldx, int64_t nrhs, int32_t steps, int32_t method, double tol,
+                             double* res_norms, double* grad_norms, int32_t* steps_done, void* stream);
 
 /* Waits for `stream`, then reports the factor's numerical status: *info = 0
  * for full column rank, j + 1 if column j had a zero Householder norm.

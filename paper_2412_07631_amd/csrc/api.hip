@@ -82,7 +82,8 @@ hipError_t trsm_set_max_lds(size_t bytes);
 template <typename TS>
 hipError_t launch_rinv(const TS* A, int64_t lda, int64_t n, TS* RiR, TS* RiC, double* Ri64, double* M, hipStream_t s);
 template <typename TS>
-hipError_t launch_rt(const TS* A, int64_t lda, int64_t n, TS* Rt, hipStream_t s);
+hipError_t launch_rt(const TS* A, int64_t lda, int64_t n, int ob, TS* Rt, hipStream_t s);
+size_t rt_elems(int64_t n, int ob);
 template <typename TS>
 hipError_t launch_copy_block(const TS* src, int64_t lds, TS* dst, int64_t ldd, int rows, int cols, hipStream_t s,
                              const int32_t* desc);
@@ -96,6 +97,9 @@ hipError_t launch_convert(const TI* X, int64_t ldx, TO* Y, int64_t ldy, int64_t 
 template <typename TD>
 hipError_t launch_accumulate(double* X, int64_t ldx, const TD* D, int64_t ldd, int64_t rows, int cols,
                              hipStream_t s);
+template <typename TD>
+hipError_t launch_corr_ratio(const TD* D, int64_t ldd, const double* X, int64_t ldx, int64_t rows, int cols,
+                             double* ratio, unsigned long long* maxw, hipStream_t s);
 template <typename T>
 hipError_t launch_zero_rows(T* Y, int64_t ldy, int64_t r0, int64_t r1, int cols, hipStream_t s);
 hipError_t launch_colnorm(const double* X, int64_t ldx, int64_t rows, int cols, double* out, hipStream_t s);
@@ -103,6 +107,13 @@ hipError_t launch_residual_t(const int64_t* col_ptr, const int32_t* row, const d
                              const double* R, int64_t ldr, double* S, int64_t lds, int nrhs, hipStream_t s);
 hipError_t launch_csc(const int64_t* row_ptr, const int32_t* col, const double* val, int64_t m, int64_t n,
                       int64_t* col_ptr, int32_t* row, double* cval, int32_t* work, hipStream_t s);
+hipError_t launch_group_count(const int64_t* ptr, const int32_t* idx, int64_t rows, int group, int64_t* gptr,
+                              int32_t* err, hipStream_t s);
+hipError_t launch_group_fill(const int64_t* ptr, const int32_t* idx, const double* val, int64_t rows, int group,
+                             const int64_t* gptr, int32_t* gidx, double* gval, int64_t count, hipStream_t s);
+hipError_t launch_group_spmm(const int64_t* gptr, const int32_t* gidx, const double* gval, int group, int64_t rows,
+                             const double* Z, const double* B, double* out, int64_t ld, int nrhs, bool sub,
+                             hipStream_t s);
 hipError_t launch_spmv_rows_t(const int64_t* ptr, const int32_t* idx, const double* val, int64_t rows,
                               const double* Xt, const double* Bt, double* Rt, int64_t ld, int nrhs, hipStream_t s);
 hipError_t launch_spmv_cols_t(const int64_t* ptr, const int32_t* idx, const double* val, int64_t cols,
@@ -214,6 +225,7 @@ struct ct_factor {
     void* RiR = nullptr;
     void* RiC = nullptr;
     void* Rt = nullptr;
+    int rt_ob = 256;   // outer block of the two-level row-major R copy (see rt_kernel)
     // row-major copies of the outer reflector blocks (in-memory factors),
     // written by the factorization and reused by every solve
     void* VtAll = nullptr;
@@ -248,6 +260,11 @@ struct Layout {
 
 static size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Outer block of the blocked triangular solves: the rows above an outer
+// block of 1024 columns are updated once, by one product with K = 1024,
+// instead of four times with K = 256 (each update reads and writes them).
+static int rt_ob_for(int64_t n) { return n >= 2048 ? 1024 : 256; }
+
 static Layout layout(int64_t m, int64_t n, int prec, int64_t max_nrhs, int nbo, bool r_copies = true)
 {
     Layout L;
@@ -274,7 +291,7 @@ static Layout layout(int64_t m, int64_t n, int prec, int64_t max_nrhs, int nbo, 
     const int64_t nbt = (n + 255) / 256;
     L.Ri = off; off += r_copies ? up256((size_t)2 * nbt * 256 * 256 * es) : 0;
     L.Ri64 = off; off += r_copies ? up256((size_t)nbt * 256 * 256 * 8) : 0;
-    L.Rt = off; off += r_copies ? up256((size_t)256 * 256 * (size_t)(nbt * (nbt - 1) / 2) * es) : 0;
+    L.Rt = off; off += r_copies ? up256(rt_elems(n, rt_ob_for(n)) * es) : 0;
     // reflector blocks, row-major: block b holds (m - b nbo) rows of nbo
     L.VtAll = off; off += r_copies ? up256((size_t)(nblocks * m - nbo * (nblocks * (nblocks - 1) / 2)) * nbo * es) : 0;
     L.Tf = off; off += prec == CT_PREC_F64 ? 0 : up256((size_t)nblocks * nbo * nbo * 4);
@@ -973,37 +990,61 @@ static int trsm_impl(const ct_factor* fc, TS* B, int64_t nrhs, int64_t ldb, hipS
     const int tb = g_dev.trsm_block;
     const int64_t nb = (n + tb - 1) / tb;
     if (f->Rt) {
-        // per 256-row block, last first: X_b = R_bb^{-1} B_b (copy to scratch,
-        // then a product with the stored inverse), then B[0:k0] -= R[0:k0, b] X_b
-        // with the row-major copy of the block column; both on the NT kernel
+        // two levels of blocks, last first.  Inside an outer block of ob
+        // columns, per 256-row block b: X_b = R_bb^{-1} B_b (a product with the
+        // stored inverse), then the block's rows above b: B[K0:k0] -= R[K0:k0, b] X_b;
+        // after the outer block: B[0:K0] -= R[0:K0, K0:K0+w] X_B, one product
+        // with K = w.  Both updates read row-major copies of R (rt_kernel), so
+        // every product is an NT product with K-contiguous operands.
         const NtPlan* plan = &f->solve_plan[bucket_of(nrhs)];
         const NtPlan diag_plan{32, 1024};     // 256-row products: narrow tiles for more workgroups
         TS* S = (TS*)f->Wq;
-        const int64_t nb2 = (n + 255) / 256;
-        for (int64_t b = nb2 - 1; b >= 0; --b) {
-            const int64_t k0 = b * 256;
-            const int bo = (int)std::min<int64_t>(256, n - k0);
+        const int ob = f->rt_ob;
+        const int64_t nbo = (n + ob - 1) / ob, q = ob / 256;
+        const TS* Rt = (const TS*)f->Rt;
+        const TS* Rin = Rt + (size_t)ob * ob * (size_t)(nbo * (nbo - 1) / 2);
+        auto update = [&](const TS* X, int64_t ldx, int64_t P, int K, int64_t yrow, int64_t orow) -> int {
             int nz;
-            bool done = false;
             if constexpr (sizeof(TS) == 4)
                 if (x3 && !desc) {
-                    CT_HIP(launch_diag_x3((const float*)f->RiR + (size_t)b * 256 * 256, B + k0, ldb, bo, (int)nrhs, s));
-                    done = true;
+                    CT_HIP(launch_nt_lp<M_BF16X3>(X, ldx, B + yrow, ldb, B + orow, ldb, P, (int)nrhs, K, true, 0, &nz,
+                                                  s, nullptr, nullptr));
+                    return 0;
                 }
-            if (!done) {
-                CT_HIP((launch_copy_block<TS>(B + k0, ldb, S, 256, bo, (int)nrhs, s, desc)));
-                CT_HIP(launch_nt<TS>((const TS*)f->RiR + (size_t)b * 256 * 256, 256, S, 256, B + k0, ldb, bo,
-                                     (int)nrhs, bo, false, 0, &nz, s, &diag_plan, desc, 0, 1));
+            CT_HIP(launch_nt<TS>(X, ldx, B + yrow, ldb, B + orow, ldb, P, (int)nrhs, K, true, 0, &nz, s, plan, desc,
+                                 1, 1));
+            return 0;
+        };
+        for (int64_t Bk = nbo - 1; Bk >= 0; --Bk) {
+            const int64_t K0 = Bk * ob;
+            const int64_t w = std::min<int64_t>(ob, n - K0);
+            for (int64_t i = (w + 255) / 256 - 1; i >= 0; --i) {
+                const int64_t k0 = K0 + 256 * i, b = k0 / 256;
+                const int bo = (int)std::min<int64_t>(256, n - k0);
+                int nz;
+                bool done = false;
+                if constexpr (sizeof(TS) == 4)
+                    if (x3 && !desc) {
+                        CT_HIP(launch_diag_x3((const float*)f->RiR + (size_t)b * 256 * 256, B + k0, ldb, bo, (int)nrhs,
+                                              s));
+                        done = true;
+                    }
+                if (!done) {
+                    CT_HIP((launch_copy_block<TS>(B + k0, ldb, S, 256, bo, (int)nrhs, s, desc)));
+                    CT_HIP(launch_nt<TS>((const TS*)f->RiR + (size_t)b * 256 * 256, 256, S, 256, B + k0, ldb, bo,
+                                         (int)nrhs, bo, false, 0, &nz, s, &diag_plan, desc, 0, 1));
+                }
+                if (i > 0) {
+                    const TS* Ri = Rin + (size_t)Bk * 256 * 256 * (size_t)(q * (q - 1) / 2) +
+                                   (size_t)256 * 256 * (size_t)(i * (i - 1) / 2);
+                    int r = update(Ri, 256, 256 * i, bo, k0, K0);
+                    if (r) return r;
+                }
             }
-            if (k0 == 0) continue;
-            const TS* Rtb = (const TS*)f->Rt + (size_t)256 * 256 * (size_t)(b * (b - 1) / 2);
-            if constexpr (sizeof(TS) == 4)
-                if (x3 && !desc) {
-                    CT_HIP(launch_nt_lp<M_BF16X3>(Rtb, 256, B + k0, ldb, B, ldb, k0, (int)nrhs, bo, true, 0, &nz, s,
-                                                  nullptr, nullptr));
-                    continue;
-                }
-            CT_HIP(launch_nt<TS>(Rtb, 256, B + k0, ldb, B, ldb, k0, (int)nrhs, bo, true, 0, &nz, s, plan, desc, 1, 1));
+            if (K0 > 0) {
+                int r = update(Rt + (size_t)ob * ob * (size_t)(Bk * (Bk - 1) / 2), ob, K0, (int)w, K0, 0);
+                if (r) return r;
+            }
         }
         return 0;
     }
@@ -1036,39 +1077,61 @@ static int trsm_lt_impl(const ct_factor* fc, TS* Y, int64_t k, int64_t ldy, hipS
     const int tb = g_dev.trsm_block;
     const int64_t nb = (n + tb - 1) / tb;
     if (f->RiC && !f->st) {
-        // right-looking, first block first: Z_b = R_bb^{-T} Y_b with the stored
-        // inverse, then Y[k0+bo:n] -= R[k0:k0+bo, k0+bo:n]^T Z_b, whose X rows
-        // are the later columns of R read in place (K-contiguous down a column)
+        // right-looking, first block first, in two levels of blocks: inside an
+        // outer block of ob columns, per 256-row block b: Z_b = R_bb^{-T} Y_b
+        // with the stored inverse, then the outer block's later rows:
+        // Y[k0+bo:K0+w] -= R[k0:k0+bo, k0+bo:K0+w]^T Z_b; after the outer block:
+        // Y[K0+w:n] -= R[K0:K0+w, K0+w:n]^T Z_B, one product with K = w.  The X
+        // rows of both are later columns of R read in place (K-contiguous
+        // down a column).
         const NtPlan* plan = &f->solve_plan[bucket_of(k)];
         const NtPlan diag_plan{32, 1024};
         const TS* A = (const TS*)f->A;
         TS* S = (TS*)f->Wq;
-        const int64_t nb2 = (n + 255) / 256;
-        for (int64_t b = 0; b < nb2; ++b) {
-            const int64_t k0 = b * 256;
-            const int bo = (int)std::min<int64_t>(256, n - k0);
+        const int ob = f->rt_ob;
+        const int64_t nbo = (n + ob - 1) / ob;
+        auto update = [&](int64_t r0, int64_t c0, int64_t P, int K) -> int {
+            // Y[c0 : c0 + P] -= R[r0 : r0 + K, c0 : c0 + P]^T Y[r0 : r0 + K]
             int nz;
-            bool done = false;
             if constexpr (sizeof(TS) == 4)
                 if (x3) {
-                    CT_HIP(launch_diag_x3((const float*)f->RiC + (size_t)b * 256 * 256, Y + k0, ldy, bo, (int)k, s));
-                    done = true;
+                    CT_HIP(launch_nt_lp<M_BF16X3>(A + r0 + c0 * lda, lda, Y + r0, ldy, Y + c0, ldy, P, (int)k, K, true,
+                                                  0, &nz, s, nullptr, nullptr));
+                    return 0;
                 }
-            if (!done) {
-                CT_HIP((launch_copy_block<TS>(Y + k0, ldy, S, 256, bo, (int)k, s, nullptr)));
-                CT_HIP(launch_nt<TS>((const TS*)f->RiC + (size_t)b * 256 * 256, 256, S, 256, Y + k0, ldy, bo, (int)k,
-                                     bo, false, 0, &nz, s, &diag_plan));
+            CT_HIP(launch_nt<TS>(A + r0 + c0 * lda, lda, Y + r0, ldy, Y + c0, ldy, P, (int)k, K, true, 0, &nz, s,
+                                 plan));
+            return 0;
+        };
+        for (int64_t Bk = 0; Bk < nbo; ++Bk) {
+            const int64_t K0 = Bk * ob;
+            const int64_t w = std::min<int64_t>(ob, n - K0);
+            for (int64_t k0 = K0; k0 < K0 + w; k0 += 256) {
+                const int64_t b = k0 / 256;
+                const int bo = (int)std::min<int64_t>(256, n - k0);
+                int nz;
+                bool done = false;
+                if constexpr (sizeof(TS) == 4)
+                    if (x3) {
+                        CT_HIP(launch_diag_x3((const float*)f->RiC + (size_t)b * 256 * 256, Y + k0, ldy, bo, (int)k, s));
+                        done = true;
+                    }
+                if (!done) {
+                    CT_HIP((launch_copy_block<TS>(Y + k0, ldy, S, 256, bo, (int)k, s, nullptr)));
+                    CT_HIP(launch_nt<TS>((const TS*)f->RiC + (size_t)b * 256 * 256, 256, S, 256, Y + k0, ldy, bo,
+                                         (int)k, bo, false, 0, &nz, s, &diag_plan));
+                }
+                const int64_t rest_in = K0 + w - k0 - bo;
+                if (rest_in > 0) {
+                    int r = update(k0, k0 + bo, rest_in, bo);
+                    if (r) return r;
+                }
             }
-            const int64_t rest = n - k0 - bo;
-            if (rest <= 0) continue;
-            if constexpr (sizeof(TS) == 4)
-                if (x3) {
-                    CT_HIP(launch_nt_lp<M_BF16X3>(A + k0 + (k0 + bo) * lda, lda, Y + k0, ldy, Y + k0 + bo, ldy, rest,
-                                                  (int)k, bo, true, 0, &nz, s, nullptr, nullptr));
-                    continue;
-                }
-            CT_HIP(launch_nt<TS>(A + k0 + (k0 + bo) * lda, lda, Y + k0, ldy, Y + k0 + bo, ldy, rest, (int)k, bo, true, 0,
-                                 &nz, s, plan));
+            const int64_t rest = n - K0 - w;
+            if (rest > 0) {
+                int r = update(K0, K0 + w, rest, (int)w);
+                if (r) return r;
+            }
         }
         return 0;
     }
@@ -1108,8 +1171,8 @@ static int backward_impl(const ct_factor* fc, const TS* G, int64_t k, int64_t ld
 
 template <typename TS>
 static int refined_impl(const ct_factor* f, const ct_sparse* sp, const double* B, int64_t ldb, double* X,
-                        int64_t ldx, int64_t nrhs, int steps, int method, char* scratch, double* rnorms,
-                        double* gnorms, hipStream_t s)
+                        int64_t ldx, int64_t nrhs, int steps, int method, double tol, char* scratch, double* rnorms,
+                        double* gnorms, int32_t* steps_done, hipStream_t s)
 {
     const int64_t m = f->m, n = f->n;
     const int64_t ld = (m + 15) / 16 * 16;             // column-major correction block
@@ -1135,16 +1198,26 @@ static int refined_impl(const ct_factor* f, const ct_sparse* sp, const double* B
     if (r) return r;
     CT_HIP((launch_convert<TS, double>(C, ld, X, ldx, n, nr, s)));
     CT_HIP((launch_transpose<TS, double, true, false>(C, Xt, n, nr, ld, lt, s)));
+    int taken = 0;
+    bool converged = false;
     for (int st = 0; st <= steps; ++st) {
         // r_st = b - A x_st (FP64)
-        CT_HIP(launch_spmv_rows_t(sp->row_ptr, sp->col, sp->val, m, Xt, Bt, Rt, lt, nr, s));
+        if (sp->group_r > 0)
+            CT_HIP(launch_group_spmm(sp->grow_ptr, sp->grow_col, sp->grow_val, sp->group_r, m, Xt, Bt, Rt, lt, nr,
+                                     true, s));
+        else
+            CT_HIP(launch_spmv_rows_t(sp->row_ptr, sp->col, sp->val, m, Xt, Bt, Rt, lt, nr, s));
         if (rnorms) CT_HIP(launch_colnorm_t(Rt, lt, m, nr, rnorms + (size_t)st * nrhs, Np, s));
         const bool need_grad = method == CT_REFINE_SNE ? st < steps : false;
         if (have_csc && (need_grad || gnorms)) {
-            CT_HIP(launch_spmv_cols_t(sp->col_ptr, sp->row, sp->cval, n, Rt, St, lt, nr, s));
+            if (sp->group_c > 0)
+                CT_HIP(launch_group_spmm(sp->gcol_ptr, sp->gcol_row, sp->gcol_val, sp->group_c, n, Rt, nullptr, St,
+                                         lt, nr, false, s));
+            else
+                CT_HIP(launch_spmv_cols_t(sp->col_ptr, sp->row, sp->cval, n, Rt, St, lt, nr, s));
             if (gnorms) CT_HIP(launch_colnorm_t(St, lt, n, nr, gnorms + (size_t)st * nrhs, Np, s));
         }
-        if (st == steps) break;
+        if (st == steps || converged) break;
         if (method == CT_REFINE_SNE) {
             // x += R~^{-1} R~^{-T} (A^T r)
             CT_HIP((launch_transpose<double, TS, false, false>(St, C, n, nr, ld, lt, s)));
@@ -1160,7 +1233,21 @@ static int refined_impl(const ct_factor* f, const ct_sparse* sp, const double* B
         if (r) return r;
         CT_HIP((launch_accumulate<TS>(X, ldx, C, ld, n, nr, s)));
         CT_HIP((launch_transpose<TS, double, true, true>(C, Xt, n, nr, ld, lt, s)));
+        ++taken;
+        if (tol > 0.0) {
+            // stop rule: every slice's correction below tol relative to its
+            // updated image; the next pass computes the final residual only
+            unsigned long long* maxw = (unsigned long long*)(Np + 256 * lt - 1);
+            CT_HIP((launch_corr_ratio<TS>(C, ld, X, ldx, n, nr, Np, maxw, s)));
+            unsigned long long h = 0;
+            CT_HIP(hipMemcpyAsync(&h, maxw, sizeof h, hipMemcpyDeviceToHost, s));
+            CT_HIP(hipStreamSynchronize(s));
+            double mx;
+            memcpy(&mx, &h, sizeof mx);
+            converged = mx <= tol;
+        }
     }
+    if (steps_done) *steps_done = taken;
     return 0;
 }
 
@@ -1278,15 +1365,16 @@ static int r_copies(ct_factor* f, char* work, const Layout& L, hipStream_t s)
     f->RiR = work + L.Ri;
     f->RiC = work + L.Ri + (size_t)((n + 255) / 256) * 256 * 256 * es;
     f->Rt = work + L.Rt;
+    f->rt_ob = rt_ob_for(n);
     double* Ri64 = (double*)(work + L.Ri64);
     double* M = (double*)f->Wq;      // free once the factorization is done
     hipError_t e;
     if (f->f64) {
         e = launch_rinv<double>((const double*)f->A, lda, n, (double*)f->RiR, (double*)f->RiC, Ri64, M, s);
-        if (e == hipSuccess) e = launch_rt<double>((const double*)f->A, lda, n, (double*)f->Rt, s);
+        if (e == hipSuccess) e = launch_rt<double>((const double*)f->A, lda, n, f->rt_ob, (double*)f->Rt, s);
     } else {
         e = launch_rinv<float>((const float*)f->A, lda, n, (float*)f->RiR, (float*)f->RiC, Ri64, M, s);
-        if (e == hipSuccess) e = launch_rt<float>((const float*)f->A, lda, n, (float*)f->Rt, s);
+        if (e == hipSuccess) e = launch_rt<float>((const float*)f->A, lda, n, f->rt_ob, (float*)f->Rt, s);
     }
     if (e != hipSuccess) return fail(-1000 - (int)e, "R copies: %s", hipGetErrorString(e));
     return 0;
@@ -1839,9 +1927,35 @@ int ct_build_csc(int64_t m, int64_t n, const int64_t* row_ptr, const int32_t* co
 }
 
 
+int ct_group_sparse(int64_t rows, const int64_t* ptr, const int32_t* idx, const double* val, int32_t group,
+                    int64_t* gptr, int32_t* gidx, double* gval, int64_t* count, int32_t* work, void* stream)
+{
+    CT_ARG(rows > 0, 1, "rows");
+    CT_ARG(ptr && idx && val, 2, "sparse arrays");
+    CT_ARG(group == 1 || group == 2 || group == 4 || group == 8, 5, "group (1, 2, 4 or 8)");
+    CT_ARG(gptr != nullptr, 6, "gptr");
+    CT_ARG((gidx == nullptr) == (gval == nullptr), 7, "gidx/gval (both or neither)");
+    CT_ARG(count != nullptr, 9, "count");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t ng = (rows + group - 1) / group;
+    if (gidx == nullptr) {
+        CT_ARG(work != nullptr, 10, "work");
+        CT_HIP(launch_group_count(ptr, idx, rows, group, gptr, work, s));
+        int32_t err = 0;
+        CT_HIP(hipMemcpyAsync(count, gptr + ng, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        CT_HIP(hipMemcpyAsync(&err, work, sizeof err, hipMemcpyDeviceToHost, s));
+        CT_HIP(hipStreamSynchronize(s));
+        if (err) return fail(-2005, "a group of %d rows stores more than 8192 entries; use a smaller group", group);
+        return 0;
+    }
+    CT_ARG(*count >= 0, 9, "count");
+    CT_HIP(launch_group_fill(ptr, idx, val, rows, group, gptr, gidx, gval, *count, s));
+    return 0;
+}
+
 int ct_solve_refined(const ct_factor* f, const ct_sparse* sp, const double* B, int64_t ldb, double* X, int64_t ldx,
-                     int64_t nrhs, int32_t steps, int32_t method, void* scratch, size_t scratch_bytes,
-                     double* res_norms, double* grad_norms, void* stream)
+                     int64_t nrhs, int32_t steps, int32_t method, double tol, void* scratch, size_t scratch_bytes,
+                     double* res_norms, double* grad_norms, int32_t* steps_done, void* stream)
 {
     CT_ARG(f != nullptr, 1, "f");
     CT_ARG(sp != nullptr && sp->row_ptr && sp->col && sp->val && sp->m == f->m && sp->n == f->n, 2,
@@ -1851,16 +1965,18 @@ int ct_solve_refined(const ct_factor* f, const ct_sparse* sp, const double* B, i
     CT_ARG(nrhs >= 0 && nrhs <= f->max_nrhs, 7, "nrhs (0..max_nrhs)");
     CT_ARG(steps >= 0 && steps <= 64, 8, "steps");
     CT_ARG(method == CT_REFINE_QR || method == CT_REFINE_SNE, 9, "method");
+    CT_ARG(tol >= 0.0, 10, "tol");
     CT_ARG(method != CT_REFINE_SNE || (sp->col_ptr && sp->row && sp->cval), 2, "A (CT_REFINE_SNE needs the CSC copy)");
     size_t need = 0;
     ct_refine_workspace(f->m, f->n, nrhs, &need);
-    CT_ARG(scratch != nullptr && aligned(scratch) && scratch_bytes >= need, 10, "scratch");
+    CT_ARG(scratch != nullptr && aligned(scratch) && scratch_bytes >= need, 11, "scratch");
+    if (steps_done) *steps_done = 0;
     if (nrhs == 0) return 0;
     hipStream_t s = (hipStream_t)stream;
-    return f->f64 ? refined_impl<double>(f, sp, B, ldb, X, ldx, nrhs, steps, method, (char*)scratch, res_norms,
-                                         grad_norms, s)
-                  : refined_impl<float>(f, sp, B, ldb, X, ldx, nrhs, steps, method, (char*)scratch, res_norms,
-                                        grad_norms, s);
+    return f->f64 ? refined_impl<double>(f, sp, B, ldb, X, ldx, nrhs, steps, method, tol, (char*)scratch,
+                                         res_norms, grad_norms, steps_done, s)
+                  : refined_impl<float>(f, sp, B, ldb, X, ldx, nrhs, steps, method, tol, (char*)scratch,
+                                        res_norms, grad_norms, steps_done, s);
 }
 
 }  // extern "C"
@@ -1896,8 +2012,8 @@ static int static_scratch(void** out)
 extern "C" {
 
 int ct_solve_refined_noalloc(const ct_factor* f, const ct_sparse* sp, const double* B, int64_t ldb, double* X,
-                             int64_t ldx, int64_t nrhs, int32_t steps, int32_t method, double* res_norms,
-                             double* grad_norms, void* stream)
+                             int64_t ldx, int64_t nrhs, int32_t steps, int32_t method, double tol,
+                             double* res_norms, double* grad_norms, int32_t* steps_done, void* stream)
 {
     CT_ARG(f != nullptr, 1, "f");
     CT_ARG(nrhs >= 0 && nrhs <= f->max_nrhs, 7, "nrhs (0..max_nrhs)");
@@ -1912,8 +2028,8 @@ int ct_solve_refined_noalloc(const ct_factor* f, const ct_sparse* sp, const doub
     // every word of the scratch is written before it is read (the slice
     // blocks by transposes and products, the norm partials by their first
     // pass), so nothing left by an earlier call needs clearing
-    return ct_solve_refined(f, sp, B, ldb, X, ldx, nrhs, steps, method, ptr, kStaticScratchBytes, res_norms,
-                            grad_norms, stream);
+    return ct_solve_refined(f, sp, B, ldb, X, ldx, nrhs, steps, method, tol, ptr, kStaticScratchBytes, res_norms,
+                            grad_norms, steps_done, stream);
 }
 
 int ct_status(const ct_factor* f, int64_t* info, void* stream)

@@ -8,10 +8,13 @@
 //
 //   ctqr_bench [--n-pix 256] [--views 120] [--bins 640]
 //              [--prec f64|f32|bf16|f16|bf16x3] [--nrhs 16] [--copy-mib 0]
-//              [--stream-gib G --tile-cols 1024] [--nb-out 0]
+//              [--stream-gib G --tile-cols 1024] [--nb-out 0] [--refine S]
 // With --stream-gib the matrix is factored from pinned host memory
 // (ct_qr_factor_streamed) with a device buffer of G GiB, and the time
-// includes every host<->device transfer.
+// includes every host<->device transfer.  With --refine S the in-memory run
+// also solves the nrhs right-hand sides with S steps of FP64-residual
+// refinement (ct_solve_refined, semi-normal-equations steps) and times it;
+// --group G (default 8, 0: none) sets the grouping of its sparse products.
 //
 // Scanner: grid width 1, source-isocentre distance 2, source-detector 4, flat
 // detector whose fan covers the circle inscribed in the image (the reading of
@@ -61,7 +64,7 @@ int main(int argc, char** argv)
     long copy_mib = 0;
     double stream_gib = 0.0;
     long tile_cols = 1024;
-    int nb_out = 0;
+    int nb_out = 0, refine = -1, group = 8;
     const char* pname = "bf16x3";
     for (int i = 1; i + 1 < argc; i += 2) {
         if (!strcmp(argv[i], "--n-pix")) n_pix = atoi(argv[i + 1]);
@@ -73,6 +76,8 @@ int main(int argc, char** argv)
         else if (!strcmp(argv[i], "--stream-gib")) stream_gib = atof(argv[i + 1]);
         else if (!strcmp(argv[i], "--tile-cols")) tile_cols = atol(argv[i + 1]);
         else if (!strcmp(argv[i], "--nb-out")) nb_out = atoi(argv[i + 1]);
+        else if (!strcmp(argv[i], "--refine")) refine = atoi(argv[i + 1]);
+        else if (!strcmp(argv[i], "--group")) group = atoi(argv[i + 1]);
         else {
             fprintf(stderr, "unknown option %s\n", argv[i]);
             return 2;
@@ -196,6 +201,96 @@ int main(int argc, char** argv)
     printf("info %lld qr_ms %.1f qr_tflops %.2f solve_ms %.2f\n", (long long)info, qr_ms, fl / (qr_ms * 1e-3) / 1e12,
            sol_ms);
     fflush(stdout);
+    if (refine >= 0) {
+        // FP64 CSR and CSC copies of A, FP64 right-hand sides (the same
+        // pattern), then the refined solve twice (the second one timed)
+        int64_t *row_ptr, *col_ptr;
+        HIP_OK(hipMalloc(&row_ptr, (size_t)(m + 1) * 8));
+        CT_OK(ct_build_csr(&g, row_ptr, nullptr, nullptr, 0, s));
+        int64_t nnz = 0;
+        HIP_OK(hipMemcpy(&nnz, row_ptr + m, 8, hipMemcpyDeviceToHost));
+        int32_t *col, *row, *cwork;
+        double *val, *cval, *Bd, *Xd;
+        HIP_OK(hipMalloc(&col, (size_t)nnz * 4));
+        HIP_OK(hipMalloc(&val, (size_t)nnz * 8));
+        HIP_OK(hipMalloc(&row, (size_t)nnz * 4));
+        HIP_OK(hipMalloc(&cval, (size_t)nnz * 8));
+        HIP_OK(hipMalloc(&col_ptr, (size_t)(n + 1) * 8));
+        HIP_OK(hipMalloc(&cwork, (size_t)n * 4));
+        CT_OK(ct_build_csr(&g, row_ptr, col, val, nnz, s));
+        CT_OK(ct_build_csc(m, n, row_ptr, col, val, col_ptr, row, cval, cwork, s));
+        const int64_t ldx = (n + 15) / 16 * 16;
+        HIP_OK(hipMalloc(&Bd, (size_t)nrhs * lda * 8));
+        HIP_OK(hipMalloc(&Xd, (size_t)nrhs * ldx * 8));
+        {
+            std::vector<double> h((size_t)nrhs * lda);
+            uint64_t x = 0x2545F4914F6CDD1Dull;
+            for (auto& v : h) {
+                x ^= x << 13; x ^= x >> 7; x ^= x << 17;
+                v = (double)(x >> 11) / 9007199254740992.0;
+            }
+            HIP_OK(hipMemcpy(Bd, h.data(), h.size() * 8, hipMemcpyHostToDevice));
+        }
+        size_t rbytes = 0;
+        CT_OK(ct_refine_workspace(m, n, nrhs, &rbytes));
+        void* rw;
+        HIP_OK(hipMalloc(&rw, rbytes));
+        ct_sparse sp{m, n, nnz, row_ptr, col, val, col_ptr, row, cval};
+        // grouped copies of the CSR and CSC matrices (ct_group_sparse)
+        std::vector<void*> gbufs;
+        auto grouped = [&](int64_t rows, const int64_t* ptr, const int32_t* idx, const double* v, int32_t& g,
+                           const int64_t*& gp, const int32_t*& gi, const double*& gv) {
+            int32_t* w;
+            HIP_OK(hipMalloc(&w, 4));
+            gbufs.push_back(w);
+            for (g = group; g >= 1; g /= 2) {
+                int64_t* gptr;
+                HIP_OK(hipMalloc(&gptr, (size_t)((rows + g - 1) / g + 1) * 8));
+                int64_t cnt = 0;
+                int rc = ct_group_sparse(rows, ptr, idx, v, g, gptr, nullptr, nullptr, &cnt, w, s);
+                if (rc == -2005) {
+                    HIP_OK(hipFree(gptr));
+                    continue;
+                }
+                CT_OK(rc);
+                int32_t* gidx;
+                double* gval;
+                HIP_OK(hipMalloc(&gidx, (size_t)cnt * 4));
+                HIP_OK(hipMalloc(&gval, (size_t)cnt * g * 8));
+                CT_OK(ct_group_sparse(rows, ptr, idx, v, g, gptr, gidx, gval, &cnt, w, s));
+                gbufs.push_back(gptr);
+                gbufs.push_back(gidx);
+                gbufs.push_back(gval);
+                gp = gptr;
+                gi = gidx;
+                gv = gval;
+                printf("grouped %lld rows by %d: %lld columns stored (%.2f per row entry)\n", (long long)rows, g,
+                       (long long)cnt, (double)cnt * g / (double)nnz);
+                return;
+            }
+            g = 0;
+        };
+        if (group > 0) {
+            grouped(m, row_ptr, col, val, sp.group_r, sp.grow_ptr, sp.grow_col, sp.grow_val);
+            grouped(n, col_ptr, row, cval, sp.group_c, sp.gcol_ptr, sp.gcol_row, sp.gcol_val);
+        }
+        float rms = 0;
+        for (int rep = 0; rep < 2; ++rep) {
+            HIP_OK(hipEventRecord(ev[0], s));
+            CT_OK(ct_solve_refined(f, &sp, Bd, lda, Xd, ldx, nrhs, refine, CT_REFINE_SNE, 0.0, rw, rbytes, nullptr,
+                                   nullptr, nullptr, s));
+            HIP_OK(hipEventRecord(ev[1], s));
+            HIP_OK(hipEventSynchronize(ev[1]));
+            HIP_OK(hipEventElapsedTime(&rms, ev[0], ev[1]));
+        }
+        printf("refined: nnz %lld steps %d solve_ms %.2f slices_per_s %.1f\n", (long long)nnz, refine, rms,
+               nrhs / (rms * 1e-3));
+        fflush(stdout);
+        for (void* p : {(void*)row_ptr, (void*)col_ptr, (void*)col, (void*)row, (void*)cwork, (void*)val,
+                        (void*)cval, (void*)Bd, (void*)Xd, rw})
+            HIP_OK(hipFree(p));
+        for (void* p : gbufs) HIP_OK(hipFree(p));
+    }
     CT_OK(ct_factor_destroy(f));
     HIP_OK(hipFree(A));
     HIP_OK(hipFree(tau));

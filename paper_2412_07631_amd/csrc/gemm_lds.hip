@@ -1076,12 +1076,12 @@ void nt_set_cus(int cus) { if (cus > 0) g_nt_cus = cus; }
 
 // Split-K factor for a launch of `tiles` tiles (one workgroup per CU): the
 // smallest that fills the CUs' last round to at least 90 % (or the best one
-// up to 8), keeping at least 16 K steps per slice.
+// up to 64), keeping at least 16 K steps per slice.
 static int dl_split(int tiles, int64_t K, int bk)
 {
     int best = 1;
     double best_eff = 0.0;
-    for (int nz = 1; nz <= 8 && K / nz >= 16 * bk; ++nz) {
+    for (int nz = 1; nz <= 64 && K / nz >= 16 * bk; ++nz) {
         const int64_t w = (int64_t)tiles * nz;
         const int64_t rounds = (w + g_nt_cus - 1) / g_nt_cus;
         const double eff = (double)w / (double)(rounds * g_nt_cus);

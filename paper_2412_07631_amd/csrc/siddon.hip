@@ -269,6 +269,12 @@ hipError_t launch_siddon_csr(const GeomDev& g, int64_t* row_ptr, int32_t* col, d
     return hipGetLastError();
 }
 
+hipError_t launch_csr_scan(int64_t* ptr, int64_t m, hipStream_t s)
+{
+    csr_scan_kernel<<<1, 1024, 0, s>>>(ptr, m);
+    return hipGetLastError();
+}
+
 hipError_t launch_siddon_rows(const double* rays, int64_t r, int32_t N, double W, double* rows, hipStream_t s)
 {
     const int64_t n = (int64_t)N * N;

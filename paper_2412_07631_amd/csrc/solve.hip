@@ -4,6 +4,8 @@
 // these diagonal solves with GEMM updates of the rows above).
 #include "ct_internal.h"
 
+#include <algorithm>
+
 namespace ctqr {
 
 constexpr int kTrsmBlock = 128;
@@ -168,35 +170,67 @@ __global__ void __launch_bounds__(256) rinv_store_kernel(const double* __restric
     }
 }
 
-// Row-major copies of the part of each 256-column block of R above its
-// diagonal block: for block b (columns k0 = 256 b .. k0 + bo),
-// Rt_b[p * 256 + c] = R[p][k0 + c] for rows p < k0 (zero for c >= bo).  Block b
-// starts at element 256 * 256 * b (b - 1) / 2.  Tiles of 16 rows x 256 columns
-// pass through LDS so that both the column-major reads and the row-major
-// writes are coalesced.
+// Row-major copies of R above its diagonal, for the products of the blocked
+// back-substitution, in two levels of blocks: outer blocks of ob columns
+// (a multiple of 256) and, inside each, 256-column blocks.
+//   outer block B (columns K0 = ob B .. K0 + ob): rows 0..K0 of those
+//     columns, Rt4_B[p * ob + c] = R[p][K0 + c] (zero past column n), at
+//     element ob^2 B (B - 1) / 2;
+//   inner block i >= 1 of B (columns K0 + 256 i .. + 256): rows K0 .. K0 + 256 i,
+//     Rin_{B,i}[(p - K0) * 256 + c] = R[p][K0 + 256 i + c], at element
+//     ob^2 nbo (nbo - 1) / 2 + B 256^2 q (q - 1) / 2 + 256^2 i (i - 1) / 2
+//     (nbo outer blocks, q = ob / 256).
+// With ob = 256 this is the one-level layout: every 256-column block's rows
+// above its diagonal block.  Tiles of 16 rows x 256 columns pass through LDS
+// so that both the column-major reads and the row-major writes are coalesced.
+// Grid: x row tiles, y outer blocks, z < q the outer block's 256-column
+// chunks, z >= q its inner blocks i = z - q + 1.
+size_t rt_elems(int64_t n, int ob)
+{
+    const int64_t nbo = (n + ob - 1) / ob, q = ob / 256;
+    return (size_t)ob * ob * (size_t)(nbo * (nbo - 1) / 2) + (size_t)nbo * 256 * 256 * (size_t)(q * (q - 1) / 2);
+}
+
 template <typename TS>
-__global__ void __launch_bounds__(256) rt_kernel(const TS* __restrict__ A, int64_t lda, int64_t n,
+__global__ void __launch_bounds__(256) rt_kernel(const TS* __restrict__ A, int64_t lda, int64_t n, int ob,
                                                  TS* __restrict__ Rt)
 {
     constexpr int B = 256, TR = 16;
     __shared__ TS tile[B][TR + 1];
-    const int64_t b = blockIdx.y;
-    const int64_t k0 = b * B;
-    const int64_t p0 = (int64_t)blockIdx.x * TR;
-    if (p0 >= k0) return;
-    const int bo = (int)((n - k0) < B ? (n - k0) : B);
+    const int64_t ob_ = ob, q = ob / 256, nbo = (n + ob - 1) / ob;
+    const int64_t Bk = blockIdx.y, K0 = Bk * ob_;
+    const int z = blockIdx.z;
+    int64_t c0, p0, p1;          // source columns c0 .. c0 + 256, rows p0 .. p1
+    TS* out;
+    int64_t ldo;
+    if (z < q) {
+        c0 = K0 + (int64_t)z * B;
+        p0 = (int64_t)blockIdx.x * TR;
+        p1 = K0;
+        out = Rt + (size_t)ob_ * ob_ * (size_t)(Bk * (Bk - 1) / 2) + (size_t)z * B;
+        ldo = ob_;
+    } else {
+        const int64_t i = z - q + 1;
+        c0 = K0 + i * B;
+        p0 = K0 + (int64_t)blockIdx.x * TR;
+        p1 = K0 + i * B;
+        out = Rt + (size_t)ob_ * ob_ * (size_t)(nbo * (nbo - 1) / 2) + (size_t)Bk * B * B * (size_t)(q * (q - 1) / 2) +
+              (size_t)B * B * (size_t)(i * (i - 1) / 2) - (size_t)K0 * B;
+        ldo = B;
+    }
+    if (p0 >= p1 || c0 >= n) return;          // (columns past n are never read)
+    const int64_t cols = n - c0;
     const int t = threadIdx.x;
     for (int e = t; e < B * TR; e += 256) {
         const int c = e / TR, r = e % TR;        // r fastest: along a column of R
         const int64_t p = p0 + r;
-        tile[c][r] = (c < bo && p < k0) ? A[p + (k0 + c) * lda] : (TS)0;
+        tile[c][r] = (c < cols && p < p1) ? A[p + (c0 + c) * lda] : (TS)0;
     }
     __syncthreads();
-    TS* out = Rt + (size_t)B * B * (size_t)(b * (b - 1) / 2);
     for (int e = t; e < B * TR; e += 256) {
-        const int r = e / B, c = e % B;          // c fastest: along a row of Rt
+        const int r = e / B, c = e % B;          // c fastest: along a row of the copy
         const int64_t p = p0 + r;
-        if (p < k0) out[p * B + c] = tile[c][r];
+        if (p < p1) out[p * ldo + c] = tile[c][r];
     }
 }
 
@@ -454,6 +488,44 @@ __global__ void __launch_bounds__(256) zero_rows_kernel(T* __restrict__ Y, int64
             Y[i + (int64_t)j * ldy] = (T)0;
 }
 
+// Relative size of a refinement correction per slice, for the stop rule:
+// ratio[j] = ||D[:, j]||_2 / ||X[:, j]||_2 (FP64 sums in a fixed-order tree,
+// one workgroup per slice), and the largest over the slices into *maxw as
+// the bit pattern of a non-negative double (ordered like the values).
+template <typename TD>
+__global__ void __launch_bounds__(256) corr_ratio_kernel(const TD* __restrict__ D, int64_t ldd,
+                                                         const double* __restrict__ X, int64_t ldx, int64_t rows,
+                                                         double* __restrict__ ratio,
+                                                         unsigned long long* __restrict__ maxw)
+{
+    __shared__ double rd[256], rx[256];
+    const int j = blockIdx.x;
+    double sd = 0.0, sx = 0.0;
+    for (int64_t i = threadIdx.x; i < rows; i += 256) {
+        const double d = (double)D[i + (int64_t)j * ldd], x = X[i + (int64_t)j * ldx];
+        sd += d * d;
+        sx += x * x;
+    }
+    rd[threadIdx.x] = sd;
+    rx[threadIdx.x] = sx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            rd[threadIdx.x] += rd[threadIdx.x + w];
+            rx[threadIdx.x] += rx[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double nd = sqrt(rd[0]), nx = sqrt(rx[0]);
+        const double r = nx > 0.0 ? nd / nx : (nd > 0.0 ? __builtin_huge_val() : 0.0);
+        ratio[j] = r;
+        atomicMax(maxw, (unsigned long long)__double_as_longlong(r));
+    }
+}
+
+__global__ void zero_word_kernel(unsigned long long* w) { *w = 0ull; }
+
 // out[j] = ||X[:, j]||_2 in FP64 (fixed-order tree, one workgroup per column)
 __global__ void __launch_bounds__(256) colnorm_kernel(const double* __restrict__ X, int64_t ldx, int64_t rows,
                                                       double* out)
@@ -512,13 +584,13 @@ hipError_t launch_rinv(const TS* A, int64_t lda, int64_t n, TS* RiR, TS* RiC, do
 }
 
 template <typename TS>
-hipError_t launch_rt(const TS* A, int64_t lda, int64_t n, TS* Rt, hipStream_t s)
+hipError_t launch_rt(const TS* A, int64_t lda, int64_t n, int ob, TS* Rt, hipStream_t s)
 {
-    const int64_t nb = (n + 255) / 256;
-    if (nb < 2) return hipSuccess;
-    const int64_t rows = (nb - 1) * 256;                // rows above the last block
-    hipLaunchKernelGGL(rt_kernel<TS>, dim3((unsigned)((rows + 15) / 16), (unsigned)nb), dim3(256), 0, s, A, lda, n,
-                       Rt);
+    const int64_t nbo = (n + ob - 1) / ob, q = ob / 256;
+    if (nbo < 2 && q < 2) return hipSuccess;
+    const int64_t rows = std::max<int64_t>((nbo - 1) * ob, ob);    // the most rows any part copies
+    hipLaunchKernelGGL(rt_kernel<TS>, dim3((unsigned)((rows + 15) / 16), (unsigned)nbo, (unsigned)(2 * q - 1)),
+                       dim3(256), 0, s, A, lda, n, ob, Rt);
     return hipGetLastError();
 }
 
@@ -638,8 +710,8 @@ hipError_t rinv_set_max_lds(size_t bytes)
 template hipError_t launch_rinv<double>(const double*, int64_t, int64_t, double*, double*, double*, double*,
                                         hipStream_t);
 template hipError_t launch_rinv<float>(const float*, int64_t, int64_t, float*, float*, double*, double*, hipStream_t);
-template hipError_t launch_rt<double>(const double*, int64_t, int64_t, double*, hipStream_t);
-template hipError_t launch_rt<float>(const float*, int64_t, int64_t, float*, hipStream_t);
+template hipError_t launch_rt<double>(const double*, int64_t, int64_t, int, double*, hipStream_t);
+template hipError_t launch_rt<float>(const float*, int64_t, int64_t, int, float*, hipStream_t);
 template hipError_t launch_copy_block<double>(const double*, int64_t, double*, int64_t, int, int, hipStream_t,
                                               const int32_t*);
 template hipError_t launch_copy_block<float>(const float*, int64_t, float*, int64_t, int, int, hipStream_t,
@@ -758,6 +830,19 @@ hipError_t launch_convert(const TI* X, int64_t ldx, TO* Y, int64_t ldy, int64_t 
     hipLaunchKernelGGL((convert_kernel<TI, TO>), grid2(rows, cols), dim3(256), 0, s, X, ldx, Y, ldy, rows, cols);
     return hipGetLastError();
 }
+
+template <typename TD>
+hipError_t launch_corr_ratio(const TD* D, int64_t ldd, const double* X, int64_t ldx, int64_t rows, int cols,
+                             double* ratio, unsigned long long* maxw, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_word_kernel, dim3(1), dim3(1), 0, s, maxw);
+    hipLaunchKernelGGL((corr_ratio_kernel<TD>), dim3(cols), dim3(256), 0, s, D, ldd, X, ldx, rows, ratio, maxw);
+    return hipGetLastError();
+}
+template hipError_t launch_corr_ratio<float>(const float*, int64_t, const double*, int64_t, int64_t, int, double*,
+                                             unsigned long long*, hipStream_t);
+template hipError_t launch_corr_ratio<double>(const double*, int64_t, const double*, int64_t, int64_t, int, double*,
+                                              unsigned long long*, hipStream_t);
 
 template <typename TD>
 hipError_t launch_accumulate(double* X, int64_t ldx, const TD* D, int64_t ldd, int64_t rows, int cols, hipStream_t s)

@@ -72,17 +72,20 @@ _sig("ct_solve_backward", [_vp, _vp, _i64, _i64, _vp, _i64, _vp])
 _sig("ct_residual", [_vp, _vp, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _i64, _vp])
 _sig("ct_refine_workspace", [_i64, _i64, _i64, ctypes.POINTER(_sz)])
 _sig("ct_build_csc", [_i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp])
+_sig("ct_group_sparse", [_i64, _vp, _vp, _vp, _i32, _vp, _vp, _vp, ctypes.POINTER(_i64), _vp, _vp])
 
 
 class Sparse(ctypes.Structure):
     _fields_ = [("m", _i64), ("n", _i64), ("nnz", _i64), ("row_ptr", _vp), ("col", _vp), ("val", _vp),
-                ("col_ptr", _vp), ("row", _vp), ("cval", _vp)]
+                ("col_ptr", _vp), ("row", _vp), ("cval", _vp), ("group_r", _i32), ("group_c", _i32),
+                ("grow_ptr", _vp), ("grow_col", _vp), ("grow_val", _vp),
+                ("gcol_ptr", _vp), ("gcol_row", _vp), ("gcol_val", _vp)]
 
 
-_sig("ct_solve_refined", [_vp, ctypes.POINTER(Sparse), _vp, _i64, _vp, _i64, _i64, _i32, _i32, _vp, _sz, _vp, _vp,
-                          _vp])
-_sig("ct_solve_refined_noalloc", [_vp, ctypes.POINTER(Sparse), _vp, _i64, _vp, _i64, _i64, _i32, _i32, _vp, _vp,
-                                  _vp])
+_sig("ct_solve_refined", [_vp, ctypes.POINTER(Sparse), _vp, _i64, _vp, _i64, _i64, _i32, _i32, ctypes.c_double,
+                          _vp, _sz, _vp, _vp, ctypes.POINTER(_i32), _vp])
+_sig("ct_solve_refined_noalloc", [_vp, ctypes.POINTER(Sparse), _vp, _i64, _vp, _i64, _i64, _i32, _i32,
+                                  ctypes.c_double, _vp, _vp, ctypes.POINTER(_i32), _vp])
 
 
 class Profile(ctypes.Structure):
@@ -349,10 +352,34 @@ def refine_workspace(m: int, n: int, nrhs: int) -> int:
     return b.value
 
 
-class SparseA:
-    """FP64 CSR and CSC copies of A on the device (kept alive with the struct)."""
+def group_sparse(rows: int, ptr, idx, val, group: int = 8, device="cuda", stream=None):
+    """Grouped copy (ct_group_sparse) of a CSR-like matrix; the group shrinks
+    (8, 4, 2, 1) while a group holds more entries than the builder takes."""
+    work = torch.zeros(1, dtype=torch.int32, device=device)
+    g = group
+    while True:
+        ng = (rows + g - 1) // g
+        gptr = torch.empty(ng + 1, dtype=torch.int64, device=device)
+        cnt = _i64(0)
+        rc = _lib.ct_group_sparse(rows, _ptr(ptr), _ptr(idx), _ptr(val), g, _ptr(gptr), None, None,
+                                  ctypes.byref(cnt), _ptr(work), _stream(stream))
+        if rc == -2005 and g > 1:
+            g //= 2
+            continue
+        _check(rc)
+        break
+    gidx = torch.empty(max(cnt.value, 1), dtype=torch.int32, device=device)
+    gval = torch.empty(max(cnt.value, 1) * g, dtype=torch.float64, device=device)
+    _check(_lib.ct_group_sparse(rows, _ptr(ptr), _ptr(idx), _ptr(val), g, _ptr(gptr), _ptr(gidx), _ptr(gval),
+                                ctypes.byref(cnt), _ptr(work), _stream(stream)))
+    return g, gptr, gidx, gval
 
-    def __init__(self, geom, device="cuda", stream=None):
+
+class SparseA:
+    """FP64 CSR and CSC copies of A on the device (kept alive with the struct),
+    and their grouped copies for the refinement's products (group 0: none)."""
+
+    def __init__(self, geom, device="cuda", stream=None, group: int = 8):
         self.m = int(geom.n_angles) * int(geom.n_det)
         self.n = int(geom.n_pix) ** 2
         self.row_ptr, self.col, self.val = build_csr(geom, device, stream)
@@ -363,9 +390,19 @@ class SparseA:
         work = torch.empty(self.n, dtype=torch.int32, device=device)
         _check(_lib.ct_build_csc(self.m, self.n, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val),
                                  _ptr(self.col_ptr), _ptr(self.row), _ptr(self.cval), _ptr(work), _stream(stream)))
+        self.group_r = self.group_c = 0
+        self.grouped_r = self.grouped_c = (None, None, None)
+        if group:
+            self.group_r, *self.grouped_r = group_sparse(self.m, self.row_ptr, self.col, self.val, group, device,
+                                                         stream)
+            self.group_c, *self.grouped_c = group_sparse(self.n, self.col_ptr, self.row, self.cval, group, device,
+                                                         stream)
         torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+        p = lambda t: None if t is None else t.data_ptr()
         self.struct = Sparse(self.m, self.n, self.nnz, self.row_ptr.data_ptr(), self.col.data_ptr(),
-                             self.val.data_ptr(), self.col_ptr.data_ptr(), self.row.data_ptr(), self.cval.data_ptr())
+                             self.val.data_ptr(), self.col_ptr.data_ptr(), self.row.data_ptr(), self.cval.data_ptr(),
+                             self.group_r, self.group_c, *[p(t) for t in self.grouped_r],
+                             *[p(t) for t in self.grouped_c])
 
     @property
     def csr(self):
@@ -374,26 +411,30 @@ class SparseA:
 
 def solve_refined(f: Factor, sp: SparseA, B: torch.Tensor, X: torch.Tensor, steps: int, method: int = REFINE_SNE,
                   nrhs: int = None, scratch: torch.Tensor = None, res_norms: torch.Tensor = None,
-                  grad_norms: torch.Tensor = None, stream=None):
-    """X (FP64) <- refined least-squares solution for the FP64 sinograms B."""
+                  grad_norms: torch.Tensor = None, stream=None, tol: float = 0.0) -> int:
+    """X (FP64) <- refined least-squares solution for the FP64 sinograms B;
+    returns the number of refinement steps taken (all `steps` unless tol > 0
+    stops earlier)."""
     nrhs = B.shape[0] if nrhs is None else nrhs
     if scratch is None:
         scratch = torch.empty(refine_workspace(f.m, f.n, nrhs), dtype=torch.uint8, device=B.device)
+    done = _i32(0)
     _check(_lib.ct_solve_refined(f.handle, ctypes.byref(sp.struct), _ptr(B), B.shape[1], _ptr(X), X.shape[1], nrhs,
-                                 int(steps), int(method), _ptr(scratch), scratch.numel(), _ptr(res_norms),
-                                 _ptr(grad_norms), _stream(stream)))
-    return X
+                                 int(steps), int(method), float(tol), _ptr(scratch), scratch.numel(), _ptr(res_norms),
+                                 _ptr(grad_norms), ctypes.byref(done), _stream(stream)))
+    return done.value
 
 
 def solve_refined_noalloc(f: Factor, sp: SparseA, B: torch.Tensor, X: torch.Tensor, steps: int,
                           method: int = REFINE_SNE, nrhs: int = None, res_norms: torch.Tensor = None,
-                          grad_norms: torch.Tensor = None, stream=None):
+                          grad_norms: torch.Tensor = None, stream=None, tol: float = 0.0) -> int:
     """solve_refined with the library's static scratch (allocates nothing)."""
     nrhs = B.shape[0] if nrhs is None else nrhs
+    done = _i32(0)
     _check(_lib.ct_solve_refined_noalloc(f.handle, ctypes.byref(sp.struct), _ptr(B), B.shape[1], _ptr(X), X.shape[1],
-                                         nrhs, int(steps), int(method), _ptr(res_norms), _ptr(grad_norms),
-                                         _stream(stream)))
-    return X
+                                         nrhs, int(steps), int(method), float(tol), _ptr(res_norms),
+                                         _ptr(grad_norms), ctypes.byref(done), _stream(stream)))
+    return done.value
 
 
 def batch_descriptor(sizes, device="cuda"):

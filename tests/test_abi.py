@@ -86,14 +86,19 @@ def test_stream_workspace_arithmetic():
     nbt = (n + 255) // 256
     nbo = (n + 255) // 256
     up = lambda x: (x + 255) // 256 * 256
-    rcopies = (up(2 * nbt * 256 * 256 * 8) + up(nbt * 256 * 256 * 8) + up(256 * 256 * (nbt * (nbt - 1) // 2) * 8)
+    # row-major copies of R above its diagonal in two levels (outer blocks of
+    # 1024 columns from n >= 2048, 256-column blocks inside)
+    ob = 1024
+    nro, q = (n + ob - 1) // ob, ob // 256
+    rt = ob * ob * (nro * (nro - 1) // 2) + nro * 256 * 256 * (q * (q - 1) // 2)
+    rcopies = (up(2 * nbt * 256 * 256 * 8) + up(nbt * 256 * 256 * 8) + up(rt * 8)
                + up((nbo * m - 256 * (nbo * (nbo - 1) // 2)) * 256 * 8))
     base = ctqr.qr_workspace(m, n, ctqr.PREC_F64, 8) - rcopies
     lo, full = ctqr.qr_stream_workspace(m, n, lda, ctqr.PREC_F64, 8, 256)
     tile = (lda * 256 * 8 + 255) // 256 * 256
     assert lo == base + 4 * tile and full == base + 9 * tile
     lo32, full32 = ctqr.qr_stream_workspace(m, n, lda, ctqr.PREC_BF16X3, 8, 1024)
-    rc32 = (up(2 * nbt * 256 * 256 * 4) + up(nbt * 256 * 256 * 8) + up(256 * 256 * (nbt * (nbt - 1) // 2) * 4)
+    rc32 = (up(2 * nbt * 256 * 256 * 4) + up(nbt * 256 * 256 * 8) + up(rt * 4)
             + up((nbo * m - 256 * (nbo * (nbo - 1) // 2)) * 256 * 4))
     base32 = ctqr.qr_workspace(m, n, ctqr.PREC_BF16X3, 8) - rc32
     assert full32 == base32 + 3 * ((lda * 1024 * 4 + 255) // 256 * 256)

@@ -331,6 +331,36 @@ def test_refined_sne_parity(ct, prec, steps, tol):
     assert gn[-1] < gn[0]
 
 
+@pytest.mark.parametrize("prec", ["bf16x3", "f32"])
+def test_refined_stop_rule(ct, prec):
+    """Stop rule of the refinement: it ends after the first step whose
+    correction is at most tol relative to every slice's image (a huge tol
+    stops after one step, tol = 0 runs them all); the images then meet the
+    oracle within tol, and the norm rows of steps not taken stay unwritten."""
+    sc, A, VR, tau = problem("multi")
+    _, P, B = sinograms(sc, A, 3, 6, 5e4)
+    Xs = O.solve(VR, tau, B)
+    Ad = gpu_system(ct, sc, torch.float32)
+    f = ct.qr_factor(Ad, sc.m, sc.n, ct.PREC_NAMES[prec], max_nrhs=8)
+    sp = ct.SparseA(sc)
+    Bd = to_dev(B, torch.float64)
+    steps = 8
+    taken = {}
+    for tol in (1e300, 1e-7, 1e-12, 0.0):
+        Xd = torch.zeros((6, ld16(sc.n)), dtype=torch.float64, device="cuda")
+        rn = torch.full(((steps + 1) * 6,), float("nan"), dtype=torch.float64, device="cuda")
+        k = ct.solve_refined(f, sp, Bd, Xd, steps, ct.REFINE_SNE, res_norms=rn, tol=tol)
+        err = max_col_rel(from_dev(Xd, sc.n), Xs)
+        rows = rn.view(steps + 1, 6).cpu().numpy()
+        print(prec, "tol %g: %d steps, max rel err %.3g" % (tol, k, err))
+        assert np.isfinite(rows[: k + 1]).all() and np.isnan(rows[k + 1:]).all()
+        if 0.0 < tol < 1.0:
+            assert err <= max(tol, 1e-11)
+        taken[tol] = k
+    assert taken[1e300] == 1 and taken[0.0] == steps
+    assert 1 <= taken[1e-7] <= taken[1e-12] <= steps
+
+
 @pytest.mark.parametrize("name,nrhs", [("multi", 6), ("ragged", 37)])
 def test_refined_bf16x3_block_updates_on_and_off(ct, name, nrhs):
     """The refinement of a BF16x3 factor runs its solves' products in BF16x3
