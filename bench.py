@@ -141,7 +141,7 @@ def main():
     ap.add_argument("--workload", default="c3_256")
     ap.add_argument("--prec", default="bf16x3", choices=["f64", "f32", "bf16", "f16", "bf16x3"])
     ap.add_argument("--refine", type=int, default=6, help="refinement steps at most")
-    ap.add_argument("--tol", type=float, default=1e-8,
+    ap.add_argument("--tol", type=float, default=1e-6,
                     help="stop rule: end the refinement once every slice's correction is at most tol relative to "
                          "its image (0: always run --refine steps); the stated bound of the mixed path's image "
                          "error against the FP64 path")

@@ -85,6 +85,8 @@ template <typename TS>
 hipError_t launch_rt(const TS* A, int64_t lda, int64_t n, int ob, TS* Rt, hipStream_t s);
 size_t rt_elems(int64_t n, int ob);
 template <typename TS>
+hipError_t launch_eye(TS* C, int64_t ld, int64_t rows, int cols, int w, hipStream_t s);
+template <typename TS>
 hipError_t launch_copy_block(const TS* src, int64_t lds, TS* dst, int64_t ldd, int rows, int cols, hipStream_t s,
                              const int32_t* desc);
 hipError_t rinv_set_max_lds(size_t bytes);
@@ -226,6 +228,10 @@ struct ct_factor {
     void* RiC = nullptr;
     void* Rt = nullptr;
     int rt_ob = 256;   // outer block of the two-level row-major R copy (see rt_kernel)
+    // BF16x3 factors: inverses of the 1024 x 1024 diagonal blocks of R (FP32),
+    // column-major (RiC4) and row-major (RiR4), for the refinement's solves
+    void* RiC4 = nullptr;
+    void* RiR4 = nullptr;
     // row-major copies of the outer reflector blocks (in-memory factors),
     // written by the factorization and reused by every solve
     void* VtAll = nullptr;
@@ -254,7 +260,7 @@ constexpr int64_t kX3MinSlices = 48;
 static int nb_out_for(int64_t n) { return g_nb_force ? g_nb_force : (n >= 16384 ? 1024 : 256); }
 
 struct Layout {
-    size_t T_all, part, gpart, words, Wp, Wq, G, Vm, Vt, Ws, Ri, Ri64, Rt, VtAll, Tf, S3, total;
+    size_t T_all, part, gpart, words, Wp, Wq, G, Vm, Vt, Ws, Ri, Ri64, Rt, Ri4, VtAll, Tf, S3, total;
     int64_t wp_elems, wq_elems;
 };
 
@@ -292,6 +298,10 @@ static Layout layout(int64_t m, int64_t n, int prec, int64_t max_nrhs, int nbo, 
     L.Ri = off; off += r_copies ? up256((size_t)2 * nbt * 256 * 256 * es) : 0;
     L.Ri64 = off; off += r_copies ? up256((size_t)nbt * 256 * 256 * 8) : 0;
     L.Rt = off; off += r_copies ? up256(rt_elems(n, rt_ob_for(n)) * es) : 0;
+    // BF16x3: the inverses of the 1024-column diagonal blocks, two layouts
+    const int64_t nb4 = (n + 1023) / 1024;
+    L.Ri4 = off; off += (r_copies && prec == CT_PREC_BF16X3 && rt_ob_for(n) == 1024)
+                            ? up256((size_t)2 * nb4 * 1024 * 1024 * 4) : 0;
     // reflector blocks, row-major: block b holds (m - b nbo) rows of nbo
     L.VtAll = off; off += r_copies ? up256((size_t)(nblocks * m - nbo * (nblocks * (nblocks - 1) / 2)) * nbo * es) : 0;
     L.Tf = off; off += prec == CT_PREC_F64 ? 0 : up256((size_t)nblocks * nbo * nbo * 4);
@@ -981,6 +991,52 @@ static int apply_qt_impl(const ct_factor* fc, TS* B, int64_t nrhs, int64_t ldb, 
 
 // x3: the diagonal steps and block-column updates on the bfloat16 MFMA in
 // BF16x3 (FP32 storage only, no batch descriptor).
+// The diagonal block of outer block Bk in the blocked back-substitution:
+// C[K0:K0+w] <- R[K0:K0+w, K0:K0+w]^{-1} C[K0:K0+w] for ncols columns, per
+// 256-row block b, last first: X_b = R_bb^{-1} C_b (a product with the stored
+// inverse), then C[K0:k0] -= R[K0:k0, b] X_b on the row-major copy of R.
+template <typename TS>
+static int inner_solve(ct_factor* f, TS* C, int64_t ldc, int64_t ncols, int64_t Bk, bool x3, const int32_t* desc,
+                       hipStream_t s)
+{
+    const int64_t n = f->n;
+    const int ob = f->rt_ob;
+    const int64_t nbo = (n + ob - 1) / ob, q = ob / 256;
+    const NtPlan* plan = &f->solve_plan[bucket_of(ncols)];
+    const NtPlan diag_plan{32, 1024};     // 256-row products: narrow tiles for more workgroups
+    TS* S = (TS*)f->Wq;
+    const TS* Rin = (const TS*)f->Rt + (size_t)ob * ob * (size_t)(nbo * (nbo - 1) / 2);
+    const int64_t K0 = Bk * ob;
+    const int64_t w = std::min<int64_t>(ob, n - K0);
+    for (int64_t i = (w + 255) / 256 - 1; i >= 0; --i) {
+        const int64_t k0 = K0 + 256 * i, b = k0 / 256;
+        const int bo = (int)std::min<int64_t>(256, n - k0);
+        int nz;
+        bool done = false;
+        if constexpr (sizeof(TS) == 4)
+            if (x3 && !desc) {
+                CT_HIP(launch_diag_x3((const float*)f->RiR + (size_t)b * 256 * 256, C + k0, ldc, bo, (int)ncols, s));
+                done = true;
+            }
+        if (!done) {
+            CT_HIP((launch_copy_block<TS>(C + k0, ldc, S, 256, bo, (int)ncols, s, desc)));
+            CT_HIP(launch_nt<TS>((const TS*)f->RiR + (size_t)b * 256 * 256, 256, S, 256, C + k0, ldc, bo, (int)ncols,
+                                 bo, false, 0, &nz, s, &diag_plan, desc, 0, 1));
+        }
+        if (i == 0) continue;
+        const TS* Ri = Rin + (size_t)Bk * 256 * 256 * (size_t)(q * (q - 1) / 2) + (size_t)256 * 256 * (size_t)(i * (i - 1) / 2);
+        if constexpr (sizeof(TS) == 4)
+            if (x3 && !desc) {
+                CT_HIP(launch_nt_lp<M_BF16X3>(Ri, 256, C + k0, ldc, C + K0, ldc, 256 * i, (int)ncols, bo, true, 0, &nz,
+                                              s, nullptr, nullptr));
+                continue;
+            }
+        CT_HIP(launch_nt<TS>(Ri, 256, C + k0, ldc, C + K0, ldc, 256 * i, (int)ncols, bo, true, 0, &nz, s, plan, desc,
+                             1, 1));
+    }
+    return 0;
+}
+
 template <typename TS>
 static int trsm_impl(const ct_factor* fc, TS* B, int64_t nrhs, int64_t ldb, hipStream_t s,
                      const int32_t* desc = nullptr, bool x3 = false)
@@ -990,61 +1046,41 @@ static int trsm_impl(const ct_factor* fc, TS* B, int64_t nrhs, int64_t ldb, hipS
     const int tb = g_dev.trsm_block;
     const int64_t nb = (n + tb - 1) / tb;
     if (f->Rt) {
-        // two levels of blocks, last first.  Inside an outer block of ob
-        // columns, per 256-row block b: X_b = R_bb^{-1} B_b (a product with the
-        // stored inverse), then the block's rows above b: B[K0:k0] -= R[K0:k0, b] X_b;
-        // after the outer block: B[0:K0] -= R[0:K0, K0:K0+w] X_B, one product
-        // with K = w.  Both updates read row-major copies of R (rt_kernel), so
-        // every product is an NT product with K-contiguous operands.
+        // two levels of blocks, last first: the diagonal block of each outer
+        // block (inner_solve, or for BF16x3 one product with the stored
+        // inverse of the whole 1024 x 1024 block), then B[0:K0] -= R[0:K0,
+        // K0:K0+w] X_B, one product with K = w on the row-major copy of R
+        // (rt_kernel), an NT product with K-contiguous operands.
         const NtPlan* plan = &f->solve_plan[bucket_of(nrhs)];
-        const NtPlan diag_plan{32, 1024};     // 256-row products: narrow tiles for more workgroups
-        TS* S = (TS*)f->Wq;
         const int ob = f->rt_ob;
-        const int64_t nbo = (n + ob - 1) / ob, q = ob / 256;
+        const int64_t nbo = (n + ob - 1) / ob;
         const TS* Rt = (const TS*)f->Rt;
-        const TS* Rin = Rt + (size_t)ob * ob * (size_t)(nbo * (nbo - 1) / 2);
-        auto update = [&](const TS* X, int64_t ldx, int64_t P, int K, int64_t yrow, int64_t orow) -> int {
-            int nz;
-            if constexpr (sizeof(TS) == 4)
-                if (x3 && !desc) {
-                    CT_HIP(launch_nt_lp<M_BF16X3>(X, ldx, B + yrow, ldb, B + orow, ldb, P, (int)nrhs, K, true, 0, &nz,
-                                                  s, nullptr, nullptr));
-                    return 0;
-                }
-            CT_HIP(launch_nt<TS>(X, ldx, B + yrow, ldb, B + orow, ldb, P, (int)nrhs, K, true, 0, &nz, s, plan, desc,
-                                 1, 1));
-            return 0;
-        };
+        const bool inv4 = x3 && !desc && f->RiR4 && (int64_t)ob * nrhs * (int64_t)sizeof(TS) <= f->wq_elems * 8;
         for (int64_t Bk = nbo - 1; Bk >= 0; --Bk) {
             const int64_t K0 = Bk * ob;
             const int64_t w = std::min<int64_t>(ob, n - K0);
-            for (int64_t i = (w + 255) / 256 - 1; i >= 0; --i) {
-                const int64_t k0 = K0 + 256 * i, b = k0 / 256;
-                const int bo = (int)std::min<int64_t>(256, n - k0);
-                int nz;
-                bool done = false;
-                if constexpr (sizeof(TS) == 4)
-                    if (x3 && !desc) {
-                        CT_HIP(launch_diag_x3((const float*)f->RiR + (size_t)b * 256 * 256, B + k0, ldb, bo, (int)nrhs,
-                                              s));
-                        done = true;
-                    }
-                if (!done) {
-                    CT_HIP((launch_copy_block<TS>(B + k0, ldb, S, 256, bo, (int)nrhs, s, desc)));
-                    CT_HIP(launch_nt<TS>((const TS*)f->RiR + (size_t)b * 256 * 256, 256, S, 256, B + k0, ldb, bo,
-                                         (int)nrhs, bo, false, 0, &nz, s, &diag_plan, desc, 0, 1));
-                }
-                if (i > 0) {
-                    const TS* Ri = Rin + (size_t)Bk * 256 * 256 * (size_t)(q * (q - 1) / 2) +
-                                   (size_t)256 * 256 * (size_t)(i * (i - 1) / 2);
-                    int r = update(Ri, 256, 256 * i, bo, k0, K0);
-                    if (r) return r;
+            int nz;
+            if constexpr (sizeof(TS) == 4) {
+                if (inv4) {
+                    TS* S = (TS*)f->Wq;
+                    CT_HIP((launch_copy_block<TS>(B + K0, ldb, S, ob, (int)w, (int)nrhs, s, nullptr)));
+                    CT_HIP(launch_nt_lp<M_BF16X3>((const float*)f->RiR4 + (size_t)Bk * ob * ob, ob, S, ob, B + K0, ldb,
+                                                  w, (int)nrhs, w, false, 0, &nz, s, nullptr, nullptr));
                 }
             }
-            if (K0 > 0) {
-                int r = update(Rt + (size_t)ob * ob * (size_t)(Bk * (Bk - 1) / 2), ob, K0, (int)w, K0, 0);
+            if (!inv4) {
+                int r = inner_solve<TS>(f, B, ldb, nrhs, Bk, x3, desc, s);
                 if (r) return r;
             }
+            if (K0 == 0) continue;
+            const TS* X = Rt + (size_t)ob * ob * (size_t)(Bk * (Bk - 1) / 2);
+            if constexpr (sizeof(TS) == 4)
+                if (x3 && !desc) {
+                    CT_HIP(launch_nt_lp<M_BF16X3>(X, ob, B + K0, ldb, B, ldb, K0, (int)nrhs, w, true, 0, &nz, s,
+                                                  nullptr, nullptr));
+                    continue;
+                }
+            CT_HIP(launch_nt<TS>(X, ob, B + K0, ldb, B, ldb, K0, (int)nrhs, w, true, 0, &nz, s, plan, desc, 1, 1));
         }
         return 0;
     }
@@ -1103,10 +1139,19 @@ static int trsm_lt_impl(const ct_factor* fc, TS* Y, int64_t k, int64_t ldy, hipS
                                  plan));
             return 0;
         };
+        const bool inv4 = x3 && f->RiC4 && (int64_t)ob * k * (int64_t)sizeof(TS) <= f->wq_elems * 8;
         for (int64_t Bk = 0; Bk < nbo; ++Bk) {
             const int64_t K0 = Bk * ob;
             const int64_t w = std::min<int64_t>(ob, n - K0);
-            for (int64_t k0 = K0; k0 < K0 + w; k0 += 256) {
+            if constexpr (sizeof(TS) == 4)
+                if (inv4) {
+                    // Z_B = R_BB^{-T} Y_B with the stored inverse of the whole block
+                    int nz;
+                    CT_HIP((launch_copy_block<TS>(Y + K0, ldy, S, ob, (int)w, (int)k, s, nullptr)));
+                    CT_HIP(launch_nt_lp<M_BF16X3>((const float*)f->RiC4 + (size_t)Bk * ob * ob, ob, S, ob, Y + K0, ldy,
+                                                  w, (int)k, w, false, 0, &nz, s, nullptr, nullptr));
+                }
+            for (int64_t k0 = K0; !inv4 && k0 < K0 + w; k0 += 256) {
                 const int64_t b = k0 / 256;
                 const int bo = (int)std::min<int64_t>(256, n - k0);
                 int nz;
@@ -1377,6 +1422,25 @@ static int r_copies(ct_factor* f, char* work, const Layout& L, hipStream_t s)
         if (e == hipSuccess) e = launch_rt<float>((const float*)f->A, lda, n, f->rt_ob, (float*)f->Rt, s);
     }
     if (e != hipSuccess) return fail(-1000 - (int)e, "R copies: %s", hipGetErrorString(e));
+    if (f->prec == CT_PREC_BF16X3 && f->rt_ob == 1024) {
+        // inverses of the 1024 x 1024 diagonal blocks: R_BB^{-1} I by the
+        // blocked substitution of the block itself (FP32 products), stored
+        // column-major (RiC4) and transposed to row-major (RiR4)
+        const int ob = 1024;
+        const int64_t nbo = (n + ob - 1) / ob;
+        float* Ic = (float*)(work + L.Ri4);
+        float* Ir = Ic + (size_t)nbo * ob * ob;
+        for (int64_t Bk = 0; Bk < nbo; ++Bk) {
+            const int w = (int)std::min<int64_t>(ob, n - Bk * ob);
+            float* C = Ic + (size_t)Bk * ob * ob;
+            CT_HIP(launch_eye<float>(C, ob, ob, ob, w, s));
+            int r = inner_solve<float>(f, C - Bk * ob, ob, w, Bk, false, nullptr, s);
+            if (r) return r;
+            CT_HIP((launch_transpose<float, float, true, false>(C, Ir + (size_t)Bk * ob * ob, ob, ob, ob, ob, s)));
+        }
+        f->RiC4 = Ic;
+        f->RiR4 = Ir;
+    }
     return 0;
 }
 

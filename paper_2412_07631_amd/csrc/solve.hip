@@ -583,6 +583,25 @@ hipError_t launch_rinv(const TS* A, int64_t lda, int64_t n, TS* RiR, TS* RiC, do
     return hipGetLastError();
 }
 
+// C (column-major, ld ld, rows x cols) = the identity on its leading w x w
+// block, zero elsewhere
+template <typename TS>
+__global__ void __launch_bounds__(256) eye_kernel(TS* __restrict__ C, int64_t ld, int64_t rows, int cols, int w)
+{
+    for (int j = blockIdx.y; j < cols; j += gridDim.y)
+        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < rows; i += (int64_t)gridDim.x * 256)
+            C[i + (int64_t)j * ld] = (i == j && i < w) ? (TS)1 : (TS)0;
+}
+
+template <typename TS>
+hipError_t launch_eye(TS* C, int64_t ld, int64_t rows, int cols, int w, hipStream_t s)
+{
+    const dim3 grid((unsigned)((rows + 255) / 256), (unsigned)(cols < 65535 ? cols : 65535));
+    hipLaunchKernelGGL(eye_kernel<TS>, grid, dim3(256), 0, s, C, ld, rows, cols, w);
+    return hipGetLastError();
+}
+template hipError_t launch_eye<float>(float*, int64_t, int64_t, int, int, hipStream_t);
+
 template <typename TS>
 hipError_t launch_rt(const TS* A, int64_t lda, int64_t n, int ob, TS* Rt, hipStream_t s)
 {

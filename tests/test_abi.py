@@ -98,7 +98,8 @@ def test_stream_workspace_arithmetic():
     tile = (lda * 256 * 8 + 255) // 256 * 256
     assert lo == base + 4 * tile and full == base + 9 * tile
     lo32, full32 = ctqr.qr_stream_workspace(m, n, lda, ctqr.PREC_BF16X3, 8, 1024)
-    rc32 = (up(2 * nbt * 256 * 256 * 4) + up(nbt * 256 * 256 * 8) + up(rt * 4)
+    # (plus, for BF16x3, the inverses of the 1024-column diagonal blocks in two layouts)
+    rc32 = (up(2 * nbt * 256 * 256 * 4) + up(nbt * 256 * 256 * 8) + up(rt * 4) + up(2 * nro * 1024 * 1024 * 4)
             + up((nbo * m - 256 * (nbo * (nbo - 1) // 2)) * 256 * 4))
     base32 = ctqr.qr_workspace(m, n, ctqr.PREC_BF16X3, 8) - rc32
     assert full32 == base32 + 3 * ((lda * 1024 * 4 + 255) // 256 * 256)
