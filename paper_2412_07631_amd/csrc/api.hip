@@ -69,6 +69,9 @@ hipError_t launch_nt_x3dl(const void* Xh, const void* Xl, int64_t ldx, const voi
 // the direct-to-LDS BF16x3 products take blocks of at least this many
 // reflectors (narrower ones would leave most of a 256-row tile empty)
 constexpr int kX3dlMinWidth = 256;
+// up to this many columns (the solves' right-hand sides) the FP32 operands
+// are split as they are read instead of being split in a pass of their own
+constexpr int kX3dlSplitAtRead = 2048;
 void nt_set_cus(int cus);
 hipError_t launch_split_x3(const float* src, int64_t lds, void* hi, void* lo, int64_t ldd, int64_t rows, int64_t cols,
                            hipStream_t s);
@@ -363,9 +366,10 @@ static int64_t ldvt_of(int nbv) { return (nbv + 15) / 16 * 16; }
 // Masked copies of the reflector block into f->Vm / f->Vt
 template <typename TS>
 static int prep_block(ct_factor* f, const TS* V, int64_t ldv, int64_t mk, int nbv, hipStream_t s,
-                      TS* vt_dst = nullptr)
+                      TS* vt_dst = nullptr, bool with_vt = true)
 {
-    CT_HIP(launch_prep_v<TS>(V, ldv, mk, nbv, (TS*)f->Vm, f->ldvm, vt_dst ? vt_dst : (TS*)f->Vt, ldvt_of(nbv), s));
+    CT_HIP(launch_prep_v<TS>(V, ldv, mk, nbv, (TS*)f->Vm, f->ldvm,
+                             with_vt ? (vt_dst ? vt_dst : (TS*)f->Vt) : nullptr, ldvt_of(nbv), s));
     return 0;
 }
 
@@ -428,7 +432,11 @@ static int larfb_nt(ct_factor* f, int64_t mk, int nbv, const double* T, int64_t 
             }
         } else {
             if (o.mask) return fail(-1, "%s", "internal: masked operand on the low-precision kernel");
-            if (MODE == M_BF16X3 && f->S3) {
+            if (MODE == M_BF16X3 && f->S3 && nbv >= kX3dlMinWidth && nc <= kX3dlSplitAtRead) {
+                // few columns (a solve): both operands split as they are read
+                CT_HIP(launch_nt_x3dl(o.vm, nullptr, o.ldvm, C, nullptr, ldc, (float*)f->Wp, nbv, nbv, nc, mk, false,
+                                      f->wp_elems * 2, &nz, s));
+            } else if (MODE == M_BF16X3 && f->S3) {
                 // the block's bfloat16 halves, column-major like Vm
                 char* hi = (char*)f->S3;
                 char* lo = hi + (size_t)o.ldvm * nbv * 2;
@@ -478,6 +486,8 @@ static int larfb_nt(ct_factor* f, int64_t mk, int nbv, const double* T, int64_t 
         if constexpr (MODE == M_F64 || MODE == M_F32)
             CT_HIP(launch_nt<TS>((const TS*)o.vt, o.ldvt, (const TS*)f->Wq, ldw, C, ldc, mk, nc, nbv, true, 0, &nz2, s,
                                  plan, desc, 0, 1));
+        else if (MODE == M_BF16X3 && f->S3 && nbv >= kX3dlMinWidth && nc <= kX3dlSplitAtRead)
+            CT_HIP(launch_nt_x3dl(o.vt, nullptr, o.ldvt, f->Wq, nullptr, ldw, C, ldc, mk, nc, nbv, true, 0, &nz2, s));
         else if (MODE == M_BF16X3 && f->S3) {
             // V (row-major) and W' in bfloat16 halves: V to the split scratch,
             // W' to the split-K sum buffer, which is free by now
@@ -972,7 +982,8 @@ static int apply_qt_impl(const ct_factor* fc, TS* B, int64_t nrhs, int64_t ldb, 
         op = &ops;
         if constexpr (sizeof(TS) == 4)
             if (x3 && transpose && !desc && f->VtAll) {
-                r = prep_block<TS>(f, Vb + k0, f->lda, f->m - k0, bo, s);
+                // the masked column-major copy only: the row-major one is VtAll's
+                r = prep_block<TS>(f, Vb + k0, f->lda, f->m - k0, bo, s, nullptr, false);
                 if (r) return r;
                 ops.vm = f->Vm;
                 ops.ldvm = f->ldvm;
@@ -1076,8 +1087,8 @@ static int trsm_impl(const ct_factor* fc, TS* B, int64_t nrhs, int64_t ldb, hipS
             const TS* X = Rt + (size_t)ob * ob * (size_t)(Bk * (Bk - 1) / 2);
             if constexpr (sizeof(TS) == 4)
                 if (x3 && !desc) {
-                    CT_HIP(launch_nt_lp<M_BF16X3>(X, ob, B + K0, ldb, B, ldb, K0, (int)nrhs, w, true, 0, &nz, s,
-                                                  nullptr, nullptr));
+                    CT_HIP(launch_nt_x3dl(X, nullptr, ob, B + K0, nullptr, ldb, B, ldb, K0, (int)nrhs, w, true, 0, &nz,
+                                          s));
                     continue;
                 }
             CT_HIP(launch_nt<TS>(X, ob, B + K0, ldb, B, ldb, K0, (int)nrhs, w, true, 0, &nz, s, plan, desc, 1, 1));
@@ -1131,8 +1142,12 @@ static int trsm_lt_impl(const ct_factor* fc, TS* Y, int64_t k, int64_t ldy, hipS
             int nz;
             if constexpr (sizeof(TS) == 4)
                 if (x3) {
-                    CT_HIP(launch_nt_lp<M_BF16X3>(A + r0 + c0 * lda, lda, Y + r0, ldy, Y + c0, ldy, P, (int)k, K, true,
-                                                  0, &nz, s, nullptr, nullptr));
+                    if (K >= 256 && (r0 % 4) == 0)
+                        CT_HIP(launch_nt_x3dl(A + r0 + c0 * lda, nullptr, lda, Y + r0, nullptr, ldy, Y + c0, ldy, P,
+                                              (int)k, K, true, 0, &nz, s));
+                    else
+                        CT_HIP(launch_nt_lp<M_BF16X3>(A + r0 + c0 * lda, lda, Y + r0, ldy, Y + c0, ldy, P, (int)k, K,
+                                                      true, 0, &nz, s, nullptr, nullptr));
                     return 0;
                 }
             CT_HIP(launch_nt<TS>(A + r0 + c0 * lda, lda, Y + r0, ldy, Y + c0, ldy, P, (int)k, K, true, 0, &nz, s,

@@ -325,6 +325,7 @@ __global__ void __launch_bounds__(256) prep_v_kernel(const T* __restrict__ V, in
         tile[ii][kk] = v;
     }
     __syncthreads();
+    if (!Vt) return;                                   // (the column-major copy only)
     for (int e = t; e < 64 * 64; e += 256) {
         const int kk = e / 64, ii = e % 64;            // ii fastest: coalesced along the row of Vt
         const int64_t k = k0 + kk;
@@ -814,10 +815,31 @@ __device__ __forceinline__ int dl_swz32(int r) { return (r ^ (r >> 3)) & 7; }
 
 constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | 0xF70; }
 
-// YF32: Y is FP32 (the trailing matrix in W = V^T C), loaded into LDS as is
-// and split into its bfloat16 halves when the fragments are read
-// (hi = bf16(y), lo = bf16(y - hi), round to nearest even, as everywhere).
-template <class CF, bool SUB, bool YF32>
+// Split of 8 FP32 values (two 16-byte LDS reads) into bfloat16 halves,
+// hi = bf16(y), lo = bf16(y - hi), round to nearest even, as everywhere; in
+// pairs: one packed conversion gives both high halves, whose FP32 values are
+// the packed word's halves moved into place.
+__device__ __forceinline__ void split8(const f4_t& y0, const f4_t& y1, bf8_t& bh, bf8_t& bl)
+{
+    typedef __bf16 bf2_t __attribute__((ext_vector_type(2)));
+    typedef float f2_t __attribute__((ext_vector_type(2)));
+    u4v hp, lp;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const f2_t yv = e < 2 ? f2_t{y0[2 * e], y0[2 * e + 1]} : f2_t{y1[2 * e - 4], y1[2 * e - 3]};
+        const uint32_t h = __builtin_bit_cast(uint32_t, __builtin_convertvector(yv, bf2_t));
+        const f2_t hf = {__uint_as_float(h << 16), __uint_as_float(h & 0xffff0000u)};
+        hp[e] = h;
+        lp[e] = __builtin_bit_cast(uint32_t, __builtin_convertvector(yv - hf, bf2_t));
+    }
+    bh = __builtin_bit_cast(bf8_t, hp);
+    bl = __builtin_bit_cast(bf8_t, lp);
+}
+
+// XF32 / YF32: that operand is FP32 (the trailing matrix in W = V^T C; the
+// FP32 factor copies a solve reads), loaded into LDS as is and split into its
+// bfloat16 halves when the fragments are read.
+template <class CF, bool SUB, bool XF32, bool YF32>
 __global__ void __launch_bounds__(CF::NT, 1) gemm_x3_dl_kernel(NtArgs a)
 {
     extern __shared__ __attribute__((aligned(1024))) char dl_lds[];
@@ -843,7 +865,16 @@ __global__ void __launch_bounds__(CF::NT, 1) gemm_x3_dl_kernel(NtArgs a)
 #pragma unroll
     for (int i = 0; i < CF::LPW; ++i) {
         const int idx = CF::LPW * wv + i;
-        if (idx < CF::XBLK) {
+        if (XF32 && idx < CF::XBLK) {
+            const int blk = idx;                       // 8 rows of 128 bytes
+            const int r = lane >> 3, ch = (lane & 7) ^ dl_swz32((blk & 1) * 8 + r);
+            int64_t p = p0 + blk * 8 + r;
+            if (p >= a.P) p = a.P - 1;
+            src[i] = (const char*)a.X + (p * a.ldx + ch * 4) * 4;
+            dst[i] = blk * 1024;
+            ksh[i] = 2;
+            kk0[i] = ch * 4;
+        } else if (idx < CF::XBLK) {
             const int h = idx / (CF::BP / 16), rb = idx % (CF::BP / 16);
             const int r = lane >> 2, ch = (lane & 3) ^ dl_swz16(r);
             int64_t p = p0 + rb * 16 + r;
@@ -882,7 +913,9 @@ __global__ void __launch_bounds__(CF::NT, 1) gemm_x3_dl_kernel(NtArgs a)
 
     const int c = lane & 15, g = lane >> 4;
     const int wp = (wv / CF::WVQ) * 16 * CF::WTP, wq = (wv % CF::WVQ) * 16 * CF::WTQ;
-    const int xfrag = (c * 4 + (g ^ dl_swz16(c))) * 16;
+    const int xfrag = XF32 ? (c >> 3) * 1024 + (c & 7) * 128 + 16 * ((2 * g) ^ dl_swz32(c))
+                           : (c * 4 + (g ^ dl_swz16(c))) * 16;
+    const int xfrag1 = XF32 ? (c >> 3) * 1024 + (c & 7) * 128 + 16 * ((2 * g + 1) ^ dl_swz32(c)) : 0;
     const int yfrag0 = YF32 ? (c >> 3) * 1024 + (c & 7) * 128 + 16 * ((2 * g) ^ dl_swz32(c))
                             : (c * 4 + (g ^ dl_swz16(c))) * 16;
     const int yfrag1 = YF32 ? (c >> 3) * 1024 + (c & 7) * 128 + 16 * ((2 * g + 1) ^ dl_swz32(c)) : 0;
@@ -901,23 +934,12 @@ __global__ void __launch_bounds__(CF::NT, 1) gemm_x3_dl_kernel(NtArgs a)
         for (int j = 0; j < CF::WTQ; ++j) {
             if constexpr (YF32) {
                 const char* yb = base + 2 * CF::XHALF + (wq + 16 * j) * 128;
+                // (the two reads into locals first: passed straight into the
+                // call, this compiler version made the first LDS read wait for
+                // every load in flight, the next stage's included)
                 const f4_t y0 = *(const f4_t*)(yb + yfrag0);
                 const f4_t y1 = *(const f4_t*)(yb + yfrag1);
-                // pairs: one packed conversion gives both high halves, whose
-                // FP32 values are the packed word's halves moved into place
-                typedef __bf16 bf2_t __attribute__((ext_vector_type(2)));
-                typedef float f2_t __attribute__((ext_vector_type(2)));
-                u4v hp, lp;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const f2_t yv = e < 2 ? f2_t{y0[2 * e], y0[2 * e + 1]} : f2_t{y1[2 * e - 4], y1[2 * e - 3]};
-                    const uint32_t h = __builtin_bit_cast(uint32_t, __builtin_convertvector(yv, bf2_t));
-                    const f2_t hf = {__uint_as_float(h << 16), __uint_as_float(h & 0xffff0000u)};
-                    hp[e] = h;
-                    lp[e] = __builtin_bit_cast(uint32_t, __builtin_convertvector(yv - hf, bf2_t));
-                }
-                bh[j] = __builtin_bit_cast(bf8_t, hp);
-                bl[j] = __builtin_bit_cast(bf8_t, lp);
+                split8(y0, y1, bh[j], bl[j]);
             } else {
                 const int rb = (wq >> 4) + j;
                 bh[j] = *(const bf8_t*)(base + 2 * CF::XHALF + rb * 1024 + yfrag0);
@@ -927,8 +949,16 @@ __global__ void __launch_bounds__(CF::NT, 1) gemm_x3_dl_kernel(NtArgs a)
 #pragma unroll
         for (int i = 0; i < CF::WTP; ++i) {
             const int rb = (wp >> 4) + i;
-            const bf8_t ah = *(const bf8_t*)(base + rb * 1024 + xfrag);
-            const bf8_t al = *(const bf8_t*)(base + CF::XHALF + rb * 1024 + xfrag);
+            bf8_t ah, al;
+            if constexpr (XF32) {
+                const char* xb = base + (wp + 16 * i) * 128;
+                const f4_t x0 = *(const f4_t*)(xb + xfrag);
+                const f4_t x1 = *(const f4_t*)(xb + xfrag1);
+                split8(x0, x1, ah, al);
+            } else {
+                ah = *(const bf8_t*)(base + rb * 1024 + xfrag);
+                al = *(const bf8_t*)(base + CF::XHALF + rb * 1024 + xfrag);
+            }
 #pragma unroll
             for (int j = 0; j < CF::WTQ; ++j) {
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
@@ -1060,8 +1090,12 @@ static hipError_t dl_set_lds()
 {
     static bool done = false;
     if (done) return hipSuccess;
-    const void* k[3] = {(const void*)gemm_x3_dl_kernel<CF, true, false>, (const void*)gemm_x3_dl_kernel<CF, false, false>,
-                        (const void*)gemm_x3_dl_kernel<CF, false, true>};
+    const void* k[6] = {(const void*)gemm_x3_dl_kernel<CF, true, false, false>,
+                        (const void*)gemm_x3_dl_kernel<CF, false, false, false>,
+                        (const void*)gemm_x3_dl_kernel<CF, false, false, true>,
+                        (const void*)gemm_x3_dl_kernel<CF, true, true, true>,
+                        (const void*)gemm_x3_dl_kernel<CF, false, true, true>,
+                        (const void*)gemm_x3_dl_kernel<CF, true, false, true>};
     for (const void* f : k) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, CF::LDS);
         if (e != hipSuccess) return e;
@@ -1092,7 +1126,8 @@ static int dl_split(int tiles, int64_t K, int bk)
 }
 
 template <class CF>
-static hipError_t launch_x3dl_cfg(NtArgs& a, bool sub, bool yf32, int64_t ocap, int* nz_out, hipStream_t s)
+static hipError_t launch_x3dl_cfg(NtArgs& a, bool sub, bool xf32, bool yf32, int64_t ocap, int* nz_out,
+                                  hipStream_t s)
 {
     hipError_t e = dl_set_lds<CF>();
     if (e != hipSuccess) return e;
@@ -1112,32 +1147,38 @@ static hipError_t launch_x3dl_cfg(NtArgs& a, bool sub, bool yf32, int64_t ocap, 
     a.kslice = ks;
     *nz_out = nz;
     const dim3 grid(padded_tiles(tiles), nz);
-    if (sub)
-        hipLaunchKernelGGL((gemm_x3_dl_kernel<CF, true, false>), grid, dim3(CF::NT), CF::LDS, s, a);
-    else if (yf32)
-        hipLaunchKernelGGL((gemm_x3_dl_kernel<CF, false, true>), grid, dim3(CF::NT), CF::LDS, s, a);
-    else
-        hipLaunchKernelGGL((gemm_x3_dl_kernel<CF, false, false>), grid, dim3(CF::NT), CF::LDS, s, a);
+#define CT_X3DL(S_, X_, Y_) hipLaunchKernelGGL((gemm_x3_dl_kernel<CF, S_, X_, Y_>), grid, dim3(CF::NT), CF::LDS, s, a)
+    if (xf32 && !yf32) return hipErrorInvalidValue;
+    if (sub) {
+        if (xf32) CT_X3DL(true, true, true);
+        else if (yf32) CT_X3DL(true, false, true);
+        else CT_X3DL(true, false, false);
+    } else {
+        if (xf32) CT_X3DL(false, true, true);
+        else if (yf32) CT_X3DL(false, false, true);
+        else CT_X3DL(false, false, false);
+    }
+#undef CT_X3DL
     return hipGetLastError();
 }
 
 // out (+)= X Y^T with X = Xhi + Xlo (P x K) and Y = Yhi + Ylo (Q x K), the
-// four planes bfloat16 -- or, with Yl null and not sub, Y given in FP32 at Yh
-// and split as it is read -- all K-contiguous, leading dimensions multiples
-// of 8 elements, 16-byte aligned bases.  sub: out -= X Y^T (no split-K);
-// otherwise split-K partials at out + z ldo Q, as launch_nt_lp.
+// planes bfloat16; a null low plane means that operand is FP32 (at Xh / Yh)
+// and is split as it is read (X in FP32 only with Y in FP32 too).  All
+// K-contiguous, leading dimensions multiples of 8 elements (4 for FP32),
+// 16-byte aligned bases.  sub: out -= X Y^T (no split-K); otherwise split-K
+// partials at out + z ldo Q, as launch_nt_lp.
 hipError_t launch_nt_x3dl(const void* Xh, const void* Xl, int64_t ldx, const void* Yh, const void* Yl, int64_t ldy,
                           float* out, int64_t ldo, int64_t P, int Q, int64_t K, bool sub, int64_t ocap, int* nz_out,
                           hipStream_t s)
 {
-    if (sub && !Yl) return hipErrorInvalidValue;
     NtArgs a;
     a.X = Xh; a.Xlo = Xl; a.ldx = ldx; a.Y = Yh; a.Ylo = Yl; a.ldy = ldy; a.out = out; a.ldo = ldo;
     a.P = P; a.Q = Q; a.K = K; a.sub = sub ? 1 : 0;
     a.desc = nullptr; a.desc_y = 0; a.desc_out = 0; a.maskx = 0; a.tout = 0; a.upper = 0;
-    const bool yf32 = !Yl;
-    if (g_x3dl_cfg == 1) return launch_x3dl_cfg<DlBig>(a, sub, yf32, ocap, nz_out, s);
-    return launch_x3dl_cfg<DlSmall>(a, sub, yf32, ocap, nz_out, s);
+    const bool xf32 = !Xl, yf32 = !Yl;
+    if (g_x3dl_cfg == 1) return launch_x3dl_cfg<DlBig>(a, sub, xf32, yf32, ocap, nz_out, s);
+    return launch_x3dl_cfg<DlSmall>(a, sub, xf32, yf32, ocap, nz_out, s);
 }
 
 }  // namespace ctqr
