@@ -15,6 +15,8 @@
 // also solves the nrhs right-hand sides with S steps of FP64-residual
 // refinement (ct_solve_refined, semi-normal-equations steps) and times it;
 // --group G (default 8, 0: none) sets the grouping of its sparse products.
+// --adjoint K times ct_solve_backward on K gradients (K <= nrhs) next to a
+// forward solve of K slices.
 //
 // Scanner: grid width 1, source-isocentre distance 2, source-detector 4, flat
 // detector whose fan covers the circle inscribed in the image (the reading of
@@ -64,7 +66,7 @@ int main(int argc, char** argv)
     long copy_mib = 0;
     double stream_gib = 0.0;
     long tile_cols = 1024;
-    int nb_out = 0, refine = -1, group = 8;
+    int nb_out = 0, refine = -1, group = 8, adjoint = 0;
     const char* pname = "bf16x3";
     for (int i = 1; i + 1 < argc; i += 2) {
         if (!strcmp(argv[i], "--n-pix")) n_pix = atoi(argv[i + 1]);
@@ -78,6 +80,7 @@ int main(int argc, char** argv)
         else if (!strcmp(argv[i], "--nb-out")) nb_out = atoi(argv[i + 1]);
         else if (!strcmp(argv[i], "--refine")) refine = atoi(argv[i + 1]);
         else if (!strcmp(argv[i], "--group")) group = atoi(argv[i + 1]);
+        else if (!strcmp(argv[i], "--adjoint")) adjoint = atoi(argv[i + 1]);
         else {
             fprintf(stderr, "unknown option %s\n", argv[i]);
             return 2;
@@ -201,6 +204,29 @@ int main(int argc, char** argv)
     printf("info %lld qr_ms %.1f qr_tflops %.2f solve_ms %.2f\n", (long long)info, qr_ms, fl / (qr_ms * 1e-3) / 1e12,
            sol_ms);
     fflush(stdout);
+    if (adjoint > 0 && adjoint <= nrhs) {
+        // gradB = Q R^{-T} G for K columns of the right-hand sides as G, and
+        // the forward solve of the same K columns, each timed twice
+        void* Gb;
+        HIP_OK(hipMalloc(&Gb, (size_t)adjoint * lda * es));
+        HIP_OK(hipMemcpy(Gb, B, (size_t)adjoint * lda * es, hipMemcpyDeviceToDevice));
+        float fms = 0, bms = 0;
+        for (int rep = 0; rep < 2; ++rep) {
+            HIP_OK(hipEventRecord(ev[0], s));
+            CT_OK(ct_apply_qt(f, Gb, adjoint, lda, s));
+            CT_OK(ct_trsm_solve(f, Gb, adjoint, lda, s));
+            HIP_OK(hipEventRecord(ev[1], s));
+            HIP_OK(hipEventRecord(ev[2], s));
+            CT_OK(ct_solve_backward(f, B, adjoint, lda, Gb, lda, s));
+            HIP_OK(hipEventRecord(ev[3], s));
+            HIP_OK(hipEventSynchronize(ev[3]));
+            HIP_OK(hipEventElapsedTime(&fms, ev[0], ev[1]));
+            HIP_OK(hipEventElapsedTime(&bms, ev[2], ev[3]));
+        }
+        printf("adjoint: %d gradients %.2f ms, forward solve of %d slices %.2f ms\n", adjoint, bms, adjoint, fms);
+        fflush(stdout);
+        HIP_OK(hipFree(Gb));
+    }
     if (refine >= 0) {
         // FP64 CSR and CSC copies of A, FP64 right-hand sides (the same
         // pattern), then the refined solve twice (the second one timed)
