@@ -30,6 +30,7 @@ METRIC = "QR TFLOP/s + slices/s at 256^2: FP32/BF16+refine vs FP64 on MI355X, re
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "f16": 2500.0, "bf16x3": 2500.0}
 ISSUE_FACTOR = {"f64": 1, "f32": 1, "bf16": 1, "f16": 1, "bf16x3": 3}
 HBM_PEAK_GBS = 8000.0
+ROOT = os.path.dirname(os.path.abspath(__file__))
 
 
 def log(*a):
@@ -141,6 +142,28 @@ def batched_leg(ctqr, synth, torch, f, sc, Bd, dev, total, sp, X64=None):
             "graph_vs_fp64": vs64,
             "adjoint_gradients": k, "adjoint_ms": bwd_ms, "forward_same_slices_ms": fwd_ms, "fd_step": h,
             "fd_err_by_norms": fd_err}
+
+
+def counted_traffic(prec, dom):
+    """HBM bytes per launch of the roofline kernel from the committed
+    hardware-counter summary (FETCH_SIZE and WRITE_SIZE passes, scaled by the
+    same counters on a plain copy), or None when there is none for this
+    kernel or the kernel's source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "x3dl_update_c3_256_traffic.json")
+    if prec != "bf16x3" or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_2412_07631_amd", "csrc", "gemm_lds.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != rec.get("source_sha256_16"):
+        return None
+    k = rec.get("sub" if dom == "update_cvw" else "vtc")
+    if not k:
+        return None
+    return {"bytes_per_launch": k["traffic_bytes_per_launch"], "fetch_bytes_per_launch": k["fetch_bytes_per_launch"],
+            "write_bytes_per_launch": k["write_bytes_per_launch"], "over_algorithmic":
+            k["traffic_bytes_per_launch"] / k["algorithmic_bytes_per_launch"],
+            "source": "profiles/x3dl_update_c3_256_traffic.json"}
 
 
 def main():
@@ -449,7 +472,7 @@ def main():
         # 1024-wide blocks: the direct-to-LDS kernel on 256 x 256 tiles; both
         # operands of C -= V W' arrive split into bfloat16 halves, V of
         # W = V^T C too, while C is split as it is read
-        tname = "gemm_x3_dl_kernel<DlCfg<8, 4, 2, 4, 2>, %s>"
+        tname = "gemm_x3_dl_kernel<DlCfg<8, 4, 2, 4, 2, 1>, %s>"
         kname = (tname % "true, false, false") + " (C -= V W')" if dom == "update_cvw" else \
             (tname % "false, false, true") + " (W = V^T C)"
     else:
@@ -471,8 +494,9 @@ def main():
                                "frac_of_peak": achieved * issue / peak}
     roofline = {**bound, "kernel": kname, "flop_per_byte": intensity, "ridge_flop_per_byte": ridge,
                 "launches": d["launches"], "avg_launch_ms": d["ms"] / max(d["launches"], 1),
+                "algorithmic_bytes_per_launch": d["bytes"] / max(d["launches"], 1),
                 "algorithmic_gbs": d["bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0,
-                "traffic": None,
+                "traffic": counted_traffic(args.prec, dom),
                 "other_kernel": {k: {"tflops": prof[k]["flop"] / (prof[k]["ms"] * 1e-3) / 1e12 if prof[k]["ms"] else 0,
                                      "ms": prof[k]["ms"]} for k in prof if k != dom}}
 

@@ -60,6 +60,14 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("driver build failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
     os.replace(exe + ".tmp", exe)
+    # probe of the hot kernels for hardware-counter passes (no cooperative launches)
+    probe = os.path.join(HERE, "kernel_probe")
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-O2", "-std=c++17", os.path.join(CSRC, "kernel_probe.cpp"),
+           "-o", probe + ".tmp", "-L" + HERE, "-lctqr", "-Wl,-rpath,$ORIGIN"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("probe build failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
+    os.replace(probe + ".tmp", probe)
     if verbose:
         print("built", OUT, "and", exe)
     return OUT
