@@ -89,6 +89,14 @@ int ct_build_system(const ct_geometry* g, int dtype, void* A, int64_t lda, void*
 int ct_build_csr(const ct_geometry* g, int64_t* row_ptr, int32_t* col, double* val, int64_t nnz_cap,
                  void* stream);
 
+/* Flag OR'ed into prec for ct_qr_workspace and ct_qr_factor: keep no
+ * solve-side copies (the row-major reflector blocks, the inverses of R's
+ * diagonal blocks and the row-major copy of R above its diagonal), which at
+ * 512^2 would take about 290 GB next to the 278 GB FP32 matrix.  The factor
+ * is the same; its solves read V and R in place (more passes, slower), and
+ * its workspace is about 14 GB at 512^2 with 1024-column blocks. */
+#define CT_QR_NO_SOLVE_COPIES 0x100
+
 /* Workspace bytes for ct_qr_factor of an m x n matrix at precision prec that
  * will later solve up to max_nrhs right-hand sides per call. */
 int ct_qr_workspace(int64_t m, int64_t n, int prec, int64_t max_nrhs, size_t* bytes);

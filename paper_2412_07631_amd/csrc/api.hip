@@ -1350,10 +1350,12 @@ int ct_qr_workspace(int64_t m, int64_t n, int prec, int64_t max_nrhs, size_t* by
 {
     CT_ARG(m > 0, 1, "m");
     CT_ARG(n > 0 && n <= m, 2, "n (need 0 < n <= m)");
+    const bool copies = !(prec & CT_QR_NO_SOLVE_COPIES);
+    prec &= ~CT_QR_NO_SOLVE_COPIES;
     CT_ARG(prec >= CT_PREC_F64 && prec <= CT_PREC_BF16X3, 3, "prec");
     CT_ARG(max_nrhs >= 0, 4, "max_nrhs");
     CT_ARG(bytes != nullptr, 5, "bytes");
-    *bytes = layout(m, n, prec, max_nrhs, nb_out_for(n)).total;
+    *bytes = layout(m, n, prec, max_nrhs, nb_out_for(n), copies).total;
     return 0;
 }
 
@@ -1705,12 +1707,14 @@ int ct_qr_factor(void* A, int64_t m, int64_t n, int64_t lda, int prec, double* t
     CT_ARG(m > 0, 2, "m");
     CT_ARG(n > 0 && n <= m, 3, "n (need 0 < n <= m)");
     CT_ARG(lda >= m && lda % 16 == 0, 4, "lda");
+    const bool copies = !(prec & CT_QR_NO_SOLVE_COPIES);
+    prec &= ~CT_QR_NO_SOLVE_COPIES;
     CT_ARG(prec >= CT_PREC_F64 && prec <= CT_PREC_BF16X3, 5, "prec");
     CT_ARG(tau != nullptr, 6, "tau");
     CT_ARG(work != nullptr && aligned(work), 7, "work");
     CT_ARG(max_nrhs >= 0, 9, "max_nrhs");
     CT_ARG(f_out != nullptr, 10, "f");
-    const Layout L = layout(m, n, prec, max_nrhs, nb_out_for(n));
+    const Layout L = layout(m, n, prec, max_nrhs, nb_out_for(n), copies);
     CT_ARG(work_bytes >= L.total, 8, "work_bytes (see ct_qr_workspace)");
     int r = device_setup();
     if (r) return r;
@@ -1725,9 +1729,9 @@ int ct_qr_factor(void* A, int64_t m, int64_t n, int64_t lda, int prec, double* t
     }
     CT_HIP(hipMemsetAsync((char*)work + L.words, 0, 256, s));
     CT_HIP(panel_reset(f->part, f->gpart, s));
-    f->VtAll = (char*)work + L.VtAll;
+    f->VtAll = copies ? (char*)work + L.VtAll : nullptr;
     int rc = f->f64 ? factor_impl<double>(f, s) : factor_impl<float>(f, s);
-    if (!rc) rc = r_copies(f, (char*)work, L, s);
+    if (!rc && copies) rc = r_copies(f, (char*)work, L, s);
     if (rc) {
         delete f;
         return rc;

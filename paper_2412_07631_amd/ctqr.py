@@ -24,6 +24,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 F64, F32 = 0, 1
+QR_NO_SOLVE_COPIES = 0x100    # flag OR'ed into prec: no solve-side copies (lean workspace)
 REFINE_QR, REFINE_SNE = 0, 1
 PREC_F64, PREC_F32, PREC_BF16, PREC_F16, PREC_BF16X3 = 0, 1, 2, 3, 4
 PREC_NAMES = {"f64": PREC_F64, "f32": PREC_F32, "bf16": PREC_BF16, "f16": PREC_F16, "bf16x3": PREC_BF16X3}
@@ -187,15 +188,18 @@ class Factor:
             self.handle = None
 
 
-def qr_factor(A: torch.Tensor, m: int, n: int, prec: int, max_nrhs: int = 512, stream=None) -> Factor:
-    """Factor A (an (n, lda) tensor holding the m x n matrix) in place."""
+def qr_factor(A: torch.Tensor, m: int, n: int, prec: int, max_nrhs: int = 512, stream=None,
+              solve_copies: bool = True) -> Factor:
+    """Factor A (an (n, lda) tensor holding the m x n matrix) in place
+    (solve_copies=False: the lean workspace of CT_QR_NO_SOLVE_COPIES)."""
     want = torch.float64 if prec == PREC_F64 else torch.float32
     if A.dtype != want:
         raise TypeError("A must be %s for this precision" % want)
+    p = prec if solve_copies else prec | QR_NO_SOLVE_COPIES
     tau = torch.zeros(n, dtype=torch.float64, device=A.device)
-    work = torch.empty(qr_workspace(m, n, prec, max_nrhs), dtype=torch.uint8, device=A.device)
+    work = torch.empty(qr_workspace(m, n, p, max_nrhs), dtype=torch.uint8, device=A.device)
     h = _vp()
-    _check(_lib.ct_qr_factor(_ptr(A), m, n, A.shape[1], prec, _ptr(tau), _ptr(work), work.numel(), max_nrhs,
+    _check(_lib.ct_qr_factor(_ptr(A), m, n, A.shape[1], p, _ptr(tau), _ptr(work), work.numel(), max_nrhs,
                              ctypes.byref(h), _stream(stream)))
     return Factor(h, A, tau, work, m, n, prec, max_nrhs)
 

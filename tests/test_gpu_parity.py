@@ -331,6 +331,38 @@ def test_refined_sne_parity(ct, prec, steps, tol):
     assert gn[-1] < gn[0]
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
+def test_lean_factor_without_solve_copies(ct, prec):
+    """CT_QR_NO_SOLVE_COPIES: the same factor in a smaller workspace; its
+    solves (which then read V and R in place), the refinement and the
+    adjoint give the oracle's results like those of the full factor."""
+    sc, A, VR, tau = problem("multi")
+    _, P, B = sinograms(sc, A, 3, 50, 5e4)
+    Xs = O.solve(VR, tau, B)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    full = ct.qr_workspace(sc.m, sc.n, ct.PREC_NAMES[prec], 64)
+    lean = ct.qr_workspace(sc.m, sc.n, ct.PREC_NAMES[prec] | ct.QR_NO_SOLVE_COPIES, 64)
+    assert lean < full
+    Ad = gpu_system(ct, sc, dt)
+    f = ct.qr_factor(Ad, sc.m, sc.n, ct.PREC_NAMES[prec], max_nrhs=64, solve_copies=False)
+    assert ct.status(f) == 0
+    assert f.work.numel() == lean
+    VRd = from_dev(Ad, sc.m)
+    tol_r = {"f64": 1e-12, "f32": 1e-5, "bf16x3": 1e-3}[prec]
+    assert rel(np.triu(VRd[: sc.n]), np.triu(VR[: sc.n])) <= tol_r
+    sp = ct.SparseA(sc)
+    Xd = torch.zeros((50, ld16(sc.n)), dtype=torch.float64, device="cuda")
+    k = ct.solve_refined(f, sp, to_dev(B, torch.float64), Xd, 6, ct.REFINE_SNE, tol=1e-10)
+    err = max_col_rel(from_dev(Xd, sc.n), Xs)
+    print(prec, "lean factor: %d refinement steps, max rel err %.3g" % (k, err))
+    assert err <= 1e-9
+    if prec == "f64":
+        Bd = to_dev(B, torch.float64)
+        ct.apply_qt(f, Bd)
+        ct.trsm_solve(f, Bd)
+        assert max_col_rel(from_dev(Bd, sc.n), Xs) <= 1e-10
+
+
 @pytest.mark.parametrize("prec", ["bf16x3", "f32"])
 def test_refined_stop_rule(ct, prec):
     """Stop rule of the refinement: it ends after the first step whose
