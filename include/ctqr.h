@@ -185,6 +185,17 @@ int ct_debug_block_width(int nb_out);
  * previous mode, or -1 (argument 1 invalid) for another value. */
 int ct_debug_refine_x3(int mode);
 
+/* Test hook: width of the Householder panels (0: 32 columns, or 16 when a
+ * 32-column panel of the matrix's height does not fit in the LDS of all CUs;
+ * 16 or 32 forces it).  Returns -1 for other values. */
+int ct_debug_panel_width(int nbi);
+
+/* Progress of long in-memory factorizations: with blocks > 0, ct_qr_factor
+ * waits for its stream after every `blocks` outer blocks (and the last) and
+ * writes "ct_qr_factor: <j> of <n> columns factored" to stderr; 0 (the
+ * default) turns this off.  Returns -1 for blocks < 0. */
+int ct_debug_progress(int64_t blocks);
+
 /* B <- Q^T B (Eq. (solve), first half; ormqr).  B: m x nrhs, same storage
  * type as the factor's A, nrhs <= max_nrhs.  Rows n..m-1 of the result hold
  * the least-squares residual components. */

@@ -255,11 +255,13 @@ struct ct_factor {
 constexpr int kNbStream = 256;
 
 static int g_nb_force = 0;   // test hook: forced outer block width (0: by size)
+static int g_nbi_force = 0;  // test hook: forced panel width (0: 32, or 16 for panels too tall for 32)
 // BF16x3 products in the refinement of a BF16x3 factor: 0 never, 1 from
 // kX3MinSlices slices (below that the extra launches cost more than the
 // products save), 2 always
 static int g_x3_refine = 1;
 constexpr int64_t kX3MinSlices = 48;
+static int64_t g_progress_blocks = 0;   // ct_debug_progress
 static int nb_out_for(int64_t n) { return g_nb_force ? g_nb_force : (n >= 16384 ? 1024 : 256); }
 
 struct Layout {
@@ -623,6 +625,13 @@ static int factor_cols(ct_factor* f, TS* C, int64_t c0, int64_t c1, hipStream_t 
             int r = larfb_mode<TS, 0>(f, mode, Ab, lda, mk, bo, Tb, nbo, Ab + bo * lda, lda, (int)nc, s, true, true,
                                       &ops);
             if (r) return r;
+        }
+        if (g_progress_blocks > 0 && !f->st && ((b + 1) % g_progress_blocks == 0 || k0 + bo >= c1)) {
+            // progress line once the device has finished this block
+            CT_HIP(hipStreamSynchronize(s));
+            fprintf(stderr, "ct_qr_factor: %lld of %lld columns factored\n", (long long)(k0 + bo),
+                    (long long)f->n);
+            fflush(stderr);
         }
     }
     return 0;
@@ -1396,10 +1405,10 @@ static int init_factor(ct_factor* f, void* A, int64_t m, int64_t n, int64_t lda,
     for (int b = 0; b < 5; ++b) f->solve_plan[b] = NtPlan{b < 2 ? 32 : 128, 1024};
 
     const size_t lds_words = g_dev.lds_max / 8 - panel_aux_words();
-    int nbi = 32;
+    int nbi = g_nbi_force ? g_nbi_force : 32;
     int rw = (int)(lds_words / nbi);
     if ((rw & 1) == 0) --rw;
-    if ((m + rw - 1) / rw > g_dev.cus) {
+    if (!g_nbi_force && (m + rw - 1) / rw > g_dev.cus) {
         nbi = 16;
         rw = (int)(lds_words / nbi);
         if ((rw & 1) == 0) --rw;
@@ -1900,6 +1909,20 @@ int ct_quality(const double* X, int64_t ldx, const double* ref, int64_t ldr, int
     CT_ARG(out != nullptr || k == 0, 9, "out");
     if (k == 0) return 0;
     CT_HIP(launch_quality(X, ldx, ref, ldr, n_pix, k, crop, window, out, (hipStream_t)stream));
+    return 0;
+}
+
+int ct_debug_panel_width(int nbi)
+{
+    if (nbi != 0 && nbi != 16 && nbi != 32) return fail(-1, "%s", "invalid argument nbi (0, 16 or 32)");
+    g_nbi_force = nbi;
+    return 0;
+}
+
+int ct_debug_progress(int64_t blocks)
+{
+    if (blocks < 0) return fail(-1, "%s", "invalid argument blocks (>= 0)");
+    g_progress_blocks = blocks;
     return 0;
 }
 

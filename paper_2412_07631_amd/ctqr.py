@@ -62,6 +62,8 @@ _sig("ct_debug_wait_limit", [_i64])
 _sig("ct_debug_panel_cholesky", [ctypes.c_int])
 _sig("ct_debug_block_width", [ctypes.c_int])
 _sig("ct_debug_refine_x3", [ctypes.c_int])
+_sig("ct_debug_progress", [_i64])
+_sig("ct_debug_panel_width", [ctypes.c_int])
 _sig("ct_quality", [_vp, _i64, _vp, _i64, _i32, _i64, _vp, _i32, _vp, _vp])
 _sig("ct_factor_save", [_vp, ctypes.c_char_p, _vp])
 _sig("ct_factor_file_info", [ctypes.c_char_p, _i64, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
@@ -298,6 +300,16 @@ def debug_block_width(nb_out: int):
     """Force the outer block width of later factorizations (0 restores the
     size-based default)."""
     _check(_lib.ct_debug_block_width(nb_out))
+
+
+def debug_panel_width(nbi: int):
+    """Force the panel width (16 or 32; 0: by the matrix's height)."""
+    _check(_lib.ct_debug_panel_width(int(nbi)))
+
+
+def debug_progress(blocks: int):
+    """Progress lines on stderr every `blocks` outer blocks of a factorization (0: off)."""
+    _check(_lib.ct_debug_progress(int(blocks)))
 
 
 def debug_refine_x3(mode: int) -> int:

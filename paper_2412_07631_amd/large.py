@@ -37,6 +37,11 @@ def main():
     ap.add_argument("--batch", type=int, default=128)
     ap.add_argument("--refine", type=int, default=6, help="refinement steps at most")
     ap.add_argument("--tol", type=float, default=1e-6, help="stop rule of the refinement")
+    ap.add_argument("--prec", default="bf16x3", choices=["f32", "bf16x3"], help="arithmetic of the factorization")
+    ap.add_argument("--check-columns", type=int, default=16, help="sampled columns of the Q^T a_j check")
+    ap.add_argument("--geometry", default=None,
+                    help="N,views,bins: the workload's seeds and dose with another scanner (same proportions "
+                         "at a smaller size, say)")
     args = ap.parse_args()
 
     import torch
@@ -44,6 +49,9 @@ def main():
 
     w = synth.WORKLOADS[args.workload]
     sc = synth.workload_scanner(args.workload)
+    if args.geometry:
+        N, views, bins = (int(v) for v in args.geometry.split(","))
+        sc = synth.scanner(N, views, bins)
     m, n = sc.m, sc.n
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
@@ -60,19 +68,49 @@ def main():
     build_ms = e0.elapsed_time(e1)
     log("A built: %.1f GiB in %.1f ms" % (A.numel() * 4 / 2**30, build_ms))
 
+    ctqr.debug_progress(16)                                 # a line every 16384 columns
     e0.record(stream)
-    f = ctqr.qr_factor(A, m, n, ctqr.PREC_BF16X3, max_nrhs=args.batch, solve_copies=False)
+    f = ctqr.qr_factor(A, m, n, ctqr.PREC_NAMES[args.prec], max_nrhs=args.batch, solve_copies=False)
     e1.record(stream)
     info = ctqr.status(f)
     qr_ms = e0.elapsed_time(e1)
+    ctqr.debug_progress(0)
     flops = 2.0 * m * n * n - 2.0 * n ** 3 / 3.0
-    log("QR (BF16x3): %.1f s, %.1f TFLOP/s, info %d" % (qr_ms / 1e3, flops / (qr_ms * 1e-3) / 1e12, info))
+    log("QR (%s): %.1f s, %.1f TFLOP/s, info %d" % (args.prec, qr_ms / 1e3, flops / (qr_ms * 1e-3) / 1e12, info))
     if info != 0:
         raise RuntimeError("rank deficiency reported at column %d" % (info - 1))
+    # a lower bound of kappa(A) = kappa(R): the spread of R's diagonal
+    ld = A.shape[1]
+    diag = A.view(-1)[torch.arange(n, device=dev) * (ld + 1)].abs().double()
+    rdiag = {"max": float(diag.max().item()), "min": float(diag.min().item())}
+    rdiag["ratio"] = rdiag["max"] / rdiag["min"]
+    log("|R_jj|: max %.4g min %.4g ratio %.4g (a lower bound of kappa(A))" % (rdiag["max"], rdiag["min"],
+                                                                            rdiag["ratio"]))
+    del diag
 
     sp = ctqr.SparseA(sc, group=0)
     a_fro = float(torch.linalg.vector_norm(sp.val).item())
     log("sparse copies: nnz %d, ||A||_F %.6g" % (sp.nnz, a_fro))
+
+    # the factorization itself, column by column: Q^T a_j = [R_{0:j, j}; 0]
+    # for sampled columns j (a_j the FP32 column that was factored, from the
+    # CSC copy; R_{0:j, j} read from the factored matrix)
+    cols = sorted(set(int(c) for c in np.linspace(0, n - 1, args.check_columns)))
+    cp = sp.col_ptr.cpu().numpy()
+    Bc = torch.zeros((len(cols), ctqr.ld16(m)), dtype=torch.float32, device=dev)
+    for i, j in enumerate(cols):
+        rows = sp.row[cp[j]:cp[j + 1]].long()
+        Bc[i, rows] = sp.cval[cp[j]:cp[j + 1]].float()
+    anorm = Bc[:, :m].double().norm(dim=1)
+    ctqr.apply_qt(f, Bc)
+    col_err = []
+    for i, j in enumerate(cols):
+        want = torch.zeros(m, dtype=torch.float64, device=dev)
+        want[: j + 1] = A[j, : j + 1].double()
+        col_err.append(float(((Bc[i, :m].double() - want).norm() / anorm[i]).item()))
+    log("Q^T a_j = [r_j; 0] on %d columns: worst %.3g at column %d" % (
+        len(cols), max(col_err), cols[int(np.argmax(col_err))]))
+    del Bc
 
     out_batches = []
     solve_ms = 0.0
@@ -117,7 +155,9 @@ def main():
             k, steps, ms, k / (ms * 1e-3), eta, e))
         del Xtd, Pnl, Bd, X, Xn, rn, gn
 
-    res = {"workload": args.workload, "m": m, "n": n, "matrix_gib_fp32": A.numel() * 4 / 2**30,
+    res = {"workload": args.workload, "precision": args.prec, "m": m, "n": n, "r_diag": rdiag,
+           "qt_column_check": {"columns": cols, "rel_err": col_err},
+           "matrix_gib_fp32": A.numel() * 4 / 2**30,
            "workspace_gib": f.work.numel() / 2**30, "build_ms": build_ms, "qr_ms": qr_ms,
            "qr_tflops": flops / (qr_ms * 1e-3) / 1e12, "slices": done, "slices_per_s": done / (solve_ms * 1e-3),
            "refine_tol": args.tol, "batches": out_batches}

@@ -332,6 +332,36 @@ def test_refined_sne_parity(ct, prec, steps, tol):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
+@pytest.mark.parametrize("panel_path", ["cholqr2", "columnwise"])
+def test_sixteen_column_panels_match_oracle(ct, prec, panel_path):
+    """Panels of 16 columns (what the factorization uses when a 32-column
+    panel of a very tall matrix does not fit in the LDS of all CUs), in both
+    panel forms: R, V and tau against the oracle, and the refined solve."""
+    sc, A, VR, tau = problem("multi")
+    dt = torch.float64 if prec == "f64" else torch.float32
+    Ad = gpu_system(ct, sc, dt)
+    ct.debug_panel_width(16)
+    ct.debug_panel_cholesky(panel_path == "cholqr2")
+    try:
+        f = ct.qr_factor(Ad, sc.m, sc.n, ct.PREC_NAMES[prec], max_nrhs=8)
+        assert ct.status(f) == 0
+    finally:
+        ct.debug_panel_width(0)
+        ct.debug_panel_cholesky(True)
+    VRd = from_dev(Ad, sc.m)
+    tol = {"f64": 1e-12, "f32": 1e-5, "bf16x3": 1e-3}[prec]
+    assert rel(np.triu(VRd[: sc.n]), np.triu(VR[: sc.n])) <= tol
+    assert rel(np.tril(VRd, -1), np.tril(VR, -1)) <= tol * 10
+    assert np.max(np.abs(f.tau.cpu().numpy() - tau)) <= tol * 10
+    _, P, B = sinograms(sc, A, 3, 6, 5e4)
+    Xs = O.solve(VR, tau, B)
+    sp = ct.SparseA(sc)
+    Xd = torch.zeros((6, ld16(sc.n)), dtype=torch.float64, device="cuda")
+    ct.solve_refined(f, sp, to_dev(B, torch.float64), Xd, 6, ct.REFINE_SNE, tol=1e-11)
+    assert max_col_rel(from_dev(Xd, sc.n), Xs) <= 1e-9
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
 def test_lean_factor_without_solve_copies(ct, prec):
     """CT_QR_NO_SOLVE_COPIES: the same factor in a smaller workspace; its
     solves (which then read V and R in place), the refinement and the
