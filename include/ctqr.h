@@ -262,11 +262,27 @@ typedef struct ct_sparse {
  *   CT_REFINE_SNE: x += R~^{-1} R~^{-T} A^T (b - A x)   (corrected semi-normal
  *     equations, Bjorck 1987).  Its fixed point is A^T (b - A x) = 0, the
  *     least-squares solution itself; each step contracts the error by about
- *     kappa(A) u_factor.  Needs the CSC copy. */
-enum { CT_REFINE_QR = 0, CT_REFINE_SNE = 1 };
+ *     kappa(A) u_factor.  Needs the CSC copy.
+ *   CT_REFINE_PCGLS: conjugate gradients on A^T A x = A^T b with the
+ *     preconditioner (R~^T R~)^{-1}, i.e. CGLS on A R~^{-1} (Bjorck,
+ *     Numerical Methods for Least Squares Problems, 1996, ch. 7), started
+ *     from x_0.  Each step costs what an SNE step costs (A p, A^T s, one
+ *     solve with R~^T and one with R~) plus per-slice dot products; the
+ *     residual s and x are FP64 and take the same step, so s = b - A x to FP64
+ *     rounding.  Where kappa(A) u_factor is near or above 1 the stationary
+ *     SNE step stops contracting, while the Krylov iteration still converges
+ *     (the singular values of A R~^{-1} stay clustered near 1 but for a few).
+ *     Needs the CSC copy and ct_refine_workspace_for's larger scratch. */
+enum { CT_REFINE_QR = 0, CT_REFINE_SNE = 1, CT_REFINE_PCGLS = 2 };
 
-/* Scratch bytes for ct_solve_refined with nrhs right-hand sides. */
+/* Scratch bytes for ct_solve_refined with nrhs right-hand sides and method
+ * CT_REFINE_QR or CT_REFINE_SNE. */
 int ct_refine_workspace(int64_t m, int64_t n, int64_t nrhs, size_t* bytes);
+
+/* Scratch bytes for ct_solve_refined with nrhs right-hand sides and the given
+ * method (CT_REFINE_PCGLS adds n x nrhs FP64 for the search directions).
+ * Returns -4 for an unknown method. */
+int ct_refine_workspace_for(int64_t m, int64_t n, int64_t nrhs, int32_t method, size_t* bytes);
 
 /* Reconstruction with iterative refinement on the FP64 residual r = b - A x:
  *   x_0 = R~^{-1} Q~^T b, then up to `steps` refinement steps of kind `method`.
@@ -280,7 +296,10 @@ int ct_refine_workspace(int64_t m, int64_t n, int64_t nrhs, size_t* bytes);
  * receives the number of steps taken.  If not NULL, res_norms receives
  * ||r_s||_2 and grad_norms ||A^T r_s||_2 (the latter needs the CSC copy) for
  * s = 0..steps_done, (steps + 1) x nrhs, step-major; later rows are not
- * written.  On a CT_PREC_BF16X3 factor the solves inside use BF16x3 products
+ * written.  With CT_REFINE_PCGLS the correction is the step c_j p_j and
+ * res_norms rows 1..steps_done-1 hold the norms of the recurred residual
+ * (equal to ||b - A x|| up to rounding); row steps_done is recomputed from b.
+ * On a CT_PREC_BF16X3 factor the solves inside use BF16x3 products
  * from 48 slices up (see ct_debug_refine_x3); other factors use their
  * storage precision. */
 int ct_solve_refined(const ct_factor* f, const ct_sparse* A, const double* B, int64_t ldb, double* X,
@@ -293,7 +312,7 @@ int ct_solve_refined(const ct_factor* f, const ct_sparse* A, const double* B, in
  * ct_solve_refined, whose kernels it runs; its scratch is a statically
  * allocated 128 MiB device array, one per GPU, held until the process ends
  * (up to 40 slices at 256^2 with 76800 rays, 160 at 128^2 with 23040).
- * A call whose ct_refine_workspace size exceeds 128 MiB returns -7 (nrhs) and
+ * A call whose ct_refine_workspace_for size exceeds 128 MiB returns -7 (nrhs) and
  * launches nothing.  The call itself allocates nothing (no hipMalloc, no
  * library allocation).  Every call on a GPU shares that GPU's array: calls
  * that overlap on one GPU (different streams or host threads without

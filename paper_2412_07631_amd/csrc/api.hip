@@ -108,6 +108,12 @@ hipError_t launch_corr_ratio(const TD* D, int64_t ldd, const double* X, int64_t 
 template <typename T>
 hipError_t launch_zero_rows(T* Y, int64_t ldy, int64_t r0, int64_t r1, int cols, hipStream_t s);
 hipError_t launch_colnorm(const double* X, int64_t ldx, int64_t rows, int cols, double* out, hipStream_t s);
+template <typename T>
+hipError_t launch_colsq(const T* C, int64_t ldc, int64_t rows, int cols, double* out, hipStream_t s);
+hipError_t launch_cg_update(const double* x, double* y, int64_t rows, int nrhs, int64_t ld, const double* num,
+                            const double* den, int mode, hipStream_t s);
+hipError_t launch_cg_ratio(const double* gam, const double* qn, const double* pn, const double* xn, int nrhs,
+                           unsigned long long* maxw, hipStream_t s);
 hipError_t launch_residual_t(const int64_t* col_ptr, const int32_t* row, const double* cval, int64_t n,
                              const double* R, int64_t ldr, double* S, int64_t lds, int nrhs, hipStream_t s);
 hipError_t launch_csc(const int64_t* row_ptr, const int32_t* col, const double* val, int64_t m, int64_t n,
@@ -1252,7 +1258,7 @@ static int refined_impl(const ct_factor* f, const ct_sparse* sp, const double* B
     double* Xt = (double*)p; p += up256((size_t)n * lt * 8);
     double* St = (double*)p; p += up256((size_t)n * lt * 8);
     TS* C = (TS*)p; p += up256((size_t)ld * nrhs * 8);
-    double* Np = (double*)p;                            // column-norm partials (256 x nrhs)
+    double* Np = (double*)p; p += up256((size_t)256 * lt * 8);  // column-norm partials (256 x nrhs)
     const bool have_csc = sp->col_ptr && sp->row && sp->cval;
     const int nr = (int)nrhs;
     // a BF16x3 factor's corrections are solved with BF16x3 block updates:
@@ -1267,6 +1273,94 @@ static int refined_impl(const ct_factor* f, const ct_sparse* sp, const double* B
     if (r) return r;
     CT_HIP((launch_convert<TS, double>(C, ld, X, ldx, n, nr, s)));
     CT_HIP((launch_transpose<TS, double, true, false>(C, Xt, n, nr, ld, lt, s)));
+    // A p (sign flipped: out = -A p) and A^T s over the sparse copies
+    auto neg_a_times = [&](const double* Zt, const double* Bz, double* Out) {
+        return sp->group_r > 0 ? launch_group_spmm(sp->grow_ptr, sp->grow_col, sp->grow_val, sp->group_r, m, Zt, Bz,
+                                                   Out, lt, nr, true, s)
+                               : launch_spmv_rows_t(sp->row_ptr, sp->col, sp->val, m, Zt, Bz, Out, lt, nr, s);
+    };
+    auto at_times = [&](const double* Zt, double* Out) {
+        return sp->group_c > 0 ? launch_group_spmm(sp->gcol_ptr, sp->gcol_row, sp->gcol_val, sp->group_c, n, Zt,
+                                                   nullptr, Out, lt, nr, false, s)
+                               : launch_spmv_cols_t(sp->col_ptr, sp->row, sp->cval, n, Zt, Out, lt, nr, s);
+    };
+    if (method == CT_REFINE_PCGLS) {
+        // Conjugate gradients on A^T A x = A^T b preconditioned with
+        // (R~^T R~)^{-1} (CGLS on A R~^{-1}), from x_0 above.  The residual s
+        // and the image x are FP64 and are updated with the same step c p and
+        // the same FP64 product A p, so s stays b - A x to FP64 rounding; the
+        // preconditioner runs in the factor's arithmetic.
+        double* Pt = (double*)p; p += up256((size_t)n * lt * 8);
+        double* gam = (double*)p;                       // gamma (two rows), ||A p||, ||p||, ||x||
+        double* qn = gam + 2 * lt;
+        double* pn = qn + lt;
+        double* xn = pn + lt;
+        double* Qt = Bt;                                // b is taken again from B at the end
+        CT_HIP(neg_a_times(Xt, Bt, Rt));                // s_0 = b - A x_0
+        if (rnorms) CT_HIP(launch_colnorm_t(Rt, lt, m, nr, rnorms, Np, s));
+        CT_HIP(at_times(Rt, St));                       // A^T s_0
+        if (gnorms) CT_HIP(launch_colnorm_t(St, lt, n, nr, gnorms, Np, s));
+        int cur = 0, taken = 0;
+        // z = (R~^T R~)^{-1} r for r in St, gamma = r^T z = ||R~^{-T} r||^2 into gam + row * lt
+        auto precondition = [&](int row) -> int {
+            CT_HIP((launch_transpose<double, TS, false, false>(St, C, n, nr, ld, lt, s)));
+            int e = trsm_lt_impl<TS>(f, C, nrhs, ld, s, x3);
+            if (e) return e;
+            CT_HIP((launch_colsq<TS>(C, ld, n, nr, gam + (size_t)row * lt, s)));
+            return trsm_impl<TS>(f, C, nrhs, ld, s, nullptr, x3);
+        };
+        if (steps > 0) {
+            r = precondition(cur);
+            if (r) return r;
+            CT_HIP((launch_transpose<TS, double, true, false>(C, Pt, n, nr, ld, lt, s)));   // p_0 = z_0
+        }
+        bool last = steps == 0;
+        while (!last) {
+            CT_HIP(neg_a_times(Pt, nullptr, Qt));       // Qt = -A p
+            CT_HIP(launch_colnorm_t(Qt, lt, m, nr, qn, Np, s));
+            const double* g = gam + (size_t)cur * lt;
+            CT_HIP(launch_cg_update(Pt, Xt, n, nr, lt, g, qn, 0, s));   // x += c p
+            CT_HIP(launch_cg_update(Qt, Rt, m, nr, lt, g, qn, 0, s));   // s -= c A p
+            ++taken;
+            last = taken == steps;
+            if (tol > 0.0) {
+                unsigned long long* maxw = (unsigned long long*)(Np + 256 * lt - 1);
+                CT_HIP(launch_colnorm_t(Pt, lt, n, nr, pn, Np, s));
+                CT_HIP(launch_colnorm_t(Xt, lt, n, nr, xn, Np, s));
+                CT_HIP(launch_cg_ratio(g, qn, pn, xn, nr, maxw, s));
+                unsigned long long h = 0;
+                CT_HIP(hipMemcpyAsync(&h, maxw, sizeof h, hipMemcpyDeviceToHost, s));
+                CT_HIP(hipStreamSynchronize(s));
+                double mx;
+                memcpy(&mx, &h, sizeof mx);
+                last = last || mx <= tol;
+            }
+            if (last) break;
+            if (rnorms) CT_HIP(launch_colnorm_t(Rt, lt, m, nr, rnorms + (size_t)taken * nrhs, Np, s));
+            CT_HIP(at_times(Rt, St));                   // r = A^T s
+            if (gnorms) CT_HIP(launch_colnorm_t(St, lt, n, nr, gnorms + (size_t)taken * nrhs, Np, s));
+            r = precondition(cur ^ 1);
+            if (r) return r;
+            CT_HIP((launch_transpose<TS, double, true, false>(C, St, n, nr, ld, lt, s)));   // z
+            CT_HIP(launch_cg_update(St, Pt, n, nr, lt, gam + (size_t)(cur ^ 1) * lt, g, 1, s));  // p = z + beta p
+            cur ^= 1;
+        }
+        if (taken > 0) {
+            // the image, and the last residual recomputed from b (not the recurrence)
+            CT_HIP((launch_transpose<double, double, false, false>(Xt, X, n, nr, ldx, lt, s)));
+            CT_HIP((launch_transpose<double, double, true, false>(B, Bt, m, nr, ldb, lt, s)));
+            if (rnorms || gnorms) {
+                CT_HIP(neg_a_times(Xt, Bt, Rt));
+                if (rnorms) CT_HIP(launch_colnorm_t(Rt, lt, m, nr, rnorms + (size_t)taken * nrhs, Np, s));
+                if (gnorms && have_csc) {
+                    CT_HIP(at_times(Rt, St));
+                    CT_HIP(launch_colnorm_t(St, lt, n, nr, gnorms + (size_t)taken * nrhs, Np, s));
+                }
+            }
+        }
+        if (steps_done) *steps_done = taken;
+        return 0;
+    }
     int taken = 0;
     bool converged = false;
     for (int st = 0; st <= steps; ++st) {
@@ -2020,6 +2114,17 @@ int ct_refine_workspace(int64_t m, int64_t n, int64_t nrhs, size_t* bytes)
     return 0;
 }
 
+int ct_refine_workspace_for(int64_t m, int64_t n, int64_t nrhs, int32_t method, size_t* bytes)
+{
+    CT_ARG(method == CT_REFINE_QR || method == CT_REFINE_SNE || method == CT_REFINE_PCGLS, 4, "method");
+    CT_ARG(bytes != nullptr, 5, "bytes");
+    int r = ct_refine_workspace(m, n, nrhs, bytes);
+    if (r) return r;
+    const int64_t lt = (nrhs + 15) / 16 * 16;
+    if (method == CT_REFINE_PCGLS) *bytes += up256((size_t)n * lt * 8) + up256((size_t)5 * lt * 8);
+    return 0;
+}
+
 int ct_build_csc(int64_t m, int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
                  int64_t* col_ptr, int32_t* row, double* cval, int32_t* work, void* stream)
 {
@@ -2070,11 +2175,12 @@ int ct_solve_refined(const ct_factor* f, const ct_sparse* sp, const double* B, i
     CT_ARG(X != nullptr && ldx >= f->n, 5, "X/ldx");
     CT_ARG(nrhs >= 0 && nrhs <= f->max_nrhs, 7, "nrhs (0..max_nrhs)");
     CT_ARG(steps >= 0 && steps <= 64, 8, "steps");
-    CT_ARG(method == CT_REFINE_QR || method == CT_REFINE_SNE, 9, "method");
+    CT_ARG(method == CT_REFINE_QR || method == CT_REFINE_SNE || method == CT_REFINE_PCGLS, 9, "method");
     CT_ARG(tol >= 0.0, 10, "tol");
-    CT_ARG(method != CT_REFINE_SNE || (sp->col_ptr && sp->row && sp->cval), 2, "A (CT_REFINE_SNE needs the CSC copy)");
+    CT_ARG(method == CT_REFINE_QR || (sp->col_ptr && sp->row && sp->cval), 2,
+           "A (CT_REFINE_SNE and CT_REFINE_PCGLS need the CSC copy)");
     size_t need = 0;
-    ct_refine_workspace(f->m, f->n, nrhs, &need);
+    ct_refine_workspace_for(f->m, f->n, nrhs, method, &need);
     CT_ARG(scratch != nullptr && aligned(scratch) && scratch_bytes >= need, 11, "scratch");
     if (steps_done) *steps_done = 0;
     if (nrhs == 0) return 0;
@@ -2123,8 +2229,9 @@ int ct_solve_refined_noalloc(const ct_factor* f, const ct_sparse* sp, const doub
 {
     CT_ARG(f != nullptr, 1, "f");
     CT_ARG(nrhs >= 0 && nrhs <= f->max_nrhs, 7, "nrhs (0..max_nrhs)");
+    CT_ARG(method == CT_REFINE_QR || method == CT_REFINE_SNE || method == CT_REFINE_PCGLS, 9, "method");
     size_t need = 0;
-    ct_refine_workspace(f->m, f->n, nrhs, &need);
+    ct_refine_workspace_for(f->m, f->n, nrhs, method, &need);
     if (need > kStaticScratchBytes)
         return fail(-7, "invalid argument nrhs: %lld slices need %zu bytes of scratch, above the %zu-byte static "
                         "scratch of ct_solve_refined_noalloc", (long long)nrhs, need, kStaticScratchBytes);

@@ -546,6 +546,70 @@ __global__ void __launch_bounds__(256) colnorm_kernel(const double* __restrict__
     if (threadIdx.x == 0) out[j] = sqrt(red[0]);
 }
 
+// Sums of squares of the columns of a column-major block (fixed-order tree,
+// one workgroup per column): out[j] = sum_i C[i + j ldc]^2, in FP64.
+template <typename T>
+__global__ void __launch_bounds__(256) colsq_kernel(const T* __restrict__ C, int64_t ldc, int64_t rows,
+                                                    double* __restrict__ out)
+{
+    __shared__ double red[256];
+    const int j = blockIdx.x;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < rows; i += 256) {
+        const double v = (double)C[i + (int64_t)j * ldc];
+        s += v * v;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = red[0];
+}
+
+// Per-slice coefficient of the conjugate-gradient updates: num / den^2 when den
+// is a norm (the step length gamma / ||A p||^2), num / den otherwise (the
+// ratio of successive gammas); zero where the denominator vanishes (a slice
+// whose residual is already zero keeps its image).
+__device__ inline double cg_coef(const double* num, const double* den, int j, bool den_is_norm)
+{
+    const double d = den_is_norm ? den[j] * den[j] : den[j];
+    return d > 0.0 ? num[j] / d : 0.0;
+}
+
+// Slice-contiguous blocks (element (i, j) at i * ld + j), one coefficient c_j
+// per slice:  mode 0: y += c_j x,  mode 1: y = x + c_j y.
+__global__ void __launch_bounds__(256) cg_update_kernel(const double* __restrict__ x, double* __restrict__ y,
+                                                        int64_t rows, int nrhs, int64_t ld,
+                                                        const double* __restrict__ num,
+                                                        const double* __restrict__ den, int mode)
+{
+    const int64_t total = rows * ld;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int j = (int)(e % ld);
+        if (j >= nrhs) continue;
+        const double c = cg_coef(num, den, j, mode == 0);
+        y[e] = mode == 0 ? y[e] + c * x[e] : x[e] + c * y[e];
+    }
+}
+
+// Stop rule of the conjugate-gradient refinement: the step of slice j is
+// c_j p_j with c_j = gamma_j / ||A p_j||^2; its size relative to the updated
+// image, max over slices into *maxw (the bits of a non-negative double).
+__global__ void __launch_bounds__(256) cg_ratio_kernel(const double* __restrict__ gam,
+                                                       const double* __restrict__ qn,
+                                                       const double* __restrict__ pn,
+                                                       const double* __restrict__ xn, int nrhs,
+                                                       unsigned long long* __restrict__ maxw)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= nrhs) return;
+    const double step = fabs(cg_coef(gam, qn, j, true)) * pn[j];
+    const double r = xn[j] > 0.0 ? step / xn[j] : (step > 0.0 ? __builtin_huge_val() : 0.0);
+    atomicMax(maxw, (unsigned long long)__double_as_longlong(r));
+}
+
 // ------------------------------------------------------------------ launchers
 static inline dim3 grid2(int64_t rows, int cols)
 {
@@ -875,6 +939,34 @@ hipError_t launch_zero_rows(T* Y, int64_t ldy, int64_t r0, int64_t r1, int cols,
 {
     if (r1 <= r0) return hipSuccess;
     hipLaunchKernelGGL((zero_rows_kernel<T>), grid2(r1 - r0, cols), dim3(256), 0, s, Y, ldy, r0, r1, cols);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_colsq(const T* C, int64_t ldc, int64_t rows, int cols, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL((colsq_kernel<T>), dim3(cols), dim3(256), 0, s, C, ldc, rows, out);
+    return hipGetLastError();
+}
+template hipError_t launch_colsq<float>(const float*, int64_t, int64_t, int, double*, hipStream_t);
+template hipError_t launch_colsq<double>(const double*, int64_t, int64_t, int, double*, hipStream_t);
+
+hipError_t launch_cg_update(const double* x, double* y, int64_t rows, int nrhs, int64_t ld, const double* num,
+                            const double* den, int mode, hipStream_t s)
+{
+    int64_t g = (rows * ld + 255) / 256;
+    if (g > 16384) g = 16384;
+    hipLaunchKernelGGL(cg_update_kernel, dim3((unsigned)(g > 0 ? g : 1)), dim3(256), 0, s, x, y, rows, nrhs, ld, num,
+                       den, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_ratio(const double* gam, const double* qn, const double* pn, const double* xn, int nrhs,
+                           unsigned long long* maxw, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_word_kernel, dim3(1), dim3(1), 0, s, maxw);
+    hipLaunchKernelGGL(cg_ratio_kernel, dim3((unsigned)((nrhs + 255) / 256)), dim3(256), 0, s, gam, qn, pn, xn, nrhs,
+                       maxw);
     return hipGetLastError();
 }
 

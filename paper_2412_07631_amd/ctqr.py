@@ -25,7 +25,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 F64, F32 = 0, 1
 QR_NO_SOLVE_COPIES = 0x100    # flag OR'ed into prec: no solve-side copies (lean workspace)
-REFINE_QR, REFINE_SNE = 0, 1
+REFINE_QR, REFINE_SNE, REFINE_PCGLS = 0, 1, 2
 PREC_F64, PREC_F32, PREC_BF16, PREC_F16, PREC_BF16X3 = 0, 1, 2, 3, 4
 PREC_NAMES = {"f64": PREC_F64, "f32": PREC_F32, "bf16": PREC_BF16, "f16": PREC_F16, "bf16x3": PREC_BF16X3}
 
@@ -74,6 +74,7 @@ _sig("ct_trsm_solve", [_vp, _vp, _i64, _i64, _vp])
 _sig("ct_solve_backward", [_vp, _vp, _i64, _i64, _vp, _i64, _vp])
 _sig("ct_residual", [_vp, _vp, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _i64, _vp])
 _sig("ct_refine_workspace", [_i64, _i64, _i64, ctypes.POINTER(_sz)])
+_sig("ct_refine_workspace_for", [_i64, _i64, _i64, _i32, ctypes.POINTER(_sz)])
 _sig("ct_build_csc", [_i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp])
 _sig("ct_group_sparse", [_i64, _vp, _vp, _vp, _i32, _vp, _vp, _vp, ctypes.POINTER(_i64), _vp, _vp])
 
@@ -362,9 +363,9 @@ def residual(csr, m: int, X: torch.Tensor, B: torch.Tensor, R: torch.Tensor, nrh
     return R
 
 
-def refine_workspace(m: int, n: int, nrhs: int) -> int:
+def refine_workspace(m: int, n: int, nrhs: int, method: int = REFINE_SNE) -> int:
     b = _sz(0)
-    _check(_lib.ct_refine_workspace(m, n, nrhs, ctypes.byref(b)))
+    _check(_lib.ct_refine_workspace_for(m, n, nrhs, int(method), ctypes.byref(b)))
     return b.value
 
 
@@ -433,7 +434,7 @@ def solve_refined(f: Factor, sp: SparseA, B: torch.Tensor, X: torch.Tensor, step
     stops earlier)."""
     nrhs = B.shape[0] if nrhs is None else nrhs
     if scratch is None:
-        scratch = torch.empty(refine_workspace(f.m, f.n, nrhs), dtype=torch.uint8, device=B.device)
+        scratch = torch.empty(refine_workspace(f.m, f.n, nrhs, method), dtype=torch.uint8, device=B.device)
     done = _i32(0)
     _check(_lib.ct_solve_refined(f.handle, ctypes.byref(sp.struct), _ptr(B), B.shape[1], _ptr(X), X.shape[1], nrhs,
                                  int(steps), int(method), float(tol), _ptr(scratch), scratch.numel(), _ptr(res_norms),

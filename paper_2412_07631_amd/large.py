@@ -38,6 +38,8 @@ def main():
     ap.add_argument("--refine", type=int, default=6, help="refinement steps at most")
     ap.add_argument("--tol", type=float, default=1e-6, help="stop rule of the refinement")
     ap.add_argument("--prec", default="bf16x3", choices=["f32", "bf16x3"], help="arithmetic of the factorization")
+    ap.add_argument("--method", default="pcgls", choices=["sne", "pcgls"],
+                    help="refinement: stationary semi-normal steps or preconditioned conjugate gradients")
     ap.add_argument("--check-columns", type=int, default=16, help="sampled columns of the Q^T a_j check")
     ap.add_argument("--geometry", default=None,
                     help="N,views,bins: the workload's seeds and dose with another scanner (same proportions "
@@ -115,7 +117,8 @@ def main():
     out_batches = []
     solve_ms = 0.0
     done = 0
-    scratch = torch.empty(ctqr.refine_workspace(m, n, args.batch), dtype=torch.uint8, device=dev)
+    method = {"sne": ctqr.REFINE_SNE, "pcgls": ctqr.REFINE_PCGLS}[args.method]
+    scratch = torch.empty(ctqr.refine_workspace(m, n, args.batch, method), dtype=torch.uint8, device=dev)
     while done < args.slices:
         k = min(args.batch, args.slices - done)
         ids = list(range(done, done + k))
@@ -134,7 +137,7 @@ def main():
         rn = torch.zeros((args.refine + 1) * k, dtype=torch.float64, device=dev)
         gn = torch.zeros((args.refine + 1) * k, dtype=torch.float64, device=dev)
         e0.record(stream)
-        steps = ctqr.solve_refined(f, sp, Bd, X, args.refine, ctqr.REFINE_SNE, nrhs=k, scratch=scratch, res_norms=rn,
+        steps = ctqr.solve_refined(f, sp, Bd, X, args.refine, method, nrhs=k, scratch=scratch, res_norms=rn,
                                    grad_norms=gn, tol=args.tol)
         e1.record(stream)
         torch.cuda.synchronize()
@@ -145,7 +148,7 @@ def main():
         eta = float(np.max(gnv[-1] / (a_fro * rnv[-1])))
         # noiseless sinograms: the phantoms themselves come back
         Xn = torch.zeros_like(X)
-        ctqr.solve_refined(f, sp, Pnl, Xn, args.refine, ctqr.REFINE_SNE, nrhs=k, scratch=scratch, tol=args.tol)
+        ctqr.solve_refined(f, sp, Pnl, Xn, args.refine, method, nrhs=k, scratch=scratch, tol=args.tol)
         e = ((Xn[:, :n] - Xtd[:, :n]).norm(dim=1) / Xtd[:, :n].norm(dim=1)).max().item()
         rec = {"slices": k, "solve_ms": ms, "steps": steps, "ls_optimality_max": eta,
                "grad_norm_by_step_max": [float(np.max(g)) for g in gnv], "noiseless_rel_err_max": e}
@@ -155,7 +158,8 @@ def main():
             k, steps, ms, k / (ms * 1e-3), eta, e))
         del Xtd, Pnl, Bd, X, Xn, rn, gn
 
-    res = {"workload": args.workload, "precision": args.prec, "m": m, "n": n, "r_diag": rdiag,
+    res = {"workload": args.workload, "precision": args.prec, "refinement": args.method, "m": m, "n": n,
+           "r_diag": rdiag,
            "qt_column_check": {"columns": cols, "rel_err": col_err},
            "matrix_gib_fp32": A.numel() * 4 / 2**30,
            "workspace_gib": f.work.numel() / 2**30, "build_ms": build_ms, "qr_ms": qr_ms,

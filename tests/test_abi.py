@@ -71,6 +71,27 @@ def test_binding_marshals_without_gpu():
         raise AssertionError("expected an argument error")
 
 
+def test_refine_workspace_by_method():
+    """The Krylov refinement needs n x lt FP64 more (its search directions)
+    plus five rows of per-slice scalars; the other methods share one size;
+    an unknown method is argument 4."""
+    from paper_2412_07631_amd import ctqr
+    up = lambda x: (x + 255) // 256 * 256
+    m, n = 3360, 2304
+    for nrhs in (1, 16, 37):
+        lt = (nrhs + 15) // 16 * 16
+        base = ctqr.refine_workspace(m, n, nrhs, ctqr.REFINE_SNE)
+        assert base == ctqr.refine_workspace(m, n, nrhs, ctqr.REFINE_QR)
+        assert base == 2 * up(m * lt * 8) + 2 * up(n * lt * 8) + up(m * nrhs * 8) + up(256 * lt * 8)
+        assert ctqr.refine_workspace(m, n, nrhs, ctqr.REFINE_PCGLS) == base + up(n * lt * 8) + up(5 * lt * 8)
+    try:
+        ctqr.refine_workspace(m, n, 4, 7)
+    except ctqr.CtError as e:
+        assert e.code == -4
+    else:
+        raise AssertionError("expected an argument error")
+
+
 def test_stream_workspace_arithmetic():
     """Streamed factorization: the minimum device buffer is the in-memory
     workspace without its solve-side copies (the diagonal-block inverses of R,
