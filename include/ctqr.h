@@ -90,11 +90,12 @@ int ct_build_csr(const ct_geometry* g, int64_t* row_ptr, int32_t* col, double* v
                  void* stream);
 
 /* Flag OR'ed into prec for ct_qr_workspace and ct_qr_factor: keep no
- * solve-side copies (the row-major reflector blocks, the inverses of R's
- * diagonal blocks and the row-major copy of R above its diagonal), which at
- * 512^2 would take about 290 GB next to the 278 GB FP32 matrix.  The factor
- * is the same; its solves read V and R in place (more passes, slower), and
- * its workspace is about 14 GB at 512^2 with 1024-column blocks. */
+ * row-major solve-side copies (of the reflector blocks and of R above its
+ * diagonal), which at 512^2 would take about 275 GB next to the 278 GB FP32
+ * matrix.  The factor is the same; the inverses of R's 256 x 256 diagonal
+ * blocks (and for CT_PREC_BF16X3 of its 1024 x 1024 ones) are still kept, and
+ * the solves read V and R in place, R's off-diagonal blocks in NN products.
+ * The workspace is about 16.5 GB at 512^2 with 1024-column blocks. */
 #define CT_QR_NO_SOLVE_COPIES 0x100
 
 /* Workspace bytes for ct_qr_factor of an m x n matrix at precision prec that

@@ -282,7 +282,17 @@ static size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 // instead of four times with K = 256 (each update reads and writes them).
 static int rt_ob_for(int64_t n) { return n >= 2048 ? 1024 : 256; }
 
-static Layout layout(int64_t m, int64_t n, int prec, int64_t max_nrhs, int nbo, bool r_copies = true)
+// Solve-side copies kept by a factorization: none (streamed factors), the
+// diagonal-block inverses only (in-memory factors without the row-major
+// copies, CT_QR_NO_SOLVE_COPIES), or all of them.
+enum CopyLevel { kCopiesNone = 0, kCopiesInverses = 1, kCopiesAll = 2 };
+
+// The FP64 scratch of the 256-block inverses borrows Wp when it is large enough
+// (it is free once the factorization is done) in a factorization without the
+// row-major copies.
+static bool ri64_in_wp(const Layout& L, int64_t n) { return L.wp_elems >= ((n + 255) / 256) * 256 * 256; }
+
+static Layout layout(int64_t m, int64_t n, int prec, int64_t max_nrhs, int nbo, int level = kCopiesAll)
 {
     Layout L;
     const int64_t nblocks = (n + nbo - 1) / nbo;
@@ -306,15 +316,16 @@ static Layout layout(int64_t m, int64_t n, int prec, int64_t max_nrhs, int nbo, 
     // / 2 elements)
     const size_t es = prec == CT_PREC_F64 ? 8 : 4;
     const int64_t nbt = (n + 255) / 256;
-    L.Ri = off; off += r_copies ? up256((size_t)2 * nbt * 256 * 256 * es) : 0;
-    L.Ri64 = off; off += r_copies ? up256((size_t)nbt * 256 * 256 * 8) : 0;
-    L.Rt = off; off += r_copies ? up256(rt_elems(n, rt_ob_for(n)) * es) : 0;
+    const bool inv = level >= kCopiesInverses, all = level == kCopiesAll;
+    L.Ri = off; off += inv ? up256((size_t)2 * nbt * 256 * 256 * es) : 0;
+    L.Ri64 = off; off += (all || (inv && !ri64_in_wp(L, n))) ? up256((size_t)nbt * 256 * 256 * 8) : 0;
+    L.Rt = off; off += all ? up256(rt_elems(n, rt_ob_for(n)) * es) : 0;
     // BF16x3: the inverses of the 1024-column diagonal blocks, two layouts
     const int64_t nb4 = (n + 1023) / 1024;
-    L.Ri4 = off; off += (r_copies && prec == CT_PREC_BF16X3 && rt_ob_for(n) == 1024)
+    L.Ri4 = off; off += (inv && prec == CT_PREC_BF16X3 && rt_ob_for(n) == 1024)
                             ? up256((size_t)2 * nb4 * 1024 * 1024 * 4) : 0;
     // reflector blocks, row-major: block b holds (m - b nbo) rows of nbo
-    L.VtAll = off; off += r_copies ? up256((size_t)(nblocks * m - nbo * (nblocks * (nblocks - 1) / 2)) * nbo * es) : 0;
+    L.VtAll = off; off += all ? up256((size_t)(nblocks * m - nbo * (nblocks * (nblocks - 1) / 2)) * nbo * es) : 0;
     L.Tf = off; off += prec == CT_PREC_F64 ? 0 : up256((size_t)nblocks * nbo * nbo * 4);
     L.S3 = off; off += prec == CT_PREC_BF16X3 ? up256((size_t)ldm * nbo * 4) : 0;
     L.total = off;
@@ -1031,7 +1042,7 @@ static int inner_solve(ct_factor* f, TS* C, int64_t ldc, int64_t ncols, int64_t 
     const NtPlan* plan = &f->solve_plan[bucket_of(ncols)];
     const NtPlan diag_plan{32, 1024};     // 256-row products: narrow tiles for more workgroups
     TS* S = (TS*)f->Wq;
-    const TS* Rin = (const TS*)f->Rt + (size_t)ob * ob * (size_t)(nbo * (nbo - 1) / 2);
+    const TS* Rin = f->Rt ? (const TS*)f->Rt + (size_t)ob * ob * (size_t)(nbo * (nbo - 1) / 2) : nullptr;
     const int64_t K0 = Bk * ob;
     const int64_t w = std::min<int64_t>(ob, n - K0);
     for (int64_t i = (w + 255) / 256 - 1; i >= 0; --i) {
@@ -1050,6 +1061,17 @@ static int inner_solve(ct_factor* f, TS* C, int64_t ldc, int64_t ncols, int64_t 
                                  bo, false, 0, &nz, s, &diag_plan, desc, 0, 1));
         }
         if (i == 0) continue;
+        if (!Rin) {
+            // C[K0:k0] -= R[K0:k0, k0:k0+bo] X_b with R read in place (column-major)
+            const TS* Rc = (const TS*)f->A + K0 + k0 * f->lda;
+            if constexpr (sizeof(TS) == 8)
+                CT_HIP((launch_nn_sub<M_F64, TS, TS, TS, false>(Rc, f->lda, C + k0, nullptr, ldc, C + K0, ldc, 256 * i,
+                                                                (int)ncols, bo, s, desc)));
+            else
+                CT_HIP((launch_nn_sub<M_F32, TS, TS, TS, false>(Rc, f->lda, C + k0, nullptr, ldc, C + K0, ldc, 256 * i,
+                                                                (int)ncols, bo, s, desc)));
+            continue;
+        }
         const TS* Ri = Rin + (size_t)Bk * 256 * 256 * (size_t)(q * (q - 1) / 2) + (size_t)256 * 256 * (size_t)(i * (i - 1) / 2);
         if constexpr (sizeof(TS) == 4)
             if (x3 && !desc) {
@@ -1071,12 +1093,13 @@ static int trsm_impl(const ct_factor* fc, TS* B, int64_t nrhs, int64_t ldb, hipS
     const int64_t n = f->n, lda = f->lda;
     const int tb = g_dev.trsm_block;
     const int64_t nb = (n + tb - 1) / tb;
-    if (f->Rt) {
+    if (f->RiR && !f->st) {
         // two levels of blocks, last first: the diagonal block of each outer
         // block (inner_solve, or for BF16x3 one product with the stored
         // inverse of the whole 1024 x 1024 block), then B[0:K0] -= R[0:K0,
-        // K0:K0+w] X_B, one product with K = w on the row-major copy of R
-        // (rt_kernel), an NT product with K-contiguous operands.
+        // K0:K0+w] X_B, one product with K = w: on the row-major copy of R
+        // (rt_kernel), an NT product with K-contiguous operands, or without
+        // that copy an NN product reading R in place.
         const NtPlan* plan = &f->solve_plan[bucket_of(nrhs)];
         const int ob = f->rt_ob;
         const int64_t nbo = (n + ob - 1) / ob;
@@ -1099,6 +1122,16 @@ static int trsm_impl(const ct_factor* fc, TS* B, int64_t nrhs, int64_t ldb, hipS
                 if (r) return r;
             }
             if (K0 == 0) continue;
+            if (!Rt) {
+                const TS* Rc = (const TS*)f->A + K0 * lda;
+                if constexpr (sizeof(TS) == 8)
+                    CT_HIP((launch_nn_sub<M_F64, TS, TS, TS, false>(Rc, lda, B + K0, nullptr, ldb, B, ldb, K0,
+                                                                    (int)nrhs, (int)w, s, desc)));
+                else
+                    CT_HIP((launch_nn_sub<M_F32, TS, TS, TS, false>(Rc, lda, B + K0, nullptr, ldb, B, ldb, K0,
+                                                                    (int)nrhs, (int)w, s, desc)));
+                continue;
+            }
             const TS* X = Rt + (size_t)ob * ob * (size_t)(Bk * (Bk - 1) / 2);
             if constexpr (sizeof(TS) == 4)
                 if (x3 && !desc) {
@@ -1458,7 +1491,7 @@ int ct_qr_workspace(int64_t m, int64_t n, int prec, int64_t max_nrhs, size_t* by
     CT_ARG(prec >= CT_PREC_F64 && prec <= CT_PREC_BF16X3, 3, "prec");
     CT_ARG(max_nrhs >= 0, 4, "max_nrhs");
     CT_ARG(bytes != nullptr, 5, "bytes");
-    *bytes = layout(m, n, prec, max_nrhs, nb_out_for(n), copies).total;
+    *bytes = layout(m, n, prec, max_nrhs, nb_out_for(n), copies ? kCopiesAll : kCopiesInverses).total;
     return 0;
 }
 
@@ -1520,26 +1553,29 @@ static int init_factor(ct_factor* f, void* A, int64_t m, int64_t n, int64_t lda,
 // nres resident tiles, then the staging slots (none when every tile is resident).
 static size_t tile_bytes(int64_t lda, int64_t wt, size_t es) { return up256((size_t)lda * wt * es); }
 
-// Solve-side copies of R of an in-memory factor (diagonal-block inverses and
-// row-major block columns), from V\R in place.
-static int r_copies(ct_factor* f, char* work, const Layout& L, hipStream_t s)
+// Solve-side copies of R of an in-memory factor, from V\R in place: the
+// diagonal-block inverses always, the row-major block columns of R when
+// `row_major` (without them the solves read R in place).
+static int r_copies(ct_factor* f, char* work, const Layout& L, hipStream_t s, bool row_major)
 {
     if (g_dev.trsm_block != 128) return 0;
     const int64_t n = f->n, lda = f->lda;
     const size_t es = f->f64 ? 8 : 4;
     f->RiR = work + L.Ri;
     f->RiC = work + L.Ri + (size_t)((n + 255) / 256) * 256 * 256 * es;
-    f->Rt = work + L.Rt;
+    f->Rt = row_major ? work + L.Rt : nullptr;
     f->rt_ob = rt_ob_for(n);
-    double* Ri64 = (double*)(work + L.Ri64);
+    double* Ri64 = (double*)(row_major || !ri64_in_wp(L, n) ? work + L.Ri64 : (char*)f->Wp);
     double* M = (double*)f->Wq;      // free once the factorization is done
     hipError_t e;
     if (f->f64) {
         e = launch_rinv<double>((const double*)f->A, lda, n, (double*)f->RiR, (double*)f->RiC, Ri64, M, s);
-        if (e == hipSuccess) e = launch_rt<double>((const double*)f->A, lda, n, f->rt_ob, (double*)f->Rt, s);
+        if (e == hipSuccess && row_major)
+            e = launch_rt<double>((const double*)f->A, lda, n, f->rt_ob, (double*)f->Rt, s);
     } else {
         e = launch_rinv<float>((const float*)f->A, lda, n, (float*)f->RiR, (float*)f->RiC, Ri64, M, s);
-        if (e == hipSuccess) e = launch_rt<float>((const float*)f->A, lda, n, f->rt_ob, (float*)f->Rt, s);
+        if (e == hipSuccess && row_major)
+            e = launch_rt<float>((const float*)f->A, lda, n, f->rt_ob, (float*)f->Rt, s);
     }
     if (e != hipSuccess) return fail(-1000 - (int)e, "R copies: %s", hipGetErrorString(e));
     if (f->prec == CT_PREC_BF16X3 && f->rt_ob == 1024) {
@@ -1790,7 +1826,7 @@ int ct_factor_load(const char* path, void* A, int64_t lda, double* tau, void* wo
     CT_HIP(panel_reset(f->part, f->gpart, s));
     f->VtAll = (char*)work + L.VtAll;
     int rc = f->f64 ? block_copies<double>(f, s) : block_copies<float>(f, s);
-    if (!rc) rc = r_copies(f, (char*)work, L, s);
+    if (!rc) rc = r_copies(f, (char*)work, L, s, true);
     if (!rc) {
         e = hipStreamSynchronize(s);
         if (e != hipSuccess) rc = fail(-1000 - (int)e, "load: %s", hipGetErrorString(e));
@@ -1817,7 +1853,7 @@ int ct_qr_factor(void* A, int64_t m, int64_t n, int64_t lda, int prec, double* t
     CT_ARG(work != nullptr && aligned(work), 7, "work");
     CT_ARG(max_nrhs >= 0, 9, "max_nrhs");
     CT_ARG(f_out != nullptr, 10, "f");
-    const Layout L = layout(m, n, prec, max_nrhs, nb_out_for(n), copies);
+    const Layout L = layout(m, n, prec, max_nrhs, nb_out_for(n), copies ? kCopiesAll : kCopiesInverses);
     CT_ARG(work_bytes >= L.total, 8, "work_bytes (see ct_qr_workspace)");
     int r = device_setup();
     if (r) return r;
@@ -1834,7 +1870,7 @@ int ct_qr_factor(void* A, int64_t m, int64_t n, int64_t lda, int prec, double* t
     CT_HIP(panel_reset(f->part, f->gpart, s));
     f->VtAll = copies ? (char*)work + L.VtAll : nullptr;
     int rc = f->f64 ? factor_impl<double>(f, s) : factor_impl<float>(f, s);
-    if (!rc && copies) rc = r_copies(f, (char*)work, L, s);
+    if (!rc) rc = r_copies(f, (char*)work, L, s, copies);
     if (rc) {
         delete f;
         return rc;
@@ -1855,7 +1891,7 @@ int ct_qr_stream_workspace(int64_t m, int64_t n, int64_t lda, int prec, int64_t 
     CT_ARG(min_bytes != nullptr, 7, "min_bytes");
     const size_t es = prec == CT_PREC_F64 ? 8 : 4;
     const int64_t nt = (n + tile_cols - 1) / tile_cols;
-    const size_t base = layout(m, n, prec, max_nrhs, kNbStream, false).total, tb = tile_bytes(lda, tile_cols, es);
+    const size_t base = layout(m, n, prec, max_nrhs, kNbStream, kCopiesNone).total, tb = tile_bytes(lda, tile_cols, es);
     *min_bytes = base + std::min<int64_t>(nt, kSlots) * tb;
     if (all_resident_bytes) *all_resident_bytes = base + nt * tb;
     return 0;
@@ -1888,7 +1924,7 @@ int ct_qr_factor_streamed(void* A_host, int64_t m, int64_t n, int64_t lda, int p
         }
     }
     hipStream_t s = (hipStream_t)stream;
-    const Layout L = layout(m, n, prec, max_nrhs, kNbStream, false);
+    const Layout L = layout(m, n, prec, max_nrhs, kNbStream, kCopiesNone);
     const size_t es = prec == CT_PREC_F64 ? 8 : 4;
     const size_t tb = tile_bytes(lda, tile_cols, es);
     const int64_t nt = (n + tile_cols - 1) / tile_cols;
