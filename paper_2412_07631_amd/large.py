@@ -90,6 +90,9 @@ def main():
                                                                             rdiag["ratio"]))
     del diag
 
+    free, _ = torch.cuda.mem_get_info(0)
+    log("device memory free after the factorization: %.1f GiB (workspace %.1f GiB)" % (
+        free / 2**30, f.work.numel() / 2**30))
     sp = ctqr.SparseA(sc, group=0)
     a_fro = float(torch.linalg.vector_norm(sp.val).item())
     log("sparse copies: nnz %d, ||A||_F %.6g" % (sp.nnz, a_fro))
