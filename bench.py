@@ -178,7 +178,8 @@ def main():
                     help="stop rule: end the refinement once every slice's correction is at most tol relative to "
                          "its image (0: always run --refine steps); the stated bound of the mixed path's image "
                          "error against the FP64 path")
-    ap.add_argument("--method", default="sne", choices=["sne", "qr"])
+    ap.add_argument("--method", default="sne", choices=["sne", "pcgls", "qr"],
+                    help="refinement: semi-normal steps, preconditioned conjugate gradients, or Q^T corrections")
     ap.add_argument("--nrhs", type=int, default=None, help="slices per batch (default: the workload's)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference path")
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 path")
@@ -209,7 +210,7 @@ def main():
     m, n = sc.m, sc.n
     nrhs = args.nrhs or w["slices"]
     prec = ctqr.PREC_NAMES[args.prec]
-    method = ctqr.REFINE_SNE if args.method == "sne" else ctqr.REFINE_QR
+    method = {"sne": ctqr.REFINE_SNE, "pcgls": ctqr.REFINE_PCGLS, "qr": ctqr.REFINE_QR}[args.method]
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     log("workload %s: m=%d n=%d nrhs=%d prec=%s refine=%d(%s)" % (args.workload, m, n, nrhs, args.prec,
@@ -247,7 +248,7 @@ def main():
     dt_store = torch.float64 if prec == ctqr.PREC_F64 else torch.float32
     A = torch.empty((n, ctqr.ld16(m)), dtype=dt_store, device=dev)
     X = torch.zeros((nrhs, ctqr.ld16(n)), dtype=torch.float64, device=dev)
-    scratch = torch.empty(ctqr.refine_workspace(m, n, nrhs), dtype=torch.uint8, device=dev)
+    scratch = torch.empty(ctqr.refine_workspace(m, n, nrhs, method), dtype=torch.uint8, device=dev)
     rn = torch.zeros((args.refine + 1) * nrhs, dtype=torch.float64, device=dev)
     gn = torch.zeros((args.refine + 1) * nrhs, dtype=torch.float64, device=dev)
 
