@@ -374,6 +374,30 @@ int ct_solve_graph_create(const ct_factor* f, void* B, int64_t ldb, int64_t b_co
 int ct_solve_graph_launch(ct_solve_graph* g, void* stream);
 int ct_solve_graph_destroy(ct_solve_graph* g);
 
+/* B[0:n] <- R^{-1} Q^T B (Eq. (solve)) in one persistent launch: one
+ * workgroup per CU (a cooperative launch, refused rather than run with part
+ * of the grid waiting), the batch taken 32 columns at a time (16 for an FP64
+ * factor).  Per outer reflector block, W = V^T B is summed over row groups,
+ * W' = T^T W, and B -= V W', with a grid-wide barrier between the phases; the
+ * back-substitution then runs over R's 256-row blocks, each owned by one
+ * workgroup that publishes its x_q to the others through a flag as soon as
+ * every later block has been applied to it (Sec. 2.1's ormqr and trsm in one
+ * kernel).  Needs an in-memory factor with its solve-side copies (not
+ * CT_QR_NO_SOLVE_COPIES, not streamed) and n <= 1024 x CUs; otherwise returns
+ * -2007.  Uses the factor's update buffer as scratch, so it is ordered with
+ * the factor's other solves like them.  A cross-workgroup wait that times out
+ * (0.5 s) makes the launch end early and the next ct_status return -2006.
+ * B: m x nrhs (ldb), the factor's storage type, any nrhs >= 0. */
+int ct_solve_fused(const ct_factor* f, void* B, int64_t nrhs, int64_t ldb, void* stream);
+
+/* ct_solve_graph_create with the solve captured as the single launch of
+ * ct_solve_fused (plus its reset node): the graph is the batch check, one
+ * fused solve of the current batch and the advance of the cursor.  Same
+ * arguments, descriptor rules and errors as ct_solve_graph_create, plus
+ * ct_solve_fused's requirements on the factor. */
+int ct_solve_graph_create_fused(const ct_factor* f, void* B, int64_t ldb, int64_t b_cols, int64_t max_cols,
+                                int32_t* desc, void* stream, ct_solve_graph** g);
+
 /* Autotuner of the solve kernels: for each batch-size bucket (<= 8, <= 32,
  * <= 128, <= 512 columns, up to max_nrhs) it times every candidate launch
  * plan -- tile width 16/32/64/128 along the slices and the split-K workgroup

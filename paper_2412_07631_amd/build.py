@@ -18,7 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libctqr.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["siddon.hip", "panel.hip", "gemm.hip", "gemm_lds.hip", "solve.hip", "sparse.hip", "quality.hip", "api.hip"]
+SOURCES = ["siddon.hip", "panel.hip", "gemm.hip", "gemm_lds.hip", "solve.hip", "sparse.hip", "fused.hip", "quality.hip",
+           "api.hip"]
 ARCH = os.environ.get("CTQR_ARCH", "gfx950")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

@@ -110,6 +110,26 @@ hipError_t launch_zero_rows(T* Y, int64_t ldy, int64_t r0, int64_t r1, int cols,
 hipError_t launch_colnorm(const double* X, int64_t ldx, int64_t rows, int cols, double* out, hipStream_t s);
 template <typename T>
 hipError_t launch_colsq(const T* C, int64_t ldc, int64_t rows, int cols, double* out, hipStream_t s);
+struct FusedArgs {
+    const void* A;
+    int64_t lda;
+    const void* Vt;
+    const double* T;
+    const void* RiC;
+    int64_t m, n;
+    int nbo, nblocks;
+    void* B;
+    int64_t ldb;
+    int nrhs;
+    const int32_t* rec;
+    char* scratch;
+    int nrg_cap;
+    int32_t* err;
+    uint64_t wait_ticks;
+};
+template <typename TS>
+hipError_t launch_fused_solve(const FusedArgs& a, int G, bool cooperative, hipStream_t s);
+int fused_row_groups(int nbo, int64_t n, size_t es, size_t bytes);
 hipError_t launch_cg_update(const double* x, double* y, int64_t rows, int nrhs, int64_t ld, const double* num,
                             const double* den, int mode, hipStream_t s);
 hipError_t launch_cg_ratio(const double* gam, const double* qn, const double* pn, const double* xn, int nrhs,
@@ -2299,6 +2319,11 @@ int ct_status(const ct_factor* f, int64_t* info, void* stream)
         CT_HIP(hipStreamSynchronize(s));
         return fail(-2003, "%s", "a graph-captured solve met an invalid batch descriptor entry and solved nothing");
     }
+    if (err & 8) {
+        CT_HIP(hipMemsetAsync(f->err, 0, 4, s));
+        CT_HIP(hipStreamSynchronize(s));
+        return fail(-2006, "%s", "a cross-workgroup wait of the fused solve timed out; its result is incomplete");
+    }
     return 0;
 }
 
@@ -2309,14 +2334,72 @@ int ct_factor_destroy(ct_factor* f)
     return 0;
 }
 
+// ------------------------------------------------------------- fused solve
+// One persistent launch for B <- R^{-1} Q^T B (fused.hip): needs an in-memory
+// factor with its solve-side copies (row-major reflector blocks, inverses of
+// R's 256 x 256 diagonal blocks); its scratch is the factor's update buffer.
+static int fused_solve(const ct_factor* f, void* B, int64_t ldb, int64_t nrhs, const int32_t* rec, bool coop,
+                       hipStream_t s)
+{
+    if (f->st || !f->VtAll || !f->RiC)
+        return fail(-2007, "%s", "the fused solve needs an in-memory factor with its solve-side copies");
+    int r = device_setup();
+    if (r) return r;
+    const int G = g_dev.cus;
+    const int64_t nbq = (f->n + 255) / 256;
+    if (nbq > (int64_t)4 * G) return fail(-2007, "%s", "the fused solve takes at most 1024 x CUs columns");
+    const size_t es = f->f64 ? 8 : 4;
+    const int nrg = fused_row_groups(f->nb_out, f->n, es, (size_t)f->wp_elems * 8);
+    if (nrg < 1) return fail(-2007, "%s", "the factor's update buffer is too small for the fused solve");
+    FusedArgs a;
+    a.A = f->A; a.lda = f->lda; a.Vt = f->VtAll; a.T = f->T_all; a.RiC = f->RiC;
+    a.m = f->m; a.n = f->n; a.nbo = f->nb_out; a.nblocks = (int)f->nblocks;
+    a.B = B; a.ldb = ldb; a.nrhs = (int)nrhs; a.rec = rec;
+    a.scratch = (char*)f->Wp; a.nrg_cap = nrg; a.err = f->err; a.wait_ticks = kWaitTicks;
+    hipError_t e = f->f64 ? launch_fused_solve<double>(a, G, coop, s) : launch_fused_solve<float>(a, G, coop, s);
+    if (e != hipSuccess) return fail(-1000 - (int)e, "fused solve launch: %s", hipGetErrorString(e));
+    return 0;
+}
+
+extern "C" {
+
+int ct_solve_fused(const ct_factor* f, void* B, int64_t nrhs, int64_t ldb, void* stream)
+{
+    CT_ARG(f != nullptr, 1, "f");
+    CT_ARG(B != nullptr && aligned(B), 2, "B");
+    CT_ARG(nrhs >= 0 && nrhs <= (int64_t)1 << 30, 3, "nrhs");
+    CT_ARG(ldb >= f->m && ldb % 16 == 0, 4, "ldb");
+    if (nrhs == 0) return 0;
+    return fused_solve(f, B, ldb, nrhs, nullptr, true, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
 // ------------------------------------------------------------- graph solves
 struct ct_solve_graph {
     hipGraph_t graph;
     hipGraphExec_t exec;
 };
 
+static int graph_create(const ct_factor* f, void* B, int64_t ldb, int64_t b_cols, int64_t max_cols, int32_t* desc,
+                        void* stream, ct_solve_graph** out, bool fused);
+
 int ct_solve_graph_create(const ct_factor* f, void* B, int64_t ldb, int64_t b_cols, int64_t max_cols, int32_t* desc,
                           void* stream, ct_solve_graph** out)
+{
+    return graph_create(f, B, ldb, b_cols, max_cols, desc, stream, out, false);
+}
+
+int ct_solve_graph_create_fused(const ct_factor* f, void* B, int64_t ldb, int64_t b_cols, int64_t max_cols,
+                                int32_t* desc, void* stream, ct_solve_graph** out)
+{
+    return graph_create(f, B, ldb, b_cols, max_cols, desc, stream, out, true);
+}
+
+}  // extern "C"
+
+static int graph_create(const ct_factor* f, void* B, int64_t ldb, int64_t b_cols, int64_t max_cols, int32_t* desc,
+                        void* stream, ct_solve_graph** out, bool fused)
 {
     CT_ARG(f != nullptr, 1, "f");
     CT_ARG(B != nullptr && aligned(B), 2, "B");
@@ -2337,10 +2420,11 @@ int ct_solve_graph_create(const ct_factor* f, void* B, int64_t ldb, int64_t b_co
         hipError_t e = launch_begin_batch(desc, f->batch_rec, (int)max_cols, b_cols, f->err, s);
         if (e != hipSuccess) r = fail(-1000 - (int)e, "begin batch: %s", hipGetErrorString(e));
     }
-    if (!r)
+    if (!r && fused) r = fused_solve(f, B, ldb, max_cols, rec, true, s);
+    if (!r && !fused)
         r = f->f64 ? apply_qt_impl<double>(f, (double*)B, max_cols, ldb, s, true, rec)
                    : apply_qt_impl<float>(f, (float*)B, max_cols, ldb, s, true, rec);
-    if (!r)
+    if (!r && !fused)
         r = f->f64 ? trsm_impl<double>(f, (double*)B, max_cols, ldb, s, rec)
                    : trsm_impl<float>(f, (float*)B, max_cols, ldb, s, rec);
     if (!r) {
@@ -2365,6 +2449,8 @@ int ct_solve_graph_create(const ct_factor* f, void* B, int64_t ldb, int64_t b_co
     *out = g;
     return 0;
 }
+
+extern "C" {
 
 int ct_solve_graph_launch(ct_solve_graph* g, void* stream)
 {

@@ -101,6 +101,8 @@ _sig("ct_profile_begin", [])
 _sig("ct_profile_end", [ctypes.POINTER(Profile)])
 _sig("ct_status", [_vp, ctypes.POINTER(_i64), _vp])
 _sig("ct_solve_graph_create", [_vp, _vp, _i64, _i64, _i64, _vp, _vp, ctypes.POINTER(_vp)])
+_sig("ct_solve_graph_create_fused", [_vp, _vp, _i64, _i64, _i64, _vp, _vp, ctypes.POINTER(_vp)])
+_sig("ct_solve_fused", [_vp, _vp, _i64, _i64, _vp])
 _sig("ct_solve_graph_launch", [_vp, _vp])
 _sig("ct_solve_graph_destroy", [_vp])
 _sig("ct_autotune_solve", [_vp, _vp, _i64, _i64, ctypes.c_char_p, _vp])
@@ -343,6 +345,13 @@ def apply_qt(f: Factor, B: torch.Tensor, nrhs: int = None, stream=None):
     return B
 
 
+def solve_fused(f: Factor, B: torch.Tensor, nrhs: int = None, stream=None):
+    """B[:, :n] <- R^{-1} Q^T B in one persistent launch (ct_solve_fused)."""
+    nrhs = B.shape[0] if nrhs is None else nrhs
+    _check(_lib.ct_solve_fused(f.handle, _ptr(B), nrhs, B.shape[1], _stream(stream)))
+    return B
+
+
 def trsm_solve(f: Factor, B: torch.Tensor, nrhs: int = None, stream=None):
     nrhs = B.shape[0] if nrhs is None else nrhs
     _check(_lib.ct_trsm_solve(f.handle, _ptr(B), nrhs, B.shape[1], _stream(stream)))
@@ -470,14 +479,16 @@ class SolveGraph:
     """A captured solve (Q^T then R^{-1}) over the batch descriptor `desc` of
     columns inside B; each launch solves the current batch and advances it."""
 
-    def __init__(self, f: Factor, B: torch.Tensor, max_cols: int, desc: torch.Tensor, stream=None):
+    def __init__(self, f: Factor, B: torch.Tensor, max_cols: int, desc: torch.Tensor, stream=None,
+                 fused: bool = False):
         self.f, self.B, self.desc = f, B, desc
         st = stream if stream is not None else torch.cuda.Stream()
         self.stream = st
         h = _vp()
+        create = _lib.ct_solve_graph_create_fused if fused else _lib.ct_solve_graph_create
         with torch.cuda.stream(st):
-            _check(_lib.ct_solve_graph_create(f.handle, _ptr(B), B.shape[1], B.shape[0], int(max_cols),
-                                              _ptr(desc), _vp(st.cuda_stream), ctypes.byref(h)))
+            _check(create(f.handle, _ptr(B), B.shape[1], B.shape[0], int(max_cols), _ptr(desc),
+                          _vp(st.cuda_stream), ctypes.byref(h)))
         self.handle = h
 
     def launch(self, stream=None):
