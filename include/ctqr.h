@@ -383,7 +383,7 @@ int ct_solve_graph_destroy(ct_solve_graph* g);
  * workgroup that publishes its x_q to the others through a flag as soon as
  * every later block has been applied to it (Sec. 2.1's ormqr and trsm in one
  * kernel).  Needs an in-memory factor with its solve-side copies (not
- * CT_QR_NO_SOLVE_COPIES, not streamed) and n <= 1024 x CUs; otherwise returns
+ * CT_QR_NO_SOLVE_COPIES, not streamed) and n <= 512 x CUs; otherwise returns
  * -2007.  Uses the factor's update buffer as scratch, so it is ordered with
  * the factor's other solves like them.  A cross-workgroup wait that times out
  * (0.5 s) makes the launch end early and the next ct_status return -2006.

@@ -2343,11 +2343,12 @@ static int fused_solve(const ct_factor* f, void* B, int64_t ldb, int64_t nrhs, c
 {
     if (f->st || !f->VtAll || !f->RiC)
         return fail(-2007, "%s", "the fused solve needs an in-memory factor with its solve-side copies");
+    if (f->nb_out > 1024) return fail(-2007, "%s", "the fused solve takes outer blocks of at most 1024 columns");
     int r = device_setup();
     if (r) return r;
     const int G = g_dev.cus;
     const int64_t nbq = (f->n + 255) / 256;
-    if (nbq > (int64_t)4 * G) return fail(-2007, "%s", "the fused solve takes at most 1024 x CUs columns");
+    if (nbq > (int64_t)2 * G) return fail(-2007, "%s", "the fused solve takes at most 512 x CUs columns");
     const size_t es = f->f64 ? 8 : 4;
     const int nrg = fused_row_groups(f->nb_out, f->n, es, (size_t)f->wp_elems * 8);
     if (nrg < 1) return fail(-2007, "%s", "the factor's update buffer is too small for the fused solve");
