@@ -8,7 +8,9 @@ once; then batches of 1, 2, 4, ... up to --max-nrhs noisy sinograms are
 reconstructed by X = R^-1 Q^T B (FP64 and FP32 factors) or by the BF16x3
 factor followed by FP64-residual refinement (semi-normal steps, or the
 preconditioned conjugate-gradient steps with --method pcgls, up to --refine
-steps under the stop rule --tol), and the batch's event time gives slices/s.  Every step runs in the library's
+steps under the stop rule --tol), and the batch's event time gives slices/s.
+The precisions named by --fused are timed a second time through the one-launch
+fused solve (ct_solve_fused).  Every step runs in the library's
 kernels; the inputs are seeded synthetic phantoms and Poisson noise.
 
     python -m paper_2412_07631_amd.sweep [--workload c3_256] [--max-nrhs 2048]
@@ -64,6 +66,8 @@ def main():
     ap.add_argument("--method", default="sne", choices=["sne", "pcgls"])
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--out", default=None, help="markdown summary file")
+    ap.add_argument("--fused", default="f32", help="precisions also timed through the one-launch fused solve "
+                                                 "(comma-separated, empty for none)")
     args = ap.parse_args()
     dev = "cuda"
     sc = synth.workload_scanner(args.workload)
@@ -90,28 +94,33 @@ def main():
         f = ctqr.qr_factor(A, m, n, p, max_nrhs=args.max_nrhs)
         assert ctqr.status(f) == 0
         refined = prec == "bf16x3"
-        label = prec + ("+%s" % args.method if refined else "")
+        variants = [(prec + ("+%s" % args.method if refined else ""), False)]
+        if prec in args.fused.split(","):
+            variants.append((prec + " fused", True))
 
-        def solve(k):
+        def solve(k, fused=False):
             if refined:
                 Xd = torch.zeros((k, ctqr.ld16(n)), dtype=torch.float64, device=dev)
                 steps = ctqr.solve_refined(f, sp, Ball[:k], Xd, args.refine, method, tol=args.tol)
                 return Xd[:, :n], steps
-            Bk = Ball[:k].to(dt)
-            ctqr.apply_qt(f, Bk)
-            ctqr.trsm_solve(f, Bk)
+            Bk = Ball[:k].to(dt, copy=True)          # the solves work in place
+            if fused:
+                ctqr.solve_fused(f, Bk)
+            else:
+                ctqr.apply_qt(f, Bk)
+                ctqr.trsm_solve(f, Bk)
             return Bk[:, :n].double(), 0
 
         if prec == "f64":
             Xref, _ = solve(args.max_nrhs)
             Xref = Xref.clone()
-        for k in sizes:
+        for (label, fused), k in ((v, k) for v in variants for k in sizes):
             best, X, steps = None, None, 0
             for _ in range(args.reps):
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 torch.cuda.synchronize()
                 e0.record()
-                X, steps = solve(k)
+                X, steps = solve(k, fused)
                 e1.record()
                 torch.cuda.synchronize()
                 ms = e0.elapsed_time(e1)
@@ -127,6 +136,7 @@ def main():
                 rec["max_rel_err_vs_fp64"] = err
                 rec["bound"] = BOUND[prec]
                 rec["check"] = "ok" if err <= BOUND[prec] else "FAIL"
+                rec["status"] = ctqr.status(f)
                 worst[label] = max(worst.get(label, 0.0), err)
                 if err > BOUND[prec]:
                     failed.append((label, k, err))
@@ -148,7 +158,8 @@ def main():
             for k in sizes:
                 fo.write("| %d | " % k + " | ".join("%.1f" % table[k].get(p, float("nan")) for p in labels) + " |\n")
             fo.write("\nLargest relative image error against the FP64 path over all batch sizes: " +
-                     ", ".join("%s %.2e (bound %.0e)" % (l, worst[l], BOUND[l.split("+")[0]]) for l in worst) + "\n")
+                     ", ".join("%s %.2e (bound %.0e)" % (l, worst[l], BOUND[l.split("+")[0].split(" ")[0]])
+                               for l in worst) + "\n")
     if failed:
         print("outside the bound: %s" % failed, file=sys.stderr)
         sys.exit(1)
