@@ -159,8 +159,9 @@ int ct_stream_inject_failure(int64_t tile, int64_t after_updates);
  * the error word that ct_status reports as -2001, and every later wait of the
  * same factorization ends at once, so a factorization whose workgroups could
  * not all be resident fails in bounded time instead of waiting forever.  For
- * tests: set the limit in 100 MHz ticks for later factorizations (ticks < 0
- * restores the default; 0 makes every wait give up). */
+ * tests: set the limit in 100 MHz ticks for later factorizations and fused
+ * solves (ct_solve_fused, whose time-outs ct_status reports as -2006; ticks
+ * < 0 restores the default; 0 makes every wait give up). */
 int ct_debug_wait_limit(int64_t ticks);
 /* A Householder panel (Sec. 2.1, the geqrf step) is factored first from two
  * Gram reductions (CholeskyQR2 followed by reconstruction of the Householder

@@ -130,6 +130,7 @@ struct FusedArgs {
 template <typename TS>
 hipError_t launch_fused_solve(const FusedArgs& a, int G, bool cooperative, hipStream_t s);
 int fused_row_groups(int nbo, int64_t n, size_t es, size_t bytes);
+uint64_t panel_wait_limit();
 hipError_t launch_cg_update(const double* x, double* y, int64_t rows, int nrhs, int64_t ld, const double* num,
                             const double* den, int mode, hipStream_t s);
 hipError_t launch_cg_ratio(const double* gam, const double* qn, const double* pn, const double* xn, int nrhs,
@@ -2356,7 +2357,7 @@ static int fused_solve(const ct_factor* f, void* B, int64_t ldb, int64_t nrhs, c
     a.A = f->A; a.lda = f->lda; a.Vt = f->VtAll; a.T = f->T_all; a.RiC = f->RiC;
     a.m = f->m; a.n = f->n; a.nbo = f->nb_out; a.nblocks = (int)f->nblocks;
     a.B = B; a.ldb = ldb; a.nrhs = (int)nrhs; a.rec = rec;
-    a.scratch = (char*)f->Wp; a.nrg_cap = nrg; a.err = f->err; a.wait_ticks = kWaitTicks;
+    a.scratch = (char*)f->Wp; a.nrg_cap = nrg; a.err = f->err; a.wait_ticks = panel_wait_limit();
     hipError_t e = f->f64 ? launch_fused_solve<double>(a, G, coop, s) : launch_fused_solve<float>(a, G, coop, s);
     if (e != hipSuccess) return fail(-1000 - (int)e, "fused solve launch: %s", hipGetErrorString(e));
     return 0;

@@ -902,6 +902,7 @@ __global__ void __launch_bounds__(256) panel_cqr_kernel(PanelArgs<TS> a)
 // --------------------------------------------------------------- launcher
 static uint64_t g_wait_ticks = kWaitTicks;
 void panel_set_wait_limit(int64_t ticks) { g_wait_ticks = ticks < 0 ? kWaitTicks : (uint64_t)ticks; }
+uint64_t panel_wait_limit() { return g_wait_ticks; }
 
 // LDS: the panel plus the reduction scratch and the T factor.
 size_t panel_lds_bytes(int nbp, int rw) { return ((size_t)nbp * rw + kPanelAux) * sizeof(double); }
@@ -994,16 +995,23 @@ hipError_t panel_set_max_lds(size_t bytes)
     return hipSuccess;
 }
 
-// Workgroups of the column-wise panel kernel (at `shmem` bytes of LDS) that
-// one compute unit holds at once, the smaller of the two storage types.
+// Workgroups of a panel kernel (at `shmem` bytes of LDS) that one compute
+// unit holds at once: the smallest over both forms and storage types.
 hipError_t panel_max_active(int* per_cu, size_t shmem)
 {
-    int a = 0, b = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, (const void*)panel_qr_kernel<float>, 256, shmem);
-    if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void*)panel_qr_kernel<double>, 256, shmem);
-    *per_cu = a < b ? a : b;
-    return e;
+    // both panel forms, both storage types: the smallest residency of the
+    // kernels a factorization may launch with this LDS size
+    const void* k[4] = {(const void*)panel_qr_kernel<float>, (const void*)panel_qr_kernel<double>,
+                        (const void*)panel_cqr_kernel<float>, (const void*)panel_cqr_kernel<double>};
+    int lo = 1 << 30;
+    for (const void* f : k) {
+        int a = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, f, 256, shmem);
+        if (e != hipSuccess) return e;
+        if (a < lo) lo = a;
+    }
+    *per_cu = lo;
+    return hipSuccess;
 }
 
 template hipError_t launch_panel<double>(double*, int64_t, int64_t, int, int, double*, double*, int64_t, double*,

@@ -188,3 +188,17 @@ def test_factor_file_header_checks_without_gpu(tmp_path):
                               ctypes.c_void_p(256), 1024, 8, ctypes.byref(h), None) == -6
     assert lib.ct_factor_load(str(hdr).encode(), ctypes.c_void_p(256), 3000, ctypes.c_void_p(256),
                               ctypes.c_void_p(256), 1 << 40, 8, ctypes.byref(h), None) == -3
+
+
+def test_fused_solve_argument_errors_without_gpu():
+    """ct_solve_fused and its graph form validate their arguments before any
+    device work."""
+    lib = ctypes.CDLL(LIB)
+    lib.ct_solve_fused.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p]
+    assert lib.ct_solve_fused(None, ctypes.c_void_p(256), 4, 64, None) == -1
+    lib.ct_solve_graph_create_fused.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                                ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                                ctypes.POINTER(ctypes.c_void_p)]
+    h = ctypes.c_void_p()
+    assert lib.ct_solve_graph_create_fused(None, ctypes.c_void_p(256), 64, 4, 4, ctypes.c_void_p(256),
+                                           ctypes.c_void_p(256), ctypes.byref(h)) == -1

@@ -154,3 +154,28 @@ def test_fused_graph_uneven_batches(ct, prec):
     with pytest.raises(ct.CtError) as e:
         ct.status(f)
     assert e.value.code == -2003
+
+
+def test_fused_wait_limit_fails_fast_and_recovers(ct):
+    """With the wait limit forced to zero from the host, the fused solve's
+    grid barriers and flag waits give up at once: the launch ends (no hang)
+    and ct_status reports -2006 once; with the default limit restored the
+    next fused solve is correct."""
+    sc, A, VR, tau = problem("multi")
+    _, P, B = sinograms(sc, A, 3, 5, 5e4)
+    Xs = O.solve(VR, tau, B)
+    f, dt = factor(ct, sc, "f32", 8)
+    ct.debug_wait_limit(0)
+    try:
+        Bd = to_dev(B, dt)
+        ct.solve_fused(f, Bd)
+        with pytest.raises(ct.CtError) as e:
+            ct.status(f)
+        assert e.value.code == -2006
+    finally:
+        ct.debug_wait_limit(-1)
+    assert ct.status(f) == 0
+    Bd = to_dev(B, dt)
+    ct.solve_fused(f, Bd)
+    assert ct.status(f) == 0
+    assert max_col_rel(from_dev(Bd, sc.n), Xs) <= 1e-4
