@@ -144,18 +144,30 @@ def batched_leg(ctqr, synth, torch, f, sc, Bd, dev, total, sp, X64=None):
             "fd_err_by_norms": fd_err}
 
 
+def code_hash(path):
+    """SHA-256 prefix of a source file's code: comments and blank lines
+    removed, so that editing a comment does not invalidate counters taken
+    on the same code."""
+    import hashlib
+    import re
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    lines = [l.rstrip() for l in text.split("\n") if l.strip()]
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()[:16]
+
+
 def counted_traffic(prec, dom):
     """HBM bytes per launch of the roofline kernel from the committed
     hardware-counter summary (FETCH_SIZE and WRITE_SIZE passes, scaled by the
     same counters on a plain copy), or None when there is none for this
     kernel or the kernel's source has changed since the counters were taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "x3dl_update_c3_256_traffic.json")
     if prec != "bf16x3" or not os.path.exists(path):
         return None
     rec = json.load(open(path))
     src = os.path.join(ROOT, "paper_2412_07631_amd", "csrc", "gemm_lds.hip")
-    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != rec.get("source_sha256_16"):
+    if code_hash(src) != rec.get("code_sha256_16"):
         return None
     k = rec.get("sub" if dom == "update_cvw" else "vtc")
     if not k:

@@ -778,7 +778,7 @@ template hipError_t launch_nt_lp<M_BF16X3>(const void*, int64_t, const void*, in
 // A stage holds, for each half of each operand, the tile's rows as 64-byte
 // records (K step 32) in 1 KB blocks of 16 rows; one load instruction of a
 // wavefront fills one block (lane l writes bytes 16 l .. 16 l + 15), and lane
-// l fetches chunk (l & 3) ^ ((r >> 1) & 3) of row r = l >> 2, so that the
+// l fetches chunk (l & 3) ^ dl_swz16(r) of row r = l >> 2, so that the
 // sixteen rows a fragment read touches spread over all banks.  The stages
 // form a ring: while one is multiplied the next ones are in flight, and one
 // barrier per K step both publishes a landed stage and frees the stage read
