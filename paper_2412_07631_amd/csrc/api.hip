@@ -110,26 +110,9 @@ hipError_t launch_zero_rows(T* Y, int64_t ldy, int64_t r0, int64_t r1, int cols,
 hipError_t launch_colnorm(const double* X, int64_t ldx, int64_t rows, int cols, double* out, hipStream_t s);
 template <typename T>
 hipError_t launch_colsq(const T* C, int64_t ldc, int64_t rows, int cols, double* out, hipStream_t s);
-struct FusedArgs {
-    const void* A;
-    int64_t lda;
-    const void* Vt;
-    const double* T;
-    const void* RiC;
-    int64_t m, n;
-    int nbo, nblocks;
-    void* B;
-    int64_t ldb;
-    int nrhs;
-    const int32_t* rec;
-    char* scratch;
-    int nrg_cap;
-    int32_t* err;
-    uint64_t wait_ticks;
-};
 template <typename TS>
 hipError_t launch_fused_solve(const FusedArgs& a, int G, bool cooperative, hipStream_t s);
-int fused_row_groups(int nbo, int64_t n, size_t es, size_t bytes);
+int fused_row_groups(int nbo, int64_t n, size_t es, size_t bytes, int kc, int cap);
 uint64_t panel_wait_limit();
 hipError_t launch_cg_update(const double* x, double* y, int64_t rows, int nrhs, int64_t ld, const double* num,
                             const double* den, int mode, hipStream_t s);
@@ -2351,13 +2334,14 @@ static int fused_solve(const ct_factor* f, void* B, int64_t ldb, int64_t nrhs, c
     const int64_t nbq = (f->n + 255) / 256;
     if (nbq > (int64_t)2 * G) return fail(-2007, "%s", "the fused solve takes at most 512 x CUs columns");
     const size_t es = f->f64 ? 8 : 4;
-    const int nrg = fused_row_groups(f->nb_out, f->n, es, (size_t)f->wp_elems * 8);
-    if (nrg < 1) return fail(-2007, "%s", "the factor's update buffer is too small for the fused solve");
+    const int nrg = fused_row_groups(f->nb_out, f->n, es, (size_t)f->wp_elems * 8, es == 4 ? 32 : 16, 32);
+    const int nrw = fused_row_groups(f->nb_out, f->n, es, (size_t)f->wp_elems * 8, 8, G);
+    if (nrg < 1 || nrw < 1) return fail(-2007, "%s", "the factor's update buffer is too small for the fused solve");
     FusedArgs a;
     a.A = f->A; a.lda = f->lda; a.Vt = f->VtAll; a.T = f->T_all; a.RiC = f->RiC;
     a.m = f->m; a.n = f->n; a.nbo = f->nb_out; a.nblocks = (int)f->nblocks;
     a.B = B; a.ldb = ldb; a.nrhs = (int)nrhs; a.rec = rec;
-    a.scratch = (char*)f->Wp; a.nrg_cap = nrg; a.err = f->err; a.wait_ticks = panel_wait_limit();
+    a.scratch = (char*)f->Wp; a.nrg_cap = nrg; a.nrw = nrw; a.err = f->err; a.wait_ticks = panel_wait_limit();
     hipError_t e = f->f64 ? launch_fused_solve<double>(a, G, coop, s) : launch_fused_solve<float>(a, G, coop, s);
     if (e != hipSuccess) return fail(-1000 - (int)e, "fused solve launch: %s", hipGetErrorString(e));
     return 0;

@@ -101,4 +101,24 @@ struct ErrWord {
     int32_t flags;
 };
 
+// Arguments of the persistent fused solve (fused.hip), filled by api.hip.
+struct FusedArgs {
+    const void* A;        // V\R in place, column-major
+    int64_t lda;
+    const void* Vt;       // row-major reflector blocks: block b at vt_off(b), ld round16(width)
+    const double* T;      // T of block b at b nbo^2, column-major, upper triangular
+    const void* RiC;      // inverses of the 256 x 256 diagonal blocks of R, column-major, block q at q 256^2
+    int64_t m, n;
+    int nbo, nblocks;
+    void* B;
+    int64_t ldb;
+    int nrhs;             // columns (eager), or the largest batch (graph)
+    const int32_t* rec;   // batch record (offset, count) of a graph-captured solve, or null
+    char* scratch;
+    int nrg_cap;          // row groups of the W partials at most (wide chunks)
+    int nrw;              // row ranges of the narrow FP32 chunks (one per workgroup at most)
+    int32_t* err;
+    uint64_t wait_ticks;
+};
+
 }  // namespace ctqr

@@ -27,24 +27,6 @@ namespace ctqr {
 constexpr int kFusedMaxOwn = 2;     // 256-row blocks per workgroup in the back-substitution
 constexpr int kFusedErr = 8;
 
-struct FusedArgs {
-    const void* A;        // V\R in place, column-major
-    int64_t lda;
-    const void* Vt;       // row-major reflector blocks: block b at vt_off(b), ld round16(width)
-    const double* T;      // T of block b at b nbo^2, column-major, upper triangular
-    const void* RiC;      // inverses of the 256 x 256 diagonal blocks of R, column-major, block q at q 256^2
-    int64_t m, n;
-    int nbo, nblocks;
-    void* B;
-    int64_t ldb;
-    int nrhs;             // columns (eager), or the largest batch (graph)
-    const int32_t* rec;   // batch record (offset, count) of a graph-captured solve, or null
-    char* scratch;
-    int nrg_cap;          // row groups of the W partials at most
-    int32_t* err;
-    uint64_t wait_ticks;
-};
-
 __host__ __device__ inline size_t fused_up256(size_t x) { return (x + 255) / 256 * 256; }
 
 // Scratch layout (bytes): barrier words, per-block flags, W (KC x nbo FP64),
@@ -99,10 +81,15 @@ __device__ inline bool fused_wait(uint32_t* p, uint32_t v, bool want_ne, int32_t
 
 // Grid-wide barrier: the last workgroup to arrive resets the count and
 // advances the generation; the others wait for the generation to change.
-// Self-resetting, so one reset before the launch is all it needs.
+// Self-resetting, so one reset before the launch is all it needs.  Only
+// thread 0 fences at agent scope: the workgroup barrier before it waits for
+// every wavefront's stores to reach L2 (and orders them before thread 0's
+// release, which writes L2 back), and its acquire (an L2 and L1 invalidate)
+// comes before the barrier after it.  One writeback and one invalidate per
+// workgroup instead of one per wavefront: 6 us a barrier instead of 20 on
+// 256 workgroups.
 __device__ inline bool fused_sync(uint32_t* bar, uint32_t& gen, int G, int32_t* err, uint64_t ticks, int* flag)
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t* count = bar;
@@ -122,7 +109,6 @@ __device__ inline bool fused_sync(uint32_t* bar, uint32_t& gen, int G, int32_t* 
         *flag = ok ? 1 : 0;
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return *flag != 0;
 }
 
@@ -359,6 +345,332 @@ __device__ __forceinline__ void fused_phase_c(const FusedArgs& a, char* lds, TS*
     __syncthreads();
 }
 
+// ------------------------------------------------- Q^T phases, narrow FP32 chunks
+// Chunks of at most kNarrow columns of an FP32 factor.  The rows of a block
+// are split in nrw contiguous ranges, one per workgroup, and thread t owns
+// columns 4t .. 4t+3 of the row-major reflector copy: one wavefront load reads
+// 1 KB of a row, the workgroup reads whole rows, and every workgroup streams
+// one contiguous stretch of the block.  Phase C walks its range backwards, so
+// that the rows phase A read last (the likeliest still cached) come first.
+// LDS: the range's B rows (row-major, 8 floats a row) at 0, the FP64 W of
+// phase B2 and the reduction buffers at kNarrowWs.
+constexpr int kNarrow = 8;
+constexpr int kNarrowCh = 1024;                       // B rows staged at a time
+constexpr int kNarrowGr = 8;                          // rows per group (8 rows x 8 columns = 64 lanes)
+constexpr int kNarrowStage = kNarrowCh + 4 * kNarrowGr; // staged rows: phase A reads up to 4 groups past the chunk
+constexpr size_t kNarrowWs = 34816;
+static_assert(kNarrowWs >= (size_t)kNarrowStage * kNarrow * 4, "B rows overlap the FP64 W");
+static_assert(kNarrowWs + (1024 + 4) * kNarrow * 8 <= 131072, "narrow phases exceed the LDS of the wide ones");
+
+__device__ __forceinline__ void narrow_range(int64_t mk, int nrw, int g, int64_t& rb, int64_t& re)
+{
+    const int64_t rpw = (mk + nrw - 1) / nrw;
+    rb = (int64_t)g * rpw;
+    if (rb > mk) rb = mk;
+    re = rb + rpw < mk ? rb + rpw : mk;
+}
+
+// Reduce-scatter over the 64 lanes of a wavefront: N values a lane (N a power
+// of two, 2..64) are summed over the lanes, value i ending in lane i (64 / N)
+// .. lane (i + 1)(64 / N) - 1; halving steps with lane offsets 32, 16, ...,
+// then a butterfly over the offsets left, so that every such lane holds the
+// whole sum.  Fixed order: the result does not depend on timing.
+template <typename T, int N, int n>
+__device__ __forceinline__ void wave_rs_step(T (&v)[N], int lane)
+{
+    if constexpr (n > 1) {
+        constexpr int o = 32 * n / N, h = n / 2;
+        const bool up = (lane & o) != 0;
+#pragma unroll
+        for (int k = 0; k < h; ++k) {
+            const T send = up ? v[k] : v[k + h];
+            const T keep = up ? v[k + h] : v[k];
+            v[k] = keep + __shfl_xor(send, o);
+        }
+        wave_rs_step<T, N, h>(v, lane);
+    }
+}
+
+template <typename T, int o>
+__device__ __forceinline__ T wave_bfly(T x)
+{
+    if constexpr (o >= 1) return wave_bfly<T, o / 2>(x + __shfl_xor(x, o));
+    else return x;
+}
+
+template <typename T, int N>
+__device__ __forceinline__ T wave_reduce_scatter(T (&v)[N], int lane)
+{
+    static_assert(N >= 2 && N <= 64 && (N & (N - 1)) == 0, "N: a power of two up to 64");
+    wave_rs_step<T, N, N>(v, lane);
+    return wave_bfly<T, 32 / N>(v[0]);
+}
+
+// Stage B[k0 + r, j] for rows c0 .. c0 + kNarrowStage - 1 (zero past c1 and
+// for j >= kc) into Bs, row-major; all loads issued before the first store.
+__device__ __forceinline__ void narrow_stage_b(const FusedArgs& a, float* Bs, const float* Bc, int kc, int64_t k0,
+                                               int64_t c0, int64_t c1)
+{
+    constexpr int NI = (kNarrowStage + 255) / 256;
+    float bv[NI][kNarrow];
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int64_t r = c0 + threadIdx.x + 256 * k;
+#pragma unroll
+        for (int j = 0; j < kNarrow; ++j) bv[k][j] = (r < c1 && j < kc) ? Bc[k0 + r + (int64_t)j * a.ldb] : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int i = threadIdx.x + 256 * k;
+        if (i < kNarrowStage) {
+            *(float4*)(Bs + 8 * i) = float4{bv[k][0], bv[k][1], bv[k][2], bv[k][3]};
+            *(float4*)(Bs + 8 * i + 4) = float4{bv[k][4], bv[k][5], bv[k][6], bv[k][7]};
+        }
+    }
+}
+
+// A: P[g][j][c] = sum over the rows r of range g of V[r, c] B[k0 + r, j].
+__device__ __forceinline__ void narrow_phase_a(const FusedArgs& a, char* lds, const float* Bc, int kc, int64_t b,
+                                               int bo, int64_t mk, float* P)
+{
+    const int g = blockIdx.x, t = threadIdx.x;
+    if (g >= a.nrw) return;
+    int64_t rb, re;
+    narrow_range(mk, a.nrw, g, rb, re);
+    const int64_t k0 = b * a.nbo;
+    const int ldv = (bo + 15) / 16 * 16;
+    const float* Vb = (const float*)a.Vt + fused_vt_off(a, b) + 4 * t;
+    const bool cv = 4 * t < ldv;
+    float* Bs = (float*)lds;
+    float acc[kNarrow][4];
+#pragma unroll
+    for (int j = 0; j < kNarrow; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[j][q] = 0.f;
+    constexpr int GR = kNarrowGr;
+    for (int64_t c0 = rb; c0 < re; c0 += kNarrowCh) {
+        const int64_t c1 = c0 + kNarrowCh < re ? c0 + kNarrowCh : re;
+        float4 va[GR], vb[GR];
+        auto ld = [&](float4 (&v)[GR], int64_t r0) {
+#pragma unroll
+            for (int u = 0; u < GR; ++u) {
+                const int64_t r = r0 + u;
+                v[u] = (r < c1 && cv) ? *(const float4*)(Vb + r * ldv) : float4{0.f, 0.f, 0.f, 0.f};
+            }
+        };
+        auto mac = [&](const float4 (&v)[GR], int64_t r0) {
+            const float* br = Bs + 8 * (r0 - c0);
+#pragma unroll
+            for (int u = 0; u < GR; ++u) {
+                const float4 b0 = *(const float4*)(br + 8 * u), b1 = *(const float4*)(br + 8 * u + 4);
+                const float bj[kNarrow] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+#pragma unroll
+                for (int j = 0; j < kNarrow; ++j) {
+                    acc[j][0] += v[u].x * bj[j];
+                    acc[j][1] += v[u].y * bj[j];
+                    acc[j][2] += v[u].z * bj[j];
+                    acc[j][3] += v[u].w * bj[j];
+                }
+            }
+        };
+        lds_barrier();                      // the previous chunk's reads of Bs are done
+        narrow_stage_b(a, Bs, Bc, kc, k0, c0, c1);
+        ld(va, c0);
+        ld(vb, c0 + GR);
+        lds_barrier();
+        for (int64_t r0 = c0; r0 < c1; r0 += 2 * GR) {
+            mac(va, r0);
+            ld(va, r0 + 2 * GR);
+            mac(vb, r0 + GR);
+            ld(vb, r0 + 3 * GR);
+        }
+    }
+    if (4 * t < a.nbo)
+#pragma unroll
+        for (int j = 0; j < kNarrow; ++j)
+            *(float4*)(P + ((size_t)g * kNarrow + j) * a.nbo + 4 * t) = float4{acc[j][0], acc[j][1], acc[j][2], acc[j][3]};
+}
+
+// B1: W[c][j] = sum of the nrw partials (fixed order, FP64); workgroup g
+// takes the column quads g, g + G, ..., thread p loads partial p.
+__device__ __forceinline__ void narrow_phase_b1(const FusedArgs& a, char* lds, int bo, const float* P, double* W)
+{
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    double* red = (double*)(lds + kNarrowWs);          // 4 waves x 32
+    const int nq = (bo + 3) / 4;
+    for (int cq = blockIdx.x; cq < nq; cq += gridDim.x) {
+        double v[4 * kNarrow];
+#pragma unroll
+        for (int e = 0; e < 4 * kNarrow; ++e) v[e] = 0.0;
+        for (int p = t; p < a.nrw; p += 256) {
+            float4 x[kNarrow];
+#pragma unroll
+            for (int j = 0; j < kNarrow; ++j) x[j] = *(const float4*)(P + ((size_t)p * kNarrow + j) * a.nbo + 4 * cq);
+#pragma unroll
+            for (int j = 0; j < kNarrow; ++j) {
+                v[4 * j] += (double)x[j].x;
+                v[4 * j + 1] += (double)x[j].y;
+                v[4 * j + 2] += (double)x[j].z;
+                v[4 * j + 3] += (double)x[j].w;
+            }
+        }
+        const double s = wave_reduce_scatter<double, 4 * kNarrow>(v, lane);
+        if ((lane & 1) == 0) red[wv * 32 + (lane >> 1)] = s;
+        __syncthreads();
+        if (t < 32) {
+            const int c = 4 * cq + (t & 3), j = t >> 2;
+            if (c < bo) W[(size_t)c * kNarrow + j] = ((red[t] + red[32 + t]) + red[64 + t]) + red[96 + t];
+        }
+        __syncthreads();
+    }
+}
+
+// B2: W'[c][j] = sum_{l <= c} T[l, c] W[l][j]; W in LDS, workgroup g takes
+// columns g, g + G, ..., four at a time with all their loads of T issued
+// together (thread t: rows t, t + 256, t + 512, t + 768).
+__device__ __forceinline__ void narrow_phase_b2(const FusedArgs& a, char* lds, int64_t b, int bo, const double* W,
+                                                float* Wt)
+{
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6, G = gridDim.x;
+    if ((int)blockIdx.x >= bo) return;
+    double* Ws = (double*)(lds + kNarrowWs);            // bo x 8
+    double* red = Ws + 1024 * kNarrow;                  // 4 waves x 8
+    for (int e = t; e < bo * kNarrow / 2; e += 256) ((double2*)Ws)[e] = ((const double2*)W)[e];
+    __syncthreads();
+    const double* Tb = a.T + (size_t)b * a.nbo * a.nbo;
+    for (int c0 = blockIdx.x; c0 < bo; c0 += 4 * G) {
+        double tv[4][4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int c = c0 + k * G;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int l = t + 256 * i;
+                tv[k][i] = (c < bo && l <= c) ? Tb[(size_t)c * a.nbo + l] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int c = c0 + k * G;
+            if (c >= bo) break;
+            double sj[kNarrow];
+#pragma unroll
+            for (int j = 0; j < kNarrow; ++j) sj[j] = 0.0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int l = t + 256 * i;
+                if (l <= c) {
+                    const double2* w = (const double2*)(Ws + (size_t)l * kNarrow);
+#pragma unroll
+                    for (int j = 0; j < kNarrow / 2; ++j) {
+                        const double2 x = w[j];
+                        sj[2 * j] += tv[k][i] * x.x;
+                        sj[2 * j + 1] += tv[k][i] * x.y;
+                    }
+                }
+            }
+            const double s = wave_reduce_scatter<double, kNarrow>(sj, lane);
+            if ((lane & 7) == 0) red[wv * kNarrow + (lane >> 3)] = s;
+            __syncthreads();
+            if (t < kNarrow)
+                Wt[(size_t)c * kNarrow + t] = (float)(((red[t] + red[kNarrow + t]) + red[2 * kNarrow + t]) + red[3 * kNarrow + t]);
+            __syncthreads();
+        }
+    }
+}
+
+// C: B[k0 + r, j] -= sum_c V[r, c] W'[c][j] over the rows of range g, last row
+// group first; thread t holds W' of its four columns, each group of 8 rows is
+// reduce-scattered over the wavefront (lane 8u + j: row u, column j) and the
+// four wavefronts' sums added by wavefront 0 (double-buffered, one barrier a
+// group).  The B values come from the LDS copy phase A staged when the range
+// is one chunk.
+__device__ __forceinline__ void narrow_phase_c(const FusedArgs& a, char* lds, float* Bc, int kc, int64_t b, int bo,
+                                               int64_t mk, const float* Wt)
+{
+    const int g = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    if (g >= a.nrw) return;
+    int64_t rb, re;
+    narrow_range(mk, a.nrw, g, rb, re);
+    if (rb >= re) return;
+    const int64_t k0 = b * a.nbo;
+    const int ldv = (bo + 15) / 16 * 16;
+    const float* Vb = (const float*)a.Vt + fused_vt_off(a, b) + 4 * t;
+    const bool cv = 4 * t < ldv;
+    const int nvc = bo - 4 * t;                         // valid columns of this thread (<= 0: none)
+    float w[4][kNarrow];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int c = 4 * t + q;
+        if (c < bo) {
+            const float4 x0 = *(const float4*)(Wt + (size_t)c * kNarrow), x1 = *(const float4*)(Wt + (size_t)c * kNarrow + 4);
+            w[q][0] = x0.x; w[q][1] = x0.y; w[q][2] = x0.z; w[q][3] = x0.w;
+            w[q][4] = x1.x; w[q][5] = x1.y; w[q][6] = x1.z; w[q][7] = x1.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < kNarrow; ++j) w[q][j] = 0.f;
+        }
+    }
+    float* Bs = (float*)lds;
+    float* red = (float*)(lds + kNarrowWs);             // 2 x 4 waves x 64
+    constexpr int GR = kNarrowGr;
+    const int64_t nch = (re - rb + kNarrowCh - 1) / kNarrowCh;
+    for (int64_t ch = nch - 1; ch >= 0; --ch) {
+        const int64_t c0 = rb + ch * kNarrowCh;
+        const int64_t c1 = c0 + kNarrowCh < re ? c0 + kNarrowCh : re;
+        const int ng = (int)((c1 - c0 + GR - 1) / GR);
+        // group i: rows c1 - GR (i + 1) .. c1 - GR i - 1, those below c0 masked
+        float4 va[GR], vb[GR];
+        auto ld = [&](float4 (&v)[GR], int i) {
+#pragma unroll
+            for (int u = 0; u < GR; ++u) {
+                const int64_t r = c1 - (int64_t)GR * (i + 1) + u;
+                float4 x = (i < ng && r >= c0 && cv) ? *(const float4*)(Vb + r * ldv) : float4{0.f, 0.f, 0.f, 0.f};
+                if (nvc < 4) {
+                    x.y = nvc > 1 ? x.y : 0.f;
+                    x.z = nvc > 2 ? x.z : 0.f;
+                    x.w = 0.f;
+                    x.x = nvc > 0 ? x.x : 0.f;
+                }
+                v[u] = x;
+            }
+        };
+        auto grp = [&](const float4 (&v)[GR], int i) {
+            float pv[GR * kNarrow];
+#pragma unroll
+            for (int u = 0; u < GR; ++u)
+#pragma unroll
+                for (int j = 0; j < kNarrow; ++j)
+                    pv[u * kNarrow + j] = v[u].x * w[0][j] + v[u].y * w[1][j] + v[u].z * w[2][j] + v[u].w * w[3][j];
+            const float sv = wave_reduce_scatter<float, GR * kNarrow>(pv, lane);
+            float* rd = red + (i & 1) * 256;
+            rd[wv * 64 + lane] = sv;
+            lds_barrier();
+            if (t < 64) {
+                const float sum = ((rd[t] + rd[64 + t]) + rd[128 + t]) + rd[192 + t];
+                const int u = t >> 3, j = t & 7;
+                const int64_t r = c1 - (int64_t)GR * (i + 1) + u;
+                if (r >= c0 && j < kc) Bc[k0 + r + (int64_t)j * a.ldb] = Bs[8 * (r - c0) + j] - sum;
+            }
+        };
+        if (nch > 1) {
+            lds_barrier();
+            narrow_stage_b(a, Bs, Bc, kc, k0, c0, c1);
+        }
+        ld(va, 0);
+        ld(vb, 1);
+        lds_barrier();
+        for (int i = 0; i < ng; i += 2) {
+            grp(va, i);
+            ld(va, i + 2);
+            if (i + 1 < ng) {
+                grp(vb, i + 1);
+                ld(vb, i + 3);
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------ back-substitution
 // Columns of R (or of a stored inverse) are taken RW at a time, all RW loads
 // of a thread issued together; the critical path (the owner of the next
@@ -434,7 +746,8 @@ __device__ __forceinline__ void fused_solve_block(const FusedArgs& a, TS* ys, TS
 #pragma unroll
         for (int j = 0; j < KC; ++j)
             if (j < kc) Bc[256 * q + t + (int64_t)j * a.ldb] = acc[j];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // the workgroup barrier waits for every wavefront's stores; thread 0's
+    // release writes them back before the flag (as in fused_sync)
     __syncthreads();
     if (t == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -486,6 +799,17 @@ __device__ __forceinline__ bool fused_chunk(const FusedArgs& a, char* lds, int* 
         const int64_t rmax = (mk + 63) / 64;
         if (nrg > rmax) nrg = (int)rmax;
         if (nrg < 1) nrg = 1;
+        if constexpr (sizeof(TS) == 4 && KC == kNarrow) {
+            narrow_phase_a(a, lds, Bc, kc, b, bo, mk, P);
+            if (!fused_sync(bar, gen, G, a.err, a.wait_ticks, sflag)) return false;
+            narrow_phase_b1(a, lds, bo, P, W);
+            if (!fused_sync(bar, gen, G, a.err, a.wait_ticks, sflag)) return false;
+            narrow_phase_b2(a, lds, b, bo, W, Wt);
+            if (!fused_sync(bar, gen, G, a.err, a.wait_ticks, sflag)) return false;
+            narrow_phase_c(a, lds, Bc, kc, b, bo, mk, Wt);
+            if (!fused_sync(bar, gen, G, a.err, a.wait_ticks, sflag)) return false;
+            continue;
+        }
         fused_phase_a<TS, KC>(a, lds, Bc, kc, b, bo, mk, nrg, ncg, P);
         if (!fused_sync(bar, gen, G, a.err, a.wait_ticks, sflag)) return false;
         fused_phase_b1<TS, KC>(a, bo, nrg, P, W);
@@ -532,10 +856,13 @@ __device__ __forceinline__ bool fused_chunk(const FusedArgs& a, char* lds, int* 
         }
         if (!have) {
             // x_b published by its owner
-            if (t == 0) *sflag = fused_wait(flags + bb, stamp, false, a.err, a.wait_ticks) ? 1 : 0;
+            if (t == 0) {
+                const bool ok = fused_wait(flags + bb, stamp, false, a.err, a.wait_ticks);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                *sflag = ok ? 1 : 0;
+            }
             __syncthreads();
             if (!*sflag) return false;
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             const TS* src = Xp + (size_t)bb * 256 * KC;
             TS* dst = ys + (1 + cur) * 256 * KC;
             for (int e = 4 * t; e < 256 * KC; e += 1024) *(typename Vec4<TS>::t*)(dst + e) = ld4<TS>(src + e);
@@ -605,7 +932,7 @@ __global__ void fused_reset_kernel(uint32_t* bar, uint32_t* flags, int64_t nbq)
 
 template <typename TS>
 static constexpr int fused_kc() { return sizeof(TS) == 4 ? 32 : 16; }
-constexpr int kFusedSmall = 8;
+constexpr int kFusedSmall = kNarrow;
 
 template <typename TS>
 static size_t fused_lds_bytes()
@@ -618,16 +945,17 @@ static size_t fused_lds_bytes()
     return m > s ? m : s;
 }
 
-// Scratch bytes with nrg row groups; the largest nrg that fits `bytes`.
-int fused_row_groups(int nbo, int64_t n, size_t es, size_t bytes)
+// Row groups of the W partials (chunks of kc columns) that fit `bytes` of
+// scratch after the fixed part of the layout, at most cap; 0: none fits.
+int fused_row_groups(int nbo, int64_t n, size_t es, size_t bytes, int kc, int cap)
 {
     const int KC = es == 4 ? 32 : 16;
     const int64_t nbq = (n + 255) / 256;
     const FusedLayout L0 = fused_layout(nbo, nbq, 0, KC, es);
     if (bytes <= L0.total) return 0;
-    const size_t per = (size_t)KC * nbo * es;
+    const size_t per = (size_t)kc * nbo * es;
     const size_t r = (bytes - L0.total) / per;
-    return r > 32 ? 32 : (int)r;
+    return r > (size_t)cap ? cap : (int)r;
 }
 
 template <typename TS>
