@@ -252,6 +252,10 @@ struct ct_factor {
     void* Tf = nullptr;
     // bfloat16 high / low parts of the current reflector block (BF16x3 updates)
     void* S3 = nullptr;
+    // FP32 factors: blockdiag(R_qq^{-1}) R right of the 256 x 256 diagonal
+    // blocks (fused_rh_off), built by the first fused solve and owned by the
+    // factor (library allocation)
+    mutable void* Rh = nullptr;
 };
 
 // Outer block width.  The trailing update of a block of nbo reflectors reads
@@ -2313,7 +2317,10 @@ int ct_status(const ct_factor* f, int64_t* info, void* stream)
 
 int ct_factor_destroy(ct_factor* f)
 {
-    if (f) delete f->st;
+    if (f) {
+        delete f->st;
+        if (f->Rh) (void)hipFree(f->Rh);
+    }
     delete f;
     return 0;
 }
@@ -2322,6 +2329,36 @@ int ct_factor_destroy(ct_factor* f)
 // One persistent launch for B <- R^{-1} Q^T B (fused.hip): needs an in-memory
 // factor with its solve-side copies (row-major reflector blocks, inverses of
 // R's 256 x 256 diagonal blocks); its scratch is the factor's update buffer.
+// The fused solve's Rh for an FP32 factor: blockdiag(R_qq^{-1}) R right of
+// the diagonal blocks, one product of R_qq^{-1} (row-major copy) with R's block
+// row q read in place (K = 256) per block row.  Built once, by the first fused
+// solve or graph; if the allocation fails the solves go without it (the
+// back-substitution then multiplies by each inverse on the chain).
+static int fused_prepare(const ct_factor* f, hipStream_t s)
+{
+    const int64_t n = f->n, nbq = (n + 255) / 256;
+    if (f->f64 || f->Rh || f->st || !f->RiR || nbq < 2) return 0;
+    void* p = nullptr;
+    if (hipMalloc(&p, fused_rh_off(nbq - 1, n) * sizeof(float)) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    for (int64_t q = 0; q + 1 < nbq; ++q) {
+        int nz;
+        hipError_t e = launch_nt<float>((const float*)f->RiR + (size_t)q * 256 * 256, 256,
+                                        (const float*)f->A + 256 * q + 256 * (q + 1) * f->lda, f->lda,
+                                        (float*)p + fused_rh_off(q, n), 256, 256, (int)(n - 256 * (q + 1)), 256, false,
+                                        0, &nz, s);
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(p);
+            return fail(-1000 - (int)e, "fused solve, R_qq^{-1} R: %s", hipGetErrorString(e));
+        }
+    }
+    f->Rh = p;
+    return 0;
+}
+
 static int fused_solve(const ct_factor* f, void* B, int64_t ldb, int64_t nrhs, const int32_t* rec, bool coop,
                        hipStream_t s)
 {
@@ -2338,7 +2375,11 @@ static int fused_solve(const ct_factor* f, void* B, int64_t ldb, int64_t nrhs, c
     const int nrw = fused_row_groups(f->nb_out, f->n, es, (size_t)f->wp_elems * 8, 8, G);
     if (nrg < 1 || nrw < 1) return fail(-2007, "%s", "the factor's update buffer is too small for the fused solve");
     FusedArgs a;
-    a.A = f->A; a.lda = f->lda; a.Vt = f->VtAll; a.T = f->T_all; a.RiC = f->RiC;
+    if (!rec) {
+        r = fused_prepare(f, s);
+        if (r) return r;
+    }
+    a.A = f->A; a.lda = f->lda; a.Vt = f->VtAll; a.T = f->T_all; a.RiC = f->RiC; a.Rh = f->Rh;
     a.m = f->m; a.n = f->n; a.nbo = f->nb_out; a.nblocks = (int)f->nblocks;
     a.B = B; a.ldb = ldb; a.nrhs = (int)nrhs; a.rec = rec;
     a.scratch = (char*)f->Wp; a.nrg_cap = nrg; a.nrw = nrw; a.err = f->err; a.wait_ticks = panel_wait_limit();
@@ -2397,6 +2438,11 @@ static int graph_create(const ct_factor* f, void* B, int64_t ldb, int64_t b_cols
     CT_ARG(out != nullptr, 8, "g");
     CT_ARG(f->st == nullptr, 1, "f (graph-captured solves need a factor held in device memory)");
     hipStream_t s = (hipStream_t)stream;
+    if (fused) {
+        // built outside the capture: the graph only reads it
+        int r = fused_prepare(f, s);
+        if (r) return r;
+    }
     ct_solve_graph* g = new (std::nothrow) ct_solve_graph();
     if (!g) return fail(-1001, "%s", "out of host memory");
     CT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));

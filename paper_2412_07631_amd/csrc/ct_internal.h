@@ -108,6 +108,7 @@ struct FusedArgs {
     const void* Vt;       // row-major reflector blocks: block b at vt_off(b), ld round16(width)
     const double* T;      // T of block b at b nbo^2, column-major, upper triangular
     const void* RiC;      // inverses of the 256 x 256 diagonal blocks of R, column-major, block q at q 256^2
+    const void* Rh;       // FP32 factors: blockdiag(R_qq^{-1}) R right of the diagonal blocks (fused_rh_off), or null
     int64_t m, n;
     int nbo, nblocks;
     void* B;
@@ -120,5 +121,14 @@ struct FusedArgs {
     int32_t* err;
     uint64_t wait_ticks;
 };
+
+// Element offset of block row q in the fused solve's Rh (block row q: the
+// 256 x (n - 256(q+1)) part of blockdiag(R_qq^{-1}) R right of the diagonal
+// block, column-major with leading dimension 256); fused_rh_off(nbq - 1, n) is
+// the whole size.
+__host__ __device__ inline size_t fused_rh_off(int64_t q, int64_t n)
+{
+    return (size_t)256 * (size_t)(q * n - 256 * (q * (q + 1) / 2));
+}
 
 }  // namespace ctqr

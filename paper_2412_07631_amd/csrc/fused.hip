@@ -39,7 +39,7 @@ __host__ __device__ inline FusedLayout fused_layout(int nbo, int64_t nbq, int nr
 {
     FusedLayout L;
     L.flags = 256;
-    L.W = L.flags + fused_up256((size_t)nbq * 4);
+    L.W = L.flags + fused_up256((size_t)nbq * 16);   // four flags a block (one a quarter)
     L.Wt = L.W + fused_up256((size_t)KC * nbo * 8);
     L.Xp = L.Wt + fused_up256((size_t)nbo * KC * es);
     L.P = L.Xp + fused_up256((size_t)nbq * 256 * KC * es);
@@ -776,6 +776,167 @@ __device__ __forceinline__ const TS* r_block(const FusedArgs& a, int64_t q, int6
     return (const TS*)a.A + (256 * q + threadIdx.x) + 256 * b * a.lda;
 }
 
+// ------------------------------------ back-substitution, narrow FP32 chunks
+// With Rh = blockdiag(R_qq^{-1}) R (right of the diagonal blocks),
+//   x_q = R_qq^{-1} c_q - sum_{b > q} Rh[q, b] x_b,
+// so the chain of dependent blocks has no inverse product on it.  Each
+// 256-row block is split in four quarters of 64 rows; quarter Q = 4q + s
+// belongs to workgroup Q mod G (its k-th: Q = g + k G), and wavefront w holds
+// the partial sums over columns 64w .. 64w + 63 of every product, lane i row
+// i of the quarter.  Step bb, once the four quarters of x_bb are published:
+// the owner of a quarter of block bb - 1 applies x_bb with the slice it loaded
+// before waiting, adds its four wavefronts' sums and publishes those 64 rows
+// of x_{bb-1} (flag per quarter); then every workgroup applies x_bb to its
+// other quarters, the highest block first (the next on the chain).
+constexpr int kNarrowMaxQ = 8;     // quarters a workgroup (blocks <= 2 G)
+
+// Columns 64w .. 64w + 63 of block b in rows 64 s + lane of block q of Rh
+// (zero past the last column).
+__device__ __forceinline__ void narrow_slice(const FusedArgs& a, int64_t q, int s, int64_t b, float (&S)[64])
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int bo = (int)(a.n - 256 * b < 256 ? a.n - 256 * b : 256);
+    const float* base = (const float*)a.Rh + fused_rh_off(q, a.n) + (size_t)(256 * (b - q - 1) + 64 * w) * 256 + 64 * s + lane;
+#pragma unroll
+    for (int u = 0; u < 64; ++u) S[u] = 64 * w + u < bo ? base[(size_t)u * 256] : 0.f;
+}
+
+// p (+|-)= sum_u S[u] x[64 w + u][:]; x in LDS, 8 floats a row (a broadcast read)
+template <bool SUB>
+__device__ __forceinline__ void narrow_fma(float (&p)[kNarrow], const float (&S)[64], const float* xs)
+{
+    const float* xr = xs + 64 * (threadIdx.x >> 6) * kNarrow;
+#pragma unroll
+    for (int u = 0; u < 64; ++u) {
+        const float4 x0 = *(const float4*)(xr + u * 8), x1 = *(const float4*)(xr + u * 8 + 4);
+        const float xv[kNarrow] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+#pragma unroll
+        for (int j = 0; j < kNarrow; ++j) {
+            if (SUB)
+                p[j] -= S[u] * xv[j];
+            else
+                p[j] += S[u] * xv[j];
+        }
+    }
+}
+
+// Sum the four wavefronts' partials of quarter (q, s), store its rows of x
+// (zero past the last row) in the published copy and in B, then the flag.
+__device__ __forceinline__ void narrow_publish(const FusedArgs& a, float* red, const float (&p)[kNarrow], int64_t q, int s,
+                                               float* Bc, int kc, float* Xp, uint32_t* flags, uint32_t stamp)
+{
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    float* r = red + (w * 64 + lane) * kNarrow;
+    *(float4*)r = float4{p[0], p[1], p[2], p[3]};
+    *(float4*)(r + 4) = float4{p[4], p[5], p[6], p[7]};
+    __syncthreads();
+    const int i = t >> 2, jj = (t & 3) * 2;
+    const int bo = (int)(a.n - 256 * q < 256 ? a.n - 256 * q : 256);
+    const bool valid = 64 * s + i < bo;
+    float x0 = 0.f, x1 = 0.f;
+    if (valid) {
+        x0 = ((red[i * 8 + jj] + red[(64 + i) * 8 + jj]) + red[(128 + i) * 8 + jj]) + red[(192 + i) * 8 + jj];
+        x1 = ((red[i * 8 + jj + 1] + red[(64 + i) * 8 + jj + 1]) + red[(128 + i) * 8 + jj + 1]) + red[(192 + i) * 8 + jj + 1];
+    }
+    const int64_t row = 256 * q + 64 * s + i;
+    *(float2*)(Xp + (size_t)row * kNarrow + jj) = float2{x0, x1};
+    if (valid) {
+        if (jj < kc) Bc[row + (int64_t)jj * a.ldb] = x0;
+        if (jj + 1 < kc) Bc[row + (int64_t)(jj + 1) * a.ldb] = x1;
+    }
+    __syncthreads();
+    if (t == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(flags + 4 * q + s, stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__device__ __forceinline__ bool narrow_backsub(const FusedArgs& a, char* lds, int* sflag, float* Bc, int kc,
+                                               uint32_t* flags, float* Xp, uint32_t stamp)
+{
+    const int G = gridDim.x, g = blockIdx.x, t = threadIdx.x, w = t >> 6;
+    const int64_t nbq = (a.n + 255) / 256;
+    float* xs = (float*)lds;                      // 256 x 8
+    float* red = xs + 256 * kNarrow;              // 4 wavefronts x 64 rows x 8
+    float p[kNarrowMaxQ][kNarrow];
+    // p = wavefront w's part of R_qq^{-1} c_q for every quarter owned
+#pragma unroll
+    for (int k = 0; k < kNarrowMaxQ; ++k) {
+#pragma unroll
+        for (int j = 0; j < kNarrow; ++j) p[k][j] = 0.f;
+        const int64_t Qd = g + (int64_t)G * k;
+        if (Qd < 4 * nbq) {
+            const int64_t q = Qd >> 2;
+            const int s = (int)(Qd & 3);
+            const int bo = (int)(a.n - 256 * q < 256 ? a.n - 256 * q : 256);
+            float S[64];
+            const float* Ri = (const float*)a.RiC + (size_t)q * 65536 + (size_t)(64 * w) * 256 + 64 * s + (t & 63);
+#pragma unroll
+            for (int u = 0; u < 64; ++u) S[u] = 64 * w + u < bo ? Ri[(size_t)u * 256] : 0.f;
+            __syncthreads();                      // earlier readers of xs are done
+            {
+                float bv[kNarrow];
+#pragma unroll
+                for (int j = 0; j < kNarrow; ++j) bv[j] = (t < bo && j < kc) ? Bc[256 * q + t + (int64_t)j * a.ldb] : 0.f;
+                *(float4*)(xs + t * 8) = float4{bv[0], bv[1], bv[2], bv[3]};
+                *(float4*)(xs + t * 8 + 4) = float4{bv[4], bv[5], bv[6], bv[7]};
+            }
+            __syncthreads();
+            narrow_fma<false>(p[k], S, xs);
+        }
+    }
+    const int64_t last = nbq - 1;
+#pragma unroll
+    for (int k = 0; k < kNarrowMaxQ; ++k) {
+        const int64_t Qd = g + (int64_t)G * k;
+        if (Qd < 4 * nbq && (Qd >> 2) == last) narrow_publish(a, red, p[k], last, (int)(Qd & 3), Bc, kc, Xp, flags, stamp);
+    }
+    for (int64_t bb = last; bb >= 1; --bb) {
+        const int64_t an = bb - 1;
+        int kan = -1, san = 0;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            if ((4 * an + s) % G == g) {
+                kan = (int)((4 * an + s) / G);
+                san = s;
+            }
+        float S[64];
+        if (kan >= 0) narrow_slice(a, an, san, bb, S);     // the critical path's slice, before the wait
+        if (t == 0) {
+            bool ok = true;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) ok = ok && fused_wait(flags + 4 * bb + s, stamp, false, a.err, a.wait_ticks);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            *sflag = ok ? 1 : 0;
+        }
+        __syncthreads();
+        if (!*sflag) return false;
+        {
+            const float4* src = (const float4*)(Xp + (size_t)bb * 256 * kNarrow);
+            ((float4*)xs)[t] = src[t];
+            ((float4*)xs)[t + 256] = src[t + 256];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kNarrowMaxQ; ++k)
+            if (k == kan) {
+                narrow_fma<true>(p[k], S, xs);
+                narrow_publish(a, red, p[k], an, san, Bc, kc, Xp, flags, stamp);
+            }
+#pragma unroll
+        for (int k = kNarrowMaxQ - 1; k >= 0; --k) {
+            const int64_t Qd = g + (int64_t)G * k;
+            const int64_t q = Qd >> 2;
+            if (Qd < 4 * nbq && q < an) {
+                float S2[64];
+                narrow_slice(a, q, (int)(Qd & 3), bb, S2);
+                narrow_fma<true>(p[k], S2, xs);
+            }
+        }
+    }
+    return true;
+}
+
 // One chunk of at most KC columns: Q^T then R^{-1}.  False: a wait gave up.
 template <typename TS, int KC>
 __device__ __forceinline__ bool fused_chunk(const FusedArgs& a, char* lds, int* sflag, uint32_t* bar, uint32_t& gen, TS* Bc, int kc,
@@ -820,6 +981,8 @@ __device__ __forceinline__ bool fused_chunk(const FusedArgs& a, char* lds, int* 
         if (!fused_sync(bar, gen, G, a.err, a.wait_ticks, sflag)) return false;
     }
     // ---- R^{-1}
+    if constexpr (sizeof(TS) == 4 && KC == kNarrow)
+        if (a.Rh) return narrow_backsub(a, lds, sflag, Bc, kc, flags, Xp, stamp);
     constexpr int RW = Rw<TS, KC>::v;
     TS* ys = (TS*)lds;                  // then two x buffers of 256 x KC
     TS y[kFusedMaxOwn][KC];
@@ -927,7 +1090,7 @@ __global__ void fused_reset_kernel(uint32_t* bar, uint32_t* flags, int64_t nbq)
 {
     const int t = threadIdx.x;
     if (t == 0) bar[0] = 0u;
-    for (int64_t q = t; q < nbq; q += 256) flags[q] = 0u;
+    for (int64_t q = t; q < 4 * nbq; q += 256) flags[q] = 0u;
 }
 
 template <typename TS>

@@ -179,3 +179,36 @@ def test_fused_wait_limit_fails_fast_and_recovers(ct):
     ct.solve_fused(f, Bd)
     assert ct.status(f) == 0
     assert max_col_rel(from_dev(Bd, sc.n), Xs) <= 1e-4
+
+
+def test_fused_solve_many_quarters_per_workgroup(ct):
+    """144 x 144 pixels (n = 20736, 81 row blocks of R, 324 quarters of 64
+    rows): more quarters than workgroups, so some workgroups own two in the
+    back-substitution of 1..8 columns.  No oracle at this size: the fused solve
+    is checked against the multi-kernel solve of the same FP32 factor (itself
+    checked against the oracle above), 1e-4 per column, and against A x = b
+    through the normal equations of a consistent right-hand side."""
+    sc = synth.scanner(144, 100, 300)
+    m, n = sc.m, sc.n
+    Ad = torch.empty((n, ld16(m)), dtype=torch.float32, device="cuda")
+    ct.build_system(sc, Ad)
+    A64 = Ad[:, :m].double()
+    f = ct.qr_factor(Ad, m, n, ct.PREC_F32, max_nrhs=8)
+    assert ct.status(f) == 0
+    g = torch.Generator(device="cpu").manual_seed(7)
+    Xt = torch.rand((8, n), generator=g, dtype=torch.float64).to("cuda")
+    Bt = Xt @ A64                                    # rows: A x for 8 images
+    for k in (1, 8):
+        Bf = torch.zeros((k, ld16(m)), dtype=torch.float32, device="cuda")
+        Bf[:, :m] = Bt[:k].float()
+        Bm = Bf.clone()
+        ct.solve_fused(f, Bf)
+        ct.apply_qt(f, Bm)
+        ct.trsm_solve(f, Bm)
+        assert ct.status(f) == 0
+        Xf, Xm = Bf[:, :n].double(), Bm[:, :n].double()
+        diff = ((Xf - Xm).norm(dim=1) / Xm.norm(dim=1)).max().item()
+        err = ((Xf - Xt[:k]).norm(dim=1) / Xt[:k].norm(dim=1)).max().item()
+        print("n", n, "columns", k, "fused vs multi-kernel %.3g, vs the exact images %.3g" % (diff, err))
+        assert diff <= 1e-4
+        assert err <= 1e-2
