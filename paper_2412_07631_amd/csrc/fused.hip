@@ -429,7 +429,9 @@ __device__ __forceinline__ void narrow_stage_b(const FusedArgs& a, float* Bs, co
     }
 }
 
-// A: P[g][j][c] = sum over the rows r of range g of V[r, c] B[k0 + r, j].
+// A: P[c / 4][g][j][c % 4] = sum over the rows r of range g of V[r, c] B[k0 + r, j]
+// (thread t writes the 128 contiguous bytes of its column quad; phase B1 then
+// reads one contiguous stretch per quad).
 __device__ __forceinline__ void narrow_phase_a(const FusedArgs& a, char* lds, const float* Bc, int kc, int64_t b,
                                                int bo, int64_t mk, float* P)
 {
@@ -488,11 +490,12 @@ __device__ __forceinline__ void narrow_phase_a(const FusedArgs& a, char* lds, co
     if (4 * t < a.nbo)
 #pragma unroll
         for (int j = 0; j < kNarrow; ++j)
-            *(float4*)(P + ((size_t)g * kNarrow + j) * a.nbo + 4 * t) = float4{acc[j][0], acc[j][1], acc[j][2], acc[j][3]};
+            *(float4*)(P + (((size_t)t * a.nrw + g) * kNarrow + j) * 4) = float4{acc[j][0], acc[j][1], acc[j][2], acc[j][3]};
 }
 
 // B1: W[c][j] = sum of the nrw partials (fixed order, FP64); workgroup g
-// takes the column quads g, g + G, ..., thread p loads partial p.
+// takes the column quads g, g + G, ..., thread p loads partial p (128
+// contiguous bytes: the workgroup reads its quad's partials in one stretch).
 __device__ __forceinline__ void narrow_phase_b1(const FusedArgs& a, char* lds, int bo, const float* P, double* W)
 {
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -505,7 +508,7 @@ __device__ __forceinline__ void narrow_phase_b1(const FusedArgs& a, char* lds, i
         for (int p = t; p < a.nrw; p += 256) {
             float4 x[kNarrow];
 #pragma unroll
-            for (int j = 0; j < kNarrow; ++j) x[j] = *(const float4*)(P + ((size_t)p * kNarrow + j) * a.nbo + 4 * cq);
+            for (int j = 0; j < kNarrow; ++j) x[j] = *(const float4*)(P + (((size_t)cq * a.nrw + p) * kNarrow + j) * 4);
 #pragma unroll
             for (int j = 0; j < kNarrow; ++j) {
                 v[4 * j] += (double)x[j].x;
@@ -787,7 +790,8 @@ __device__ __forceinline__ const TS* r_block(const FusedArgs& a, int64_t q, int6
 // the owner of a quarter of block bb - 1 applies x_bb with the slice it loaded
 // before waiting, adds its four wavefronts' sums and publishes those 64 rows
 // of x_{bb-1} (flag per quarter); then every workgroup applies x_bb to its
-// other quarters, the highest block first (the next on the chain).
+// other quarters, the highest block first (the next on the chain).  (Loading
+// the next block's slice before the wait too made the chain slower.)
 constexpr int kNarrowMaxQ = 8;     // quarters a workgroup (blocks <= 2 G)
 
 // Columns 64w .. 64w + 63 of block b in rows 64 s + lane of block q of Rh
