@@ -137,11 +137,61 @@ def batched_leg(ctqr, synth, torch, f, sc, Bd, dev, total, sp, X64=None):
     # the inner product itself (random directions can cancel)
     scale = gB[:nd].double().norm(dim=1) * D.norm(dim=1)
     fd_err = float(((fd - an).abs() / scale).max().item())
+    small = small_batch_leg(ctqr, torch, f, src, n)
     return {"sinograms": total, "batches": len(sizes), "graph_slices_per_s": total / (g_ms * 1e-3),
             "eager_slices_per_s": total / (eager_ms * 1e-3), "graph_vs_eager_max_rel_diff": agree,
             "graph_vs_fp64": vs64,
             "adjoint_gradients": k, "adjoint_ms": bwd_ms, "forward_same_slices_ms": fwd_ms, "fd_step": h,
-            "fd_err_by_norms": fd_err}
+            "fd_err_by_norms": fd_err, "small_batch": small}
+
+
+def small_batch_leg(ctqr, torch, f, src, n):
+    """Latency of a small batch (1 and 8 slices) on the same factor: the
+    multi-kernel solve (apply_qt + trsm), the one-launch fused solve, and the
+    fused solve captured in a graph over a one-batch descriptor; best of 3,
+    after one untimed call (the factor's first fused solve also builds the
+    blockdiag(R_qq^-1) R copy its back-substitution reads)."""
+    out = {}
+    for k in (1, 8):
+        B0 = src[:k].clone()
+        ws = ctqr.solve_fused(f, B0.clone())
+        desc = ctqr.batch_descriptor([k], device=B0.device)
+        Bg = B0.clone()
+        g = ctqr.SolveGraph(f, Bg, k, desc, fused=True)
+        torch.cuda.synchronize()
+
+        def timed(fn):
+            best = 1e30
+            for _ in range(3):
+                B = B0.clone()
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fn(B)
+                e1.record()
+                torch.cuda.synchronize()
+                best = min(best, e0.elapsed_time(e1))
+            return best, B
+
+        multi_ms, Bm = timed(lambda B: (ctqr.apply_qt(f, B), ctqr.trsm_solve(f, B)))
+        fused_ms, Bf = timed(lambda B: ctqr.solve_fused(f, B))
+        best = 1e30
+        for _ in range(3):
+            Bg.copy_(B0)
+            desc[0] = 0
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(g.stream)
+            g.launch(g.stream)
+            e1.record(g.stream)
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        Xm = Bm[:, :n].double()
+        diff = max(float(((X[:, :n].double() - Xm).norm(dim=1) / Xm.norm(dim=1)).max().item()) for X in (Bf, Bg))
+        out[str(k)] = {"multi_kernel_ms": multi_ms, "fused_ms": fused_ms, "fused_graph_ms": best,
+                       "fused_vs_multi_max_rel_diff": diff}
+        del ws, g
+    return out
 
 
 def code_hash(path):
@@ -471,6 +521,9 @@ def main():
         fb = f32 if f32 is not None else f
         batched = batched_leg(ctqr, synth, torch, fb, sc, Bd, dev, args.batched_total, sp, X64d)
         batched["factor"] = "f32" if f32 is not None else args.prec
+        for k, v in batched["small_batch"].items():
+            log("%s slice(s): multi-kernel solve %.2f ms, fused %.2f ms, fused graph %.2f ms (max rel diff %.1e)" % (
+                k, v["multi_kernel_ms"], v["fused_ms"], v["fused_graph_ms"], v["fused_vs_multi_max_rel_diff"]))
     del f32
 
     # ------------------------------------------------------ roofline (live)
