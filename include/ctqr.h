@@ -377,13 +377,21 @@ int ct_solve_graph_destroy(ct_solve_graph* g);
 
 /* B[0:n] <- R^{-1} Q^T B (Eq. (solve)) in one persistent launch: one
  * workgroup per CU (a cooperative launch, refused rather than run with part
- * of the grid waiting), the batch taken 32 columns at a time (16 for an FP64
- * factor).  Per outer reflector block, W = V^T B is summed over row groups,
- * W' = T^T W, and B -= V W', with a grid-wide barrier between the phases; the
- * back-substitution then runs over R's 256-row blocks, each owned by one
- * workgroup that publishes its x_q to the others through a flag as soon as
- * every later block has been applied to it (Sec. 2.1's ormqr and trsm in one
- * kernel).  Needs an in-memory factor with its solve-side copies (not
+ * of the grid waiting), Sec. 2.1's ormqr and trsm in one kernel.  Per outer
+ * reflector block, W = V^T B is summed over row ranges, W' = T^T W, and
+ * B -= V W', with a grid-wide barrier between the phases; then the
+ * back-substitution over R's 256-row blocks, whose results are published to
+ * the other workgroups through flags as soon as every later block has been
+ * applied.  A batch of at most 8 columns of an FP32-storage factor takes the
+ * latency path: R_qq^{-1} folded into R (Rh = blockdiag(R_qq^{-1}) R), each
+ * block split over four workgroups.  The first fused solve (or fused
+ * graph) of an FP32-storage factor allocates and computes Rh (4 (n^2/2 -
+ * 128 n) bytes for n a multiple of 256, about 8.6 GB at n = 65536; freed by
+ * ct_factor_destroy; if the allocation fails the solves run without it,
+ * slower), so that every later fused solve of the factor, eager or
+ * captured, runs the same arithmetic.  Larger batches go 32 columns at a time (16 for an
+ * FP64 factor), faster through ct_apply_qt + ct_trsm_solve above 8 columns.
+ * Needs an in-memory factor with its solve-side copies (not
  * CT_QR_NO_SOLVE_COPIES, not streamed) and n <= 512 x CUs; otherwise returns
  * -2007.  Uses the factor's update buffer as scratch, so it is ordered with
  * the factor's other solves like them.  A cross-workgroup wait that times out
@@ -395,7 +403,8 @@ int ct_solve_fused(const ct_factor* f, void* B, int64_t nrhs, int64_t ldb, void*
  * ct_solve_fused (plus its reset node): the graph is the batch check, one
  * fused solve of the current batch and the advance of the cursor.  Same
  * arguments, descriptor rules and errors as ct_solve_graph_create, plus
- * ct_solve_fused's requirements on the factor. */
+ * ct_solve_fused's requirements on the factor; Rh (see ct_solve_fused) is
+ * built before the capture. */
 int ct_solve_graph_create_fused(const ct_factor* f, void* B, int64_t ldb, int64_t b_cols, int64_t max_cols,
                                 int32_t* desc, void* stream, ct_solve_graph** g);
 
