@@ -583,75 +583,81 @@ __device__ __forceinline__ void narrow_phase_b2(const FusedArgs& a, char* lds, i
 }
 
 // C: B[k0 + r, j] -= sum_c V[r, c] W'[c][j] over the rows of range g, last row
-// group first; thread t holds W' of its four columns, each group of 8 rows is
-// reduce-scattered over the wavefront (lane 8u + j: row u, column j) and the
-// four wavefronts' sums added by wavefront 0 (double-buffered, one barrier a
-// group).  The B values come from the LDS copy phase A staged when the range
-// is one chunk.
+// group first, as MFMA products (16 x 16 x 4, FP32): wavefront w takes columns
+// 256w .. 256w + 255 of 16 rows at a time, lane (c, g4) = (lane % 16, lane / 16)
+// loading row c's columns 256w + 16k + 4g4 .. +3 (k < 16) as one 16-byte
+// vector whose four values are the A operands of four MFMAs; the B operands
+// (W' of the same columns, rhs c, zero for c >= 8) stay in registers.  The
+// four wavefronts' 16 x 16 tiles are added through LDS (double-buffered, one
+// barrier a group).  The B values come from the LDS copy phase A staged when
+// the range is one chunk.
+constexpr int kNarrowCr = 16;                 // rows per MFMA group
+
 __device__ __forceinline__ void narrow_phase_c(const FusedArgs& a, char* lds, float* Bc, int kc, int64_t b, int bo,
                                                int64_t mk, const float* Wt)
 {
-    const int g = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    const int g = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int c16 = lane & 15, g4 = lane >> 4;
     if (g >= a.nrw) return;
     int64_t rb, re;
     narrow_range(mk, a.nrw, g, rb, re);
     if (rb >= re) return;
     const int64_t k0 = b * a.nbo;
     const int ldv = (bo + 15) / 16 * 16;
-    const float* Vb = (const float*)a.Vt + fused_vt_off(a, b) + 4 * t;
-    const bool cv = 4 * t < ldv;
-    const int nvc = bo - 4 * t;                         // valid columns of this thread (<= 0: none)
-    float w[4][kNarrow];
+    const int cb = 256 * w + 4 * g4;              // this lane's first column; slab k adds 16k
+    const float* Vb = (const float*)a.Vt + fused_vt_off(a, b) + cb;
+    float wf[16][4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int c = 4 * t + q;
-        if (c < bo) {
-            const float4 x0 = *(const float4*)(Wt + (size_t)c * kNarrow), x1 = *(const float4*)(Wt + (size_t)c * kNarrow + 4);
-            w[q][0] = x0.x; w[q][1] = x0.y; w[q][2] = x0.z; w[q][3] = x0.w;
-            w[q][4] = x1.x; w[q][5] = x1.y; w[q][6] = x1.z; w[q][7] = x1.w;
-        } else {
+    for (int k = 0; k < 16; ++k)
 #pragma unroll
-            for (int j = 0; j < kNarrow; ++j) w[q][j] = 0.f;
+        for (int q = 0; q < 4; ++q) {
+            const int col = cb + 16 * k + q;
+            wf[k][q] = (c16 < kNarrow && col < bo) ? Wt[(size_t)col * kNarrow + c16] : 0.f;
         }
-    }
     float* Bs = (float*)lds;
-    float* red = (float*)(lds + kNarrowWs);             // 2 x 4 waves x 64
-    constexpr int GR = kNarrowGr;
+    float* red = (float*)(lds + kNarrowWs);       // 2 x 4 wavefronts x 16 x 16
+    constexpr int GR = kNarrowCr;
     const int64_t nch = (re - rb + kNarrowCh - 1) / kNarrowCh;
     for (int64_t ch = nch - 1; ch >= 0; --ch) {
         const int64_t c0 = rb + ch * kNarrowCh;
         const int64_t c1 = c0 + kNarrowCh < re ? c0 + kNarrowCh : re;
         const int ng = (int)((c1 - c0 + GR - 1) / GR);
         // group i: rows c1 - GR (i + 1) .. c1 - GR i - 1, those below c0 masked
-        float4 va[GR], vb[GR];
-        auto ld = [&](float4 (&v)[GR], int i) {
+        float4 va[16], vb[16];
+        auto ld = [&](float4 (&v)[16], int i) {
+            const int64_t r = c1 - (int64_t)GR * (i + 1) + c16;
+            const bool rv = i < ng && r >= c0;
 #pragma unroll
-            for (int u = 0; u < GR; ++u) {
-                const int64_t r = c1 - (int64_t)GR * (i + 1) + u;
-                float4 x = (i < ng && r >= c0 && cv) ? *(const float4*)(Vb + r * ldv) : float4{0.f, 0.f, 0.f, 0.f};
-                if (nvc < 4) {
-                    x.y = nvc > 1 ? x.y : 0.f;
-                    x.z = nvc > 2 ? x.z : 0.f;
+            for (int k = 0; k < 16; ++k) {
+                const int col = cb + 16 * k;
+                float4 x = (rv && col < ldv) ? *(const float4*)(Vb + r * ldv + 16 * k) : float4{0.f, 0.f, 0.f, 0.f};
+                if (col + 4 > bo) {           // past the last column (the padding of a narrow last block)
+                    x.x = col < bo ? x.x : 0.f;
+                    x.y = col + 1 < bo ? x.y : 0.f;
+                    x.z = col + 2 < bo ? x.z : 0.f;
                     x.w = 0.f;
-                    x.x = nvc > 0 ? x.x : 0.f;
                 }
-                v[u] = x;
+                v[k] = x;
             }
         };
-        auto grp = [&](const float4 (&v)[GR], int i) {
-            float pv[GR * kNarrow];
+        auto grp = [&](const float4 (&v)[16], int i) {
+            f4v acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int u = 0; u < GR; ++u)
+            for (int k = 0; k < 16; ++k) {
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(v[k].x, wf[k][0], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(v[k].y, wf[k][1], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(v[k].z, wf[k][2], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(v[k].w, wf[k][3], acc, 0, 0, 0);
+            }
+            // lane (c16, g4) holds rows 4 g4 .. 4 g4 + 3 of column c16
+            float* rd = red + (i & 1) * 1024;
 #pragma unroll
-                for (int j = 0; j < kNarrow; ++j)
-                    pv[u * kNarrow + j] = v[u].x * w[0][j] + v[u].y * w[1][j] + v[u].z * w[2][j] + v[u].w * w[3][j];
-            const float sv = wave_reduce_scatter<float, GR * kNarrow>(pv, lane);
-            float* rd = red + (i & 1) * 256;
-            rd[wv * 64 + lane] = sv;
+            for (int q = 0; q < 4; ++q) rd[w * 256 + (4 * g4 + q) * 16 + c16] = acc[q];
             lds_barrier();
-            if (t < 64) {
-                const float sum = ((rd[t] + rd[64 + t]) + rd[128 + t]) + rd[192 + t];
+            if (t < GR * kNarrow) {
                 const int u = t >> 3, j = t & 7;
+                const float sum = ((rd[u * 16 + j] + rd[256 + u * 16 + j]) + rd[512 + u * 16 + j]) + rd[768 + u * 16 + j];
                 const int64_t r = c1 - (int64_t)GR * (i + 1) + u;
                 if (r >= c0 && j < kc) Bc[k0 + r + (int64_t)j * a.ldb] = Bs[8 * (r - c0) + j] - sum;
             }
