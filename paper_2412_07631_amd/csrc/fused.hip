@@ -4,22 +4,25 @@
 //
 // The batch is taken in chunks of KC columns.  Per chunk:
 //   Q^T B, outer block by outer block (Q = I - V T V^T per block, compact WY):
-//     A   W partials: the rows of the block split in row groups, its columns in
-//         groups of 128; each workgroup sums V[rows, cols]^T B[rows] over its
+//     A   W partials: each workgroup sums V[rows, cols]^T B[rows] over its
 //         rows (V from the row-major reflector copy, B staged in LDS)
 //     B1  W = sum of the partials (fixed order, FP64)
 //     B2  W' = T^T W (T upper triangular, FP64)
-//     C   B[rows] -= V[rows, :] W', the rows split over all workgroups
+//     C   B[rows] -= V[rows, :] W', the rows split over the workgroups
 //     with a grid-wide barrier after each phase;
-//   R^{-1}: back-substitution over 256-row blocks, block q owned by workgroup
-//     q mod G; the owner of block q, once every later block's x has been
-//     applied to its rows, multiplies by the stored inverse of R_qq and
-//     publishes x_q with a flag; every workgroup takes the published x_b in
-//     order b = last .. 1 and subtracts R[q, b] x_b from the rows it owns,
-//     first the block right below in the chain, which it then solves at once.
-// All arithmetic is FMA in the storage type (W and T W in FP64).  The
-// cross-workgroup waits are bounded in time like the factorization's (bit 3
-// of the error word on a time-out).
+//   R^{-1}: back-substitution over 256-row blocks whose x blocks are
+//     published to the other workgroups through flags as the chain of
+//     dependent blocks reaches them.
+// Two forms.  Chunks of at most 8 columns of an FP32-storage factor (the
+// latency path): one contiguous row range per workgroup in phases A and C,
+// phase C as MFMA products, and a back-substitution on Rh =
+// blockdiag(R_qq^{-1}) R with each block split over four workgroups
+// (narrow_*).  Wider chunks and FP64 factors: row groups x 128-column groups
+// in phase A, FMA products, and a back-substitution that multiplies each
+// block by its stored inverse on the chain, one workgroup per block
+// (fused_phase_*, fused_update, fused_solve_block).  The cross-workgroup
+// waits are bounded in time like the factorization's (bit 3 of the error
+// word on a time-out).
 #include "ct_internal.h"
 
 namespace ctqr {
