@@ -94,6 +94,8 @@ hipError_t launch_copy_block(const TS* src, int64_t lds, TS* dst, int64_t ldd, i
                              const int32_t* desc);
 hipError_t rinv_set_max_lds(size_t bytes);
 hipError_t launch_diag_x3(const float* Ri, float* B, int64_t ldb, int bo, int nrhs, hipStream_t s);
+hipError_t launch_diag_f32(const float* Ri, float* B, int64_t ldb, int bo, int nrhs, const int32_t* desc,
+                           hipStream_t s);
 hipError_t launch_residual(const int64_t* row_ptr, const int32_t* col, const double* val, int64_t m, const double* X,
                            int64_t ldx, const double* B, int64_t ldb, double* R, int64_t ldr, int nrhs,
                            hipStream_t s);
@@ -1058,11 +1060,14 @@ static int inner_solve(ct_factor* f, TS* C, int64_t ldc, int64_t ncols, int64_t 
         const int bo = (int)std::min<int64_t>(256, n - k0);
         int nz;
         bool done = false;
-        if constexpr (sizeof(TS) == 4)
-            if (x3 && !desc) {
+        if constexpr (sizeof(TS) == 4) {
+            if (x3 && !desc)
                 CT_HIP(launch_diag_x3((const float*)f->RiR + (size_t)b * 256 * 256, C + k0, ldc, bo, (int)ncols, s));
-                done = true;
-            }
+            else
+                CT_HIP(launch_diag_f32((const float*)f->RiR + (size_t)b * 256 * 256, C + k0, ldc, bo, (int)ncols, desc,
+                                       s));
+            done = true;
+        }
         if (!done) {
             CT_HIP((launch_copy_block<TS>(C + k0, ldc, S, 256, bo, (int)ncols, s, desc)));
             CT_HIP(launch_nt<TS>((const TS*)f->RiR + (size_t)b * 256 * 256, 256, S, 256, C + k0, ldc, bo, (int)ncols,
@@ -1227,11 +1232,14 @@ static int trsm_lt_impl(const ct_factor* fc, TS* Y, int64_t k, int64_t ldy, hipS
                 const int bo = (int)std::min<int64_t>(256, n - k0);
                 int nz;
                 bool done = false;
-                if constexpr (sizeof(TS) == 4)
-                    if (x3) {
+                if constexpr (sizeof(TS) == 4) {
+                    if (x3)
                         CT_HIP(launch_diag_x3((const float*)f->RiC + (size_t)b * 256 * 256, Y + k0, ldy, bo, (int)k, s));
-                        done = true;
-                    }
+                    else
+                        CT_HIP(launch_diag_f32((const float*)f->RiC + (size_t)b * 256 * 256, Y + k0, ldy, bo, (int)k,
+                                               nullptr, s));
+                    done = true;
+                }
                 if (!done) {
                     CT_HIP((launch_copy_block<TS>(Y + k0, ldy, S, 256, bo, (int)k, s, nullptr)));
                     CT_HIP(launch_nt<TS>((const TS*)f->RiC + (size_t)b * 256 * 256, 256, S, 256, Y + k0, ldy, bo,

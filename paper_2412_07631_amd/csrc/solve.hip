@@ -785,6 +785,88 @@ hipError_t launch_diag_x3(const float* Ri, float* B, int64_t ldb, int bo, int nr
     return hipGetLastError();
 }
 
+// The same diagonal step in FP32 on the FP32 MFMA (16 x 16 x 4), for FP32
+// factors and graph-captured solves: B[0:bo, q] <- Ri B[0:bo, q] in place,
+// one launch instead of a copy and a split product.  Workgroup w (512
+// threads) takes slices 16w .. 16w + 15 (of the batch record's columns when
+// desc is given: offset desc[0], count desc[1], at most nrhs) and stages them
+// in LDS; wave v forms rows 32v .. 32v + 31 as two 16 x 16 tiles.  Lane (c, g)
+// supplies row c's K values 16s + 4g .. 16s + 4g + 3 of each 16-wide slab s as
+// one 16-byte load (the A operands of four MFMAs), all of them issued before
+// the first product (the inverse block is read cold, once per step), and reads
+// column c's matching four values from LDS.
+template <bool FULL>
+__global__ void __launch_bounds__(512) diag_f32_kernel(const float* __restrict__ Ri, float* __restrict__ B, int64_t ldb,
+                                                       int bo, int nrhs, const int32_t* desc)
+{
+    constexpr int LDK = 256 + 4;
+    __shared__ __attribute__((aligned(16))) float Bs[16 * LDK];
+    int cnt = nrhs;
+    if (desc) {
+        B += (int64_t)desc[0] * ldb;
+        if (desc[1] < cnt) cnt = desc[1];
+    }
+    const int q0 = blockIdx.x * 16;
+    if (q0 >= cnt) return;
+    const int t = threadIdx.x;
+    const int lane = t & 63, wv = t >> 6;
+    const int c = lane & 15, g = lane >> 4;
+    f4_t a[2][16];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int p = 32 * wv + 16 * i + c;
+#pragma unroll
+        for (int sl = 0; sl < 16; ++sl) {
+            const int k = 16 * sl + 4 * g;
+            if (FULL || (p < bo && k + 4 <= bo)) {
+                a[i][sl] = *(const f4_t*)(Ri + (int64_t)p * 256 + k);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) a[i][sl][e] = (p < bo && k + e < bo) ? Ri[(int64_t)p * 256 + k + e] : 0.f;
+            }
+        }
+    }
+    {
+        const int row = t & 255, qh = (t >> 8) * 8;
+#pragma unroll
+        for (int qs = 0; qs < 8; ++qs) {
+            const int q = q0 + qh + qs;
+            Bs[(qh + qs) * LDK + row] = (q < cnt && (FULL || row < bo)) ? B[(int64_t)q * ldb + row] : 0.f;
+        }
+    }
+    __syncthreads();
+    f4_t acc[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) acc[i] = f4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int sl = 0; sl < 16; ++sl) {
+        const f4_t bq = *(const f4_t*)&Bs[c * LDK + 16 * sl + 4 * g];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][sl][e], bq[e], acc[i], 0, 0, 0);
+    }
+    const int q = q0 + c;
+    if (q >= cnt) return;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int p = 32 * wv + 16 * i + 4 * g + r;
+            if (p < bo) B[(int64_t)q * ldb + p] = acc[i][r];
+        }
+}
+
+hipError_t launch_diag_f32(const float* Ri, float* B, int64_t ldb, int bo, int nrhs, const int32_t* desc,
+                           hipStream_t s)
+{
+    if (nrhs <= 0 || bo <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((nrhs + 15) / 16));
+    if (bo == 256) hipLaunchKernelGGL(diag_f32_kernel<true>, grid, dim3(512), 0, s, Ri, B, ldb, bo, nrhs, desc);
+    else hipLaunchKernelGGL(diag_f32_kernel<false>, grid, dim3(512), 0, s, Ri, B, ldb, bo, nrhs, desc);
+    return hipGetLastError();
+}
+
 hipError_t rinv_set_max_lds(size_t bytes)
 {
     return hipFuncSetAttribute((const void*)rinv128_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
