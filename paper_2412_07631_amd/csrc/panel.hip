@@ -875,9 +875,13 @@ __global__ void __launch_bounds__(256) panel_cqr_kernel(PanelArgs<TS> a)
 #pragma unroll
                 for (int c = 0; c < 32; ++c) x[c] = (c >= i && c < nbp) ? -K3[i + 32 * c] * Sv[c] : 0.0;
                 row_times_inv<true>(x, K3, nullptr);
+                double ti = 0.0;   // x[i], chosen without a dynamic index (which would put x in scratch)
 #pragma unroll
-                for (int c = 0; c < 32; ++c) L.Tl[c * 33 + i] = x[c];
-                a.tau[i] = x[i];
+                for (int c = 0; c < 32; ++c) {
+                    L.Tl[c * 33 + i] = x[c];
+                    ti = c == i ? x[c] : ti;
+                }
+                a.tau[i] = ti;
             }
         }
         __syncthreads();
