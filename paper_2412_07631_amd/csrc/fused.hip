@@ -82,6 +82,33 @@ __device__ inline bool fused_wait(uint32_t* p, uint32_t v, bool want_ne, int32_t
     }
 }
 
+// Bounded spin of thread 0 until the four words p[0..3] all equal v: the four
+// loads of a round are issued together (one memory round trip a poll, not
+// four).
+__device__ inline bool fused_wait4(uint32_t* p, uint32_t v, int32_t* err, uint64_t ticks)
+{
+    uint64_t t0 = 0;
+    uint32_t spins = 0;
+    for (;;) {
+        const uint32_t x0 = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t x1 = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t x2 = __hip_atomic_load(p + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t x3 = __hip_atomic_load(p + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (x0 == v && x1 == v && x2 == v && x3 == v) return true;
+        __builtin_amdgcn_s_sleep(1);
+        if ((++spins & 15) == 0) {
+            const uint64_t now = __builtin_amdgcn_s_memrealtime();
+            if (spins == 16) {
+                t0 = now;
+            } else if (now - t0 >= ticks) {
+                fused_err(err);
+                return false;
+            }
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & (kFusedErr | 1)) return false;
+        }
+    }
+}
+
 // Grid-wide barrier: the last workgroup to arrive resets the count and
 // advances the generation; the others wait for the generation to change.
 // Self-resetting, so one reset before the launch is all it needs.  Only
@@ -916,9 +943,7 @@ __device__ __forceinline__ bool narrow_backsub(const FusedArgs& a, char* lds, in
         float S[64];
         if (kan >= 0) narrow_slice(a, an, san, bb, S);     // the critical path's slice, before the wait
         if (t == 0) {
-            bool ok = true;
-#pragma unroll
-            for (int s = 0; s < 4; ++s) ok = ok && fused_wait(flags + 4 * bb + s, stamp, false, a.err, a.wait_ticks);
+            const bool ok = fused_wait4(flags + 4 * bb, stamp, a.err, a.wait_ticks);
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             *sflag = ok ? 1 : 0;
         }
