@@ -826,8 +826,10 @@ __device__ __forceinline__ const TS* r_block(const FusedArgs& a, int64_t q, int6
 // the owner of a quarter of block bb - 1 applies x_bb with the slice it loaded
 // before waiting, adds its four wavefronts' sums and publishes those 64 rows
 // of x_{bb-1} (flag per quarter); then every workgroup applies x_bb to its
-// other quarters, the highest block first (the next on the chain).  (Loading
-// the next block's slice before the wait too made the chain slower.)
+// other quarters, the highest block first (the next on the chain).  The
+// quarters' partial sums live in LDS, each thread's in its own slots, so that
+// a quarter is addressed by its index at run time (no unrolled copy of the
+// update per quarter).
 constexpr int kNarrowMaxQ = 8;     // quarters a workgroup (blocks <= 2 G)
 
 // Columns 64w .. 64w + 63 of block b in rows 64 s + lane of block q of Rh
@@ -891,50 +893,87 @@ __device__ __forceinline__ void narrow_publish(const FusedArgs& a, float* red, c
     }
 }
 
+__device__ __forceinline__ void narrow_pload(const float* pl, int k, float (&v)[kNarrow])
+{
+    const float4* q = (const float4*)(pl + ((size_t)k * 256 + threadIdx.x) * kNarrow);
+    const float4 a = q[0], b = q[1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+
+__device__ __forceinline__ void narrow_pstore(float* pl, int k, const float (&v)[kNarrow])
+{
+    float4* q = (float4*)(pl + ((size_t)k * 256 + threadIdx.x) * kNarrow);
+    q[0] = float4{v[0], v[1], v[2], v[3]};
+    q[1] = float4{v[4], v[5], v[6], v[7]};
+}
+
+// x_b (in LDS) applied to this workgroup's quarters below block lim, the
+// highest first: quarters 0 .. kq - 1 of the workgroup (blocks rise with k).
+__device__ __forceinline__ void narrow_bulk(const FusedArgs& a, float* pl, const float* xsrc, int64_t b, int64_t lim)
+{
+    const int G = gridDim.x, g = blockIdx.x;
+    const int64_t nbq = (a.n + 255) / 256;
+    int kq = 0;
+    for (int k = 0; k < kNarrowMaxQ; ++k) {
+        const int64_t Qd = g + (int64_t)G * k;
+        if (Qd < 4 * nbq && (Qd >> 2) < lim) kq = k + 1;
+    }
+    for (int k = kq - 1; k >= 0; --k) {
+        const int64_t Qd = g + (int64_t)G * k;
+        float S[64], v[kNarrow];
+        narrow_slice(a, Qd >> 2, (int)(Qd & 3), b, S);
+        narrow_pload(pl, k, v);
+        narrow_fma<true>(v, S, xsrc);
+        narrow_pstore(pl, k, v);
+    }
+}
+
 __device__ __forceinline__ bool narrow_backsub(const FusedArgs& a, char* lds, int* sflag, float* Bc, int kc,
                                                uint32_t* flags, float* Xp, uint32_t stamp)
 {
     const int G = gridDim.x, g = blockIdx.x, t = threadIdx.x, w = t >> 6;
     const int64_t nbq = (a.n + 255) / 256;
-    float* xs = (float*)lds;                      // 256 x 8
+    float* xs = (float*)lds;                      // 256 x 8: x_bb
     float* red = xs + 256 * kNarrow;              // 4 wavefronts x 64 rows x 8
-    float p[kNarrowMaxQ][kNarrow];
+    float* pl = red + 4 * 64 * kNarrow;           // the quarters' partial sums, each thread its own (k, t) slots
     // p = wavefront w's part of R_qq^{-1} c_q for every quarter owned
-#pragma unroll
     for (int k = 0; k < kNarrowMaxQ; ++k) {
-#pragma unroll
-        for (int j = 0; j < kNarrow; ++j) p[k][j] = 0.f;
         const int64_t Qd = g + (int64_t)G * k;
-        if (Qd < 4 * nbq) {
-            const int64_t q = Qd >> 2;
-            const int s = (int)(Qd & 3);
-            const int bo = (int)(a.n - 256 * q < 256 ? a.n - 256 * q : 256);
-            float S[64];
-            const float* Ri = (const float*)a.RiC + (size_t)q * 65536 + (size_t)(64 * w) * 256 + 64 * s + (t & 63);
+        if (Qd >= 4 * nbq) break;
+        const int64_t q = Qd >> 2;
+        const int s = (int)(Qd & 3);
+        const int bo = (int)(a.n - 256 * q < 256 ? a.n - 256 * q : 256);
+        float S[64], v[kNarrow];
+        const float* Ri = (const float*)a.RiC + (size_t)q * 65536 + (size_t)(64 * w) * 256 + 64 * s + (t & 63);
 #pragma unroll
-            for (int u = 0; u < 64; ++u) S[u] = 64 * w + u < bo ? Ri[(size_t)u * 256] : 0.f;
-            __syncthreads();                      // earlier readers of xs are done
-            {
-                float bv[kNarrow];
+        for (int u = 0; u < 64; ++u) S[u] = 64 * w + u < bo ? Ri[(size_t)u * 256] : 0.f;
+        __syncthreads();                          // earlier readers of xs are done
+        {
+            float bv[kNarrow];
 #pragma unroll
-                for (int j = 0; j < kNarrow; ++j) bv[j] = (t < bo && j < kc) ? Bc[256 * q + t + (int64_t)j * a.ldb] : 0.f;
-                *(float4*)(xs + t * 8) = float4{bv[0], bv[1], bv[2], bv[3]};
-                *(float4*)(xs + t * 8 + 4) = float4{bv[4], bv[5], bv[6], bv[7]};
-            }
-            __syncthreads();
-            narrow_fma<false>(p[k], S, xs);
+            for (int j = 0; j < kNarrow; ++j) bv[j] = (t < bo && j < kc) ? Bc[256 * q + t + (int64_t)j * a.ldb] : 0.f;
+            *(float4*)(xs + t * 8) = float4{bv[0], bv[1], bv[2], bv[3]};
+            *(float4*)(xs + t * 8 + 4) = float4{bv[4], bv[5], bv[6], bv[7]};
         }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kNarrow; ++j) v[j] = 0.f;
+        narrow_fma<false>(v, S, xs);
+        narrow_pstore(pl, k, v);
     }
     const int64_t last = nbq - 1;
-#pragma unroll
     for (int k = 0; k < kNarrowMaxQ; ++k) {
         const int64_t Qd = g + (int64_t)G * k;
-        if (Qd < 4 * nbq && (Qd >> 2) == last) narrow_publish(a, red, p[k], last, (int)(Qd & 3), Bc, kc, Xp, flags, stamp);
+        if (Qd < 4 * nbq && (Qd >> 2) == last) {
+            float v[kNarrow];
+            narrow_pload(pl, k, v);
+            narrow_publish(a, red, v, last, (int)(Qd & 3), Bc, kc, Xp, flags, stamp);
+        }
     }
     for (int64_t bb = last; bb >= 1; --bb) {
         const int64_t an = bb - 1;
         int kan = -1, san = 0;
-#pragma unroll
         for (int s = 0; s < 4; ++s)
             if ((4 * an + s) % G == g) {
                 kan = (int)((4 * an + s) / G);
@@ -955,22 +994,13 @@ __device__ __forceinline__ bool narrow_backsub(const FusedArgs& a, char* lds, in
             ((float4*)xs)[t + 256] = src[t + 256];
         }
         __syncthreads();
-#pragma unroll
-        for (int k = 0; k < kNarrowMaxQ; ++k)
-            if (k == kan) {
-                narrow_fma<true>(p[k], S, xs);
-                narrow_publish(a, red, p[k], an, san, Bc, kc, Xp, flags, stamp);
-            }
-#pragma unroll
-        for (int k = kNarrowMaxQ - 1; k >= 0; --k) {
-            const int64_t Qd = g + (int64_t)G * k;
-            const int64_t q = Qd >> 2;
-            if (Qd < 4 * nbq && q < an) {
-                float S2[64];
-                narrow_slice(a, q, (int)(Qd & 3), bb, S2);
-                narrow_fma<true>(p[k], S2, xs);
-            }
+        if (kan >= 0) {
+            float v[kNarrow];
+            narrow_pload(pl, kan, v);
+            narrow_fma<true>(v, S, xs);
+            narrow_publish(a, red, v, an, san, Bc, kc, Xp, flags, stamp);
         }
+        narrow_bulk(a, pl, xs, bb, an);
     }
     return true;
 }
