@@ -16,7 +16,9 @@
  *    Matrices are column-major with an explicit leading dimension, which must
  *    be a multiple of 16 elements; device arrays must be 256-byte aligned.
  *  - The caller allocates and frees all memory.  The library never frees a
- *    caller buffer and allocates device memory only in ct_siddon_rows.
+ *    caller buffer and allocates device memory only in ct_siddon_rows and
+ *    in the first fused solve (or fused graph) of an FP32-storage factor,
+ *    whose Rh the factor then owns (freed by ct_factor_destroy).
  *  - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
  *    work and return without waiting, except ct_status and ct_siddon_rows.
  *    Calls that share a factor must be ordered on one stream.
