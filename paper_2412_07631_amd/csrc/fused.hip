@@ -381,13 +381,13 @@ __device__ __forceinline__ void fused_phase_c(const FusedArgs& a, char* lds, TS*
 // columns 4t .. 4t+3 of the row-major reflector copy: one wavefront load reads
 // 1 KB of a row, the workgroup reads whole rows, and every workgroup streams
 // one contiguous stretch of the block.  Phase C walks its range backwards, so
-// that the rows phase A read last (the likeliest still cached) come first.
-// LDS: the range's B rows (row-major, 8 floats a row) at 0, the FP64 W of
-// phase B2 and the reduction buffers at kNarrowWs.
+// that the rows phase A read last (the likeliest still cached) come first;
+// its products are MFMAs.  LDS: the range's B rows (row-major, 8 floats a
+// row) at 0, the FP64 W of phase B2 and the reduction buffers at kNarrowWs.
 constexpr int kNarrow = 8;
 constexpr int kNarrowCh = 1024;                       // B rows staged at a time
-constexpr int kNarrowGr = 8;                          // rows per group (8 rows x 8 columns = 64 lanes)
-constexpr int kNarrowStage = kNarrowCh + 4 * kNarrowGr; // staged rows: phase A reads up to 4 groups past the chunk
+constexpr int kNarrowGr = 8;                          // rows per group of phase A's loads (two groups in flight)
+constexpr int kNarrowStage = kNarrowCh + 4 * kNarrowGr; // staged rows: phase A reads up to two groups past the chunk
 constexpr size_t kNarrowWs = 34816;
 static_assert(kNarrowWs >= (size_t)kNarrowStage * kNarrow * 4, "B rows overlap the FP64 W");
 static_assert(kNarrowWs + (1024 + 4) * kNarrow * 8 <= 131072, "narrow phases exceed the LDS of the wide ones");
