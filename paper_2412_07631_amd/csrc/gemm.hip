@@ -426,6 +426,29 @@ __global__ void __launch_bounds__(256) sum_slices_kernel(const TWp* __restrict__
     }
 }
 
+// The same sum for a small output (a few slices' worth of columns): 64
+// elements a workgroup, its four wavefronts summing every fourth slice, the
+// four partial sums added in a fixed order (four times the workgroups, a
+// quarter of the dependent loads a thread).
+template <typename TWp, typename TS>
+__global__ void __launch_bounds__(256) sum_slices4_kernel(const TWp* __restrict__ Wp, int64_t wstride, int nz,
+                                                          int64_t count, TS* __restrict__ S, const int32_t* desc,
+                                                          int per_col)
+{
+    __shared__ double red[4][64];
+    if (desc) count = (int64_t)per_col * desc_count(desc, (int)(count / per_col));
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+    double s = 0.0;
+    if (e < count) {
+#pragma unroll 8
+        for (int z = wv; z < nz; z += 4) s += (double)Wp[(int64_t)z * wstride + e];
+    }
+    red[wv][lane] = s;
+    __syncthreads();
+    if (wv == 0 && e < count) S[e] = (TS)(((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]);
+}
+
 // ------------------------------------------------------------------ launchers
 static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
@@ -507,6 +530,12 @@ template <typename TWp, typename TS>
 hipError_t launch_sum_slices(const TWp* Wp, int64_t wstride, int nz, int64_t count, TS* S, hipStream_t s,
                              const int32_t* desc, int per_col)
 {
+    if (count <= 65536 && nz >= 8) {
+        // few outputs, many slices: split the slices over the wavefronts
+        hipLaunchKernelGGL((sum_slices4_kernel<TWp, TS>), dim3((unsigned)((count + 63) / 64)), dim3(256), 0, s, Wp,
+                           wstride, nz, count, S, desc, per_col > 0 ? per_col : 1);
+        return hipGetLastError();
+    }
     int64_t blocks = (count + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL((sum_slices_kernel<TWp, TS>), dim3((unsigned)blocks), dim3(256), 0, s, Wp, wstride, nz, count,
